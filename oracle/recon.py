@@ -1,0 +1,88 @@
+"""Oracle: Algorithm 1, the MS-LLR reconstruction (Sec. III-C, III-D).
+
+TEST INFRASTRUCTURE ONLY.
+
+  X^0 = A^H b,  M^0 = Phi_D(X^0),  L^0 from M^0,  lambda1 = lambda1^0 max(L^0)
+  repeat for n = 0 .. N_max - 1:
+    Z^n     = P_S(X^n - mu [A^H(A X^n - b) + lambda1 Q*(Q(X^n) L^n)])          eq. (15)
+    P^{n+1} = SVT_{1/beta}(Q_q(X^n)) for every patch                            eq. (22)
+    X^{n+1} = (Z^n + mu lam2 beta Q*(P^{n+1})) / (1 + mu lam2 beta c)          eq. (23)
+    cost(n+1) = (1/2)||A X^{n+1} - b||^2 + lambda1 Tr(Q L^n Q^H) + lam2 sum ||Q_q X^{n+1}||_*
+    stop if cost(n)/cost(n+1) - 1 < tol
+    M^{n+1} = Phi_D(X^{n+1}),  L^{n+1} from M^{n+1},  lambda1 = lambda1^0 max(L^{n+1})
+  output X, Phi_D(X)
+
+Readings (beyond those of the operator modules):
+  * cost(0) is evaluated on X^0 with L^0 so that the first stopping test has a
+    predecessor; a tolerance of None runs exactly N_max iterations;
+  * step size mu = min(mu0, 1 / (lamA + 2 c_max lambda1 max(L))): lamA bounds
+    lambda_max(A^H A) and 2 c_max max(L) bounds the Laplacian term (Gershgorin), so the
+    paper's mu = 1 is kept whenever it is stable; lamA <= 0 keeps mu = mu0;
+  * the per-iteration match uses the subspace form with the projection basis V.
+Pins: with lambda1 = lambda2 = 0 and V = I the loop is a Landweber iteration that
+converges to the least-squares solution (numpy.linalg.lstsq on a tiny dense operator).
+"""
+import numpy as np
+
+from . import graph, match, nufft, ops
+from .patches import coverage
+
+
+def step_size(mu0, lamA, lam1, lmax, cmax):
+    if lamA is None or lamA <= 0:
+        return float(mu0)
+    return float(min(mu0, 1.0 / (lamA + 2.0 * cmax * lam1 * lmax)))
+
+
+def recon(b, traj, atoms, lut, V, N, p, s, K, r_llr, lam1_0=0.1, lam2=0.1, beta=0.2,
+          mu0=1.0, lamA=0.0, sigma2=0.0, n_max=10, tol=None, osf=2, W=6, X0=None):
+    """Return dict(X, maps, idx, rho, stats)."""
+    b = np.asarray(b, np.complex128)
+    V = np.asarray(V, np.complex128)
+    tau = 1.0 / beta
+    cmax = float(coverage(N, p, s).max())
+
+    def fwd(X):
+        return nufft.nufft_fwd(X, traj, osf, W)
+
+    def adj(r):
+        return nufft.nufft_adj(r, traj, N, osf, W)
+
+    def rebuild(X):
+        idx, rho, _, _ = match.match_subspace(X, atoms, lut, V)
+        maps = match.maps_from_match(idx, rho, lut, N)
+        g = graph.knn_laplacian(maps, p, s, K, sigma2)
+        return g
+
+    X = adj(b) if X0 is None else np.asarray(X0, np.complex128)
+    g = rebuild(X)
+    Lap, lam1 = g["L"], lam1_0 * g["lmax"]
+    mu = step_size(mu0, lamA, lam1, g["lmax"], cmax)
+    r = fwd(X) - b
+    nuc = ops.nuclear_norm(X, p, s)
+    c_prev, terms = ops.cost(r, X, Lap, lam1, lam2, nuc, p, s)
+    stats = dict(cost=[c_prev], terms=[terms], mu=[mu], lam1=[lam1], sigma2=[g["sigma2"]],
+                 lmax=[g["lmax"]], iters=0, stop="max_iter")
+    for n in range(n_max):
+        grad = adj(r) + lam1 * ops.laplacian_apply(X, Lap, p, s)
+        Z = ops.project(X - mu * grad, V)
+        QtP, _ = ops.llr_prox(X, p, s, tau, r_llr)
+        X = ops.x_update(Z, QtP, mu, lam2, beta, p, s)
+        r = fwd(X) - b
+        nuc = ops.nuclear_norm(X, p, s)
+        c, terms = ops.cost(r, X, Lap, lam1, lam2, nuc, p, s)
+        stats["cost"].append(c); stats["terms"].append(terms)
+        stats["iters"] = n + 1
+        if tol is not None and c_prev / c - 1.0 < tol:
+            stats["stop"] = "tolerance"
+            break
+        c_prev = c
+        if n + 1 < n_max:
+            g = rebuild(X)
+            Lap, lam1 = g["L"], lam1_0 * g["lmax"]
+            mu = step_size(mu0, lamA, lam1, g["lmax"], cmax)
+            stats["mu"].append(mu); stats["lam1"].append(lam1)
+            stats["sigma2"].append(g["sigma2"]); stats["lmax"].append(g["lmax"])
+    idx, rho, score, params = match.match_subspace(X, atoms, lut, V)
+    maps = match.maps_from_match(idx, rho, lut, N)
+    return dict(X=X, maps=maps, idx=idx, rho=rho, score=score, stats=stats)

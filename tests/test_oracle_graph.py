@@ -1,0 +1,79 @@
+"""Pins of the oracle's graph Laplacian (eqs. (7)-(11))."""
+import numpy as np
+import pytest
+import scipy.spatial.distance
+
+from oracle import graph, ops, patches
+
+
+def test_three_node_example_eq11():
+    w12, w13, w23 = 0.3, 0.7, 0.11
+    W = np.array([[0, w12, w13], [w12, 0, w23], [w13, w23, 0]])
+    expect = np.array([[w12 + w13, -w12, -w13],
+                       [-w12, w12 + w23, -w23],
+                       [-w13, -w23, w13 + w23]])
+    np.testing.assert_array_equal(graph.laplacian_from_weights(W), expect)
+
+
+def _rand_maps(rng, N):
+    return np.stack([rng.uniform(300, 2500, (N, N)), rng.uniform(40, 300, (N, N)), rng.uniform(0, 100, (N, N))])
+
+
+@pytest.mark.parametrize("K", [1, 4, 8])
+def test_laplacian_is_symmetric_psd_with_zero_row_sums(K):
+    rng = np.random.default_rng(K)
+    g = graph.knn_laplacian(_rand_maps(rng, 12), 4, 2, K)
+    L = g["L"]
+    assert np.allclose(L, L.T, atol=0, rtol=0)
+    assert np.max(np.abs(L.sum(axis=1))) <= 1e-12
+    assert np.linalg.eigvalsh(L).min() >= -1e-12
+    assert g["lmax"] == np.max(np.diag(L))
+
+
+def test_dense_graph_when_K_is_Np_minus_1():
+    rng = np.random.default_rng(7)
+    maps = _rand_maps(rng, 10)
+    F = graph.patch_features(maps, 4, 2)
+    Np = F.shape[0]
+    sig2 = 0.37
+    g = graph.knn_laplacian(maps, 4, 2, Np - 1, sigma2=sig2)
+    W = np.exp(-scipy.spatial.distance.cdist(F, F, "sqeuclidean") / sig2)
+    np.fill_diagonal(W, 0.0)
+    np.testing.assert_allclose(g["L"], np.diag(W.sum(1)) - W, rtol=1e-12, atol=1e-14)
+
+
+def test_features_are_patches_of_max_scaled_maps():
+    rng = np.random.default_rng(8)
+    maps = _rand_maps(rng, 8)
+    F = graph.patch_features(maps, 4, 2)
+    # patch 4 has origin (2, 2) on a 3x3 origin grid; channel 1 (T2) pixel (0, 1) of it
+    assert F[4, 16 + 1] == maps[1, 2, 3] / maps[1].max()
+
+
+def test_ties_go_to_the_lower_index():
+    d2 = np.array([[0, 1, 1, 1], [1, 0, 2, 2], [1, 2, 0, 2], [1, 2, 2, 0]], float)
+    nbr = graph.knn_lists(d2, 2)
+    np.testing.assert_array_equal(nbr, [[1, 2], [0, 2], [0, 1], [0, 1]])
+
+
+def test_median_rule_lower_median_of_positive_values():
+    d2 = np.array([[0, 0.0, 4.0], [0.0, 0, 1.0], [4.0, 1.0, 0]])
+    nbr = np.array([[1, 2], [0, 2], [1, 0]])
+    # directed values: 0, 4, 0, 1, 1, 4 -> positive sorted 1, 1, 4, 4 -> lower median 1
+    assert graph.median_rule(d2, nbr) == 1.0
+
+
+def test_trace_form_equals_half_the_pairwise_form():
+    """eq. (9) vs eq. (7): Tr(Q L Q^H) = (1/2) sum_{i,j} w_ij ||q_i - q_j||^2 for symmetric W."""
+    rng = np.random.default_rng(9)
+    N, p, s, L = 12, 4, 2, 3
+    g = graph.knn_laplacian(_rand_maps(rng, N), p, s, 3)
+    W = np.diag(np.diag(g["L"])) - g["L"]
+    X = rng.standard_normal((L, N, N)) + 1j * rng.standard_normal((L, N, N))
+    P = patches.Q(X, p, s)
+    pair = 0.0
+    for i in range(P.shape[0]):
+        for j in range(P.shape[0]):
+            pair += W[i, j] * np.sum(np.abs(P[i] - P[j]) ** 2)
+    tr = np.vdot(X, ops.laplacian_apply(X, g["L"], p, s)).real
+    assert abs(tr - 0.5 * pair) <= 1e-10 * abs(pair)
