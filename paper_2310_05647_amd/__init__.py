@@ -1,0 +1,9 @@
+"""Python binding of libmrf, the MI355X hot path of the MS-LLR MRF reconstruction.
+
+Argument marshalling only: every step runs in the HIP kernels of libmrf.so. Tensors are
+torch device tensors (PyTorch provides device memory and the stream); their data pointers
+and the current HIP stream are handed to the C-ABI calls of include/mrf.h. Importing this
+package fails loudly when libmrf.so has not been built.
+"""
+from ._lib import MrfError, lib, library_path, check  # noqa: F401
+from .nufft import NufftPlan  # noqa: F401

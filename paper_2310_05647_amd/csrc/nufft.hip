@@ -1,0 +1,529 @@
+// NUFFT pair A / A^H (eq. (1); gradient step eq. (15)) for gfx950.
+//
+// Forward, per frame (image X_l, N x N -> samples b_l, Ns):
+//   k_row_fwd  : each image row is deapodised, zero-padded to G = 2N (centred) and
+//                transformed along x (Stockham, in LDS). Writes T[l][y][kx], N x G: only the
+//                N non-zero rows of the padded grid are ever formed.
+//   k_col_fwd  : one workgroup per (frame, strip of TX grid columns). Loads the strip of T,
+//                transforms along y (all G rows, in LDS), then each wave interpolates the
+//                samples listed for its tile (TX columns x G/4 rows) with the 6 x 6
+//                Kaiser-Bessel taps that fall inside the tile: one partial sum per
+//                (sample, tile) entry. The G x G grid never goes to HBM.
+//   k_combine  : b[j] = (1/N) * sum of the sample's <= 4 partials, in tile order.
+// Adjoint, per frame (the exact transpose of the above):
+//   k_col_adj  : one workgroup per (frame, strip). Every grid point of the strip gathers the
+//                weighted samples whose 6 x 6 footprint covers it, from its tile's entry list
+//                sorted by footprint row: a deterministic spread without atomics. Then the
+//                inverse transform along y, keeping only the N rows of the crop.
+//   k_row_adj  : inverse transform along x, crop to N columns, deapodise, scale 1/N.
+// The plan (host C++) bins each sample into every tile its footprint touches (halo
+// duplication), stores the tile-local footprint origin and the 12 separable weights.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "common.hpp"
+#include "fft.hpp"
+
+namespace mrf {
+
+struct alignas(16) Entry {
+  int j;        // sample index inside the frame
+  int lb;       // tile-local footprint origin: low 16 bits column (signed), high 16 bits row
+  float wx[6];  // weights of the 6 column taps
+  float wy[6];  // weights of the 6 row taps
+  int pad[2];
+};
+static_assert(sizeof(Entry) == 64, "Entry layout");
+
+}  // namespace mrf
+
+struct mrf_nufft_plan_s {
+  int N, G, L, Ns, TX, TY, nstrips, ntiles;  // ntiles per frame = nstrips * 4
+  long long E;
+  mrf::Entry* ent;
+  int* tile_ptr;      // [L * ntiles + 1]
+  int4* samp_ent;     // [L * Ns] entry ids of each sample, -1 padded
+  float* dinv;        // [N] 1 / phi_hat((x - N/2) / G)
+  mrf::cf* tw;        // [G] exp(-2 pi i k / G)
+  size_t ws_T, ws_part, ws_bytes;
+};
+
+namespace mrf {
+
+// ------------------------------------------------------------------ kernels
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_row_fwd(const cf* __restrict__ X, cf* __restrict__ T,
+                                                    const float* __restrict__ dinv,
+                                                    const cf* __restrict__ twg, int N, int nrows) {
+  constexpr int RPB = kBlock / (G / 8);   // rows per block
+  constexpr int TS = G + 1;
+  __shared__ cf buf[RPB * TS];
+  __shared__ cf tw[G];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < G; i += kBlock) tw[i] = twg[i];
+  const long row0 = (long)blockIdx.x * RPB;
+  for (int idx = tid; idx < RPB * G; idx += kBlock) {
+    const int rr = idx / G, n = idx % G;
+    const long row = row0 + rr;
+    cf v = {0.f, 0.f};
+    const int xp = n < G / 2 ? n : n - G;
+    if (row < nrows && xp >= -N / 2 && xp < N / 2) {
+      const int x = xp + N / 2, y = (int)(row % N);
+      v = cscale(X[row * N + x], dinv[x] * dinv[y]);
+    }
+    buf[rr * TS + n] = v;
+  }
+  __syncthreads();
+  lds_fft<G, RPB, 1, TS, false, false>(buf, tw);
+  for (int idx = tid; idx < RPB * G; idx += kBlock) {
+    const int rr = idx / G, n = idx % G;
+    const long row = row0 + rr;
+    if (row < nrows) T[row * G + n] = buf[rr * TS + n];
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_row_adj(const cf* __restrict__ T, cf* __restrict__ X,
+                                                    const float* __restrict__ dinv,
+                                                    const cf* __restrict__ twg, int N, int nrows,
+                                                    float scale) {
+  constexpr int RPB = kBlock / (G / 8);
+  constexpr int TS = G + 1;
+  __shared__ cf buf[RPB * TS];
+  __shared__ cf tw[G];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < G; i += kBlock) tw[i] = twg[i];
+  const long row0 = (long)blockIdx.x * RPB;
+  for (int idx = tid; idx < RPB * G; idx += kBlock) {
+    const int rr = idx / G, n = idx % G;
+    const long row = row0 + rr;
+    buf[rr * TS + n] = row < nrows ? T[row * G + n] : cf{0.f, 0.f};
+  }
+  __syncthreads();
+  lds_fft<G, RPB, 1, TS, false, true>(buf, tw);
+  for (int idx = tid; idx < RPB * N; idx += kBlock) {
+    const int rr = idx / N, x = idx % N;
+    const long row = row0 + rr;
+    if (row < nrows) {
+      int n = x - N / 2;
+      if (n < 0) n += G;
+      const int y = (int)(row % N);
+      X[row * N + x] = cscale(buf[rr * TS + n], dinv[x] * dinv[y] * scale);
+    }
+  }
+}
+
+template <int G, int TX>
+__global__ __launch_bounds__(kBlock) void k_col_fwd(const cf* __restrict__ T, const Entry* __restrict__ ent,
+                                                    const int* __restrict__ tile_ptr,
+                                                    const cf* __restrict__ twg,
+                                                    cf* __restrict__ partial, int N) {
+  constexpr int P = TX + 1;
+  constexpr int TY = G / 4;
+  __shared__ cf S[G * P];
+  __shared__ cf tw[G];
+  const int sx = blockIdx.x, f = blockIdx.y, tid = threadIdx.x;
+  const int c0 = sx * TX;
+  for (int i = tid; i < G; i += kBlock) tw[i] = twg[i];
+  const cf* Tf = T + (size_t)f * N * G;
+  for (int idx = tid; idx < G * TX; idx += kBlock) {
+    const int row = idx / TX, c = idx % TX;
+    const int yp = row < G / 2 ? row : row - G;
+    cf v = {0.f, 0.f};
+    if (yp >= -N / 2 && yp < N / 2) v = Tf[(size_t)(yp + N / 2) * G + c0 + c];
+    S[row * P + c] = v;
+  }
+  __syncthreads();
+  lds_fft<G, TX, P, 1, true, false>(S, tw);
+  const int w = tid >> 6, lane = tid & 63;
+  const int tile = (f * (G / TX) + sx) * 4 + w;
+  const int e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
+  const cf* Sw = S + w * TY * P;
+  for (int e = e0 + lane; e < e1; e += 64) {
+    const Entry en = ent[e];
+    const int lbx = (short)(en.lb & 0xffff), lby = en.lb >> 16;
+    cf acc = {0.f, 0.f};
+#pragma unroll
+    for (int dy = 0; dy < 6; ++dy) {
+      const int row = lby + dy;
+      if (row < 0 || row >= TY) continue;
+      cf racc = {0.f, 0.f};
+#pragma unroll
+      for (int dx = 0; dx < 6; ++dx) {
+        const int col = lbx + dx;
+        if (col < 0 || col >= TX) continue;
+        const cf s = Sw[row * P + col];
+        racc.x += en.wx[dx] * s.x;
+        racc.y += en.wx[dx] * s.y;
+      }
+      acc.x += en.wy[dy] * racc.x;
+      acc.y += en.wy[dy] * racc.y;
+    }
+    partial[e] = acc;
+  }
+}
+
+template <int G, int TX>
+__global__ __launch_bounds__(kBlock) void k_col_adj(const cf* __restrict__ r, const Entry* __restrict__ ent,
+                                                    const int* __restrict__ tile_ptr,
+                                                    const cf* __restrict__ twg, cf* __restrict__ T,
+                                                    int N, int Ns) {
+  constexpr int P = TX + 1;
+  constexpr int TY = G / 4;
+  constexpr int RPI = 64 / TX;   // grid rows per wave iteration
+  __shared__ cf S[G * P];
+  __shared__ cf tw[G];
+  const int sx = blockIdx.x, f = blockIdx.y, tid = threadIdx.x;
+  const int c0 = sx * TX;
+  for (int i = tid; i < G; i += kBlock) tw[i] = twg[i];
+  const int w = tid >> 6, lane = tid & 63;
+  const int col = lane % TX, rsub = lane / TX;
+  const int tile = (f * (G / TX) + sx) * 4 + w;
+  const int e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
+  const cf* rf = r + (size_t)f * Ns;
+  cf* Sw = S + w * TY * P;
+  int start = e0;
+  for (int rg = 0; rg < TY; rg += RPI) {
+    const int row = rg + rsub;
+    const int lo = rg - 5, hi = rg + RPI - 1;
+    while (start < e1 && (ent[start].lb >> 16) < lo) ++start;
+    cf acc = {0.f, 0.f};
+    for (int e = start; e < e1; ++e) {
+      const int lb = ent[e].lb;
+      const int lby = lb >> 16;
+      if (lby > hi) break;
+      const int dy = row - lby, dx = col - (short)(lb & 0xffff);
+      if (dy >= 0 && dy < 6 && dx >= 0 && dx < 6) {
+        const float wgt = ent[e].wy[dy] * ent[e].wx[dx];
+        const cf rv = rf[ent[e].j];
+        acc.x += wgt * rv.x;
+        acc.y += wgt * rv.y;
+      }
+    }
+    Sw[row * P + col] = acc;
+  }
+  __syncthreads();
+  lds_fft<G, TX, P, 1, true, true>(S, tw);
+  cf* Tf = T + (size_t)f * N * G;
+  for (int idx = tid; idx < N * TX; idx += kBlock) {
+    const int y = idx / TX, c = idx % TX;
+    int n = y - N / 2;
+    if (n < 0) n += G;
+    Tf[(size_t)y * G + c0 + c] = S[n * P + c];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_combine(const cf* __restrict__ partial,
+                                                    const int4* __restrict__ samp_ent,
+                                                    cf* __restrict__ b, long total, float scale) {
+  const long i = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= total) return;
+  const int4 e = samp_ent[i];
+  cf acc = partial[e.x];
+  if (e.y >= 0) acc = cadd(acc, partial[e.y]);
+  if (e.z >= 0) acc = cadd(acc, partial[e.z]);
+  if (e.w >= 0) acc = cadd(acc, partial[e.w]);
+  b[i] = cscale(acc, scale);
+}
+
+// ------------------------------------------------------------------ host: plan
+namespace {
+
+double kb_beta(int W, int osf) {
+  const double a = (double)W / osf, b = osf - 0.5;
+  return M_PI * std::sqrt(a * a * b * b - 0.8);
+}
+
+double bessel_i0(double z) {  // power series sum (z/2)^{2k} / (k!)^2
+  const double q = 0.25 * z * z;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 200; ++k) {
+    term *= q / ((double)k * k);
+    sum += term;
+    if (term <= 1e-18 * sum) break;
+  }
+  return sum;
+}
+
+double kb_kernel(double t, int W, double beta) {
+  const double a = 1.0 - (2.0 * t / W) * (2.0 * t / W);
+  return a < 0.0 ? 0.0 : bessel_i0(beta * std::sqrt(a));
+}
+
+double kb_ft(double s, int W, double beta) {
+  const double a = beta * beta - (M_PI * W * s) * (M_PI * W * s);
+  if (a > 0) {
+    const double r = std::sqrt(a);
+    return W * std::sinh(r) / r;
+  }
+  if (a < 0) {
+    const double r = std::sqrt(-a);
+    return W * std::sin(r) / r;
+  }
+  return W;
+}
+
+struct FrameBins {
+  std::vector<Entry> ent;           // sorted, grouped by tile
+  std::vector<int> count;           // per tile
+  std::vector<int> samp_of;         // per entry: sample index (== ent.j)
+};
+
+void bin_frame(const float* traj, int l, const mrf_nufft_plan_s& p, double beta, FrameBins& out) {
+  const int G = p.G, TX = p.TX, TY = p.TY, W = 6;
+  std::vector<std::vector<Entry>> tiles(p.ntiles);
+  for (int j = 0; j < p.Ns; ++j) {
+    const double ux = (double)traj[2 * ((size_t)l * p.Ns + j) + 0] * G / (2.0 * M_PI);
+    const double uy = (double)traj[2 * ((size_t)l * p.Ns + j) + 1] * G / (2.0 * M_PI);
+    const long bx = (long)std::floor(ux) - W / 2 + 1;
+    const long by = (long)std::floor(uy) - W / 2 + 1;
+    Entry e{};
+    e.j = j;
+    for (int d = 0; d < W; ++d) {
+      e.wx[d] = (float)kb_kernel(ux - (double)(bx + d), W, beta);
+      e.wy[d] = (float)kb_kernel(uy - (double)(by + d), W, beta);
+    }
+    // tiles are at least 8 cells wide, so a 6-cell footprint meets at most 2 strips / blocks
+    int strips[2], nst = 0, blks[2], nbk = 0;
+    for (int d = 0; d < W; ++d) {
+      const int s = (int)(((bx + d) % G + G) % G) / TX;
+      if (!(nst > 0 && strips[0] == s) && !(nst > 1 && strips[1] == s)) strips[nst++] = s;
+      const int b = (int)(((by + d) % G + G) % G) / TY;
+      if (!(nbk > 0 && blks[0] == b) && !(nbk > 1 && blks[1] == b)) blks[nbk++] = b;
+    }
+    for (int a = 0; a < nst; ++a) {
+      for (int c = 0; c < nbk; ++c) {
+        long lx = ((bx - (long)strips[a] * TX) % G + G) % G;
+        if (lx >= G - (W - 1)) lx -= G;
+        long ly = ((by - (long)blks[c] * TY) % G + G) % G;
+        if (ly >= G - (W - 1)) ly -= G;
+        Entry q = e;
+        q.lb = (int)((uint32_t)(lx & 0xffff) | ((uint32_t)ly << 16));
+        tiles[strips[a] * 4 + blks[c]].push_back(q);
+      }
+    }
+  }
+  out.ent.clear();
+  out.count.assign(p.ntiles, 0);
+  for (int t = 0; t < p.ntiles; ++t) {
+    auto& v = tiles[t];
+    std::stable_sort(v.begin(), v.end(), [](const Entry& a, const Entry& b) {
+      const int ra = a.lb >> 16, rb = b.lb >> 16;
+      return ra != rb ? ra < rb : a.j < b.j;
+    });
+    out.count[t] = (int)v.size();
+    out.ent.insert(out.ent.end(), v.begin(), v.end());
+  }
+}
+
+template <typename F>
+void parallel_for(int n, F fn) {
+  int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  nt = std::min(nt, n);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&, t] {
+      for (int i = t; i < n; i += nt) fn(i);
+    });
+  for (auto& x : th) x.join();
+}
+
+}  // namespace
+
+static bool supported_g(int G) { return G == 32 || G == 64 || G == 128 || G == 256 || G == 512 || G == 1024; }
+
+}  // namespace mrf
+
+using namespace mrf;
+
+extern "C" mrf_status mrf_nufft_plan_create(const mrf_nufft_desc* d, const float* traj, hipStream_t stream,
+                                            mrf_nufft_plan_t* out) {
+  clear_error();
+  MRF_REQUIRE(d && traj && out, MRF_INVALID_ARG, "nufft_plan_create: null argument");
+  *out = nullptr;
+  MRF_REQUIRE(d->kb_width == 6, MRF_NOT_SUPPORTED, "nufft_plan_create: kb_width must be 6");
+  MRF_REQUIRE(d->oversamp == 2, MRF_NOT_SUPPORTED, "nufft_plan_create: oversamp must be 2");
+  MRF_REQUIRE(d->nframes >= 1 && d->nsamp >= 1, MRF_INVALID_ARG, "nufft_plan_create: nframes, nsamp must be >= 1");
+  const int N = d->n, G = 2 * N;
+  MRF_REQUIRE(N >= 16 && N <= 512 && supported_g(G), MRF_SHAPE, "nufft_plan_create: n must be a power of two in [16, 512]");
+  int TX = d->tile_cols ? d->tile_cols : (G == 1024 ? 8 : 16);
+  MRF_REQUIRE(TX == 8 || TX == 16 || TX == 32, MRF_INVALID_ARG, "nufft_plan_create: tile_cols must be 0, 8, 16 or 32");
+  MRF_REQUIRE(TX <= G / 2 && (long)G * TX <= 8192, MRF_SHAPE, "nufft_plan_create: tile_cols too large for this grid");
+  MRF_REQUIRE((long)d->nframes * d->nsamp < (1L << 30), MRF_SHAPE, "nufft_plan_create: too many samples");
+
+  auto* p = new mrf_nufft_plan_s{};
+  p->N = N; p->G = G; p->L = d->nframes; p->Ns = d->nsamp; p->TX = TX; p->TY = G / 4;
+  p->nstrips = G / TX; p->ntiles = p->nstrips * 4;
+
+  const size_t nsamp_tot = (size_t)p->L * p->Ns;
+  std::vector<float> htraj(2 * nsamp_tot);
+  hipError_t e = hipMemcpyAsync(htraj.data(), traj, htraj.size() * sizeof(float), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(MRF_DEVICE, std::string("nufft_plan_create: trajectory copy: ") + hipGetErrorString(e));
+  }
+  for (size_t i = 0; i < htraj.size(); ++i) {
+    if (!(htraj[i] >= -(float)M_PI && htraj[i] <= (float)M_PI)) {
+      delete p;
+      return fail(MRF_INVALID_ARG, "nufft_plan_create: trajectory outside [-pi, pi] or not finite");
+    }
+  }
+  const double beta = kb_beta(6, 2);
+  std::vector<FrameBins> bins(p->L);
+  parallel_for(p->L, [&](int l) { bin_frame(htraj.data(), l, *p, beta, bins[l]); });
+
+  std::vector<int> tile_ptr((size_t)p->L * p->ntiles + 1);
+  long long acc = 0;
+  for (int l = 0; l < p->L; ++l)
+    for (int t = 0; t < p->ntiles; ++t) {
+      tile_ptr[(size_t)l * p->ntiles + t] = (int)acc;
+      acc += bins[l].count[t];
+    }
+  tile_ptr.back() = (int)acc;
+  if (acc >= (1LL << 31)) {
+    delete p;
+    return fail(MRF_SHAPE, "nufft_plan_create: too many tile entries");
+  }
+  p->E = acc;
+  std::vector<Entry> ent((size_t)acc);
+  std::vector<int4> samp_ent(nsamp_tot, int4{-1, -1, -1, -1});
+  parallel_for(p->L, [&](int l) {
+    const size_t base = tile_ptr[(size_t)l * p->ntiles];
+    std::copy(bins[l].ent.begin(), bins[l].ent.end(), ent.begin() + base);
+    for (size_t k = 0; k < bins[l].ent.size(); ++k) {
+      int4& s = samp_ent[(size_t)l * p->Ns + bins[l].ent[k].j];
+      const int id = (int)(base + k);
+      if (s.x < 0) s.x = id; else if (s.y < 0) s.y = id; else if (s.z < 0) s.z = id; else s.w = id;
+    }
+    bins[l] = FrameBins{};
+  });
+
+  std::vector<float> dinv(N);
+  for (int x = 0; x < N; ++x) dinv[x] = (float)(1.0 / kb_ft((double)(x - N / 2) / G, 6, beta));
+  std::vector<cf> tw(G);
+  for (int k = 0; k < G; ++k) tw[k] = cf{(float)std::cos(-2.0 * M_PI * k / G), (float)std::sin(-2.0 * M_PI * k / G)};
+
+  auto cleanup = [&]() {
+    hipFree(p->ent); hipFree(p->tile_ptr); hipFree(p->samp_ent); hipFree(p->dinv); hipFree(p->tw);
+    delete p;
+  };
+  if (hipMalloc(&p->ent, std::max<size_t>(1, ent.size()) * sizeof(Entry)) != hipSuccess ||
+      hipMalloc(&p->tile_ptr, tile_ptr.size() * sizeof(int)) != hipSuccess ||
+      hipMalloc(&p->samp_ent, samp_ent.size() * sizeof(int4)) != hipSuccess ||
+      hipMalloc(&p->dinv, N * sizeof(float)) != hipSuccess || hipMalloc(&p->tw, G * sizeof(cf)) != hipSuccess) {
+    cleanup();
+    return fail(MRF_OOM, "nufft_plan_create: device allocation of plan tables failed");
+  }
+  e = hipMemcpy(p->ent, ent.data(), ent.size() * sizeof(Entry), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->tile_ptr, tile_ptr.data(), tile_ptr.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->samp_ent, samp_ent.data(), samp_ent.size() * sizeof(int4), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->dinv, dinv.data(), N * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->tw, tw.data(), G * sizeof(cf), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(MRF_DEVICE, std::string("nufft_plan_create: table upload: ") + hipGetErrorString(e));
+  }
+  p->ws_T = ((size_t)p->L * N * G * sizeof(cf) + 255) & ~(size_t)255;
+  p->ws_part = ((size_t)p->E * sizeof(cf) + 255) & ~(size_t)255;
+  p->ws_bytes = p->ws_T + p->ws_part;
+  *out = p;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_nufft_plan_destroy(mrf_nufft_plan_t p) {
+  clear_error();
+  if (!p) return MRF_OK;
+  hipFree(p->ent); hipFree(p->tile_ptr); hipFree(p->samp_ent); hipFree(p->dinv); hipFree(p->tw);
+  delete p;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_nufft_workspace_size(mrf_nufft_plan_t p, size_t* bytes) {
+  clear_error();
+  MRF_REQUIRE(p && bytes, MRF_INVALID_ARG, "nufft_workspace_size: null argument");
+  *bytes = p->ws_bytes;
+  return MRF_OK;
+}
+
+namespace mrf {
+
+template <int G, int TX>
+static void launch_fwd_g(const mrf_nufft_plan_s* p, const cf* img, cf* T, cf* part, hipStream_t s) {
+  const int nrows = p->L * p->N;
+  constexpr int RPB = kBlock / (G / 8);
+  k_row_fwd<G><<<ceil_div(nrows, RPB), kBlock, 0, s>>>(img, T, p->dinv, p->tw, p->N, nrows);
+  k_col_fwd<G, TX><<<dim3(G / TX, p->L), kBlock, 0, s>>>(T, p->ent, p->tile_ptr, p->tw, part, p->N);
+}
+
+template <int G, int TX>
+static void launch_adj_g(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, cf* T, hipStream_t s) {
+  const int nrows = p->L * p->N;
+  constexpr int RPB = kBlock / (G / 8);
+  k_col_adj<G, TX><<<dim3(G / TX, p->L), kBlock, 0, s>>>(ksp, p->ent, p->tile_ptr, p->tw, T, p->N, p->Ns);
+  k_row_adj<G><<<ceil_div(nrows, RPB), kBlock, 0, s>>>(T, img, p->dinv, p->tw, p->N, nrows, 1.0f / p->N);
+}
+
+#define MRF_DISPATCH_G_TX(FN, ...)                                                   \
+  switch (p->G * 100 + p->TX) {                                                      \
+    case 32 * 100 + 8: FN<32, 8>(__VA_ARGS__); break;                                \
+    case 32 * 100 + 16: FN<32, 16>(__VA_ARGS__); break;                              \
+    case 64 * 100 + 8: FN<64, 8>(__VA_ARGS__); break;                                \
+    case 64 * 100 + 16: FN<64, 16>(__VA_ARGS__); break;                              \
+    case 64 * 100 + 32: FN<64, 32>(__VA_ARGS__); break;                              \
+    case 128 * 100 + 8: FN<128, 8>(__VA_ARGS__); break;                              \
+    case 128 * 100 + 16: FN<128, 16>(__VA_ARGS__); break;                            \
+    case 128 * 100 + 32: FN<128, 32>(__VA_ARGS__); break;                            \
+    case 256 * 100 + 8: FN<256, 8>(__VA_ARGS__); break;                              \
+    case 256 * 100 + 16: FN<256, 16>(__VA_ARGS__); break;                            \
+    case 256 * 100 + 32: FN<256, 32>(__VA_ARGS__); break;                            \
+    case 512 * 100 + 8: FN<512, 8>(__VA_ARGS__); break;                              \
+    case 512 * 100 + 16: FN<512, 16>(__VA_ARGS__); break;                            \
+    case 1024 * 100 + 8: FN<1024, 8>(__VA_ARGS__); break;                            \
+    default: return fail(MRF_SHAPE, "nufft: unsupported grid / tile combination");  \
+  }
+
+mrf_status nufft_fwd_partials(const mrf_nufft_plan_s* p, const cf* img, void* ws, hipStream_t s) {
+  cf* T = (cf*)ws;
+  cf* part = (cf*)((char*)ws + p->ws_T);
+  MRF_DISPATCH_G_TX(launch_fwd_g, p, img, T, part, s);
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+
+const cf* nufft_partials(const mrf_nufft_plan_s* p, void* ws) { return (const cf*)((char*)ws + p->ws_T); }
+const int4* nufft_samp_ent(const mrf_nufft_plan_s* p) { return p->samp_ent; }
+
+mrf_status nufft_adj_impl(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, void* ws, hipStream_t s) {
+  cf* T = (cf*)ws;
+  MRF_DISPATCH_G_TX(launch_adj_g, p, ksp, img, T, s);
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+
+}  // namespace mrf
+
+extern "C" mrf_status mrf_nufft_fwd(mrf_nufft_plan_t p, const mrf_c64* img, mrf_c64* ksp, void* ws, size_t ws_bytes,
+                                    hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(p && img && ksp, MRF_INVALID_ARG, "nufft_fwd: null argument");
+  MRF_REQUIRE(ws && ws_bytes >= p->ws_bytes, MRF_WORKSPACE, "nufft_fwd: workspace missing or too small");
+  mrf_status st = nufft_fwd_partials(p, (const cf*)img, ws, s);
+  if (st != MRF_OK) return st;
+  const long total = (long)p->L * p->Ns;
+  k_combine<<<ceil_div(total, kBlock), kBlock, 0, s>>>(nufft_partials(p, ws), p->samp_ent, (cf*)ksp, total,
+                                                       1.0f / p->N);
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_nufft_adj(mrf_nufft_plan_t p, const mrf_c64* ksp, mrf_c64* img, void* ws, size_t ws_bytes,
+                                    hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(p && img && ksp, MRF_INVALID_ARG, "nufft_adj: null argument");
+  MRF_REQUIRE(ws && ws_bytes >= p->ws_bytes, MRF_WORKSPACE, "nufft_adj: workspace missing or too small");
+  return nufft_adj_impl(p, (const cf*)ksp, (cf*)img, ws, s);
+}

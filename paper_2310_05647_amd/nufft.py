@@ -1,0 +1,66 @@
+"""NUFFT pair binding: mrf_nufft_plan_create / mrf_nufft_fwd / mrf_nufft_adj."""
+import ctypes
+
+import torch
+
+from ._lib import NufftDesc, check, lib
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, shape, name):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+        raise ValueError("%s must be a contiguous CUDA %s tensor of shape %s" % (name, dtype, tuple(shape)))
+
+
+class NufftPlan:
+    """Plan of A / A^H for a fixed trajectory traj [L, Ns, 2] (float32, rad/pixel, device)."""
+
+    def __init__(self, n, traj, tile_cols=0, stream=None):
+        L, Ns, two = traj.shape
+        _need(traj, torch.float32, (L, Ns, 2), "traj")
+        self.n, self.L, self.Ns = int(n), int(L), int(Ns)
+        desc = NufftDesc(self.n, self.L, self.Ns, 6, 2, int(tile_cols))
+        h = ctypes.c_void_p()
+        check(lib.mrf_nufft_plan_create(ctypes.byref(desc), _ptr(traj), _stream(stream), ctypes.byref(h)),
+              "mrf_nufft_plan_create")
+        self.handle = h
+        sz = ctypes.c_size_t()
+        check(lib.mrf_nufft_workspace_size(h, ctypes.byref(sz)), "mrf_nufft_workspace_size")
+        self.ws = torch.empty(max(1, sz.value), dtype=torch.uint8, device=traj.device)
+
+    def fwd(self, img, out=None, stream=None):
+        _need(img, torch.complex64, (self.L, self.n, self.n), "img")
+        if out is None:
+            out = torch.empty((self.L, self.Ns), dtype=torch.complex64, device=img.device)
+        _need(out, torch.complex64, (self.L, self.Ns), "ksp")
+        check(lib.mrf_nufft_fwd(self.handle, _ptr(img), _ptr(out), _ptr(self.ws), self.ws.numel(), _stream(stream)),
+              "mrf_nufft_fwd")
+        return out
+
+    def adj(self, ksp, out=None, stream=None):
+        _need(ksp, torch.complex64, (self.L, self.Ns), "ksp")
+        if out is None:
+            out = torch.empty((self.L, self.n, self.n), dtype=torch.complex64, device=ksp.device)
+        _need(out, torch.complex64, (self.L, self.n, self.n), "img")
+        check(lib.mrf_nufft_adj(self.handle, _ptr(ksp), _ptr(out), _ptr(self.ws), self.ws.numel(), _stream(stream)),
+              "mrf_nufft_adj")
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.mrf_nufft_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

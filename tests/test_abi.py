@@ -1,0 +1,48 @@
+"""Host-only checks of the C-ABI: every declared symbol is exported; argument checks fail cleanly."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(mrf_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2310_05647_amd as m
+    names = _declared()
+    assert len(names) >= 8
+    missing = [n for n in sorted(names) if not hasattr(m.lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_version():
+    import paper_2310_05647_amd as m
+    assert m.lib.mrf_status_string(0) == b"MRF_OK"
+    assert m.lib.mrf_status_string(7) == b"MRF_NOT_SUPPORTED"
+    assert m.lib.mrf_version() >= 100
+
+
+def test_nufft_plan_rejects_bad_descriptors_before_touching_the_device():
+    import paper_2310_05647_amd as m
+    from paper_2310_05647_amd._lib import NufftDesc
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    cases = [(NufftDesc(64, 10, 100, 5, 2, 0), 7), (NufftDesc(64, 10, 100, 6, 3, 0), 7),
+             (NufftDesc(48, 10, 100, 6, 2, 0), 2), (NufftDesc(64, 0, 100, 6, 2, 0), 1),
+             (NufftDesc(64, 10, 100, 6, 2, 12), 1), (NufftDesc(512, 10, 100, 6, 2, 16), 2)]
+    for desc, expect in cases:
+        st = m.lib.mrf_nufft_plan_create(ctypes.byref(desc), fake, None, ctypes.byref(h))
+        assert st == expect, (desc.n, desc.kb_width, st, m.lib.mrf_last_error())
+        assert m.lib.mrf_last_error() != b""
+    assert m.lib.mrf_nufft_plan_create(None, fake, None, ctypes.byref(h)) == 1
