@@ -46,6 +46,14 @@ const char* mrf_last_error(void);
 /* Library version as major*10000 + minor*100 + patch. */
 int mrf_version(void);
 
+/* Per-kernel timing for benchmarks. While enabled, every kernel launch of the library is
+ * bracketed by two HIP events recorded on the stream the kernel is launched on. */
+mrf_status mrf_timing_enable(int on);
+/* Synchronises the recorded events and writes one line per kernel name into buf (host):
+ * "<name> <launches> <total_ms> <min_ms> <max_ms>\n", truncated to buf_len - 1 bytes.
+ * Clears the records. */
+mrf_status mrf_timing_report(char* buf, size_t buf_len);
+
 /* ====================================================================================
  * NUFFT pair: the single-coil acquisition operator A = F_u of eq. (1) and its adjoint A^H,
  * used in the gradient step eq. (15) and for X^0 = A^H b (Algorithm 1).
@@ -64,8 +72,8 @@ typedef struct mrf_nufft_desc {
   int nsamp;      /* Ns >= 1 samples per frame                                         */
   int kb_width;   /* must be 6                                                         */
   int oversamp;   /* must be 2 (grid side G = 2N)                                      */
-  int tile_cols;  /* grid columns per spread/interpolation strip: 0 = default (16;
-                     8 when G = 1024); otherwise 8, 16 or 32 with G*tile_cols <= 8192   */
+  int tile_cols;  /* grid columns per spread/interpolation strip: 0 = default (8;
+                     16 when G = 32); otherwise 8, 16, or 32 (G <= 128), at most G/2    */
 } mrf_nufft_desc;
 
 /* Builds the plan for a fixed trajectory: traj is device float32 [L][Ns][2] (wx, wy).

@@ -5,5 +5,5 @@ torch device tensors (PyTorch provides device memory and the stream); their data
 and the current HIP stream are handed to the C-ABI calls of include/mrf.h. Importing this
 package fails loudly when libmrf.so has not been built.
 """
-from ._lib import MrfError, lib, library_path, check  # noqa: F401
+from ._lib import MrfError, lib, library_path, check, timing_enable, timing_report  # noqa: F401
 from .nufft import NufftPlan  # noqa: F401

@@ -7,7 +7,7 @@ library_path = os.path.join(_HERE, "libmrf.so")
 
 if not os.path.exists(library_path):
     raise ImportError(
-        "libmrf.so is not built (%s). Build it with `python -m paper_2310_05647_amd.build` "
+        "libmrf.so is not built (%s). Build it with `python paper_2310_05647_amd/build.py` "
         "or __graft_entry__.build(); there is no fallback implementation." % library_path)
 
 lib = ctypes.CDLL(library_path)
@@ -32,6 +32,8 @@ def _decl(name, args, res=c_int):
 _decl("mrf_status_string", [c_int], c_char_p)
 _decl("mrf_last_error", [], c_char_p)
 _decl("mrf_version", [], c_int)
+_decl("mrf_timing_enable", [c_int])
+_decl("mrf_timing_report", [c_char_p, c_size_t])
 _decl("mrf_nufft_plan_create", [P(NufftDesc), c_void_p, c_void_p, P(c_void_p)])
 _decl("mrf_nufft_plan_destroy", [c_void_p])
 _decl("mrf_nufft_workspace_size", [c_void_p, P(c_size_t)])
@@ -50,3 +52,18 @@ class MrfError(RuntimeError):
 def check(status, where):
     if status != 0:
         raise MrfError(status, where)
+
+
+def timing_enable(on=True):
+    check(lib.mrf_timing_enable(1 if on else 0), "mrf_timing_enable")
+
+
+def timing_report():
+    """Synchronises recorded launch events; returns {kernel: (launches, total_ms, min_ms, max_ms)}."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    check(lib.mrf_timing_report(buf, len(buf)), "mrf_timing_report")
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, n, tot, mn, mx = line.split()
+        out[name] = (int(n), float(tot), float(mn), float(mx))
+    return out

@@ -1,7 +1,7 @@
 """Builds libmrf.so (HIP for gfx950 + host C++) in-tree with hipcc.
 
 Every source under csrc/ is compiled to an object in csrc/_build/ (in parallel), then linked
-into paper_2310_05647_amd/libmrf.so. Usage: python -m paper_2310_05647_amd.build
+into paper_2310_05647_amd/libmrf.so. Usage: python paper_2310_05647_amd/build.py
 """
 import concurrent.futures
 import os

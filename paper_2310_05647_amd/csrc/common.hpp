@@ -50,4 +50,18 @@ __host__ __device__ inline cf cconj(cf a) { return cf{a.x, -a.y}; }
 
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
+// ------------------------------------------------------------------ per-kernel timing
+// While enabled (mrf_timing_enable), each launch wrapped by MRF_LAUNCH is bracketed by two
+// HIP events recorded on its own stream; mrf_timing_report aggregates them by name.
+bool timing_on();
+void timing_mark(const char* name, hipStream_t s, bool begin);
+
+#define MRF_LAUNCH(name, stream, ...)                                  \
+  do {                                                                 \
+    const bool t_ = ::mrf::timing_on();                                \
+    if (t_) ::mrf::timing_mark(name, stream, true);                    \
+    __VA_ARGS__;                                                       \
+    if (t_) ::mrf::timing_mark(name, stream, false);                   \
+  } while (0)
+
 }  // namespace mrf

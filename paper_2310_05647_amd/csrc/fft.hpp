@@ -13,6 +13,15 @@ namespace mrf {
 
 constexpr int kBlock = 256;
 
+// Workgroup barrier that waits only for this wave's LDS operations, so that global loads
+// issued earlier (prefetches) stay in flight across it.
+__device__ inline void lds_sync() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0); vmcnt and expcnt left at their maxima
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Radix schedule: radix-8 passes, then one radix-4 or radix-2 pass when log2(G) % 3 != 0.
 template <int G>
 struct FftPlan {
@@ -87,7 +96,7 @@ __device__ inline void stockham_pass(cf* buf, const cf* tw, int Ns) {
       for (int r = 0; r < R; ++r) v[b][r] = buf[(j + r * NB) * ES + c * TS];
     }
   }
-  __syncthreads();
+  lds_sync();
 #pragma unroll
   for (int b = 0; b < PER; ++b) {
     const int id = tid + b * kBlock;
@@ -96,11 +105,13 @@ __device__ inline void stockham_pass(cf* buf, const cf* tw, int Ns) {
       const int j = CFAST ? id / NT : id % NB;
       const int k = j % Ns;
       const int step = G / (Ns * R);
+      if (Ns > 1) {   // the first pass has only unit twiddles
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        cf t = tw[(k * r * step) & (G - 1)];
-        if (INV) t.y = -t.y;
-        v[b][r] = cmul(v[b][r], t);
+        for (int r = 1; r < R; ++r) {
+          cf t = tw[(k * r * step) & (G - 1)];
+          if (INV) t.y = -t.y;
+          v[b][r] = cmul(v[b][r], t);
+        }
       }
       dft_regs<R, INV>(v[b]);
       const int d = (j / Ns) * Ns * R + k;
@@ -108,7 +119,7 @@ __device__ inline void stockham_pass(cf* buf, const cf* tw, int Ns) {
       for (int r = 0; r < R; ++r) buf[(d + r * Ns) * ES + c * TS] = v[b][r];
     }
   }
-  __syncthreads();
+  lds_sync();
 }
 
 // Full in-LDS FFT of NT transforms of length G. tw[k] = exp(-2 pi i k / G) in LDS.

@@ -54,165 +54,317 @@ struct mrf_nufft_plan_s {
 namespace mrf {
 
 // ------------------------------------------------------------------ kernels
+// Work distribution of the column kernels: block b handles strip sx of frame chunk c. Blocks are
+// dispatched to the 8 XCDs round-robin (XCD = b mod 8); here XCD x takes the chunks c = x (mod 8)
+// with all their strips in order. Every XCD then gets the same share of the expensive strips
+// that hold the k-space centre (every frame's spiral starts there), and neighbouring strips,
+// which share 128-byte lines of T, meet in the same L2.
+constexpr int kMaxFramesPerBlock = 1;
+
+__device__ inline bool strip_and_chunk(int nstrips, int nchunks, int& sx, int& c) {
+  const int b = blockIdx.x;
+  const int q = b >> 3;
+  sx = q % nstrips;
+  c = (q / nstrips) * 8 + (b & 7);
+  return c < nchunks;
+}
+
+// Row pass, forward: rows of X (deapodised, zero-padded to G) -> T rows. Grid-stride over groups
+// of RPB rows; the next group's inputs are loaded into registers while this group transforms.
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_row_fwd(const cf* __restrict__ X, cf* __restrict__ T,
                                                     const float* __restrict__ dinv,
-                                                    const cf* __restrict__ twg, int N, int nrows) {
-  constexpr int RPB = kBlock / (G / 8);   // rows per block
+                                                    const cf* __restrict__ twg, int nrows) {
+  constexpr int N = G / 2;
+  constexpr int RPB = kBlock / (G / 8);   // rows per group
   constexpr int TS = G + 1;
+  constexpr int PIN = (RPB * N + kBlock - 1) / kBlock;   // non-zero inputs per thread
   __shared__ cf buf[RPB * TS];
   __shared__ cf tw[G];
   const int tid = threadIdx.x;
   for (int i = tid; i < G; i += kBlock) tw[i] = twg[i];
-  const long row0 = (long)blockIdx.x * RPB;
-  for (int idx = tid; idx < RPB * G; idx += kBlock) {
-    const int rr = idx / G, n = idx % G;
-    const long row = row0 + rr;
-    cf v = {0.f, 0.f};
-    const int xp = n < G / 2 ? n : n - G;
-    if (row < nrows && xp >= -N / 2 && xp < N / 2) {
-      const int x = xp + N / 2, y = (int)(row % N);
-      v = cscale(X[row * N + x], dinv[x] * dinv[y]);
+  const int ngroups = (nrows + RPB - 1) / RPB;
+  cf pre[PIN];
+  auto load = [&](int g) {
+#pragma unroll
+    for (int i = 0; i < PIN; ++i) {
+      const int idx = tid + i * kBlock;
+      const long row = (long)g * RPB + idx / N;
+      pre[i] = (idx < RPB * N && row < nrows) ? X[row * N + idx % N] : cf{0.f, 0.f};
     }
-    buf[rr * TS + n] = v;
-  }
-  __syncthreads();
-  lds_fft<G, RPB, 1, TS, false, false>(buf, tw);
-  for (int idx = tid; idx < RPB * G; idx += kBlock) {
-    const int rr = idx / G, n = idx % G;
-    const long row = row0 + rr;
-    if (row < nrows) T[row * G + n] = buf[rr * TS + n];
+  };
+  int g = blockIdx.x;
+  if (g < ngroups) load(g);
+  for (; g < ngroups; g += gridDim.x) {
+    // zero the padding, place the deapodised inputs at (x - N/2) mod G
+    for (int idx = tid; idx < RPB * (G - N); idx += kBlock) {
+      const int rr = idx / (G - N), n = N / 2 + idx % (G - N);
+      buf[rr * TS + n] = cf{0.f, 0.f};
+    }
+#pragma unroll
+    for (int i = 0; i < PIN; ++i) {
+      const int idx = tid + i * kBlock;
+      if (idx < RPB * N) {
+        const int rr = idx / N, x = idx % N;
+        const long row = (long)g * RPB + rr;
+        const int y = (int)(row % N);
+        int n = x - N / 2;
+        if (n < 0) n += G;
+        buf[rr * TS + n] = cscale(pre[i], dinv[x] * dinv[y]);
+      }
+    }
+    lds_sync();
+    if (g + (int)gridDim.x < ngroups) load(g + gridDim.x);
+    lds_fft<G, RPB, 1, TS, false, false>(buf, tw);
+    for (int idx = tid; idx < RPB * G; idx += kBlock) {
+      const int rr = idx / G, n = idx % G;
+      const long row = (long)g * RPB + rr;
+      if (row < nrows) T[row * G + n] = buf[rr * TS + n];
+    }
+    lds_sync();
   }
 }
 
+// Row pass, adjoint: T rows -> inverse transform -> crop to N columns, deapodise, scale.
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_row_adj(const cf* __restrict__ T, cf* __restrict__ X,
                                                     const float* __restrict__ dinv,
-                                                    const cf* __restrict__ twg, int N, int nrows,
-                                                    float scale) {
+                                                    const cf* __restrict__ twg, int nrows, float scale) {
+  constexpr int N = G / 2;
   constexpr int RPB = kBlock / (G / 8);
   constexpr int TS = G + 1;
+  constexpr int PIN = RPB * G / kBlock;
   __shared__ cf buf[RPB * TS];
   __shared__ cf tw[G];
   const int tid = threadIdx.x;
   for (int i = tid; i < G; i += kBlock) tw[i] = twg[i];
-  const long row0 = (long)blockIdx.x * RPB;
-  for (int idx = tid; idx < RPB * G; idx += kBlock) {
-    const int rr = idx / G, n = idx % G;
-    const long row = row0 + rr;
-    buf[rr * TS + n] = row < nrows ? T[row * G + n] : cf{0.f, 0.f};
-  }
-  __syncthreads();
-  lds_fft<G, RPB, 1, TS, false, true>(buf, tw);
-  for (int idx = tid; idx < RPB * N; idx += kBlock) {
-    const int rr = idx / N, x = idx % N;
-    const long row = row0 + rr;
-    if (row < nrows) {
-      int n = x - N / 2;
-      if (n < 0) n += G;
-      const int y = (int)(row % N);
-      X[row * N + x] = cscale(buf[rr * TS + n], dinv[x] * dinv[y] * scale);
+  const int ngroups = (nrows + RPB - 1) / RPB;
+  cf pre[PIN];
+  auto load = [&](int g) {
+#pragma unroll
+    for (int i = 0; i < PIN; ++i) {
+      const int idx = tid + i * kBlock;
+      const long row = (long)g * RPB + idx / G;
+      pre[i] = row < nrows ? T[row * G + idx % G] : cf{0.f, 0.f};
     }
+  };
+  int g = blockIdx.x;
+  if (g < ngroups) load(g);
+  for (; g < ngroups; g += gridDim.x) {
+#pragma unroll
+    for (int i = 0; i < PIN; ++i) {
+      const int idx = tid + i * kBlock;
+      buf[(idx / G) * TS + idx % G] = pre[i];
+    }
+    lds_sync();
+    if (g + (int)gridDim.x < ngroups) load(g + gridDim.x);
+    lds_fft<G, RPB, 1, TS, false, true>(buf, tw);
+    for (int idx = tid; idx < RPB * N; idx += kBlock) {
+      const int rr = idx / N, x = idx % N;
+      const long row = (long)g * RPB + rr;
+      if (row < nrows) {
+        int n = x - N / 2;
+        if (n < 0) n += G;
+        const int y = (int)(row % N);
+        X[row * N + x] = cscale(buf[rr * TS + n], dinv[x] * dinv[y] * scale);
+      }
+    }
+    lds_sync();
   }
 }
 
+// Column pass, forward: per (strip, frame) load the strip of T, transform along y, interpolate.
+// Each wave interpolates the entries of its tile (the strip's rows [w G/4, (w+1) G/4)), lane per
+// entry, with the taps that fall inside the tile; the sum over a sample's tiles is k_combine.
 template <int G, int TX>
 __global__ __launch_bounds__(kBlock) void k_col_fwd(const cf* __restrict__ T, const Entry* __restrict__ ent,
                                                     const int* __restrict__ tile_ptr,
                                                     const cf* __restrict__ twg,
-                                                    cf* __restrict__ partial, int N) {
+                                                    cf* __restrict__ partial, int L, int FC) {
+  constexpr int N = G / 2;
   constexpr int P = TX + 1;
   constexpr int TY = G / 4;
+  constexpr int NSTRIP = G / TX;
+  constexpr int PT = (N * TX + kBlock - 1) / kBlock;
   __shared__ cf S[G * P];
   __shared__ cf tw[G];
-  const int sx = blockIdx.x, f = blockIdx.y, tid = threadIdx.x;
+  __shared__ int tp[kMaxFramesPerBlock][5];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  int sx, c;
+  if (!strip_and_chunk(NSTRIP, (L + FC - 1) / FC, sx, c)) return;
+  const int fb = c * FC, fe = min(L, fb + FC);
   const int c0 = sx * TX;
   for (int i = tid; i < G; i += kBlock) tw[i] = twg[i];
-  const cf* Tf = T + (size_t)f * N * G;
-  for (int idx = tid; idx < G * TX; idx += kBlock) {
-    const int row = idx / TX, c = idx % TX;
-    const int yp = row < G / 2 ? row : row - G;
-    cf v = {0.f, 0.f};
-    if (yp >= -N / 2 && yp < N / 2) v = Tf[(size_t)(yp + N / 2) * G + c0 + c];
-    S[row * P + c] = v;
-  }
-  __syncthreads();
-  lds_fft<G, TX, P, 1, true, false>(S, tw);
-  const int w = tid >> 6, lane = tid & 63;
-  const int tile = (f * (G / TX) + sx) * 4 + w;
-  const int e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
-  const cf* Sw = S + w * TY * P;
-  for (int e = e0 + lane; e < e1; e += 64) {
-    const Entry en = ent[e];
-    const int lbx = (short)(en.lb & 0xffff), lby = en.lb >> 16;
-    cf acc = {0.f, 0.f};
+  for (int i = tid; i < (fe - fb) * 5; i += kBlock)
+    tp[i / 5][i % 5] = tile_ptr[(size_t)(fb + i / 5) * NSTRIP * 4 + sx * 4 + i % 5];
+  lds_sync();
+  cf pre[PT];
+  Entry en_pre{};
+  auto load = [&](int f) {
+    const cf* Tf = T + (size_t)f * N * G;
 #pragma unroll
-    for (int dy = 0; dy < 6; ++dy) {
-      const int row = lby + dy;
-      if (row < 0 || row >= TY) continue;
-      cf racc = {0.f, 0.f};
-#pragma unroll
-      for (int dx = 0; dx < 6; ++dx) {
-        const int col = lbx + dx;
-        if (col < 0 || col >= TX) continue;
-        const cf s = Sw[row * P + col];
-        racc.x += en.wx[dx] * s.x;
-        racc.y += en.wx[dx] * s.y;
-      }
-      acc.x += en.wy[dy] * racc.x;
-      acc.y += en.wy[dy] * racc.y;
+    for (int i = 0; i < PT; ++i) {
+      const int idx = tid + i * kBlock;
+      if (idx < N * TX) pre[i] = Tf[(size_t)(idx / TX) * G + c0 + idx % TX];
     }
-    partial[e] = acc;
+    const int e = tp[f - fb][w] + lane;
+    if (e < tp[f - fb][w + 1]) en_pre = ent[e];
+  };
+  load(fb);
+  for (int f = fb; f < fe; ++f) {
+    for (int idx = tid; idx < (G - N) * TX; idx += kBlock) S[(N / 2 + idx / TX) * P + idx % TX] = cf{0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+      const int idx = tid + i * kBlock;
+      if (idx < N * TX) {
+        int n = idx / TX - N / 2;
+        if (n < 0) n += G;
+        S[n * P + idx % TX] = pre[i];
+      }
+    }
+    const Entry first = en_pre;
+    lds_sync();
+    if (f + 1 < fe) load(f + 1);
+    lds_fft<G, TX, P, 1, true, false>(S, tw);
+    const int e0 = tp[f - fb][w], e1 = tp[f - fb][w + 1];
+    const cf* Sw = S + w * TY * P;
+    for (int e = e0 + lane; e < e1; e += 64) {
+      const Entry en = (e == e0 + lane) ? first : ent[e];
+      const int lbx = (short)(en.lb & 0xffff), lby = en.lb >> 16;
+      cf acc = {0.f, 0.f};
+#pragma unroll
+      for (int dy = 0; dy < 6; ++dy) {
+        const int row = lby + dy;
+        if (row < 0 || row >= TY) continue;
+        cf racc = {0.f, 0.f};
+#pragma unroll
+        for (int dx = 0; dx < 6; ++dx) {
+          const int col = lbx + dx;
+          if (col < 0 || col >= TX) continue;
+          const cf sv = Sw[row * P + col];
+          racc.x += en.wx[dx] * sv.x;
+          racc.y += en.wx[dx] * sv.y;
+        }
+        acc.x += en.wy[dy] * racc.x;
+        acc.y += en.wy[dy] * racc.y;
+      }
+      partial[e] = acc;
+    }
+    lds_sync();
   }
 }
 
+// Spread of one tile by one wave, atomics-free and in a fixed order. Lane t owns the grid
+// cells (row = R w + t / TX, col = t % TX) of every row window w (R = 64 / TX rows per window)
+// and accumulates them in registers. Entries are taken 64 at a time, one per lane; their
+// weights are copied to LDS so that a lane can read the tap (dy, dx) it needs. A window only
+// visits the entries whose footprint rows reach it: the tile list is sorted by footprint
+// row, so that range is found with two ballots over the lanes' footprint rows.
 template <int G, int TX>
-__global__ __launch_bounds__(kBlock) void k_col_adj(const cf* __restrict__ r, const Entry* __restrict__ ent,
-                                                    const int* __restrict__ tile_ptr,
-                                                    const cf* __restrict__ twg, cf* __restrict__ T,
-                                                    int N, int Ns) {
-  constexpr int P = TX + 1;
+__device__ inline void spread_tile(const Entry* __restrict__ ent, const cf* __restrict__ rg, int e0, int e1,
+                                   const Entry& first, cf first_r, float (*wst)[12], cf* __restrict__ Sw,
+                                   int lane) {
   constexpr int TY = G / 4;
-  constexpr int RPI = 64 / TX;   // grid rows per wave iteration
-  __shared__ cf S[G * P];
-  __shared__ cf tw[G];
-  const int sx = blockIdx.x, f = blockIdx.y, tid = threadIdx.x;
-  const int c0 = sx * TX;
-  for (int i = tid; i < G; i += kBlock) tw[i] = twg[i];
-  const int w = tid >> 6, lane = tid & 63;
+  constexpr int R = 64 / TX;
+  constexpr int NW = TY / R;
+  constexpr int P = TX + 1;
   const int col = lane % TX, rsub = lane / TX;
-  const int tile = (f * (G / TX) + sx) * 4 + w;
-  const int e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
-  const cf* rf = r + (size_t)f * Ns;
-  cf* Sw = S + w * TY * P;
-  int start = e0;
-  for (int rg = 0; rg < TY; rg += RPI) {
-    const int row = rg + rsub;
-    const int lo = rg - 5, hi = rg + RPI - 1;
-    while (start < e1 && (ent[start].lb >> 16) < lo) ++start;
-    cf acc = {0.f, 0.f};
-    for (int e = start; e < e1; ++e) {
-      const int lb = ent[e].lb;
-      const int lby = lb >> 16;
-      if (lby > hi) break;
-      const int dy = row - lby, dx = col - (short)(lb & 0xffff);
-      if (dy >= 0 && dy < 6 && dx >= 0 && dx < 6) {
-        const float wgt = ent[e].wy[dy] * ent[e].wx[dx];
-        const cf rv = rf[ent[e].j];
-        acc.x += wgt * rv.x;
-        acc.y += wgt * rv.y;
+  cf acc[NW];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) acc[w] = cf{0.f, 0.f};
+  for (int base = e0; base < e1; base += 64) {
+    const int cnt = min(64, e1 - base);
+    int lb = 0x7fff0000;       // rows beyond every window for idle lanes
+    cf rv{0.f, 0.f};
+    if (lane < cnt) {
+      const Entry en = base == e0 ? first : ent[base + lane];
+      lb = en.lb;
+      rv = base == e0 ? first_r : rg[base + lane];
+#pragma unroll
+      for (int d = 0; d < 6; ++d) {
+        wst[lane][d] = en.wx[d];
+        wst[lane][6 + d] = en.wy[d];
       }
     }
-    Sw[row * P + col] = acc;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int lby = lb >> 16;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const int row = w * R + rsub;
+      const int a = __popcll(__ballot(lby < w * R - 5));
+      const int b = __popcll(__ballot(lby <= w * R + R - 1));
+      for (int k = a; k < b; ++k) {
+        const int lbk = __builtin_amdgcn_readlane(lb, k);
+        const int dy = row - (lbk >> 16), dx = col - (short)(lbk & 0xffff);
+        const float rx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rv.x), k));
+        const float ry = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rv.y), k));
+        if (dy >= 0 && dy < 6 && dx >= 0 && dx < 6) {
+          const float wt = wst[k][6 + dy] * wst[k][dx];
+          acc[w].x += wt * rx;
+          acc[w].y += wt * ry;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  __syncthreads();
-  lds_fft<G, TX, P, 1, true, true>(S, tw);
-  cf* Tf = T + (size_t)f * N * G;
-  for (int idx = tid; idx < N * TX; idx += kBlock) {
-    const int y = idx / TX, c = idx % TX;
-    int n = y - N / 2;
-    if (n < 0) n += G;
-    Tf[(size_t)y * G + c0 + c] = S[n * P + c];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) Sw[(w * R + rsub) * P + col] = acc[w];
+}
+
+// Column pass, adjoint: per (strip, frame) spread the tile entries into the strip (each wave one
+// tile), inverse transform along y, write the N crop rows of the strip to T. The next frame's
+// first 64 entries per wave and their residual values are prefetched during the transform.
+template <int G, int TX>
+__global__ __launch_bounds__(kBlock) void k_col_adj(const cf* __restrict__ rg, const Entry* __restrict__ ent,
+                                                    const int* __restrict__ tile_ptr,
+                                                    const cf* __restrict__ twg, cf* __restrict__ T,
+                                                    int L, int FC) {
+  constexpr int N = G / 2;
+  constexpr int P = TX + 1;
+  constexpr int TY = G / 4;
+  constexpr int NSTRIP = G / TX;
+  __shared__ cf S[G * P];
+  __shared__ cf tw[G];
+  __shared__ float wst[4][64][12];
+  __shared__ int tp[kMaxFramesPerBlock][5];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  int sx, c;
+  if (!strip_and_chunk(NSTRIP, (L + FC - 1) / FC, sx, c)) return;
+  const int fb = c * FC, fe = min(L, fb + FC);
+  const int c0 = sx * TX;
+  for (int i = tid; i < G; i += kBlock) tw[i] = twg[i];
+  for (int i = tid; i < (fe - fb) * 5; i += kBlock)
+    tp[i / 5][i % 5] = tile_ptr[(size_t)(fb + i / 5) * NSTRIP * 4 + sx * 4 + i % 5];
+  lds_sync();
+  Entry en_pre{};
+  cf r_pre{0.f, 0.f};
+  auto load = [&](int f) {
+    const int e = tp[f - fb][w] + lane;
+    if (e < tp[f - fb][w + 1]) {
+      en_pre = ent[e];
+      r_pre = rg[e];
+    }
+  };
+  load(fb);
+  for (int f = fb; f < fe; ++f) {
+    const Entry first = en_pre;
+    const cf first_r = r_pre;
+    if (f + 1 < fe) load(f + 1);
+    spread_tile<G, TX>(ent, rg, tp[f - fb][w], tp[f - fb][w + 1], first, first_r, wst[w], S + w * TY * P, lane);
+    lds_sync();
+    lds_fft<G, TX, P, 1, true, true>(S, tw);
+    cf* Tf = T + (size_t)f * N * G;
+    for (int idx = tid; idx < N * TX; idx += kBlock) {
+      const int y = idx / TX, cc = idx % TX;
+      int n = y - N / 2;
+      if (n < 0) n += G;
+      Tf[(size_t)y * G + c0 + cc] = S[n * P + cc];
+    }
+    lds_sync();
   }
 }
 
@@ -227,6 +379,19 @@ __global__ __launch_bounds__(kBlock) void k_combine(const cf* __restrict__ parti
   if (e.z >= 0) acc = cadd(acc, partial[e.z]);
   if (e.w >= 0) acc = cadd(acc, partial[e.w]);
   b[i] = cscale(acc, scale);
+}
+
+// Copies each sample's value to its tile entries (the transpose of k_combine's sum).
+__global__ __launch_bounds__(kBlock) void k_gather_r(const cf* __restrict__ r, const int4* __restrict__ samp_ent,
+                                                     cf* __restrict__ rg, long total) {
+  const long i = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= total) return;
+  const int4 e = samp_ent[i];
+  const cf v = r[i];
+  rg[e.x] = v;
+  if (e.y >= 0) rg[e.y] = v;
+  if (e.z >= 0) rg[e.z] = v;
+  if (e.w >= 0) rg[e.w] = v;
 }
 
 // ------------------------------------------------------------------ host: plan
@@ -349,9 +514,10 @@ extern "C" mrf_status mrf_nufft_plan_create(const mrf_nufft_desc* d, const float
   MRF_REQUIRE(d->nframes >= 1 && d->nsamp >= 1, MRF_INVALID_ARG, "nufft_plan_create: nframes, nsamp must be >= 1");
   const int N = d->n, G = 2 * N;
   MRF_REQUIRE(N >= 16 && N <= 512 && supported_g(G), MRF_SHAPE, "nufft_plan_create: n must be a power of two in [16, 512]");
-  int TX = d->tile_cols ? d->tile_cols : (G == 1024 ? 8 : 16);
+  int TX = d->tile_cols ? d->tile_cols : (G <= 32 ? 16 : 8);
   MRF_REQUIRE(TX == 8 || TX == 16 || TX == 32, MRF_INVALID_ARG, "nufft_plan_create: tile_cols must be 0, 8, 16 or 32");
-  MRF_REQUIRE(TX <= G / 2 && (long)G * TX <= 8192, MRF_SHAPE, "nufft_plan_create: tile_cols too large for this grid");
+  MRF_REQUIRE(TX <= G / 2 && (long)G * TX <= 8192 && (TX < 32 || G <= 128), MRF_SHAPE,
+              "nufft_plan_create: tile_cols too large for this grid");
   MRF_REQUIRE((long)d->nframes * d->nsamp < (1L << 30), MRF_SHAPE, "nufft_plan_create: too many samples");
 
   auto* p = new mrf_nufft_plan_s{};
@@ -451,20 +617,41 @@ extern "C" mrf_status mrf_nufft_workspace_size(mrf_nufft_plan_t p, size_t* bytes
 
 namespace mrf {
 
+// One frame per column block: the blocks holding the k-space centre cost several times the
+// others, and many small blocks spread them over the whole chip.
+static int frames_per_chunk(const mrf_nufft_plan_s*) { return kMaxFramesPerBlock; }
+
+static int col_blocks(const mrf_nufft_plan_s* p, int FC) {
+  const int nchunks = (p->L + FC - 1) / FC;
+  return 8 * p->nstrips * ((nchunks + 7) / 8);
+}
+
+static int row_blocks(long ngroups) { return (int)std::min<long>(ngroups, 2048); }
+
 template <int G, int TX>
 static void launch_fwd_g(const mrf_nufft_plan_s* p, const cf* img, cf* T, cf* part, hipStream_t s) {
   const int nrows = p->L * p->N;
   constexpr int RPB = kBlock / (G / 8);
-  k_row_fwd<G><<<ceil_div(nrows, RPB), kBlock, 0, s>>>(img, T, p->dinv, p->tw, p->N, nrows);
-  k_col_fwd<G, TX><<<dim3(G / TX, p->L), kBlock, 0, s>>>(T, p->ent, p->tile_ptr, p->tw, part, p->N);
+  const int FC = frames_per_chunk(p);
+  MRF_LAUNCH("nufft_row_fwd", s,
+             k_row_fwd<G><<<row_blocks((nrows + RPB - 1) / RPB), kBlock, 0, s>>>(img, T, p->dinv, p->tw, nrows));
+  MRF_LAUNCH("nufft_col_fwd", s,
+             k_col_fwd<G, TX><<<col_blocks(p, FC), kBlock, 0, s>>>(T, p->ent, p->tile_ptr, p->tw, part, p->L, FC));
 }
 
 template <int G, int TX>
-static void launch_adj_g(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, cf* T, hipStream_t s) {
+static void launch_adj_g(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, cf* T, cf* rg, hipStream_t s) {
   const int nrows = p->L * p->N;
   constexpr int RPB = kBlock / (G / 8);
-  k_col_adj<G, TX><<<dim3(G / TX, p->L), kBlock, 0, s>>>(ksp, p->ent, p->tile_ptr, p->tw, T, p->N, p->Ns);
-  k_row_adj<G><<<ceil_div(nrows, RPB), kBlock, 0, s>>>(T, img, p->dinv, p->tw, p->N, nrows, 1.0f / p->N);
+  const int FC = frames_per_chunk(p);
+  const long total = (long)p->L * p->Ns;
+  MRF_LAUNCH("nufft_gather_r", s,
+             k_gather_r<<<ceil_div(total, kBlock), kBlock, 0, s>>>(ksp, p->samp_ent, rg, total));
+  MRF_LAUNCH("nufft_col_adj", s,
+             k_col_adj<G, TX><<<col_blocks(p, FC), kBlock, 0, s>>>(rg, p->ent, p->tile_ptr, p->tw, T, p->L, FC));
+  MRF_LAUNCH("nufft_row_adj", s,
+             k_row_adj<G><<<row_blocks((nrows + RPB - 1) / RPB), kBlock, 0, s>>>(T, img, p->dinv, p->tw, nrows,
+                                                                                1.0f / p->N));
 }
 
 #define MRF_DISPATCH_G_TX(FN, ...)                                                   \
@@ -479,7 +666,6 @@ static void launch_adj_g(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, cf* 
     case 128 * 100 + 32: FN<128, 32>(__VA_ARGS__); break;                            \
     case 256 * 100 + 8: FN<256, 8>(__VA_ARGS__); break;                              \
     case 256 * 100 + 16: FN<256, 16>(__VA_ARGS__); break;                            \
-    case 256 * 100 + 32: FN<256, 32>(__VA_ARGS__); break;                            \
     case 512 * 100 + 8: FN<512, 8>(__VA_ARGS__); break;                              \
     case 512 * 100 + 16: FN<512, 16>(__VA_ARGS__); break;                            \
     case 1024 * 100 + 8: FN<1024, 8>(__VA_ARGS__); break;                            \
@@ -499,7 +685,8 @@ const int4* nufft_samp_ent(const mrf_nufft_plan_s* p) { return p->samp_ent; }
 
 mrf_status nufft_adj_impl(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, void* ws, hipStream_t s) {
   cf* T = (cf*)ws;
-  MRF_DISPATCH_G_TX(launch_adj_g, p, ksp, img, T, s);
+  cf* rg = (cf*)((char*)ws + p->ws_T);
+  MRF_DISPATCH_G_TX(launch_adj_g, p, ksp, img, T, rg, s);
   MRF_CHECK_LAUNCH();
   return MRF_OK;
 }
@@ -514,8 +701,9 @@ extern "C" mrf_status mrf_nufft_fwd(mrf_nufft_plan_t p, const mrf_c64* img, mrf_
   mrf_status st = nufft_fwd_partials(p, (const cf*)img, ws, s);
   if (st != MRF_OK) return st;
   const long total = (long)p->L * p->Ns;
-  k_combine<<<ceil_div(total, kBlock), kBlock, 0, s>>>(nufft_partials(p, ws), p->samp_ent, (cf*)ksp, total,
-                                                       1.0f / p->N);
+  MRF_LAUNCH("nufft_combine", s,
+             k_combine<<<ceil_div(total, kBlock), kBlock, 0, s>>>(nufft_partials(p, ws), p->samp_ent, (cf*)ksp,
+                                                                  total, 1.0f / p->N));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
 }

@@ -1,5 +1,14 @@
-// Status strings, thread-local error messages and the version query of libmrf.
+// Status strings, thread-local error messages, the version query and per-kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <cstdio>
+#include <map>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/mrf.h"
 
@@ -35,3 +44,88 @@ extern "C" const char* mrf_status_string(mrf_status st) {
 extern "C" const char* mrf_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" int mrf_version(void) { return 100; }
+
+// ------------------------------------------------------------------ timing
+namespace {
+struct Rec {
+  const char* name;
+  hipEvent_t a, b;
+};
+std::atomic<bool> g_timing{false};
+std::mutex g_tmu;
+std::vector<Rec> g_recs;
+std::vector<hipEvent_t> g_pool;
+std::vector<std::pair<const char*, hipEvent_t>> g_open;
+
+hipEvent_t take_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+namespace mrf {
+bool timing_on() { return g_timing.load(std::memory_order_relaxed); }
+
+void timing_mark(const char* name, hipStream_t s, bool begin) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  hipEvent_t e = take_event();
+  if (!e) return;
+  hipEventRecord(e, s);
+  if (begin) {
+    g_open.emplace_back(name, e);
+  } else {
+    for (size_t i = g_open.size(); i-- > 0;) {
+      if (std::strcmp(g_open[i].first, name) == 0) {
+        g_recs.push_back(Rec{name, g_open[i].second, e});
+        g_open.erase(g_open.begin() + (long)i);
+        return;
+      }
+    }
+    g_pool.push_back(e);
+  }
+}
+}  // namespace mrf
+
+extern "C" mrf_status mrf_timing_enable(int on) {
+  mrf::clear_error();
+  g_timing.store(on != 0);
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_timing_report(char* buf, size_t len) {
+  mrf::clear_error();
+  if (!buf || len == 0) return mrf::fail(MRF_INVALID_ARG, "timing_report: null buffer");
+  std::lock_guard<std::mutex> lk(g_tmu);
+  struct Agg { long n = 0; double tot = 0, mn = 1e300, mx = 0; };
+  std::map<std::string, Agg> agg;
+  mrf_status st = MRF_OK;
+  for (auto& r : g_recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+      st = mrf::fail(MRF_DEVICE, "timing_report: event query failed");
+    } else {
+      Agg& a = agg[r.name];
+      a.n += 1; a.tot += ms; a.mn = std::min(a.mn, (double)ms); a.mx = std::max(a.mx, (double)ms);
+    }
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_recs.clear();
+  std::string out;
+  char line[256];
+  for (auto& kv : agg) {
+    std::snprintf(line, sizeof line, "%s %ld %.6f %.6f %.6f\n", kv.first.c_str(), kv.second.n, kv.second.tot,
+                  kv.second.mn, kv.second.mx);
+    out += line;
+  }
+  const size_t n = std::min(len - 1, out.size());
+  std::copy(out.begin(), out.begin() + (long)n, buf);
+  buf[n] = 0;
+  return st;
+}
