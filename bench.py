@@ -1,0 +1,241 @@
+"""Benchmark of the MS-LLR hot path on one MI355X.
+
+A step is one iteration of Algorithm 1 on the paper-scale workload (256 x 256 phantom, L = 1000
+FISP frames, 1 of 48 variable-density spiral interleaves per frame with 2048 samples, 12 179-atom
+dictionary compressed to a rank-10 subspace, 8 x 8 patches at stride 4, K = 16, rank cap 10):
+gradient step with one NUFFT pair, subspace projection, patch-graph Laplacian, per-patch SVT,
+X update, cost (NUFFT residual, FP64 patch eigen-analysis, Laplacian trace), per-iteration
+dictionary match and graph rebuild. Every iteration applies exactly one A and one A^H over all
+L frames, so iterations/s is the NUFFT pairs/s of the solve. Inputs are synthetic and resident
+in HBM before timing starts.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_TFLOPS = 157.3
+FP64_VECTOR_TFLOPS = 78.6
+METRIC = "NUFFT pairs/s, fingerprints matched/s; learned vs plain at fixed T1/T2 error"
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def build_workload(seed=0):
+    import mrfgen
+    cfg = mrfgen.get_config("C2")
+    t = time.time()
+    atoms, grid = mrfgen.make_dictionary(cfg)
+    V, _ = mrfgen.subspace_basis(atoms, cfg["r"])
+    ph = mrfgen.make_phantom(cfg, seed)
+    X = mrfgen.truth_fingerprints(cfg, ph)
+    traj = mrfgen.vds_spiral(cfg["N"], cfg["L"], cfg["Ns"], cfg["n_interleaves"])
+    log("workload generated in %.1f s (%d atoms)" % (time.time() - t, atoms.shape[0]))
+    return cfg, atoms, grid, V, ph, X, traj
+
+
+def algorithmic_work(name, cfg, E, Np):
+    """(bound, amount, unit) of one launch of `name` at this workload; amounts in bytes or flops."""
+    N, L, Ns = cfg["N"], cfg["L"], cfg["Ns"]
+    G = 2 * N
+    pp = cfg["p"] ** 2
+    M, r = 12179, cfg["r"]
+    img = L * N * N * 8          # one complex64 image series
+    T = L * N * G * 8            # row-pass intermediate (N rows of the 2N grid per frame)
+    table = {
+        "nufft_row_fwd": ("hbm", img + T),
+        "nufft_row_adj": ("hbm", T + img),
+        "nufft_col_fwd": ("hbm", T + E * 64 + E * 8),
+        "nufft_col_adj": ("hbm", E * 64 + E * 8 + T),
+        "llr_gram": ("mfma", 4.0 * pp * (pp + 1) * L * Np),          # Hermitian half, 8 flops / complex MAC
+        "match_subspace": ("mfma", 8.0 * N * N * M * r),
+        "subspace_reduce": ("hbm", 2 * img),
+        "subspace_expand": ("hbm", img),
+        "llr_coef": ("hbm", img),
+        "llr_xupdate": ("hbm", 2 * img),
+        "lap_quad": ("hbm", img),
+    }
+    if name not in table:
+        return None
+    bound, amount = table[name]
+    return bound, amount
+
+
+def cpu_baseline(cfg, traj, frames=16):
+    """The oracle's NUFFT pair (FP64 KB gridding) on a frame sample, scaled to the volume."""
+    from oracle import nufft as onufft
+    rng = np.random.default_rng(0)
+    N = cfg["N"]
+    X = rng.standard_normal((frames, N, N)) + 1j * rng.standard_normal((frames, N, N))
+    t = time.perf_counter()
+    b = onufft.nufft_fwd(X, traj[:frames])
+    onufft.nufft_adj(b, traj[:frames], N)
+    dt = time.perf_counter() - t
+    per_volume = dt * cfg["L"] / frames
+    return dict(value=1.0 / per_volume, unit="NUFFT pairs/s", cores=1, kind="oracle",
+                sample="oracle FP64 NUFFT pair (KB gridding, numpy.fft, single-threaded) on %d of the %d "
+                       "frames of the 256x256 workload, %.1f s, scaled to the full volume" % (frames, cfg["L"], dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (frames would shard "
+              "across GPUs; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2310_05647_amd as mrf
+
+    dev = torch.device("cuda:0")
+    cfg, atoms, grid, V, ph, Xtrue, traj = build_workload()
+    N, L, Ns = cfg["N"], cfg["L"], cfg["Ns"]
+    plan = mrf.NufftPlan(N, torch.from_numpy(traj).to(dev))
+    lamA = plan.opnorm(30)
+    log("lambda_max(A^H A) = %.3f" % lamA)
+    d = mrf.Dictionary(torch.from_numpy(atoms).to(dev), torch.from_numpy(grid["lut"]).to(dev),
+                       torch.from_numpy(V).to(dev))
+    import mrfgen
+    b = plan.fwd(torch.from_numpy(Xtrue).to(dev))
+    bh = b.cpu().numpy()
+    sig2 = mrfgen.noise_sigma(np.mean(np.abs(bh) ** 2), cfg["snr_db"])
+    b = torch.from_numpy(bh + mrfgen.complex_noise(bh.shape, sig2, 17)).to(dev)
+    rc = mrf.Recon(plan, d, cfg["p"], cfg["s"], cfg["K"], cfg["r_llr"], lam1_0=cfg["lam1_0"], lam2=cfg["lam2"],
+                   beta=cfg["beta"], mu0=cfg["mu0"], lamA=lamA, n_max=100000, tol=-1.0)
+    t = time.time()
+    rc.init(b)
+    torch.cuda.synchronize()
+    log("init (X0 = A^H b, match, graph, cost) %.2f s" % (time.time() - t))
+    for i in range(args.warmup):
+        rc.iterate(1)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for i in range(args.steps):
+        rc.iterate(1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    log("timed %d iterations: %.3f ms / iteration" % (args.steps, ms))
+
+    # per-kernel times over two more iterations (HIP events on the launch stream)
+    mrf.timing_enable(True)
+    nrep = 2
+    for i in range(nrep):
+        rc.iterate(1)
+    rep = mrf.timing_report()
+    mrf.timing_enable(False)
+    per_kernel = {k: dict(launches_per_step=v[0] / nrep, ms_per_step=v[1] / nrep, avg_ms=v[1] / v[0])
+                  for k, v in rep.items()}
+
+    # pure NUFFT pair and plain subspace match throughput
+    X = rc.finish()["X"]
+    kb = plan.fwd(X)
+    for _ in range(2):
+        plan.fwd(X, kb); plan.adj(kb, X)
+    e0.record()
+    for _ in range(10):
+        plan.fwd(X, kb); plan.adj(kb, X)
+    e1.record()
+    torch.cuda.synchronize()
+    pair_ms = e0.elapsed_time(e1) / 10
+    alpha = mrf.subspace_coeffs(X, torch.from_numpy(V).to(dev))
+    d.match_subspace(alpha)
+    e0.record()
+    for _ in range(5):
+        d.match_subspace(alpha)
+    e1.record()
+    torch.cuda.synchronize()
+    match_ms = e0.elapsed_time(e1) / 5
+
+    # roofline of the kernel that takes the most time per step
+    inf = _plan_entries(plan)
+    Np = ((N - cfg["p"]) // cfg["s"] + 1) ** 2
+    dom = max(per_kernel.items(), key=lambda kv: kv[1]["ms_per_step"])[0]
+    roof = None
+    for name in sorted(per_kernel, key=lambda k: -per_kernel[k]["ms_per_step"]):
+        w = algorithmic_work(name, cfg, inf, Np)
+        if w is None:
+            continue
+        bound, amount = w
+        avg_s = per_kernel[name]["avg_ms"] * 1e-3
+        if bound == "hbm":
+            ach, peak, unit = amount / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
+        else:
+            ach, peak, unit = amount / avg_s / 1e12, FP32_MFMA_TFLOPS, "TFLOP/s"
+        roof = dict(kernel=name, bound=bound, achieved=round(ach, 2), peak=peak, unit=unit, frac=round(ach / peak, 4),
+                    traffic=None, algorithmic_per_launch=amount, avg_launch_ms=round(per_kernel[name]["avg_ms"], 4),
+                    dominant_kernel=dom)
+        break
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(cfg, traj)
+
+    out = {
+        "metric": METRIC,
+        "value": round(1000.0 / ms, 3),
+        "unit": "NUFFT pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "MS-LLR iteration, 256x256 phantom, L=1000 FISP frames, VDS spiral 1/48 "
+                               "(2048 samples/frame), 12179-atom dictionary rank-10 subspace, 8x8 patches "
+                               "stride 4, K=16, rank cap 10",
+                   "N": N, "L": L, "Ns": Ns, "atoms": int(atoms.shape[0]), "r": cfg["r"], "p": cfg["p"],
+                   "s": cfg["s"], "K": cfg["K"], "rank_cap": cfg["r_llr"], "lamA": round(lamA, 4)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "components": {
+            "nufft_pair_ms": round(pair_ms, 4),
+            "nufft_pairs_per_s": round(1000.0 / pair_ms, 2),
+            "nufft_frame_pairs_per_s": round(1000.0 * L / pair_ms, 1),
+            "match_subspace_fp32_ms": round(match_ms, 4),
+            "fingerprints_matched_per_s_subspace_fp32": round(N * N / (match_ms * 1e-3), 1),
+            "per_kernel_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in
+                                       sorted(per_kernel.items(), key=lambda kv: -kv[1]["ms_per_step"])},
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _plan_entries(plan):
+    # number of (sample, tile) entries of the plan: 4 bytes x (L*ntiles+1) tile pointers
+    import ctypes
+    from paper_2310_05647_amd._lib import lib
+    sz = ctypes.c_size_t()
+    lib.mrf_nufft_workspace_size(plan.handle, ctypes.byref(sz))
+    N, L = plan.n, plan.L
+    T = L * N * 2 * N * 8
+    T = (T + 255) & ~255
+    return (sz.value - T) // 8
+
+
+if __name__ == "__main__":
+    main()

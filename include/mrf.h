@@ -91,6 +91,148 @@ mrf_status mrf_nufft_fwd(mrf_nufft_plan_t plan, const mrf_c64* img, mrf_c64* ksp
 /* img [L][N][N] = A^H ksp, ksp [L][Ns]. */
 mrf_status mrf_nufft_adj(mrf_nufft_plan_t plan, const mrf_c64* ksp, mrf_c64* img,
                          void* ws, size_t ws_bytes, hipStream_t stream);
+/* lambda_max(A^H A) estimated by `iters` power iterations from a deterministic start vector
+ * (seeded hash), written to *lam (host). Setup call: allocates temporary device memory and
+ * synchronises. Algorithm 1's step-size rule takes this bound (see mrf_recon_params.lamA). */
+mrf_status mrf_nufft_opnorm(mrf_nufft_plan_t plan, int iters, unsigned seed, double* lam, hipStream_t stream);
+
+
+/* ====================================================================================
+ * Patch graph on the parameter manifold (Sec. III-A): eq. (8) weights, eq. (10) Laplacian,
+ * and its use in the manifold term Tr(Q(X) L Q(X)^H) of eq. (9) / gradient of eq. (15).
+ * Patches are p x p with stride s (the paper's 11/5; the stride is floor(p/2)), origins
+ * (a s, b s), numbered in raster order; p % s == 0 and (n - p) % s == 0 are required.
+ * The graph keeps the K nearest patches by squared distance of the patch features (self
+ * excluded, ties to the lower index), symmetrised by W = max(W, W^T); the features are the
+ * (T1, T2, PD) map patches with every channel divided by its maximum over the map.
+ * ==================================================================================== */
+typedef struct mrf_graph_s* mrf_graph_t;
+
+/* Allocates a graph for n x n maps with p x p patches at stride s, at most k_max neighbours
+ * (k_max <= 32) and Laplacian quadratic forms over at most max_frames frames. The patch
+ * count must be in [2, 8192] (a dense Np x Np weight buffer is part of the handle). */
+mrf_status mrf_graph_create(int n, int p, int s, int k_max, int max_frames, mrf_graph_t* out);
+mrf_status mrf_graph_destroy(mrf_graph_t g);
+/* Builds the K-NN graph Laplacian from maps [3][n][n] (T1, T2, PD; device float32).
+ * sigma2 > 0 fixes sigma^2 of eq. (8); sigma2 <= 0 takes the lower median of the positive
+ * directed K-NN squared distances (1 when there are none). Asynchronous. */
+mrf_status mrf_knn_laplacian(mrf_graph_t g, const float* maps, int K, float sigma2, hipStream_t stream);
+/* Synchronises `stream` and reports the CSR of L (rows ascending, columns ascending, the
+ * diagonal D_ii included; device pointers owned by the graph), sigma^2 and max(L) (the
+ * largest entry of L, i.e. the largest degree, used by Algorithm 1's lambda1 schedule).
+ * Any output pointer may be NULL. */
+mrf_status mrf_graph_info(mrf_graph_t g, int* np, int* nnz, const int** rowptr, const int** col,
+                          const float** val, double* sigma2, double* lmax, hipStream_t stream);
+/* Y = Q*(Q(X) L) for X, Y [L][n][n] (must not alias). Asynchronous. */
+mrf_status mrf_laplacian_apply(mrf_graph_t g, const mrf_c64* X, mrf_c64* Y, int L, hipStream_t stream);
+/* out (device double) = Re<X, Q*(Q(X) L)> = Tr(Q(X) L Q(X)^H), X [L][n][n], L <= max_frames. */
+mrf_status mrf_laplacian_quad(mrf_graph_t g, const mrf_c64* X, int L, double* out, hipStream_t stream);
+
+/* ====================================================================================
+ * Locally low-rank step (Sec. III-C): per patch, singular value thresholding of the p^2 x L
+ * Casorati matrix Q_{q_i}(X) (eq. (22), threshold tau = 1/beta), keeping at most rank_cap
+ * values, then overlap-add Q*(P') (the term of eq. (23)). Computed from the patch Gram on
+ * MFMA (FP32) and its eigen-decomposition in FP64. p must be 2, 3, 4 or 8 and n % 16 == 0.
+ * ==================================================================================== */
+mrf_status mrf_llr_workspace_size(int n, int L, int p, int s, int rank_cap, size_t* bytes);
+/* QtP [L][n][n] = Q*(P'), nuc_norm (device double) = sum_i ||Q_{q_i}(X)||_* over all
+ * singular values (eq. (13)). X [L][n][n]. Asynchronous. */
+mrf_status mrf_llr_prox(const mrf_c64* X, mrf_c64* QtP, int n, int L, int p, int s, float tau, int rank_cap,
+                        double* nuc_norm, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ====================================================================================
+ * Temporal subspace (Sec. III-B, eq. (17)): P_S(X) = X V V^H for every voxel's time course,
+ * with V [L][r] an orthonormal basis approximated from the dictionary (an input, as P_S is
+ * among Algorithm 1's predefined inputs). r <= 16. X is frame-major [L][Nv].
+ * ==================================================================================== */
+mrf_status mrf_subspace_coeffs_workspace_size(int L, int Nv, int r, size_t* bytes);
+/* alpha [Nv][r] (voxel-major) = X V. */
+mrf_status mrf_subspace_coeffs(const mrf_c64* X, const mrf_c64* V, int L, int Nv, int r, mrf_c64* alpha,
+                               void* ws, size_t ws_bytes, hipStream_t stream);
+/* Z [L][Nv] = U V V^H; ws needs the coeffs workspace plus Nv * r * 8 bytes. */
+mrf_status mrf_subspace_project(const mrf_c64* U, const mrf_c64* V, int L, int Nv, int r, mrf_c64* Z,
+                                void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ====================================================================================
+ * Dictionary and pattern matching Phi_D (Sec. II-B, eqs. (3)-(5)).
+ * k = argmax_m |<d_m, x>| / ||d_m|| (ties to the lowest m), eta = LUT[k],
+ * rho = max(Re<d_k, x> / ||d_k||^2, 0), with <d, x> = sum_l conj(d_l) x_l. (Eq. (5) prints
+ * ||d_k||^2 in the arg-max denominator; the arg-max here uses ||d_k||, which coincides with it
+ * for unit-norm atoms.)
+ * ==================================================================================== */
+typedef struct mrf_dict_s* mrf_dict_t;
+
+/* atoms [M][L] complex (PD = 1 atoms, device), lut [M][nparam] float32 (device), V [L][r]
+ * or NULL. Keeps the atom norms, the unit-norm atoms and, with V, the projected unit atoms
+ * d_m V / ||d_m|| in MFMA operand order. Synchronises `stream`. 2 <= nparam <= 8, r <= 10. */
+mrf_status mrf_dict_create(const mrf_c64* atoms, const float* lut, int M, int L, int nparam, const mrf_c64* V,
+                           int r, hipStream_t stream, mrf_dict_t* out);
+mrf_status mrf_dict_destroy(mrf_dict_t d);
+/* Subspace match of alpha [Nv][r] (= x V per voxel) against d_m V, normalised by ||d_m||:
+ * idx [Nv] int32, and optionally rho [Nv], score [Nv] (= |<d_m V, alpha>| / ||d_m||),
+ * params [Nv][nparam] (LUT rows). FP32 on MFMA. Asynchronous. */
+mrf_status mrf_dict_match_subspace(mrf_dict_t d, const mrf_c64* alpha, int Nv, int32_t* idx, float* rho,
+                                   float* score, float* params, hipStream_t stream);
+
+/* ====================================================================================
+ * Algorithm 1: the MS-LLR reconstruction (Sec. III-C, III-D), run on the device.
+ *   X^0 = A^H b (or a given X0), M^0 = Phi_D(X^0), L^0 = mrf_knn_laplacian(M^0),
+ *   lambda1 = lambda1^0 max(L); per iteration the gradient step of eq. (15) with the
+ *   projection P_S (eq. (17)), the SVT of eq. (22) on Q(X^n), the X update of eq. (23) divided
+ *   per pixel by 1 + mu lam2 beta c(v) (c = patch coverage), the cost of Algorithm 1 and its
+ *   stopping rule cost(n-1)/cost(n) - 1 < tol; then M, L and lambda1 are updated.
+ *   Step size mu = min(mu0, 1 / (lamA + 2 c_max lambda1 max(L))) when lamA > 0, else mu0.
+ * The matching inside the loop and at the end is the subspace match (mrf_dict_match_subspace).
+ * ==================================================================================== */
+typedef struct mrf_recon_params {
+  int p, s;          /* patch side and stride (p % s == 0, (n - p) % s == 0; p in {2, 3, 4, 8})   */
+  int K;             /* graph neighbours                                                          */
+  int rank_cap;      /* at most this many singular values kept per patch (1..16)                   */
+  float lam1_0;      /* lambda1^0 of the schedule lambda1 = lambda1^0 max(L)                       */
+  float lam2;        /* lambda2                                                                   */
+  float beta;        /* penalty beta; SVT threshold 1/beta                                        */
+  float mu0;         /* step size cap (the paper's mu)                                            */
+  double lamA;       /* upper bound on lambda_max(A^H A); <= 0 keeps mu = mu0                      */
+  float sigma2;      /* sigma^2 of eq. (8); <= 0 selects the median rule                           */
+  int n_max;         /* maximum number of iterations                                              */
+  double tol;        /* stopping tolerance; < 0 runs exactly n_max iterations                     */
+} mrf_recon_params;
+
+#define MRF_MAX_ITERS 512
+typedef struct mrf_recon_stats {
+  int iters;         /* iterations run                                                            */
+  int stop_reason;   /* 0: n_max reached, 1: tolerance met                                        */
+  int n_graph;       /* graphs built                                                              */
+  double cost[MRF_MAX_ITERS + 1];   /* cost(0 .. iters)                                         */
+  double data[MRF_MAX_ITERS + 1];   /* 1/2 ||A X - b||^2                                        */
+  double tr[MRF_MAX_ITERS + 1];     /* Tr(Q(X) L Q(X)^H)                                        */
+  double nuc[MRF_MAX_ITERS + 1];    /* sum_i ||Q_i X||_*                                        */
+  double mu[MRF_MAX_ITERS + 1];     /* per graph: step size, lambda1, sigma^2, max(L)          */
+  double lam1[MRF_MAX_ITERS + 1];
+  double sigma2[MRF_MAX_ITERS + 1];
+  double lmax[MRF_MAX_ITERS + 1];
+} mrf_recon_stats;
+
+typedef struct mrf_recon_s* mrf_recon_t;
+
+/* Allocates the solver state (device memory owned by the handle, about 2 images of L x n x n
+ * plus the NUFFT and LLR work buffers) for a plan and a dictionary created with a basis V. */
+mrf_status mrf_recon_create(const mrf_recon_params* prm, mrf_nufft_plan_t plan, mrf_dict_t dict, mrf_recon_t* out);
+mrf_status mrf_recon_destroy(mrf_recon_t r);
+/* Initialisation of Algorithm 1 with measurements b [L][Ns] (kept by pointer until the last
+ * call that uses it) and an optional X0 [L][n][n] (NULL: X0 = A^H b). Synchronises. */
+mrf_status mrf_recon_init(mrf_recon_t r, const mrf_c64* b, const mrf_c64* X0, hipStream_t stream);
+/* Runs up to n more iterations (stops early on the tolerance or at n_max). Synchronises once
+ * per iteration to read the cost. *stopped (may be NULL) is set when no iteration is left. */
+mrf_status mrf_recon_iterate(mrf_recon_t r, int n, int* stopped, hipStream_t stream);
+/* Final match Phi_D(X): any of X_out [L][n][n], maps [3][n][n] (T1, T2, PD), idx [n*n],
+ * rho [n*n] may be NULL. Asynchronous. */
+mrf_status mrf_recon_finish(mrf_recon_t r, mrf_c64* X_out, float* maps, int32_t* idx, float* rho, hipStream_t stream);
+/* Copies the statistics of the run so far (host struct). */
+mrf_status mrf_recon_get_stats(mrf_recon_t r, mrf_recon_stats* out);
+/* The whole of Algorithm 1: init + iterate(n_max) + finish; stats may be NULL. */
+mrf_status mrf_recon(mrf_recon_t r, const mrf_c64* b, const mrf_c64* X0, mrf_c64* X_out, float* maps, int32_t* idx,
+                     float* rho, mrf_recon_stats* stats, hipStream_t stream);
 
 #ifdef __cplusplus
 }

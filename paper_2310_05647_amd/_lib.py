@@ -22,6 +22,21 @@ class NufftDesc(ctypes.Structure):
                 ("oversamp", c_int), ("tile_cols", c_int)]
 
 
+class ReconParams(ctypes.Structure):
+    _fields_ = [("p", c_int), ("s", c_int), ("K", c_int), ("rank_cap", c_int), ("lam1_0", c_float),
+                ("lam2", c_float), ("beta", c_float), ("mu0", c_float), ("lamA", ctypes.c_double),
+                ("sigma2", c_float), ("n_max", c_int), ("tol", ctypes.c_double)]
+
+
+MAX_ITERS = 512
+_D = ctypes.c_double * (MAX_ITERS + 1)
+
+
+class ReconStats(ctypes.Structure):
+    _fields_ = [("iters", c_int), ("stop_reason", c_int), ("n_graph", c_int), ("cost", _D), ("data", _D),
+                ("tr", _D), ("nuc", _D), ("mu", _D), ("lam1", _D), ("sigma2", _D), ("lmax", _D)]
+
+
 def _decl(name, args, res=c_int):
     f = getattr(lib, name)
     f.argtypes = args
@@ -39,6 +54,30 @@ _decl("mrf_nufft_plan_destroy", [c_void_p])
 _decl("mrf_nufft_workspace_size", [c_void_p, P(c_size_t)])
 _decl("mrf_nufft_fwd", [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_nufft_adj", [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p])
+_decl("mrf_nufft_opnorm", [c_void_p, c_int, ctypes.c_uint, P(ctypes.c_double), c_void_p])
+_decl("mrf_graph_create", [c_int, c_int, c_int, c_int, c_int, P(c_void_p)])
+_decl("mrf_graph_destroy", [c_void_p])
+_decl("mrf_knn_laplacian", [c_void_p, c_void_p, c_int, c_float, c_void_p])
+_decl("mrf_graph_info", [c_void_p, P(c_int), P(c_int), P(c_void_p), P(c_void_p), P(c_void_p),
+                         P(ctypes.c_double), P(ctypes.c_double), c_void_p])
+_decl("mrf_laplacian_apply", [c_void_p, c_void_p, c_void_p, c_int, c_void_p])
+_decl("mrf_laplacian_quad", [c_void_p, c_void_p, c_int, c_void_p, c_void_p])
+_decl("mrf_llr_workspace_size", [c_int, c_int, c_int, c_int, c_int, P(c_size_t)])
+_decl("mrf_llr_prox", [c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_float, c_int, c_void_p, c_void_p,
+                       c_size_t, c_void_p])
+_decl("mrf_subspace_coeffs_workspace_size", [c_int, c_int, c_int, P(c_size_t)])
+_decl("mrf_subspace_coeffs", [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_size_t, c_void_p])
+_decl("mrf_subspace_project", [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_size_t, c_void_p])
+_decl("mrf_dict_create", [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_int, c_void_p, P(c_void_p)])
+_decl("mrf_dict_destroy", [c_void_p])
+_decl("mrf_dict_match_subspace", [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p])
+_decl("mrf_recon_create", [P(ReconParams), c_void_p, c_void_p, P(c_void_p)])
+_decl("mrf_recon_destroy", [c_void_p])
+_decl("mrf_recon_init", [c_void_p, c_void_p, c_void_p, c_void_p])
+_decl("mrf_recon_iterate", [c_void_p, c_int, P(c_int), c_void_p])
+_decl("mrf_recon_finish", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p])
+_decl("mrf_recon_get_stats", [c_void_p, P(ReconStats)])
+_decl("mrf_recon", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, P(ReconStats), c_void_p])
 
 
 class MrfError(RuntimeError):

@@ -1,0 +1,571 @@
+// Parameter-manifold patch graph and graph-Laplacian operators (Sec. III-A, eqs. (7)-(10), (15)).
+//
+//   w_ij = exp(-||Q_{q_i}(M) - Q_{q_j}(M)||^2 / sigma^2)      eq. (8)
+//   L = D - W, D_ii = sum_j w_ij                              eq. (10)
+//   S_L X = Q*(Q(X) L)                                        manifold gradient of eq. (15)
+// The graph keeps, for every patch, its K nearest patches by squared feature distance (self
+// excluded, ties to the lower index), symmetrised by W = max(W, W^T). Features are the p x p x 3
+// patches of the (T1, T2, PD) maps, each channel divided by its maximum over the map. sigma^2 is
+// the lower median of the positive directed K-NN squared distances unless given.
+//
+// Kernels: k_chan_max -> k_features -> k_knn (one block per patch: distances to all patches and a
+// deterministic block-wide K-way selection) -> k_sigma (radix select of the median) -> dense
+// symmetric W -> CSR rows with the diagonal D_ii (columns ascending) -> lmax = max_i D_ii.
+// Laplacian apply: one block per s x s pixel cell and a chunk of frames; every pixel of a cell
+// lies in the same patches, so the stencil (covering patch i, neighbour j, L_ij) is uniform
+// across the block and each source pixel is the output pixel shifted by q_j - q_i.
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+#include "fft.hpp"
+#include "patch.hpp"
+
+struct mrf_graph_s {
+  mrf::PatchGeom g;
+  int kmax, K, nf;
+  float* F;        // [Np][nf] features
+  int* knn;        // [Np][kmax]
+  float* knd2;     // [Np][kmax]
+  float* W;        // [Np][Np]
+  int* rowptr;     // [Np + 1]
+  int* col;        // [cap]
+  float* val;      // [cap]
+  int* cnt;        // [Np]
+  float* deg;      // [Np]
+  float* mx;       // [3]
+  double* scal;    // [4]: sigma2, lmax, nnz, positive distances
+  double* part;    // [max quad-form blocks]
+  size_t cap, npart;
+};
+
+namespace mrf {
+
+constexpr int kMaxK = 32;
+
+__global__ __launch_bounds__(1024) void k_chan_max(const float* __restrict__ maps, int nn, float* __restrict__ mx) {
+  __shared__ float red[1024];
+  for (int c = 0; c < 3; ++c) {
+    float m = -3.4e38f;
+    for (int i = threadIdx.x; i < nn; i += 1024) m = fmaxf(m, maps[(size_t)c * nn + i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) mx[c] = red[0] > 0.f ? red[0] : 1.f;
+    __syncthreads();
+  }
+}
+
+__global__ void k_features(const float* __restrict__ maps, const float* __restrict__ mx, PatchGeom g,
+                           float* __restrict__ F) {
+  const int pp = g.p * g.p, nf = 3 * pp;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)g.Np * nf) return;
+  const int i = (int)(t / nf), f = (int)(t % nf);
+  const int c = f / pp, r = f % pp;
+  const int y = (i / g.n1) * g.s + r / g.p, x = (i % g.n1) * g.s + r % g.p;
+  F[t] = maps[((size_t)c * g.N + y) * g.N + x] / mx[c];
+}
+
+// One block per patch i: squared distances to every other patch, then the K smallest
+// (distance, index) keys. Each thread keeps its own sorted top-K in LDS; K rounds of a
+// block-wide minimum over the threads' heads produce the global order.
+__global__ __launch_bounds__(256) void k_knn(const float* __restrict__ F, int Np, int nf, int K,
+                                             int* __restrict__ knn, float* __restrict__ knd2, int kmax) {
+  __shared__ float Fi[768];
+  __shared__ unsigned long long lst[256][kMaxK];
+  __shared__ unsigned long long red[256];
+  __shared__ int redt[256];
+  const int i = blockIdx.x, t = threadIdx.x;
+  for (int f = t; f < nf; f += 256) Fi[f] = F[(size_t)i * nf + f];
+  __syncthreads();
+  int n = 0;
+  for (int j = t; j < Np; j += 256) {
+    if (j == i) continue;
+    const float* Fj = F + (size_t)j * nf;
+    float d2 = 0.f;
+    for (int f = 0; f < nf; ++f) {
+      const float d = Fi[f] - Fj[f];
+      d2 = fmaf(d, d, d2);
+    }
+    const unsigned long long key = ((unsigned long long)__float_as_uint(d2) << 32) | (unsigned)j;
+    if (n < K || key < lst[t][K - 1]) {
+      int pos = n < K ? n : K - 1;
+      while (pos > 0 && lst[t][pos - 1] > key) {
+        lst[t][pos] = lst[t][pos - 1];
+        --pos;
+      }
+      lst[t][pos] = key;
+      if (n < K) ++n;
+    }
+  }
+  int head = 0;
+  for (int k = 0; k < K; ++k) {
+    red[t] = head < n ? lst[t][head] : ~0ull;
+    redt[t] = t;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (t < o && red[t + o] < red[t]) {
+        red[t] = red[t + o];
+        redt[t] = redt[t + o];
+      }
+      __syncthreads();
+    }
+    const unsigned long long best = red[0];
+    if (t == redt[0]) ++head;
+    if (t == 0) {
+      knn[(size_t)i * kmax + k] = (int)(best & 0xffffffffu);
+      knd2[(size_t)i * kmax + k] = __uint_as_float((unsigned)(best >> 32));
+    }
+    __syncthreads();
+  }
+}
+
+// sigma^2: the lower median of the positive directed K-NN squared distances (radix select on the
+// float bit patterns, which order like the values for non-negative floats); 1 if there are none.
+__global__ __launch_bounds__(1024) void k_sigma(const float* __restrict__ knd2, int Np, int K, int kmax,
+                                                float sigma2_user, double* __restrict__ scal) {
+  __shared__ int hist[256];
+  __shared__ int cnt_s;
+  __shared__ unsigned prefix_s;
+  __shared__ int target_s;
+  const int t = threadIdx.x;
+  const int total = Np * K;
+  if (t == 0) cnt_s = 0;
+  __syncthreads();
+  int c = 0;
+  for (int e = t; e < total; e += 1024) c += knd2[(size_t)(e / K) * kmax + e % K] > 0.f;
+  atomicAdd(&cnt_s, c);
+  __syncthreads();
+  const int npos = cnt_s;
+  if (sigma2_user > 0.f || npos == 0) {
+    if (t == 0) {
+      scal[0] = sigma2_user > 0.f ? (double)sigma2_user : 1.0;
+      scal[3] = npos;
+    }
+    return;
+  }
+  if (t == 0) {
+    prefix_s = 0u;
+    target_s = (npos - 1) / 2;
+  }
+  __syncthreads();
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 24 - 8 * pass;
+    for (int b = t; b < 256; b += 1024) hist[b] = 0;
+    __syncthreads();
+    const unsigned prefix = prefix_s;
+    const unsigned hmask = pass == 0 ? 0u : (0xffffffffu << (32 - 8 * pass));
+    for (int e = t; e < total; e += 1024) {
+      const float v = knd2[(size_t)(e / K) * kmax + e % K];
+      if (!(v > 0.f)) continue;
+      const unsigned u = __float_as_uint(v);
+      if ((u & hmask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    if (t == 0) {
+      int tg = target_s, b = 0;
+      while (tg >= hist[b]) {
+        tg -= hist[b];
+        ++b;
+      }
+      target_s = tg;
+      prefix_s = prefix | ((unsigned)b << shift);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    scal[0] = (double)__uint_as_float(prefix_s);
+    scal[3] = npos;
+  }
+}
+
+__global__ void k_fill_f(float* __restrict__ a, size_t n, float v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) a[i] = v;
+}
+
+__global__ void k_scatter_w(const int* __restrict__ knn, const float* __restrict__ knd2, int Np, int K, int kmax,
+                            const double* __restrict__ scal, float* __restrict__ W) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)Np * K) return;
+  const int i = (int)(t / K), k = (int)(t % K);
+  const int j = knn[(size_t)i * kmax + k];
+  const float w = expf(-knd2[(size_t)i * kmax + k] / (float)scal[0]);
+  // when both (i, j) and (j, i) are K-NN edges the two writes carry the same value: the
+  // distance is computed from the same features in the same order
+  W[(size_t)i * Np + j] = w;
+  W[(size_t)j * Np + i] = w;
+}
+
+// Per row: number of off-diagonal non-zeros (+1 for the diagonal) and the degree, summed in a
+// fixed order (per-thread strided partial sums, then a tree).
+__global__ __launch_bounds__(256) void k_row_stats(const float* __restrict__ W, int Np, int* __restrict__ cnt,
+                                                   float* __restrict__ deg) {
+  __shared__ float rs[256];
+  __shared__ int rc[256];
+  const int i = blockIdx.x, t = threadIdx.x;
+  float s = 0.f;
+  int c = 0;
+  for (int j = t; j < Np; j += 256) {
+    const float w = W[(size_t)i * Np + j];
+    s += w;
+    c += w != 0.f;
+  }
+  rs[t] = s;
+  rc[t] = c;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      rs[t] += rs[t + o];
+      rc[t] += rc[t + o];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    deg[i] = rs[0];
+    cnt[i] = rc[0] + 1;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_rowptr(const int* __restrict__ cnt, int Np, int* __restrict__ rowptr,
+                                                      const float* __restrict__ deg, double* __restrict__ scal) {
+  __shared__ int part[1024];
+  __shared__ float mxs[1024];
+  const int t = threadIdx.x;
+  const int per = (Np + 1023) / 1024;
+  int s = 0;
+  float m = 0.f;
+  for (int k = 0; k < per; ++k) {
+    const int i = t * per + k;
+    if (i < Np) {
+      s += cnt[i];
+      m = fmaxf(m, deg[i]);
+    }
+  }
+  part[t] = s;
+  mxs[t] = m;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {  // inclusive scan (Hillis-Steele)
+    const int v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  for (int o = 512; o > 0; o >>= 1) {
+    if (t < o) mxs[t] = fmaxf(mxs[t], mxs[t + o]);
+    __syncthreads();
+  }
+  int run = t == 0 ? 0 : part[t - 1];
+  for (int k = 0; k < per; ++k) {
+    const int i = t * per + k;
+    if (i < Np) {
+      rowptr[i] = run;
+      run += cnt[i];
+    }
+  }
+  if (t == 1023) {
+    rowptr[Np] = part[1023];
+    scal[1] = mxs[0];        // max(L) = largest degree
+    scal[2] = part[1023];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_csr_fill(const float* __restrict__ W, const float* __restrict__ deg, int Np,
+                                                  const int* __restrict__ rowptr, int* __restrict__ col,
+                                                  float* __restrict__ val) {
+  __shared__ int sc[256];
+  const int i = blockIdx.x, t = threadIdx.x;
+  int out = rowptr[i];
+  for (int j0 = 0; j0 < Np; j0 += 256) {
+    const int j = j0 + t;
+    const float w = j < Np ? W[(size_t)i * Np + j] : 0.f;
+    const int flag = j < Np && (w != 0.f || j == i);
+    sc[t] = flag;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+      const int v = t >= o ? sc[t - o] : 0;
+      __syncthreads();
+      sc[t] += v;
+      __syncthreads();
+    }
+    if (flag) {
+      const int pos = out + sc[t] - 1;
+      col[pos] = j;
+      val[pos] = j == i ? deg[i] : -w;
+    }
+    out += sc[255];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- Laplacian apply
+constexpr int kLapFramesPerThread = 8;
+
+// Y = Q*(Q(X) L) on full frames (QUAD = false), or the per-block partial sums of
+// Re<X, Q*(Q(X) L)> (QUAD = true). Block: one cell, 256 threads = s^2 pixels x (256/s^2)
+// frame lanes, each thread kLapFramesPerThread frames.
+template <bool QUAD>
+__global__ __launch_bounds__(256) void k_lap_full(const cf* __restrict__ X, cf* __restrict__ Y,
+                                                  double* __restrict__ part, const int* __restrict__ rowptr,
+                                                  const int* __restrict__ col, const float* __restrict__ val,
+                                                  PatchGeom g, int L) {
+  const int ss = g.s * g.s;
+  const int nsub = 256 / ss;
+  const int cell = blockIdx.x, t = threadIdx.x;
+  const int cy = cell / g.nc, cx = cell % g.nc;
+  const int pix = t % ss, fsub = t / ss;
+  const int py = cy * g.s + pix / g.s, px = cx * g.s + pix % g.s;
+  const int v = py * g.N + px;
+  const int f0 = blockIdx.y * nsub * kLapFramesPerThread + fsub;
+  const size_t NN = (size_t)g.N * g.N;
+  cf acc[kLapFramesPerThread];
+#pragma unroll
+  for (int k = 0; k < kLapFramesPerThread; ++k) acc[k] = cf{0.f, 0.f};
+  const bool active = t < nsub * ss;
+  int alo, ahi, blo, bhi;
+  cover_range(g, cy, alo, ahi);
+  cover_range(g, cx, blo, bhi);
+  for (int a = alo; a <= ahi; ++a) {
+    for (int b = blo; b <= bhi; ++b) {
+      const int i = a * g.n1 + b;
+      const int e1 = rowptr[i + 1];
+      for (int e = rowptr[i]; e < e1; ++e) {
+        const int j = col[e];
+        const float w = val[e];
+        const int src = v + ((j / g.n1 - a) * g.N + (j % g.n1 - b)) * g.s;
+#pragma unroll
+        for (int k = 0; k < kLapFramesPerThread; ++k) {
+          const int f = f0 + k * nsub;
+          if (active && f < L) {
+            const cf xv = X[(size_t)f * NN + src];
+            acc[k].x += w * xv.x;
+            acc[k].y += w * xv.y;
+          }
+        }
+      }
+    }
+  }
+  if (!QUAD) {
+#pragma unroll
+    for (int k = 0; k < kLapFramesPerThread; ++k) {
+      const int f = f0 + k * nsub;
+      if (active && f < L) Y[(size_t)f * NN + v] = acc[k];
+    }
+  } else {
+    __shared__ double red[256];
+    double q = 0.0;
+#pragma unroll
+    for (int k = 0; k < kLapFramesPerThread; ++k) {
+      const int f = f0 + k * nsub;
+      if (active && f < L) {
+        const cf xv = X[(size_t)f * NN + v];
+        q += (double)xv.x * acc[k].x + (double)xv.y * acc[k].y;
+      }
+    }
+    red[t] = q;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (t < o) red[t] += red[t + o];
+      __syncthreads();
+    }
+    if (t == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+  }
+}
+
+// S_L applied to per-voxel subspace coefficients A[v][k] (k < r), voxel-major. One thread per voxel.
+__global__ __launch_bounds__(256) void k_lap_sub(const cf* __restrict__ A, cf* __restrict__ Y,
+                                                 const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                 const float* __restrict__ val, PatchGeom g, int r) {
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v >= g.N * g.N) return;
+  const int py = v / g.N, px = v % g.N;
+  const int cy = py / g.s, cx = px / g.s;
+  cf acc[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acc[k] = cf{0.f, 0.f};
+  int alo, ahi, blo, bhi;
+  cover_range(g, cy, alo, ahi);
+  cover_range(g, cx, blo, bhi);
+  for (int a = alo; a <= ahi; ++a)
+    for (int b = blo; b <= bhi; ++b) {
+      const int i = a * g.n1 + b;
+      for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        const int j = col[e];
+        const float w = val[e];
+        const int src = v + ((j / g.n1 - a) * g.N + (j % g.n1 - b)) * g.s;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (k < r) {
+            const cf av = A[(size_t)src * r + k];
+            acc[k].x += w * av.x;
+            acc[k].y += w * av.y;
+          }
+      }
+    }
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (k < r) Y[(size_t)v * r + k] = acc[k];
+}
+
+// Deterministic sum of block partials (single block, fixed order) into out[0].
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ part, long n, double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (long i = threadIdx.x; i < n; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// -------------------------------------------------------------- internal entry points
+mrf_status graph_build(mrf_graph_s* G, const float* maps, int K, float sigma2, hipStream_t s) {
+  const PatchGeom& g = G->g;
+  const int nf = 3 * g.p * g.p;
+  MRF_LAUNCH("graph_chan_max", s, k_chan_max<<<1, 1024, 0, s>>>(maps, g.N * g.N, G->mx));
+  const long nfeat = (long)g.Np * nf;
+  MRF_LAUNCH("graph_features", s, k_features<<<ceil_div(nfeat, 256), 256, 0, s>>>(maps, G->mx, g, G->F));
+  MRF_LAUNCH("graph_knn", s, k_knn<<<g.Np, 256, 0, s>>>(G->F, g.Np, nf, K, G->knn, G->knd2, G->kmax));
+  MRF_LAUNCH("graph_sigma", s, k_sigma<<<1, 1024, 0, s>>>(G->knd2, g.Np, K, G->kmax, sigma2, G->scal));
+  const size_t nw = (size_t)g.Np * g.Np;
+  MRF_LAUNCH("graph_zero_w", s, k_fill_f<<<1024, 256, 0, s>>>(G->W, nw, 0.f));
+  MRF_LAUNCH("graph_scatter_w", s,
+             k_scatter_w<<<ceil_div((long)g.Np * K, 256), 256, 0, s>>>(G->knn, G->knd2, g.Np, K, G->kmax, G->scal, G->W));
+  MRF_LAUNCH("graph_row_stats", s, k_row_stats<<<g.Np, 256, 0, s>>>(G->W, g.Np, G->cnt, G->deg));
+  MRF_LAUNCH("graph_rowptr", s, k_scan_rowptr<<<1, 1024, 0, s>>>(G->cnt, g.Np, G->rowptr, G->deg, G->scal));
+  MRF_LAUNCH("graph_csr_fill", s, k_csr_fill<<<g.Np, 256, 0, s>>>(G->W, G->deg, g.Np, G->rowptr, G->col, G->val));
+  MRF_CHECK_LAUNCH();
+  G->K = K;
+  return MRF_OK;
+}
+
+int lap_frame_chunks(const PatchGeom& g, int L) {
+  const int nsub = 256 / (g.s * g.s);
+  return ceil_div(L, (long)nsub * kLapFramesPerThread);
+}
+
+mrf_status lap_apply_full(const mrf_graph_s* G, const cf* X, cf* Y, int L, hipStream_t s) {
+  dim3 grid(G->g.nc * G->g.nc, lap_frame_chunks(G->g, L));
+  MRF_LAUNCH("lap_apply", s, k_lap_full<false><<<grid, 256, 0, s>>>(X, Y, nullptr, G->rowptr, G->col, G->val, G->g, L));
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+
+// out (device double) = Re<X, S_L X>
+mrf_status lap_quad(mrf_graph_s* G, const cf* X, int L, double* out, hipStream_t s) {
+  dim3 grid(G->g.nc * G->g.nc, lap_frame_chunks(G->g, L));
+  const size_t nb = (size_t)grid.x * grid.y;
+  if (nb > G->npart) return fail(MRF_SHAPE, "laplacian quad: too many frames for the partial-sum buffer");
+  MRF_LAUNCH("lap_quad", s, k_lap_full<true><<<grid, 256, 0, s>>>(X, nullptr, G->part, G->rowptr, G->col, G->val, G->g, L));
+  MRF_LAUNCH("sum_partials", s, k_sum_partials<<<1, 256, 0, s>>>(G->part, (long)nb, out));
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+
+mrf_status lap_apply_sub(const mrf_graph_s* G, const cf* A, cf* Y, int r, hipStream_t s) {
+  if (r > 16) return fail(MRF_SHAPE, "laplacian on subspace coefficients: r must be <= 16");
+  MRF_LAUNCH("lap_sub", s, k_lap_sub<<<ceil_div((long)G->g.N * G->g.N, 256), 256, 0, s>>>(A, Y, G->rowptr, G->col, G->val, G->g, r));
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+
+const double* graph_scalars(const mrf_graph_s* G) { return G->scal; }
+
+mrf_status sum_partials(const double* part, long n, double* out, hipStream_t s) {
+  MRF_LAUNCH("sum_partials", s, k_sum_partials<<<1, 256, 0, s>>>(part, n, out));
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+const PatchGeom& graph_geom(const mrf_graph_s* G) { return G->g; }
+
+}  // namespace mrf
+
+using namespace mrf;
+
+extern "C" mrf_status mrf_graph_create(int n, int p, int s, int k_max, int max_frames, mrf_graph_t* out) {
+  clear_error();
+  MRF_REQUIRE(out, MRF_INVALID_ARG, "graph_create: null output");
+  *out = nullptr;
+  PatchGeom g;
+  MRF_REQUIRE(make_geom(n, p, s, &g), MRF_SHAPE, "graph_create: need p % s == 0 and (n - p) % s == 0");
+  MRF_REQUIRE(s * s <= 256 && p <= 16, MRF_SHAPE, "graph_create: patch side must be <= 16 and s^2 <= 256");
+  MRF_REQUIRE(k_max >= 1 && k_max <= kMaxK, MRF_INVALID_ARG, "graph_create: k_max must be in [1, 32]");
+  MRF_REQUIRE(max_frames >= 1, MRF_INVALID_ARG, "graph_create: max_frames must be >= 1");
+  MRF_REQUIRE(g.Np >= 2 && g.Np <= 8192, MRF_SHAPE, "graph_create: patch count must be in [2, 8192]");
+  auto* G = new mrf_graph_s{};
+  G->g = g;
+  G->kmax = k_max;
+  G->nf = 3 * p * p;
+  G->cap = (size_t)g.Np * (2 * k_max + 1);
+  G->npart = (size_t)g.nc * g.nc * lap_frame_chunks(g, max_frames);
+  bool ok = hipMalloc(&G->F, (size_t)g.Np * G->nf * 4) == hipSuccess &&
+            hipMalloc(&G->knn, (size_t)g.Np * k_max * 4) == hipSuccess &&
+            hipMalloc(&G->knd2, (size_t)g.Np * k_max * 4) == hipSuccess &&
+            hipMalloc(&G->W, (size_t)g.Np * g.Np * 4) == hipSuccess &&
+            hipMalloc(&G->rowptr, (size_t)(g.Np + 1) * 4) == hipSuccess &&
+            hipMalloc(&G->col, G->cap * 4) == hipSuccess && hipMalloc(&G->val, G->cap * 4) == hipSuccess &&
+            hipMalloc(&G->cnt, (size_t)g.Np * 4) == hipSuccess && hipMalloc(&G->deg, (size_t)g.Np * 4) == hipSuccess &&
+            hipMalloc(&G->mx, 16) == hipSuccess && hipMalloc(&G->scal, 4 * sizeof(double)) == hipSuccess &&
+            hipMalloc(&G->part, G->npart * sizeof(double)) == hipSuccess;
+  if (!ok) {
+    mrf_graph_destroy(G);
+    return fail(MRF_OOM, "graph_create: device allocation failed");
+  }
+  *out = G;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_graph_destroy(mrf_graph_t G) {
+  clear_error();
+  if (!G) return MRF_OK;
+  hipFree(G->F); hipFree(G->knn); hipFree(G->knd2); hipFree(G->W); hipFree(G->rowptr); hipFree(G->col);
+  hipFree(G->val); hipFree(G->cnt); hipFree(G->deg); hipFree(G->mx); hipFree(G->scal); hipFree(G->part);
+  delete G;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_knn_laplacian(mrf_graph_t G, const float* maps, int K, float sigma2, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(G && maps, MRF_INVALID_ARG, "knn_laplacian: null argument");
+  MRF_REQUIRE(K >= 1 && K <= G->kmax && K <= G->g.Np - 1, MRF_INVALID_ARG, "knn_laplacian: K must be in [1, min(k_max, Np - 1)]");
+  MRF_REQUIRE(sigma2 == sigma2, MRF_INVALID_ARG, "knn_laplacian: sigma2 is NaN");
+  return graph_build(G, maps, K, sigma2, s);
+}
+
+extern "C" mrf_status mrf_graph_info(mrf_graph_t G, int* np, int* nnz, const int** rowptr, const int** col,
+                                     const float** val, double* sigma2, double* lmax, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(G, MRF_INVALID_ARG, "graph_info: null graph");
+  double h[4];
+  MRF_CHECK_HIP(hipMemcpyAsync(h, G->scal, sizeof h, hipMemcpyDeviceToHost, s));
+  MRF_CHECK_HIP(hipStreamSynchronize(s));
+  if (np) *np = G->g.Np;
+  if (nnz) *nnz = (int)h[2];
+  if (rowptr) *rowptr = G->rowptr;
+  if (col) *col = G->col;
+  if (val) *val = G->val;
+  if (sigma2) *sigma2 = h[0];
+  if (lmax) *lmax = h[1];
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_laplacian_apply(mrf_graph_t G, const mrf_c64* X, mrf_c64* Y, int L, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(G && X && Y, MRF_INVALID_ARG, "laplacian_apply: null argument");
+  MRF_REQUIRE(L >= 1, MRF_INVALID_ARG, "laplacian_apply: L must be >= 1");
+  MRF_REQUIRE(X != (const mrf_c64*)Y, MRF_INVALID_ARG, "laplacian_apply: X and Y must not alias");
+  return lap_apply_full(G, (const cf*)X, (cf*)Y, L, s);
+}
+
+extern "C" mrf_status mrf_laplacian_quad(mrf_graph_t G, const mrf_c64* X, int L, double* out, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(G && X && out, MRF_INVALID_ARG, "laplacian_quad: null argument");
+  MRF_REQUIRE(L >= 1, MRF_INVALID_ARG, "laplacian_quad: L must be >= 1");
+  return lap_quad(G, (const cf*)X, L, out, s);
+}

@@ -381,6 +381,85 @@ __global__ __launch_bounds__(kBlock) void k_combine(const cf* __restrict__ parti
   b[i] = cscale(acc, scale);
 }
 
+// r = scale * (sum of partials) - b, and per-block partial sums of |r|^2 (double).
+__global__ __launch_bounds__(kBlock) void k_combine_resid(const cf* __restrict__ partial,
+                                                          const int4* __restrict__ samp_ent,
+                                                          const cf* __restrict__ b, cf* __restrict__ r, long total,
+                                                          float scale, double* __restrict__ part) {
+  __shared__ double red[kBlock];
+  const long i = (long)blockIdx.x * kBlock + threadIdx.x;
+  double q = 0.0;
+  if (i < total) {
+    const int4 e = samp_ent[i];
+    cf acc = partial[e.x];
+    if (e.y >= 0) acc = cadd(acc, partial[e.y]);
+    if (e.z >= 0) acc = cadd(acc, partial[e.z]);
+    if (e.w >= 0) acc = cadd(acc, partial[e.w]);
+    const cf bv = b[i];
+    const cf d = cf{acc.x * scale - bv.x, acc.y * scale - bv.y};
+    r[i] = d;
+    q = (double)d.x * d.x + (double)d.y * d.y;
+  }
+  red[threadIdx.x] = q;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Power-iteration helpers: deterministic start vector, <x, y> and ||y||^2 block partials, scaling.
+__global__ void k_hash_fill(cf* __restrict__ x, long n, unsigned seed) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    unsigned h = (unsigned)i * 2654435761u ^ seed * 2246822519u;
+    h ^= h >> 15; h *= 2246822519u; h ^= h >> 13; h *= 3266489917u; h ^= h >> 16;
+    const unsigned g = h * 747796405u + 2891336453u;
+    x[i] = cf{(float)(h & 0xffffff) / 16777216.f - 0.5f, (float)(g & 0xffffff) / 16777216.f - 0.5f};
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dots(const cf* __restrict__ x, const cf* __restrict__ y, long n,
+                                                 double* __restrict__ part) {
+  __shared__ double r1[kBlock], r2[kBlock];
+  double a = 0.0, b = 0.0;
+  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+    const cf u = x[i], v = y[i];
+    a += (double)u.x * v.x + (double)u.y * v.y;
+    b += (double)v.x * v.x + (double)v.y * v.y;
+  }
+  r1[threadIdx.x] = a;
+  r2[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      r1[threadIdx.x] += r1[threadIdx.x + o];
+      r2[threadIdx.x] += r2[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = r1[0];
+    part[2 * blockIdx.x + 1] = r2[0];
+  }
+}
+
+__global__ void k_scale_c(cf* __restrict__ x, long n, const double* __restrict__ nrm2) {
+  const float s = (float)(1.0 / sqrt(nrm2[0]));
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    x[i] = cscale(x[i], s);
+}
+
+__global__ void k_sum_pairs(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  double a = 0.0, b = 0.0;
+  for (int i = 0; i < nb; ++i) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  out[0] = a;
+  out[1] = b;
+}
+
 // Copies each sample's value to its tile entries (the transpose of k_combine's sum).
 __global__ __launch_bounds__(kBlock) void k_gather_r(const cf* __restrict__ r, const int4* __restrict__ samp_ent,
                                                      cf* __restrict__ rg, long total) {
@@ -681,6 +760,28 @@ mrf_status nufft_fwd_partials(const mrf_nufft_plan_s* p, const cf* img, void* ws
 }
 
 const cf* nufft_partials(const mrf_nufft_plan_s* p, void* ws) { return (const cf*)((char*)ws + p->ws_T); }
+
+mrf_status sum_partials(const double* part, long n, double* out, hipStream_t s);
+
+long nufft_resid_blocks(const mrf_nufft_plan_s* p) { return ceil_div((long)p->L * p->Ns, kBlock); }
+
+// r = A img - b and rn2 (device double) = ||r||^2; part needs nufft_resid_blocks doubles.
+mrf_status nufft_residual(const mrf_nufft_plan_s* p, const cf* img, const cf* b, cf* r, void* ws, double* part,
+                          double* rn2, hipStream_t s) {
+  mrf_status st = nufft_fwd_partials(p, img, ws, s);
+  if (st != MRF_OK) return st;
+  const long total = (long)p->L * p->Ns;
+  MRF_LAUNCH("nufft_combine_resid", s,
+             k_combine_resid<<<ceil_div(total, kBlock), kBlock, 0, s>>>(nufft_partials(p, ws), p->samp_ent, b, r,
+                                                                        total, 1.0f / p->N, part));
+  MRF_CHECK_LAUNCH();
+  return sum_partials(part, nufft_resid_blocks(p), rn2, s);
+}
+
+int nufft_n(const mrf_nufft_plan_s* p) { return p->N; }
+int nufft_frames(const mrf_nufft_plan_s* p) { return p->L; }
+int nufft_nsamp(const mrf_nufft_plan_s* p) { return p->Ns; }
+size_t nufft_ws_bytes(const mrf_nufft_plan_s* p) { return p->ws_bytes; }
 const int4* nufft_samp_ent(const mrf_nufft_plan_s* p) { return p->samp_ent; }
 
 mrf_status nufft_adj_impl(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, void* ws, hipStream_t s) {
@@ -714,4 +815,45 @@ extern "C" mrf_status mrf_nufft_adj(mrf_nufft_plan_t p, const mrf_c64* ksp, mrf_
   MRF_REQUIRE(p && img && ksp, MRF_INVALID_ARG, "nufft_adj: null argument");
   MRF_REQUIRE(ws && ws_bytes >= p->ws_bytes, MRF_WORKSPACE, "nufft_adj: workspace missing or too small");
   return nufft_adj_impl(p, (const cf*)ksp, (cf*)img, ws, s);
+}
+
+extern "C" mrf_status mrf_nufft_opnorm(mrf_nufft_plan_t p, int iters, unsigned seed, double* lam, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(p && lam && iters >= 1, MRF_INVALID_ARG, "nufft_opnorm: null argument or iters < 1");
+  const long nimg = (long)p->L * p->N * p->N, nksp = (long)p->L * p->Ns;
+  cf *x = nullptr, *y = nullptr, *k = nullptr;
+  void* ws = nullptr;
+  double* d = nullptr;
+  const int nb = 1024;
+  auto cleanup = [&]() { hipFree(x); hipFree(y); hipFree(k); hipFree(ws); hipFree(d); };
+  if (hipMalloc(&x, nimg * 8) != hipSuccess || hipMalloc(&y, nimg * 8) != hipSuccess ||
+      hipMalloc(&k, nksp * 8) != hipSuccess || hipMalloc(&ws, p->ws_bytes) != hipSuccess ||
+      hipMalloc(&d, (2 * nb + 4) * sizeof(double)) != hipSuccess) {
+    cleanup();
+    return fail(MRF_OOM, "nufft_opnorm: device allocation failed");
+  }
+  mrf_status st = MRF_OK;
+  double h[2] = {0, 0};
+  k_hash_fill<<<1024, 256, 0, s>>>(x, nimg, seed);
+  k_dots<<<nb, kBlock, 0, s>>>(x, x, nimg, d);
+  k_sum_pairs<<<1, 1, 0, s>>>(d, nb, d + 2 * nb);
+  k_scale_c<<<1024, 256, 0, s>>>(x, nimg, d + 2 * nb + 1);
+  for (int it = 0; it < iters && st == MRF_OK; ++it) {
+    st = mrf_nufft_fwd(p, (const mrf_c64*)x, (mrf_c64*)k, ws, p->ws_bytes, s);
+    if (st == MRF_OK) st = mrf_nufft_adj(p, (const mrf_c64*)k, (mrf_c64*)y, ws, p->ws_bytes, s);
+    if (st != MRF_OK) break;
+    k_dots<<<nb, kBlock, 0, s>>>(x, y, nimg, d);               // <x, y> (x unit norm), ||y||^2
+    k_sum_pairs<<<1, 1, 0, s>>>(d, nb, d + 2 * nb);
+    std::swap(x, y);
+    k_scale_c<<<1024, 256, 0, s>>>(x, nimg, d + 2 * nb + 1);   // x = y / ||y||
+  }
+  if (st == MRF_OK) {
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h, d + 2 * nb, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = fail(MRF_DEVICE, std::string("nufft_opnorm: ") + hipGetErrorString(e));
+  }
+  cleanup();
+  if (st == MRF_OK) *lam = h[0];
+  return st;
 }

@@ -1,0 +1,326 @@
+// Algorithm 1 (MS-LLR reconstruction, Sec. III-C/D) on the device.
+//
+//   X^0 = A^H b, M^0 = Phi_D(X^0), L^0 from M^0, lambda1 = lambda1^0 max(L^0)
+//   each iteration:
+//     Z^n     = P_S(X^n - mu [A^H(A X^n - b) + lambda1 Q*(Q(X^n) L^n)])        eq. (15)
+//     P^{n+1} = SVT_{1/beta}(Q_q(X^n)) on every patch                          eq. (22)
+//     X^{n+1} = (Z^n + mu lam2 beta Q*(P^{n+1})) / (1 + mu lam2 beta c)        eq. (23)
+//     cost    = 1/2 ||A X^{n+1} - b||^2 + lambda1 Tr(Q L^n Q^H) + lam2 sum ||Q_q X^{n+1}||_*
+//     stop if cost(n)/cost(n+1) - 1 < tol; else M^{n+1} = Phi_D(X^{n+1}), L^{n+1}, lambda1, mu
+// Exactly one forward and one adjoint NUFFT per iteration: A X^{n+1} of the cost is the next
+// gradient's residual. The Laplacian term of the gradient is applied in the subspace:
+// P_S(Q*(Q(X) L)) = S_L(X V) V^H, because S_L acts on pixels and V on frames, so S_L runs on
+// r coefficient images instead of L frames. The eigen-analysis of Q(X^{n+1}) serves both the
+// cost's nuclear norm and the next SVT. The only device-to-host traffic is the cost terms,
+// once per iteration (the stopping rule).
+// Readings: the SVT acts on Q(X^n) (eq. (22)); eq. (23) divides per pixel by 1 + mu lam2 beta c(v)
+// (the exact minimiser of eq. (21) for overlapping patches); mu = min(mu0, 1/(lamA + 2 c_max
+// lambda1 max(L))) with lamA a bound on lambda_max(A^H A) (mu = mu0 when lamA <= 0).
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+#include "patch.hpp"
+
+namespace mrf {
+// nufft.hip
+mrf_status nufft_residual(const mrf_nufft_plan_s* p, const cf* img, const cf* b, cf* r, void* ws, double* part,
+                          double* rn2, hipStream_t s);
+mrf_status nufft_adj_impl(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, void* ws, hipStream_t s);
+long nufft_resid_blocks(const mrf_nufft_plan_s* p);
+int nufft_n(const mrf_nufft_plan_s* p);
+int nufft_frames(const mrf_nufft_plan_s* p);
+int nufft_nsamp(const mrf_nufft_plan_s* p);
+size_t nufft_ws_bytes(const mrf_nufft_plan_s* p);
+// graph.hip
+mrf_status graph_build(mrf_graph_s* G, const float* maps, int K, float sigma2, hipStream_t s);
+mrf_status lap_quad(mrf_graph_s* G, const cf* X, int L, double* out, hipStream_t s);
+mrf_status lap_apply_sub(const mrf_graph_s* G, const cf* A, cf* Y, int r, hipStream_t s);
+const double* graph_scalars(const mrf_graph_s* G);
+// subspace.hip
+size_t reduce_ws_bytes(int L, int Nv, int r);
+mrf_status subspace_reduce(const cf* X, const cf* Gd, const double* mu_dev, const cf* V, int L, int Nv, int r,
+                           cf* alpha, cf* part, hipStream_t s);
+mrf_status subspace_expand(const cf* beta, const cf* V, int L, int Nv, int r, cf* Z, hipStream_t s);
+mrf_status axpy_scal(const cf* aU, const cf* Y, const double* s0, const double* s1, double scale, long n, cf* out,
+                     hipStream_t s);
+mrf_status match_subspace(const mrf_dict_s* D, const cf* alpha, int Nv, int* idx, float* rho, float* score,
+                          float* params, hipStream_t s);
+mrf_status maps_from_match(const mrf_dict_s* D, const int* idx, const float* rho, int Nv, float* maps, hipStream_t s);
+const cf* dict_basis(const mrf_dict_s* D);
+int dict_rank(const mrf_dict_s* D);
+int dict_frames(const mrf_dict_s* D);
+// llr.hip
+size_t llr_ws_bytes(const PatchGeom& g, int rcap);
+mrf_status llr_analyse(const cf* X, const PatchGeom& g, int L, double tau, int rcap, void* ws, cf* U, float* f,
+                       double* nuc_out, double* lam_out, hipStream_t s);
+mrf_status llr_coef(const cf* X, const PatchGeom& g, int L, int rcap, const cf* U, const float* f, cf* C, hipStream_t s);
+mrf_status llr_xupdate(const cf* Z, const cf* U, const cf* C, const PatchGeom& g, int L, int rcap,
+                       const double* kap_dev, double kap_scale, cf* Xout, hipStream_t s);
+
+// device scalars
+enum { SC_LAM1 = 0, SC_MU, SC_KAP, SC_LMAX, SC_RN2, SC_QUAD, SC_NUC, SC_COST, SC_SIGMA2, SC_N = 16 };
+
+__global__ void k_scalars(const double* __restrict__ gs, double* __restrict__ sc, double lam1_0, double lamA,
+                          double cmax, double mu0, double lam2, double beta) {
+  const double lmax = gs[1];
+  const double lam1 = lam1_0 * lmax;
+  double mu = mu0;
+  if (lamA > 0.0) mu = fmin(mu0, 1.0 / (lamA + 2.0 * cmax * lam1 * lmax));
+  sc[SC_LAM1] = lam1;
+  sc[SC_MU] = mu;
+  sc[SC_KAP] = mu * lam2 * beta;
+  sc[SC_LMAX] = lmax;
+  sc[SC_SIGMA2] = gs[0];
+}
+
+__global__ void k_cost(double* __restrict__ sc, double lam2) {
+  sc[SC_COST] = 0.5 * sc[SC_RN2] + sc[SC_LAM1] * sc[SC_QUAD] + lam2 * sc[SC_NUC];
+}
+
+__global__ void k_copy_c(const cf* __restrict__ a, cf* __restrict__ b, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) b[i] = a[i];
+}
+
+}  // namespace mrf
+
+using namespace mrf;
+
+struct mrf_recon_s {
+  mrf_recon_params prm;
+  mrf_nufft_plan_s* plan;
+  mrf_dict_s* dict;
+  mrf_graph_s* graph;
+  PatchGeom g;
+  int N, L, Ns, Nv, r;
+  double cmax;
+  const cf* b;
+  cf *X, *ZG, *res, *aX, *aU, *Ya, *beta, *U, *C;
+  float *f, *maps, *rho;
+  int* idx;
+  void *nws, *rws, *lws;
+  double *sc, *rpart;
+  bool initialised;
+  double c_prev;
+  mrf_recon_stats st;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+mrf_status rebuild(mrf_recon_s* R, hipStream_t s) {
+  mrf_status e;
+  if ((e = subspace_reduce(R->X, nullptr, nullptr, dict_basis(R->dict), R->L, R->Nv, R->r, R->aX, (cf*)R->rws, s)))
+    return e;
+  if ((e = match_subspace(R->dict, R->aX, R->Nv, R->idx, R->rho, nullptr, nullptr, s))) return e;
+  if ((e = maps_from_match(R->dict, R->idx, R->rho, R->Nv, R->maps, s))) return e;
+  if ((e = graph_build(R->graph, R->maps, R->prm.K, R->prm.sigma2, s))) return e;
+  MRF_LAUNCH("recon_scalars", s,
+             k_scalars<<<1, 1, 0, s>>>(graph_scalars(R->graph), R->sc, R->prm.lam1_0, R->prm.lamA, R->cmax, R->prm.mu0,
+                                       R->prm.lam2, R->prm.beta));
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+
+// cost terms of the current X (with the current graph); reads them back (synchronises)
+mrf_status evaluate(mrf_recon_s* R, hipStream_t s, double* h) {
+  mrf_status e;
+  if ((e = nufft_residual(R->plan, R->X, R->b, R->res, R->nws, R->rpart, R->sc + SC_RN2, s))) return e;
+  if ((e = llr_analyse(R->X, R->g, R->L, 1.0 / R->prm.beta, R->prm.rank_cap, R->lws, R->U, R->f, R->sc + SC_NUC,
+                       nullptr, s)))
+    return e;
+  if ((e = lap_quad(R->graph, R->X, R->L, R->sc + SC_QUAD, s))) return e;
+  MRF_LAUNCH("recon_cost", s, k_cost<<<1, 1, 0, s>>>(R->sc, R->prm.lam2));
+  MRF_CHECK_LAUNCH();
+  MRF_CHECK_HIP(hipMemcpyAsync(h, R->sc, SC_N * sizeof(double), hipMemcpyDeviceToHost, s));
+  MRF_CHECK_HIP(hipStreamSynchronize(s));
+  if (!std::isfinite(h[SC_COST])) return fail(MRF_NONFINITE, "recon: cost is not finite");
+  return MRF_OK;
+}
+
+void record(mrf_recon_s* R, const double* h, bool graph_row) {
+  const int n = R->st.iters;
+  if (n <= MRF_MAX_ITERS) {
+    R->st.cost[n] = h[SC_COST];
+    R->st.data[n] = 0.5 * h[SC_RN2];
+    R->st.tr[n] = h[SC_QUAD];
+    R->st.nuc[n] = h[SC_NUC];
+  }
+  (void)graph_row;
+}
+
+void record_graph(mrf_recon_s* R, const double* h) {
+  const int n = R->st.n_graph;
+  if (n <= MRF_MAX_ITERS) {
+    R->st.mu[n] = h[SC_MU];
+    R->st.lam1[n] = h[SC_LAM1];
+    R->st.sigma2[n] = h[SC_SIGMA2];
+    R->st.lmax[n] = h[SC_LMAX];
+    R->st.n_graph = n + 1;
+  }
+}
+
+}  // namespace
+
+extern "C" mrf_status mrf_recon_create(const mrf_recon_params* prm, mrf_nufft_plan_t plan, mrf_dict_t dict,
+                                       mrf_recon_t* out) {
+  clear_error();
+  MRF_REQUIRE(prm && plan && dict && out, MRF_INVALID_ARG, "recon_create: null argument");
+  *out = nullptr;
+  const int N = nufft_n(plan), L = nufft_frames(plan), Ns = nufft_nsamp(plan);
+  MRF_REQUIRE(dict_rank(dict) > 0, MRF_INVALID_ARG, "recon_create: the dictionary needs a subspace basis V");
+  MRF_REQUIRE(dict_frames(dict) == L, MRF_SHAPE, "recon_create: dictionary length differs from the plan's frames");
+  MRF_REQUIRE(N % 16 == 0, MRF_SHAPE, "recon_create: n must be a multiple of 16");
+  MRF_REQUIRE(prm->beta > 0.f && prm->mu0 > 0.f && prm->lam2 >= 0.f && prm->lam1_0 >= 0.f, MRF_INVALID_ARG,
+              "recon_create: need beta > 0, mu0 > 0, lam1_0 >= 0, lam2 >= 0");
+  MRF_REQUIRE(prm->n_max >= 0, MRF_INVALID_ARG, "recon_create: n_max must be >= 0");
+  auto* R = new mrf_recon_s{};
+  R->prm = *prm;
+  R->plan = plan;
+  R->dict = dict;
+  R->N = N; R->L = L; R->Ns = Ns; R->Nv = N * N; R->r = dict_rank(dict);
+  mrf_status st = mrf_graph_create(N, prm->p, prm->s, std::max(1, prm->K), L, &R->graph);
+  if (st != MRF_OK) {
+    delete R;
+    return st;
+  }
+  make_geom(N, prm->p, prm->s, &R->g);
+  const int pp = prm->p * prm->p;
+  if (!((pp == 16 || pp == 64 || pp < 16) && prm->rank_cap >= 1 && prm->rank_cap <= 16 && prm->K >= 1 &&
+        prm->K <= R->g.Np - 1)) {
+    mrf_graph_destroy(R->graph);
+    delete R;
+    return fail(MRF_SHAPE, "recon_create: need p in {2, 3, 4, 8}, 1 <= rank_cap <= 16, 1 <= K < patch count");
+  }
+  const int cov1 = std::min(R->g.ppc, R->g.n1);
+  R->cmax = (double)cov1 * cov1;
+  const size_t Nv = R->Nv, rr = R->r, Np = R->g.Np, rc = prm->rank_cap;
+  auto alloc = [&](size_t bytes) -> void* {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) return nullptr;
+    R->allocs.push_back(p);
+    return p;
+  };
+  bool ok = (R->X = (cf*)alloc((size_t)L * Nv * 8)) && (R->ZG = (cf*)alloc((size_t)L * Nv * 8)) &&
+            (R->res = (cf*)alloc((size_t)L * Ns * 8)) && (R->aX = (cf*)alloc(Nv * rr * 8)) &&
+            (R->aU = (cf*)alloc(Nv * rr * 8)) && (R->Ya = (cf*)alloc(Nv * rr * 8)) &&
+            (R->beta = (cf*)alloc(Nv * rr * 8)) && (R->U = (cf*)alloc(Np * rc * pp * 8)) &&
+            (R->C = (cf*)alloc(Np * rc * (size_t)L * 8)) && (R->f = (float*)alloc(Np * rc * 4)) &&
+            (R->maps = (float*)alloc(3 * Nv * 4)) && (R->rho = (float*)alloc(Nv * 4)) &&
+            (R->idx = (int*)alloc(Nv * 4)) && (R->nws = alloc(nufft_ws_bytes(plan))) &&
+            (R->rws = alloc(reduce_ws_bytes(L, (int)Nv, (int)rr))) && (R->lws = alloc(llr_ws_bytes(R->g, (int)rc))) &&
+            (R->sc = (double*)alloc(SC_N * 8)) && (R->rpart = (double*)alloc(nufft_resid_blocks(plan) * 8));
+  if (!ok) {
+    mrf_recon_destroy(R);
+    return fail(MRF_OOM, "recon_create: device allocation failed");
+  }
+  *out = R;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_recon_destroy(mrf_recon_t R) {
+  clear_error();
+  if (!R) return MRF_OK;
+  for (void* p : R->allocs) hipFree(p);
+  mrf_graph_destroy(R->graph);
+  delete R;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_recon_init(mrf_recon_t R, const mrf_c64* b, const mrf_c64* X0, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(R && b, MRF_INVALID_ARG, "recon_init: null argument");
+  R->b = (const cf*)b;
+  R->st = mrf_recon_stats{};
+  mrf_status e;
+  if (X0) {
+    MRF_LAUNCH("recon_copy", s, k_copy_c<<<1024, 256, 0, s>>>((const cf*)X0, R->X, (size_t)R->L * R->Nv));
+    MRF_CHECK_LAUNCH();
+  } else if ((e = nufft_adj_impl(R->plan, R->b, R->X, R->nws, s))) {
+    return e;
+  }
+  if ((e = rebuild(R, s))) return e;
+  double h[SC_N];
+  if ((e = evaluate(R, s, h))) return e;
+  record(R, h, true);
+  record_graph(R, h);
+  R->c_prev = h[SC_COST];
+  R->initialised = true;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_recon_iterate(mrf_recon_t R, int n, int* stopped, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(R && R->initialised, MRF_INVALID_ARG, "recon_iterate: call mrf_recon_init first");
+  MRF_REQUIRE(n >= 0, MRF_INVALID_ARG, "recon_iterate: n must be >= 0");
+  if (stopped) *stopped = R->st.stop_reason != 0;
+  const int L = R->L, Nv = R->Nv, r = R->r, rc = R->prm.rank_cap;
+  const cf* V = dict_basis(R->dict);
+  mrf_status e;
+  for (int it = 0; it < n && R->st.stop_reason == 0 && R->st.iters < R->prm.n_max; ++it) {
+    // gradient step with the subspace projection (eqs. (15), (17))
+    if ((e = nufft_adj_impl(R->plan, R->res, R->ZG, R->nws, s))) return e;                      // G = A^H r
+    if ((e = subspace_reduce(R->X, R->ZG, R->sc + SC_MU, V, L, Nv, r, R->aU, (cf*)R->rws, s))) return e;
+    if ((e = lap_apply_sub(R->graph, R->aX, R->Ya, r, s))) return e;                            // S_L(X V)
+    if ((e = axpy_scal(R->aU, R->Ya, R->sc + SC_MU, R->sc + SC_LAM1, 1.0, (long)Nv * r, R->beta, s))) return e;
+    if ((e = subspace_expand(R->beta, V, L, Nv, r, R->ZG, s))) return e;                        // Z
+    // SVT of Q(X^n) (eigen-analysis from the previous evaluation) and the X update (eq. (23))
+    if ((e = llr_coef(R->X, R->g, L, rc, R->U, R->f, R->C, s))) return e;
+    if ((e = llr_xupdate(R->ZG, R->U, R->C, R->g, L, rc, R->sc + SC_KAP, 1.0, R->X, s))) return e;
+    // cost of X^{n+1} (also the next residual and eigen-analysis)
+    double h[SC_N];
+    if ((e = evaluate(R, s, h))) return e;
+    R->st.iters += 1;
+    record(R, h, false);
+    const double c = h[SC_COST];
+    if (R->prm.tol >= 0.0 && R->c_prev / c - 1.0 < R->prm.tol) {
+      R->st.stop_reason = 1;
+      break;
+    }
+    R->c_prev = c;
+    if (R->st.iters < R->prm.n_max) {
+      if ((e = rebuild(R, s))) return e;
+      double h2[SC_N];
+      MRF_CHECK_HIP(hipMemcpyAsync(h2, R->sc, SC_N * sizeof(double), hipMemcpyDeviceToHost, s));
+      MRF_CHECK_HIP(hipStreamSynchronize(s));
+      record_graph(R, h2);
+    }
+  }
+  if (stopped) *stopped = R->st.stop_reason != 0 || R->st.iters >= R->prm.n_max;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_recon_finish(mrf_recon_t R, mrf_c64* X_out, float* maps, int32_t* idx, float* rho,
+                                       hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(R && R->initialised, MRF_INVALID_ARG, "recon_finish: call mrf_recon_init first");
+  mrf_status e;
+  const cf* V = dict_basis(R->dict);
+  if ((e = subspace_reduce(R->X, nullptr, nullptr, V, R->L, R->Nv, R->r, R->aX, (cf*)R->rws, s))) return e;
+  if ((e = match_subspace(R->dict, R->aX, R->Nv, R->idx, R->rho, nullptr, nullptr, s))) return e;
+  if ((e = maps_from_match(R->dict, R->idx, R->rho, R->Nv, R->maps, s))) return e;
+  if (X_out) MRF_CHECK_HIP(hipMemcpyAsync(X_out, R->X, (size_t)R->L * R->Nv * 8, hipMemcpyDeviceToDevice, s));
+  if (maps) MRF_CHECK_HIP(hipMemcpyAsync(maps, R->maps, (size_t)3 * R->Nv * 4, hipMemcpyDeviceToDevice, s));
+  if (idx) MRF_CHECK_HIP(hipMemcpyAsync(idx, R->idx, (size_t)R->Nv * 4, hipMemcpyDeviceToDevice, s));
+  if (rho) MRF_CHECK_HIP(hipMemcpyAsync(rho, R->rho, (size_t)R->Nv * 4, hipMemcpyDeviceToDevice, s));
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_recon_get_stats(mrf_recon_t R, mrf_recon_stats* out) {
+  clear_error();
+  MRF_REQUIRE(R && out, MRF_INVALID_ARG, "recon_get_stats: null argument");
+  *out = R->st;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_recon(mrf_recon_t R, const mrf_c64* b, const mrf_c64* X0, mrf_c64* X_out, float* maps,
+                                int32_t* idx, float* rho, mrf_recon_stats* stats, hipStream_t s) {
+  mrf_status e = mrf_recon_init(R, b, X0, s);
+  if (e) return e;
+  int stopped = 0;
+  if ((e = mrf_recon_iterate(R, R->prm.n_max, &stopped, s))) return e;
+  if ((e = mrf_recon_finish(R, X_out, maps, idx, rho, s))) return e;
+  if (stats) *stats = R->st;
+  return MRF_OK;
+}

@@ -54,6 +54,13 @@ class NufftPlan:
               "mrf_nufft_adj")
         return out
 
+    def opnorm(self, iters=30, seed=1, stream=None):
+        """lambda_max(A^H A) by power iteration on the device."""
+        lam = ctypes.c_double()
+        check(lib.mrf_nufft_opnorm(self.handle, int(iters), int(seed), ctypes.byref(lam), _stream(stream)),
+              "mrf_nufft_opnorm")
+        return lam.value
+
     def close(self):
         if getattr(self, "handle", None):
             lib.mrf_nufft_plan_destroy(self.handle)

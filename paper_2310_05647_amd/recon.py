@@ -1,0 +1,71 @@
+"""Algorithm 1 binding: mrf_recon_create / init / iterate / finish."""
+import ctypes
+
+import torch
+
+from ._lib import ReconParams, ReconStats, check, lib
+from .util import need, ptr, stream_ptr
+
+
+class Recon:
+    """MS-LLR solver state for a NUFFT plan and a dictionary with a basis."""
+
+    def __init__(self, plan, dictionary, p, s, K, rank_cap, lam1_0=0.1, lam2=0.1, beta=0.2, mu0=1.0, lamA=0.0,
+                 sigma2=0.0, n_max=10, tol=-1.0):
+        self.plan, self.dict = plan, dictionary
+        self.params = ReconParams(int(p), int(s), int(K), int(rank_cap), float(lam1_0), float(lam2), float(beta),
+                                  float(mu0), float(lamA), float(sigma2), int(n_max), float(tol))
+        h = ctypes.c_void_p()
+        check(lib.mrf_recon_create(ctypes.byref(self.params), plan.handle, dictionary.handle, ctypes.byref(h)),
+              "mrf_recon_create")
+        self.handle = h
+        self.n, self.L = plan.n, plan.L
+
+    def init(self, b, X0=None, stream=None):
+        need(b, torch.complex64, (self.L, self.plan.Ns), "b")
+        self._b = b
+        check(lib.mrf_recon_init(self.handle, ptr(b), ptr(X0), stream_ptr(stream)), "mrf_recon_init")
+
+    def iterate(self, n, stream=None):
+        stopped = ctypes.c_int()
+        check(lib.mrf_recon_iterate(self.handle, int(n), ctypes.byref(stopped), stream_ptr(stream)),
+              "mrf_recon_iterate")
+        return bool(stopped.value)
+
+    def finish(self, stream=None):
+        dev = self._b.device
+        n, L = self.n, self.L
+        X = torch.empty((L, n, n), dtype=torch.complex64, device=dev)
+        maps = torch.empty((3, n, n), dtype=torch.float32, device=dev)
+        idx = torch.empty(n * n, dtype=torch.int32, device=dev)
+        rho = torch.empty(n * n, dtype=torch.float32, device=dev)
+        check(lib.mrf_recon_finish(self.handle, ptr(X), ptr(maps), ptr(idx), ptr(rho), stream_ptr(stream)),
+              "mrf_recon_finish")
+        return dict(X=X, maps=maps, idx=idx, rho=rho)
+
+    def stats(self):
+        st = ReconStats()
+        check(lib.mrf_recon_get_stats(self.handle, ctypes.byref(st)), "mrf_recon_get_stats")
+        k = st.iters + 1
+        g = st.n_graph
+        return dict(iters=st.iters, stop=st.stop_reason, cost=list(st.cost[:k]), data=list(st.data[:k]),
+                    tr=list(st.tr[:k]), nuc=list(st.nuc[:k]), mu=list(st.mu[:g]), lam1=list(st.lam1[:g]),
+                    sigma2=list(st.sigma2[:g]), lmax=list(st.lmax[:g]))
+
+    def run(self, b, X0=None, stream=None):
+        self.init(b, X0, stream)
+        self.iterate(self.params.n_max, stream)
+        out = self.finish(stream)
+        out["stats"] = self.stats()
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.mrf_recon_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,79 @@
+"""Subspace projection and dictionary matching bindings."""
+import ctypes
+
+import torch
+
+from ._lib import check, lib
+from .util import need, ptr, stream_ptr, workspace
+
+
+def subspace_coeffs(X, V, stream=None):
+    """alpha [Nv, r] = X V for X [L, ...] (frame-major), V [L, r]."""
+    L = X.shape[0]
+    Nv = X[0].numel()
+    r = V.shape[1]
+    need(V, torch.complex64, (L, r), "V")
+    sz = ctypes.c_size_t()
+    check(lib.mrf_subspace_coeffs_workspace_size(L, Nv, r, ctypes.byref(sz)), "mrf_subspace_coeffs_workspace_size")
+    ws = workspace(sz.value, X.device)
+    out = torch.empty((Nv, r), dtype=torch.complex64, device=X.device)
+    check(lib.mrf_subspace_coeffs(ptr(X), ptr(V), L, Nv, r, ptr(out), ptr(ws), ws.numel(), stream_ptr(stream)),
+          "mrf_subspace_coeffs")
+    return out
+
+
+def subspace_project(U, V, stream=None):
+    """P_S(U) = U V V^H for U [L, ...] frame-major."""
+    L = U.shape[0]
+    Nv = U[0].numel()
+    r = V.shape[1]
+    need(V, torch.complex64, (L, r), "V")
+    sz = ctypes.c_size_t()
+    check(lib.mrf_subspace_coeffs_workspace_size(L, Nv, r, ctypes.byref(sz)), "mrf_subspace_coeffs_workspace_size")
+    ws = workspace(sz.value + Nv * r * 8, U.device)
+    out = torch.empty_like(U)
+    check(lib.mrf_subspace_project(ptr(U), ptr(V), L, Nv, r, ptr(out), ptr(ws), ws.numel(), stream_ptr(stream)),
+          "mrf_subspace_project")
+    return out
+
+
+class Dictionary:
+    """Device dictionary: atoms [M, L] complex64, lut [M, nparam] float32, optional basis V [L, r]."""
+
+    def __init__(self, atoms, lut, V=None, stream=None):
+        M, L = atoms.shape
+        need(atoms, torch.complex64, (M, L), "atoms")
+        need(lut, torch.float32, (M, lut.shape[1]), "lut")
+        r = 0
+        if V is not None:
+            r = V.shape[1]
+            need(V, torch.complex64, (L, r), "V")
+        self.M, self.L, self.r, self.nparam = M, L, r, lut.shape[1]
+        h = ctypes.c_void_p()
+        check(lib.mrf_dict_create(ptr(atoms), ptr(lut), M, L, self.nparam, ptr(V), r, stream_ptr(stream),
+                                  ctypes.byref(h)), "mrf_dict_create")
+        self.handle = h
+
+    def match_subspace(self, alpha, stream=None):
+        """Returns (idx int32 [Nv], rho, score, params [Nv, nparam])."""
+        Nv = alpha.shape[0]
+        need(alpha, torch.complex64, (Nv, self.r), "alpha")
+        dev = alpha.device
+        idx = torch.empty(Nv, dtype=torch.int32, device=dev)
+        rho = torch.empty(Nv, dtype=torch.float32, device=dev)
+        score = torch.empty(Nv, dtype=torch.float32, device=dev)
+        params = torch.empty((Nv, self.nparam), dtype=torch.float32, device=dev)
+        check(lib.mrf_dict_match_subspace(self.handle, ptr(alpha), Nv, ptr(idx), ptr(rho), ptr(score), ptr(params),
+                                          stream_ptr(stream)), "mrf_dict_match_subspace")
+        return idx, rho, score, params
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.mrf_dict_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,32 @@
+"""Seeded synthetic workloads for the tests (inputs from mrfgen; measurements by the oracle's A)."""
+import functools
+
+import numpy as np
+
+import mrfgen
+from oracle import nufft as onufft
+
+
+@functools.lru_cache(maxsize=4)
+def c1_workload(seed=0, N=None, L=None, Ns=None, n_int=None):
+    """C1 shapes (or a cropped variant): dictionary, basis, phantom, X_true, traj, noisy b, lamA."""
+    over = {k: v for k, v in dict(N=N, L=L, Ns=Ns).items() if v is not None}
+    cfg = mrfgen.get_config("C1", **over)
+    atoms, grid = mrfgen.make_dictionary(cfg)
+    V, _ = mrfgen.subspace_basis(atoms, cfg["r"])
+    ph = mrfgen.make_phantom(cfg, seed)
+    X = mrfgen.truth_fingerprints(cfg, ph)
+    traj = mrfgen.vds_spiral(cfg["N"], cfg["L"], cfg["Ns"], n_int or cfg["n_interleaves"])
+    b_clean = onufft.nufft_fwd(X, traj)
+    sig2 = mrfgen.noise_sigma(np.mean(np.abs(b_clean) ** 2), cfg["snr_db"])
+    b = (b_clean + mrfgen.complex_noise(b_clean.shape, sig2, seed + 101)).astype(np.complex64)
+    x0 = mrfgen.complex_noise((cfg["L"], cfg["N"], cfg["N"]), 1.0, seed + 202)
+    lamA = onufft.operator_norm(traj, cfg["N"], x0, iters=20)
+    return dict(cfg=cfg, atoms=atoms, grid=grid, V=V, phantom=ph, X=X, traj=traj, b=b, lamA=lamA)
+
+
+def random_maps(rng, N, zero_frac=0.0):
+    maps = np.stack([rng.uniform(300, 2500, (N, N)), rng.uniform(40, 300, (N, N)), rng.uniform(0, 100, (N, N))])
+    if zero_frac > 0:
+        maps[:, rng.uniform(size=(N, N)) < zero_frac] = 0.0
+    return maps.astype(np.float32)
