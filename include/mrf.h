@@ -108,9 +108,9 @@ mrf_status mrf_nufft_opnorm(mrf_nufft_plan_t plan, int iters, unsigned seed, dou
  * ==================================================================================== */
 typedef struct mrf_graph_s* mrf_graph_t;
 
-/* Allocates a graph for n x n maps with p x p patches at stride s, at most k_max neighbours
- * (k_max <= 32) and Laplacian quadratic forms over at most max_frames frames. The patch
- * count must be in [2, 8192] (a dense Np x Np weight buffer is part of the handle). */
+/* Allocates a graph for n x n maps with p x p patches (p <= 8) at stride s, at most k_max
+ * neighbours (k_max <= 16) and Laplacian quadratic forms over at most max_frames frames. The
+ * patch count must be in [2, 8192] (a dense Np x Np weight buffer is part of the handle). */
 mrf_status mrf_graph_create(int n, int p, int s, int k_max, int max_frames, mrf_graph_t* out);
 mrf_status mrf_graph_destroy(mrf_graph_t g);
 /* Builds the K-NN graph Laplacian from maps [3][n][n] (T1, T2, PD; device float32).

@@ -41,7 +41,6 @@ struct mrf_graph_s {
 
 namespace mrf {
 
-constexpr int kMaxK = 32;
 
 __global__ __launch_bounds__(1024) void k_chan_max(const float* __restrict__ maps, int nn, float* __restrict__ mx) {
   __shared__ float red[1024];
@@ -70,57 +69,77 @@ __global__ void k_features(const float* __restrict__ maps, const float* __restri
   F[t] = maps[((size_t)c * g.N + y) * g.N + x] / mx[c];
 }
 
-// One block per patch i: squared distances to every other patch, then the K smallest
-// (distance, index) keys. Each thread keeps its own sorted top-K in LDS; K rounds of a
-// block-wide minimum over the threads' heads produce the global order.
+// One block per group of KR patches: squared distances to every other patch, then the K smallest
+// (distance, index) keys per patch. Each thread keeps its own sorted top-K per row in LDS; K
+// rounds of a block-wide minimum over the threads' heads produce each row's order. The KR rows
+// share every candidate row F[j] the thread loads.
+constexpr int kKnnRows = 2;
 __global__ __launch_bounds__(256) void k_knn(const float* __restrict__ F, int Np, int nf, int K,
                                              int* __restrict__ knn, float* __restrict__ knd2, int kmax) {
-  __shared__ float Fi[768];
-  __shared__ unsigned long long lst[256][kMaxK];
+  __shared__ float Fi[kKnnRows][192];
+  __shared__ unsigned long long lst[kKnnRows][256][16];
   __shared__ unsigned long long red[256];
   __shared__ int redt[256];
-  const int i = blockIdx.x, t = threadIdx.x;
-  for (int f = t; f < nf; f += 256) Fi[f] = F[(size_t)i * nf + f];
+  const int i0 = blockIdx.x * kKnnRows, t = threadIdx.x;
+  for (int f = t; f < kKnnRows * nf; f += 256) {
+    const int rr = f / nf, ff = f % nf;
+    Fi[rr][ff] = i0 + rr < Np ? F[(size_t)(i0 + rr) * nf + ff] : 0.f;
+  }
   __syncthreads();
-  int n = 0;
+  int n[kKnnRows];
+#pragma unroll
+  for (int rr = 0; rr < kKnnRows; ++rr) n[rr] = 0;
   for (int j = t; j < Np; j += 256) {
-    if (j == i) continue;
     const float* Fj = F + (size_t)j * nf;
-    float d2 = 0.f;
+    float d2[kKnnRows];
+#pragma unroll
+    for (int rr = 0; rr < kKnnRows; ++rr) d2[rr] = 0.f;
     for (int f = 0; f < nf; ++f) {
-      const float d = Fi[f] - Fj[f];
-      d2 = fmaf(d, d, d2);
-    }
-    const unsigned long long key = ((unsigned long long)__float_as_uint(d2) << 32) | (unsigned)j;
-    if (n < K || key < lst[t][K - 1]) {
-      int pos = n < K ? n : K - 1;
-      while (pos > 0 && lst[t][pos - 1] > key) {
-        lst[t][pos] = lst[t][pos - 1];
-        --pos;
+      const float x = Fj[f];
+#pragma unroll
+      for (int rr = 0; rr < kKnnRows; ++rr) {
+        const float d = Fi[rr][f] - x;
+        d2[rr] = fmaf(d, d, d2[rr]);
       }
-      lst[t][pos] = key;
-      if (n < K) ++n;
+    }
+#pragma unroll
+    for (int rr = 0; rr < kKnnRows; ++rr) {
+      if (j == i0 + rr) continue;
+      const unsigned long long key = ((unsigned long long)__float_as_uint(d2[rr]) << 32) | (unsigned)j;
+      unsigned long long* L = lst[rr][t];
+      if (n[rr] < K || key < L[K - 1]) {
+        int pos = n[rr] < K ? n[rr] : K - 1;
+        while (pos > 0 && L[pos - 1] > key) {
+          L[pos] = L[pos - 1];
+          --pos;
+        }
+        L[pos] = key;
+        if (n[rr] < K) ++n[rr];
+      }
     }
   }
-  int head = 0;
-  for (int k = 0; k < K; ++k) {
-    red[t] = head < n ? lst[t][head] : ~0ull;
-    redt[t] = t;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (t < o && red[t + o] < red[t]) {
-        red[t] = red[t + o];
-        redt[t] = redt[t + o];
+  for (int rr = 0; rr < kKnnRows; ++rr) {
+    const int i = i0 + rr;
+    int head = 0;
+    for (int k = 0; k < K; ++k) {
+      red[t] = head < n[rr] ? lst[rr][t][head] : ~0ull;
+      redt[t] = t;
+      __syncthreads();
+      for (int o = 128; o > 0; o >>= 1) {
+        if (t < o && red[t + o] < red[t]) {
+          red[t] = red[t + o];
+          redt[t] = redt[t + o];
+        }
+        __syncthreads();
+      }
+      const unsigned long long best = red[0];
+      if (t == redt[0]) ++head;
+      if (t == 0 && i < Np) {
+        knn[(size_t)i * kmax + k] = (int)(best & 0xffffffffu);
+        knd2[(size_t)i * kmax + k] = __uint_as_float((unsigned)(best >> 32));
       }
       __syncthreads();
     }
-    const unsigned long long best = red[0];
-    if (t == redt[0]) ++head;
-    if (t == 0) {
-      knn[(size_t)i * kmax + k] = (int)(best & 0xffffffffu);
-      knd2[(size_t)i * kmax + k] = __uint_as_float((unsigned)(best >> 32));
-    }
-    __syncthreads();
   }
 }
 
@@ -375,6 +394,67 @@ __global__ __launch_bounds__(256) void k_lap_full(const cf* __restrict__ X, cf* 
   }
 }
 
+// Tr(Q(X) L Q(X)^H) = sum_i L_ii ||q_i||^2 + 2 sum_{i<j} L_ij Re<q_i, q_j> (L symmetric), with
+// q_i the patch i block of X over all frames. Block: patch i and a chunk of frames; thread =
+// (pixel of the patch, frame lane), holding q_i in registers while it streams the neighbours
+// j > i. XCD x takes the frame chunks c = x (mod 8), so each XCD's L2 holds its own frames.
+template <int PP, int FPT>
+__global__ __launch_bounds__(256) void k_lap_quad_edges(const cf* __restrict__ X, const int* __restrict__ rowptr,
+                                                        const int* __restrict__ col, const float* __restrict__ val,
+                                                        PatchGeom g, int L, int nchunk, double* __restrict__ part) {
+  constexpr int NSUB = 256 / PP;
+  constexpr int FCH = NSUB * FPT;
+  __shared__ double red[256];
+  const int b = blockIdx.x;
+  const int q = b >> 3;
+  const int i = q % g.Np;
+  const int c = (q / g.Np) * 8 + (b & 7);
+  if (c >= nchunk) return;
+  const int t = threadIdx.x;
+  const int r = t % PP, fsub = t / PP;
+  const int off = (r / g.p) * g.N + r % g.p;
+  const size_t NN = (size_t)g.N * g.N;
+  const int oi = (i / g.n1) * g.s * g.N + (i % g.n1) * g.s;
+  cf qi[FPT];
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < FPT; ++k) {
+    const int f = c * FCH + fsub + k * NSUB;
+    qi[k] = f < L ? X[(size_t)f * NN + oi + off] : cf{0.f, 0.f};
+  }
+  const int e0 = rowptr[i], e1 = rowptr[i + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int j = col[e];
+    if (j < i) continue;
+    const float w = val[e];
+    if (j == i) {
+      float s = 0.f;
+#pragma unroll
+      for (int k = 0; k < FPT; ++k) s += qi[k].x * qi[k].x + qi[k].y * qi[k].y;
+      acc += (double)w * s;
+      continue;
+    }
+    const int oj = (j / g.n1) * g.s * g.N + (j % g.n1) * g.s;
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < FPT; ++k) {
+      const int f = c * FCH + fsub + k * NSUB;
+      if (f < L) {
+        const cf qj = X[(size_t)f * NN + oj + off];
+        s += qi[k].x * qj.x + qi[k].y * qj.y;
+      }
+    }
+    acc += 2.0 * (double)w * s;
+  }
+  red[t] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  if (t == 0) part[(size_t)c * g.Np + i] = red[0];
+}
+
 // S_L applied to per-voxel subspace coefficients A[v][k] (k < r), voxel-major. One thread per voxel.
 __global__ __launch_bounds__(256) void k_lap_sub(const cf* __restrict__ A, cf* __restrict__ Y,
                                                  const int* __restrict__ rowptr, const int* __restrict__ col,
@@ -410,6 +490,22 @@ __global__ __launch_bounds__(256) void k_lap_sub(const cf* __restrict__ A, cf* _
     if (k < r) Y[(size_t)v * r + k] = acc[k];
 }
 
+// First stage of a deterministic sum: block b adds the contiguous range [b*per, (b+1)*per).
+__global__ __launch_bounds__(256) void k_sum_stage(const double* __restrict__ part, long n, long per,
+                                                   double* __restrict__ out) {
+  __shared__ double red[256];
+  const long lo = (long)blockIdx.x * per, hi = lo + per < n ? lo + per : n;
+  double s = 0.0;
+  for (long i = lo + threadIdx.x; i < hi; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
 // Deterministic sum of block partials (single block, fixed order) into out[0].
 __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ part, long n, double* __restrict__ out) {
   __shared__ double red[256];
@@ -425,13 +521,16 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 }
 
 // -------------------------------------------------------------- internal entry points
+mrf_status sum_partials2(const double* part, long n, double* tmp, double* out, hipStream_t s);
+
 mrf_status graph_build(mrf_graph_s* G, const float* maps, int K, float sigma2, hipStream_t s) {
   const PatchGeom& g = G->g;
   const int nf = 3 * g.p * g.p;
   MRF_LAUNCH("graph_chan_max", s, k_chan_max<<<1, 1024, 0, s>>>(maps, g.N * g.N, G->mx));
   const long nfeat = (long)g.Np * nf;
   MRF_LAUNCH("graph_features", s, k_features<<<ceil_div(nfeat, 256), 256, 0, s>>>(maps, G->mx, g, G->F));
-  MRF_LAUNCH("graph_knn", s, k_knn<<<g.Np, 256, 0, s>>>(G->F, g.Np, nf, K, G->knn, G->knd2, G->kmax));
+  MRF_LAUNCH("graph_knn", s,
+             k_knn<<<ceil_div(g.Np, kKnnRows), 256, 0, s>>>(G->F, g.Np, nf, K, G->knn, G->knd2, G->kmax));
   MRF_LAUNCH("graph_sigma", s, k_sigma<<<1, 1024, 0, s>>>(G->knd2, g.Np, K, G->kmax, sigma2, G->scal));
   const size_t nw = (size_t)g.Np * g.Np;
   MRF_LAUNCH("graph_zero_w", s, k_fill_f<<<1024, 256, 0, s>>>(G->W, nw, 0.f));
@@ -457,12 +556,29 @@ mrf_status lap_apply_full(const mrf_graph_s* G, const cf* X, cf* Y, int L, hipSt
   return MRF_OK;
 }
 
-// out (device double) = Re<X, S_L X>
+// out (device double) = Re<X, S_L X> = Tr(Q(X) L Q(X)^H)
 mrf_status lap_quad(mrf_graph_s* G, const cf* X, int L, double* out, hipStream_t s) {
-  dim3 grid(G->g.nc * G->g.nc, lap_frame_chunks(G->g, L));
+  const PatchGeom& g = G->g;
+  const int PP = g.p * g.p;
+  int fch = 0;
+  if (PP == 64) fch = 4 * 2;
+  else if (PP == 16) fch = 16 * 2;
+  if (fch) {
+    const int nchunk = ceil_div(L, fch);
+    const size_t nb = (size_t)nchunk * g.Np;
+    if (nb > G->npart) return fail(MRF_SHAPE, "laplacian quad: too many frames for the partial-sum buffer");
+    const int grid = 8 * g.Np * ceil_div(nchunk, 8);
+    if (PP == 64)
+      MRF_LAUNCH("lap_quad", s, k_lap_quad_edges<64, 2><<<grid, 256, 0, s>>>(X, G->rowptr, G->col, G->val, g, L, nchunk, G->part));
+    else
+      MRF_LAUNCH("lap_quad", s, k_lap_quad_edges<16, 2><<<grid, 256, 0, s>>>(X, G->rowptr, G->col, G->val, g, L, nchunk, G->part));
+    MRF_CHECK_LAUNCH();
+    return sum_partials2(G->part, (long)nb, G->part + G->npart, out, s);
+  }
+  dim3 grid(g.nc * g.nc, lap_frame_chunks(g, L));
   const size_t nb = (size_t)grid.x * grid.y;
   if (nb > G->npart) return fail(MRF_SHAPE, "laplacian quad: too many frames for the partial-sum buffer");
-  MRF_LAUNCH("lap_quad", s, k_lap_full<true><<<grid, 256, 0, s>>>(X, nullptr, G->part, G->rowptr, G->col, G->val, G->g, L));
+  MRF_LAUNCH("lap_quad", s, k_lap_full<true><<<grid, 256, 0, s>>>(X, nullptr, G->part, G->rowptr, G->col, G->val, g, L));
   MRF_LAUNCH("sum_partials", s, k_sum_partials<<<1, 256, 0, s>>>(G->part, (long)nb, out));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
@@ -482,6 +598,15 @@ mrf_status sum_partials(const double* part, long n, double* out, hipStream_t s) 
   MRF_CHECK_LAUNCH();
   return MRF_OK;
 }
+
+// Sums n partials into out[0] in two fixed-order stages; tmp holds 256 doubles.
+mrf_status sum_partials2(const double* part, long n, double* tmp, double* out, hipStream_t s) {
+  const long per = (n + 255) / 256;
+  MRF_LAUNCH("sum_stage", s, k_sum_stage<<<256, 256, 0, s>>>(part, n, per, tmp));
+  MRF_LAUNCH("sum_partials", s, k_sum_partials<<<1, 256, 0, s>>>(tmp, 256, out));
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
 const PatchGeom& graph_geom(const mrf_graph_s* G) { return G->g; }
 
 }  // namespace mrf
@@ -494,8 +619,8 @@ extern "C" mrf_status mrf_graph_create(int n, int p, int s, int k_max, int max_f
   *out = nullptr;
   PatchGeom g;
   MRF_REQUIRE(make_geom(n, p, s, &g), MRF_SHAPE, "graph_create: need p % s == 0 and (n - p) % s == 0");
-  MRF_REQUIRE(s * s <= 256 && p <= 16, MRF_SHAPE, "graph_create: patch side must be <= 16 and s^2 <= 256");
-  MRF_REQUIRE(k_max >= 1 && k_max <= kMaxK, MRF_INVALID_ARG, "graph_create: k_max must be in [1, 32]");
+  MRF_REQUIRE(s * s <= 256 && p <= 8, MRF_SHAPE, "graph_create: patch side must be <= 8 and s^2 <= 256");
+  MRF_REQUIRE(k_max >= 1 && k_max <= 16, MRF_INVALID_ARG, "graph_create: k_max must be in [1, 16]");
   MRF_REQUIRE(max_frames >= 1, MRF_INVALID_ARG, "graph_create: max_frames must be >= 1");
   MRF_REQUIRE(g.Np >= 2 && g.Np <= 8192, MRF_SHAPE, "graph_create: patch count must be in [2, 8192]");
   auto* G = new mrf_graph_s{};
@@ -503,7 +628,8 @@ extern "C" mrf_status mrf_graph_create(int n, int p, int s, int k_max, int max_f
   G->kmax = k_max;
   G->nf = 3 * p * p;
   G->cap = (size_t)g.Np * (2 * k_max + 1);
-  G->npart = (size_t)g.nc * g.nc * lap_frame_chunks(g, max_frames);
+  G->npart = std::max((size_t)g.nc * g.nc * lap_frame_chunks(g, max_frames),
+                      (size_t)g.Np * ceil_div(max_frames, 4));
   bool ok = hipMalloc(&G->F, (size_t)g.Np * G->nf * 4) == hipSuccess &&
             hipMalloc(&G->knn, (size_t)g.Np * k_max * 4) == hipSuccess &&
             hipMalloc(&G->knd2, (size_t)g.Np * k_max * 4) == hipSuccess &&
@@ -512,7 +638,7 @@ extern "C" mrf_status mrf_graph_create(int n, int p, int s, int k_max, int max_f
             hipMalloc(&G->col, G->cap * 4) == hipSuccess && hipMalloc(&G->val, G->cap * 4) == hipSuccess &&
             hipMalloc(&G->cnt, (size_t)g.Np * 4) == hipSuccess && hipMalloc(&G->deg, (size_t)g.Np * 4) == hipSuccess &&
             hipMalloc(&G->mx, 16) == hipSuccess && hipMalloc(&G->scal, 4 * sizeof(double)) == hipSuccess &&
-            hipMalloc(&G->part, G->npart * sizeof(double)) == hipSuccess;
+            hipMalloc(&G->part, (G->npart + 256) * sizeof(double)) == hipSuccess;
   if (!ok) {
     mrf_graph_destroy(G);
     return fail(MRF_OOM, "graph_create: device allocation failed");

@@ -7,9 +7,10 @@
 // Steps (kernels):
 //   k_gram      G_i on MFMA (v_mfma_f32_16x16x4f32) from the real [Re P | Im P] blocks, FP32
 //   k_tridiag   complex Householder reduction of G_i to a real symmetric tridiagonal T, in FP64
-//   k_eig_tri   all eigenvalues of T by Sturm bisection (one lane per eigenvalue), the nuclear
-//               norm sum_k sigma_k, and the top r_cap eigenvectors by inverse iteration
-//   k_backxf    eigenvectors of G_i = Q D z (reflectors Q, phases D), stored with f_k
+//   k_eig_val   all eigenvalues of T by Sturm bisection (one lane per eigenvalue), the nuclear
+//               norm sum_k sigma_k, the r_cap largest eigenvalues and their factors f_k
+//   k_eig_vec   eigenvectors of T for those with f_k > 0 by inverse iteration (thread per vector)
+//   k_backxf    eigenvectors of G_i = Q D z (reflectors Q, phases D), clusters re-orthogonalised
 //   k_coef      C_i = diag(f) U_r^H P_i  (r_cap x L per patch)
 //   k_xupdate   X+ = (Z + k Q*(U_r C)) / (1 + k c), k = mu lam2 beta, c = patch coverage; a
 //               16 x 16 pixel tile stages the C rows of the patches that cover it in LDS
@@ -63,67 +64,77 @@ __global__ __launch_bounds__(256) void k_gram(const cf* __restrict__ X, PatchGeo
   constexpr int NUP = NT * (NT + 1) / 2;        // upper tiles
   constexpr int FCH = 64;                       // frames per LDS chunk
   constexpr int TPW = (2 * NUP + 3) / 4;        // accumulators per wave (re and im tiles)
+  constexpr int PER = FCH * PP / 256;           // chunk elements per thread
   __shared__ cf P[FCH][PP];
   const int i = patch_of_block(g.Np);
   if (i < 0) return;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int oy = (i / g.n1) * g.s, ox = (i % g.n1) * g.s;
   const size_t NN = (size_t)g.N * g.N;
+  // job q of this wave: tile (ta, tb) of the upper triangle, real (A1) or imaginary (A2) part
+  int ta[TPW], tb[TPW];
+  bool im[TPW], on[TPW];
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int j = w * TPW + q;
+    on[q] = j < 2 * NUP;
+    im[q] = j >= NUP;
+    int u = j % NUP, a = 0;
+    while (u >= NT - a) {
+      u -= NT - a;
+      ++a;
+    }
+    ta[q] = a;
+    tb[q] = a + u;
+  }
   f32x4 acc[TPW];
 #pragma unroll
   for (int q = 0; q < TPW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // accumulator q of wave w is job j = w * TPW + q: tile (ta, tb) = upper[j % NUP], part = j / NUP
-  for (int l0 = 0; l0 < L; l0 += FCH) {
-    const int nf = min(FCH, L - l0);
-    for (int idx = tid; idx < FCH * PP; idx += 256) {
-      const int f = idx / PP, a = idx % PP;
-      P[f][a] = f < nf ? X[(size_t)(l0 + f) * NN + (size_t)(oy + a / g.p) * g.N + ox + a % g.p] : cf{0.f, 0.f};
+  cf nxt[PER];
+  auto load = [&](int l0) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = tid + k * 256, f = idx / PP, a = idx % PP;
+      nxt[k] = l0 + f < L ? X[(size_t)(l0 + f) * NN + (size_t)(oy + a / g.p) * g.N + ox + a % g.p] : cf{0.f, 0.f};
     }
-    __syncthreads();
+  };
+  load(0);
+  for (int l0 = 0; l0 < L; l0 += FCH) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = tid + k * 256;
+      P[idx / PP][idx % PP] = nxt[k];
+    }
+    lds_sync();
+    if (l0 + FCH < L) load(l0 + FCH);   // in flight during this chunk's MFMAs
     for (int k0 = 0; k0 < 2 * FCH; k0 += 4) {
       const int k = k0 + lane / 16;
       const int f = k >> 1, part = k & 1;
 #pragma unroll
       for (int q = 0; q < TPW; ++q) {
-        const int j = w * TPW + q;
-        if (j < 2 * NUP) {
-          int u = j % NUP, ta = 0;
-          while (u >= NT - ta) {
-            u -= NT - ta;
-            ++ta;
-          }
-          const int tb = ta + u;
-          const cf pa = P[f][ta * 16 + lane % 16];
-          const cf pb = P[f][tb * 16 + lane % 16];
+        if (on[q]) {
+          const cf pa = P[f][ta[q] * 16 + lane % 16];
+          const cf pb = P[f][tb[q] * 16 + lane % 16];
           const float bval = part ? pb.y : pb.x;                  // A1[b][k]
-          float aval;
-          if (j < NUP) aval = part ? pa.y : pa.x;                 // A1[a][k]
-          else aval = part ? -pa.x : pa.y;                        // A2[a][k]
+          const float aval = !im[q] ? (part ? pa.y : pa.x)        // A1[a][k]
+                                    : (part ? -pa.x : pa.y);      // A2[a][k]
           acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(aval, bval, acc[q], 0, 0, 0);
         }
       }
     }
-    __syncthreads();
+    lds_sync();
   }
   cf* Gi = G + (size_t)i * PP * PP;
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
-    const int j = w * TPW + q;
-    if (j < 2 * NUP) {
-      int u = j % NUP, ta = 0;
-      while (u >= NT - ta) {
-        u -= NT - ta;
-        ++ta;
-      }
-      const int tb = ta + u;
-      const bool im = j >= NUP;
+    if (on[q]) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int a = ta * 16 + 4 * (lane / 16) + e, b = tb * 16 + lane % 16;
-        if (ta == tb && a > b) continue;   // diagonal tiles: the upper half writes both halves
+        const int a = ta[q] * 16 + 4 * (lane / 16) + e, b = tb[q] * 16 + lane % 16;
+        if (ta[q] == tb[q] && a > b) continue;   // diagonal tiles: the upper half writes both halves
         float* ga = (float*)&Gi[(size_t)a * PP + b];
         float* gb = (float*)&Gi[(size_t)b * PP + a];
-        if (!im) {
+        if (!im[q]) {
           ga[0] = acc[q][e];
           gb[0] = acc[q][e];
         } else {
@@ -157,83 +168,91 @@ __global__ __launch_bounds__(256) void k_gram_small(const cf* __restrict__ X, Pa
 }
 
 // ------------------------------------------------------------------ FP64 Householder
-// One wave per patch; A (n x n, Hermitian, FP64) in LDS, lane = row. For k = 0 .. n-3:
+// One 4-wave block per patch; A (n x n, Hermitian, FP64) in LDS. Lanes are rows; wave w takes
+// the columns c = w (mod 4) of the matrix-vector product and of the rank-2 update. For k = 0 .. n-3:
 //   x = A[k+1:, k], alpha = ||x||, phase = x0/|x0|, beta = -phase alpha, v = x - beta e1,
 //   tau = 1 / (alpha (alpha + |x0|)) so that H = I - tau v v^H maps x to beta e1;
 //   p = tau A22 v, K = tau/2 v^H p, w = p - K v, A22 -= v w^H + w v^H.
 // The reflectors are written out (v, tau); T has diagonal d and sub-diagonal e (complex), then
 // the phases D make it real: D_0 = 1, D_{k+1} = D_k e_k / |e_k|, e_k -> |e_k|.
-__global__ __launch_bounds__(64) void k_tridiag(const cf* __restrict__ G, int Np, int n, double* __restrict__ dd,
-                                               double* __restrict__ ee, dcplx* __restrict__ refl,
-                                               double* __restrict__ rtau, dcplx* __restrict__ phase) {
+__global__ __launch_bounds__(256) void k_tridiag(const cf* __restrict__ G, int Np, int n, double* __restrict__ dd,
+                                                double* __restrict__ ee, dcplx* __restrict__ refl,
+                                                double* __restrict__ rtau, dcplx* __restrict__ phase) {
   __shared__ dcplx A[kMaxPP][kMaxPP + 1];
-  __shared__ dcplx vs[kMaxPP];
+  __shared__ dcplx vs[kMaxPP], ws[kMaxPP], es[kMaxPP];
+  __shared__ dcplx pw[4][kMaxPP];
+  __shared__ double tau_s;
   const int i = patch_of_block(Np);
   if (i < 0) return;
-  const int r = threadIdx.x;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const cf* Gi = G + (size_t)i * n * n;
-  if (r < n)
-    for (int c = 0; c < n; ++c) {
-      const cf x = Gi[(size_t)r * n + c];
-      A[r][c] = dcplx{x.x, x.y};
-    }
+  for (int idx = t; idx < n * n; idx += 256) {
+    const cf x = Gi[idx];
+    A[idx / n][idx % n] = dcplx{x.x, x.y};
+  }
   __syncthreads();
   dcplx* Ri = refl + (size_t)i * n * n;     // reflector k stored in row k (entries k+1 .. n-1)
-  dcplx ecur{0.0, 0.0};
   for (int k = 0; k < n - 2; ++k) {
-    const bool below = r > k && r < n;
-    const dcplx x = below ? A[r][k] : dcplx{0.0, 0.0};
-    const double alpha = sqrt(wave_sum(below ? x.x * x.x + x.y * x.y : 0.0));
-    const dcplx x0 = A[k + 1][k];
-    const double ax0 = sqrt(x0.x * x0.x + x0.y * x0.y);
-    dcplx ph = ax0 > 0 ? dcplx{x0.x / ax0, x0.y / ax0} : dcplx{1.0, 0.0};
-    double tau = 0.0;
-    dcplx v{0.0, 0.0};
-    dcplx beta{0.0, 0.0};
-    if (alpha > 0.0) {
-      beta = dscale(ph, -alpha);
-      tau = 1.0 / (alpha * (alpha + ax0));
-      if (below) v = (r == k + 1) ? dsub(x, beta) : x;
+    if (w == 0) {
+      const int r = lane;
+      const bool below = r > k && r < n;
+      const dcplx x = below ? A[r][k] : dcplx{0.0, 0.0};
+      const double alpha = sqrt(wave_sum(below ? x.x * x.x + x.y * x.y : 0.0));
+      const dcplx x0 = A[k + 1][k];
+      const double ax0 = sqrt(x0.x * x0.x + x0.y * x0.y);
+      const dcplx ph = ax0 > 0 ? dcplx{x0.x / ax0, x0.y / ax0} : dcplx{1.0, 0.0};
+      double tau = 0.0;
+      dcplx v{0.0, 0.0}, beta{0.0, 0.0};
+      if (alpha > 0.0) {
+        beta = dscale(ph, -alpha);
+        tau = 1.0 / (alpha * (alpha + ax0));
+        if (below) v = (r == k + 1) ? dsub(x, beta) : x;
+      }
+      vs[r] = v;
+      if (r < n) Ri[(size_t)k * n + r] = below ? v : dcplx{0.0, 0.0};
+      if (r == 0) {
+        rtau[(size_t)i * n + k] = tau;
+        tau_s = tau;
+        es[k] = alpha > 0.0 ? beta : x0;
+      }
     }
-    if (r < n) Ri[(size_t)k * n + r] = below ? v : dcplx{0.0, 0.0};
-    if (r == 0) rtau[(size_t)i * n + k] = tau;
-    if (r == k) ecur = alpha > 0.0 ? beta : x0;   // lane k keeps e_k
+    __syncthreads();
+    const double tau = tau_s;
     if (tau != 0.0) {
-      vs[r] = v;
+      // p = tau A22 v: lane = row, wave w sums the columns c = w (mod 4); partials in LDS
+      const int r = lane;
+      dcplx pp{0.0, 0.0};
+      if (r > k && r < n)
+        for (int c = k + 1 + ((w - (k + 1)) % 4 + 4) % 4; c < n; c += 4) pp = dadd(pp, dmul(A[r][c], vs[c]));
+      pw[w][r] = pp;
       __syncthreads();
-      // p = tau A22 v (row r of A22)
-      dcplx p{0.0, 0.0};
-      if (below)
-        for (int c = k + 1; c < n; ++c) p = dadd(p, dmul(A[r][c], vs[c]));
-      p = dscale(p, tau);
-      // K = tau/2 v^H p
-      const double kr = wave_sum(below ? v.x * p.x + v.y * p.y : 0.0);
-      const double ki = wave_sum(below ? v.x * p.y - v.y * p.x : 0.0);
-      const dcplx K = dscale(dcplx{kr, ki}, 0.5 * tau);
-      const dcplx wv = dsub(p, dmul(K, v));
+      if (w == 0) {
+        const bool below = r > k && r < n;
+        const dcplx v = vs[r];
+        const dcplx pv = below ? dscale(dadd(dadd(pw[0][r], pw[1][r]), dadd(pw[2][r], pw[3][r])), tau)
+                               : dcplx{0.0, 0.0};
+        const double kr = wave_sum(below ? v.x * pv.x + v.y * pv.y : 0.0);
+        const double ki = wave_sum(below ? v.x * pv.y - v.y * pv.x : 0.0);
+        const dcplx K = dscale(dcplx{kr, ki}, 0.5 * tau);
+        ws[r] = below ? dsub(pv, dmul(K, v)) : dcplx{0.0, 0.0};
+      }
       __syncthreads();
-      vs[r] = v;
-      __shared__ dcplx ws[kMaxPP];
-      ws[r] = wv;
-      __syncthreads();
-      if (below)
-        for (int c = k + 1; c < n; ++c) {
-          // A[r][c] -= v_r conj(w_c) + w_r conj(v_c)
-          const dcplx t1 = dmul(v, dcplx{ws[c].x, -ws[c].y});
-          const dcplx t2 = dmul(wv, dcplx{vs[c].x, -vs[c].y});
+      // A22 -= v w^H + w v^H: lane = row, wave w updates the columns c = w (mod 4)
+      if (r > k && r < n) {
+        const dcplx vr = vs[r], wr = ws[r];
+        for (int c = k + 1 + ((w - (k + 1)) % 4 + 4) % 4; c < n; c += 4) {
+          const dcplx t1 = dmul(vr, dcplx{ws[c].x, -ws[c].y});
+          const dcplx t2 = dmul(wr, dcplx{vs[c].x, -vs[c].y});
           A[r][c] = dsub(A[r][c], dadd(t1, t2));
         }
+      }
       __syncthreads();
     }
   }
-  if (r == n - 2) ecur = A[n - 1][n - 2];
+  if (t == 0) es[n - 2] = A[n - 1][n - 2];
+  if (t < n) dd[(size_t)i * n + t] = A[t][t].x;
   __syncthreads();
-  // diagonal and real sub-diagonal; phases
-  if (r < n) dd[(size_t)i * n + r] = A[r][r].x;
-  __shared__ dcplx es[kMaxPP];
-  es[r] = ecur;
-  __syncthreads();
-  if (r == 0) {
+  if (t == 0) {
     dcplx D{1.0, 0.0};
     phase[(size_t)i * n + 0] = D;
     for (int k = 0; k < n - 1; ++k) {
@@ -247,154 +266,216 @@ __global__ __launch_bounds__(64) void k_tridiag(const cf* __restrict__ G, int Np
   }
 }
 
-// Number of eigenvalues of the symmetric tridiagonal (d, e) smaller than x (Sturm sequence).
-__device__ inline int sturm_count(const double* d, const double* e, int n, double x) {
-  int c = 0;
+// Number of eigenvalues of the symmetric tridiagonal (d, e^2) smaller than x, from the signs of
+// the pivots q_k = (d_k - x) - e_{k-1}^2 / q_{k-1} of the LDL^T factorisation of T - x I. The
+// matrix is scaled so that |d|, e^2 <= 1; a pivot smaller than pmin in magnitude is replaced by
+// -pmin (a perturbation of d_k by at most pmin). 1/q comes from the hardware reciprocal refined by
+// two Newton steps, which is accurate to rounding whatever the initial approximation's bits.
+constexpr double kPivMin = 1e-280;
+__device__ inline double recip(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  double e = fma(-q, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-q, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ inline int sturm_count(const double* d, const double* e2, int n, double x) {
   double q = d[0] - x;
-  if (q < 0) ++c;
+  if (fabs(q) < kPivMin) q = -kPivMin;
+  int c = q < 0.0;
   for (int k = 1; k < n; ++k) {
-    const double qq = fabs(q) < 1e-300 ? (q < 0 ? -1e-300 : 1e-300) : q;
-    q = d[k] - x - e[k - 1] * e[k - 1] / qq;
-    if (q < 0) ++c;
+    q = (d[k] - x) - e2[k - 1] * recip(q);
+    if (fabs(q) < kPivMin) q = -kPivMin;
+    c += q < 0.0;
   }
   return c;
 }
 
-// One wave per patch. Lane j finds eigenvalue j (ascending) by bisection on the Sturm count;
-// the sum of sigma = sqrt(max(lambda, 0)) is the patch's nuclear norm. Lanes 0 .. rcap-1 then
-// each compute the eigenvector of the j-th largest eigenvalue by inverse iteration on T
-// (tridiagonal LU with partial pivoting), re-orthogonalised inside clusters.
-__global__ __launch_bounds__(64) void k_eig_tri(const double* __restrict__ dd, const double* __restrict__ ee, int Np,
+__device__ inline double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// One wave per patch: all n eigenvalues of T by Sturm bisection, lane j finding the j-th smallest.
+// T is scaled by a power of two sc so that its Gershgorin disc fits in [-1, 1]. One multisection
+// sweep (lane j counts at the j-th of 64 equispaced points) brackets every eigenvalue to 1/64 of
+// the spectrum's span before the per-lane bisection. Outputs: the patch's nuclear norm
+// sum_j sqrt(max(lambda_j, 0)), the rcap largest eigenvalues (descending) and their shrinkage
+// factors f_k = (sigma_k - tau)_+ / sigma_k.
+__global__ __launch_bounds__(64) void k_eig_val(const double* __restrict__ dd, const double* __restrict__ ee, int Np,
                                                int n, double tau_thr, int rcap, double* __restrict__ nuc,
-                                               double* __restrict__ zvec, float* __restrict__ fk,
+                                               double* __restrict__ lamtop, float* __restrict__ fk,
                                                double* __restrict__ lam_out) {
-  __shared__ double d[kMaxPP], e[kMaxPP], lam[kMaxPP];
-  __shared__ double Z[kMaxRllr][kMaxPP];
-  __shared__ double wrk[kMaxRllr][4][kMaxPP];
+  __shared__ double d[kMaxPP], e2[kMaxPP], lam[kMaxPP];
+  __shared__ int cnt[64];
   const int i = patch_of_block(Np);
   if (i < 0) return;
   const int t = threadIdx.x;
+  const double dt = t < n ? dd[(size_t)i * n + t] : 0.0;
+  const double et = t < n - 1 ? fabs(ee[(size_t)i * n + t]) : 0.0;
+  const double etm = __shfl_up(et, 1);
+  const double rad = et + (t > 0 ? etm : 0.0);
+  const double g_lo = wave_min(t < n ? dt - rad : DBL_MAX);
+  const double g_hi = wave_max(t < n ? dt + rad : -DBL_MAX);
+  const double gmax = fmax(fabs(g_lo), fabs(g_hi));
+  const double sc = gmax > 0.0 ? ldexp(1.0, ilogb(gmax) + 1) : 1.0;   // power of two > gmax
+  const double isc = 1.0 / sc;
   if (t < n) {
-    d[t] = dd[(size_t)i * n + t];
-    e[t] = ee[(size_t)i * n + t];
+    d[t] = dt * isc;
+    e2[t] = (et * isc) * (et * isc);
   }
   __syncthreads();
-  // Gershgorin interval
-  double lo = 0.0, hi = 0.0;
-  for (int k = 0; k < n; ++k) {
-    const double rad = (k > 0 ? e[k - 1] : 0.0) + (k < n - 1 ? e[k] : 0.0);
-    lo = k == 0 ? d[k] - rad : fmin(lo, d[k] - rad);
-    hi = k == 0 ? d[k] + rad : fmax(hi, d[k] + rad);
-  }
-  const double span = fmax(hi - lo, 1e-300);
-  lo -= 1e-12 * span + 1e-300;
-  hi += 1e-12 * span + 1e-300;
-  double a = lo, b = hi;
-  for (int it = 0; it < 80; ++it) {   // bisection: lambda_t (ascending) lies in (a, b]
+  double lo = g_lo * isc, hi = g_hi * isc;
+  const double span = fmax(hi - lo, 1e-250);
+  lo -= 1e-12 * span + 1e-250;
+  hi += 1e-12 * span + 1e-250;
+  // multisection: cnt[j] = number of eigenvalues below x_j = lo + (j + 1) (hi - lo) / 64
+  const double h = (hi - lo) * (1.0 / 64.0);
+  const double xj = t == 63 ? hi : lo + (t + 1) * h;
+  cnt[t] = sturm_count(d, e2, n, xj);
+  __syncthreads();
+  int j = 0;
+  while (j < 63 && cnt[j] <= t) ++j;
+  double a = j == 0 ? lo : lo + j * h;
+  double b = j == 63 ? hi : lo + (j + 1) * h;
+  // bisection to 1e-13 of the span: lambda_t (ascending) lies in (a, b]
+  const double tol = 1e-13 * span;
+  for (int it = 0; it < 48; ++it) {
     const double m = 0.5 * (a + b);
-    if (m <= a || m >= b) break;
-    if (t < n && sturm_count(d, e, n, m) > t) b = m;
-    else a = m;
+    const bool done = m <= a || m >= b || b - a <= tol;
+    if (__all(done)) break;
+    if (!done) {
+      if (t < n && sturm_count(d, e2, n, m) > t) b = m;
+      else a = m;
+    }
   }
-  const double lt = 0.5 * (a + b);
+  const double lt = 0.5 * (a + b) * sc;
   if (t < n) lam[t] = lt;
-  const double sg = t < n ? sqrt(fmax(lt, 0.0)) : 0.0;
-  const double tot = wave_sum(sg);
+  const double tot = wave_sum(t < n ? sqrt(fmax(lt, 0.0)) : 0.0);
   if (t == 0) nuc[i] = tot;
   __syncthreads();
-  // eigenvectors of the rcap largest eigenvalues
-  const double scale = fmax(fabs(lo), fabs(hi));
-  if (t < rcap && t < n) {
-    const double lk = lam[n - 1 - t];
+  if (t < rcap) {
+    const double lk = t < n ? lam[n - 1 - t] : 0.0;
     const double sk = sqrt(fmax(lk, 0.0));
     const double f = sk > tau_thr ? (sk - tau_thr) / sk : 0.0;
     fk[(size_t)i * rcap + t] = (float)f;
+    lamtop[(size_t)i * rcap + t] = lk;
     if (lam_out) lam_out[(size_t)i * rcap + t] = lk;
-    double* y = Z[t];
-    double* u0 = wrk[t][0];   // LU: U diagonal, first and second super-diagonals, multipliers
-    double* u1 = wrk[t][1];
-    double* u2 = wrk[t][2];
-    double* ml = wrk[t][3];
-    // LU with partial pivoting of (T - lk I); tiny pivots replaced by eps * scale
-    const double eps = 1e-14 * scale + 1e-300;
-    double dcur = d[0] - lk, ecur = n > 1 ? e[0] : 0.0;
-    unsigned long long pivmask = 0ull;
-    for (int k = 0; k < n - 1; ++k) {
-      const double sub = e[k];
-      double nd = d[k + 1] - lk, ne = k + 1 < n - 1 ? e[k + 1] : 0.0;
-      if (fabs(dcur) >= fabs(sub)) {
-        const double piv_v = fabs(dcur) < eps ? eps : dcur;
-        u0[k] = piv_v; u1[k] = ecur; u2[k] = 0.0;
-        ml[k] = sub / piv_v;
-        dcur = nd - ml[k] * ecur;
-        ecur = ne;
-      } else {
-        pivmask |= 1ull << k;
-        u0[k] = sub; u1[k] = nd; u2[k] = ne;
-        ml[k] = dcur / sub;
-        dcur = ecur - ml[k] * nd;
-        ecur = -ml[k] * ne;
-      }
-    }
-    u0[n - 1] = fabs(dcur) < eps ? eps : dcur;
-    for (int k = 0; k < n; ++k) y[k] = 1.0 + 0.01 * ((k * 37 + t * 11) % 7);
-    for (int it = 0; it < 3; ++it) {
-      // forward: apply the row interchanges and multipliers
-      for (int k = 0; k < n - 1; ++k) {
-        if ((pivmask >> k) & 1ull) {
-          const double tmp = y[k];
-          y[k] = y[k + 1];
-          y[k + 1] = tmp - ml[k] * y[k];
-        } else {
-          y[k + 1] -= ml[k] * y[k];
-        }
-      }
-      // back substitution with U (diagonal u0, super-diagonals u1, u2)
-      for (int k = n - 1; k >= 0; --k) {
-        double s = y[k];
-        if (k + 1 < n) s -= u1[k] * y[k + 1];
-        if (k + 2 < n) s -= u2[k] * y[k + 2];
-        y[k] = s / u0[k];
-      }
-      double nr = 0.0;
-      for (int k = 0; k < n; ++k) nr += y[k] * y[k];
-      nr = 1.0 / sqrt(fmax(nr, 1e-300));
-      for (int k = 0; k < n; ++k) y[k] *= nr;
-    }
   }
-  __syncthreads();
-  // orthogonalise inside clusters (sequential over the vectors, in order)
-  if (t == 0) {
-    const int m = min(rcap, n);
-    for (int k = 1; k < m; ++k) {
-      for (int j = 0; j < k; ++j) {
-        if (fabs(lam[n - 1 - k] - lam[n - 1 - j]) <= 1e-6 * scale) {
-          double dot = 0.0;
-          for (int q = 0; q < n; ++q) dot += Z[j][q] * Z[k][q];
-          for (int q = 0; q < n; ++q) Z[k][q] -= dot * Z[j][q];
-          double nr = 0.0;
-          for (int q = 0; q < n; ++q) nr += Z[k][q] * Z[k][q];
-          nr = 1.0 / sqrt(fmax(nr, 1e-300));
-          for (int q = 0; q < n; ++q) Z[k][q] *= nr;
-        }
-      }
-    }
-  }
-  __syncthreads();
-  for (int k = 0; k < min(rcap, n); ++k)
-    if (t < n) zvec[((size_t)i * rcap + k) * n + t] = Z[k][t];
 }
 
-// u_k = H_0 H_1 ... H_{n-3} D z_k for the rcap vectors; lane = row. Stores U[i][k][a] (FP32).
-__global__ __launch_bounds__(64) void k_backxf(const double* __restrict__ zvec, const dcplx* __restrict__ refl,
-                                              const double* __restrict__ rtau, const dcplx* __restrict__ phase,
-                                              int Np, int n, int rcap, cf* __restrict__ U) {
+// Eigenvectors of T for the rcap largest eigenvalues by inverse iteration, one thread per
+// (patch, k). Each sweep factors T - lambda_k I = P L U (partial pivoting; a pivot below
+// 1e-14 |T| is replaced by that bound) while it eliminates the right-hand side, then
+// back-substitutes with U; three sweeps from a fixed start vector. Components with f_k = 0 get a
+// zero vector. The thread's shifted T, U and right-hand side live in LDS, interleaved by thread.
+constexpr int kEvT = 16;   // threads per block
+__global__ __launch_bounds__(kEvT) void k_eig_vec(const double* __restrict__ dd, const double* __restrict__ ee,
+                                                  const double* __restrict__ lamtop, const float* __restrict__ fk,
+                                                  int Np, int n, int rcap, double* __restrict__ zvec) {
+  __shared__ double ds[kMaxPP][kEvT], es[kMaxPP][kEvT];
+  __shared__ double ui[kMaxPP][kEvT], u1[kMaxPP][kEvT], u2[kMaxPP][kEvT], y[kMaxPP][kEvT];
+  const int t = threadIdx.x;
+  const long gid = (long)blockIdx.x * kEvT + t;
+  if (gid >= (long)Np * rcap) return;
+  const int i = (int)(gid / rcap), k = (int)(gid % rcap);
+  double* z = zvec + ((size_t)i * rcap + k) * n;
+  if (k >= n || fk[(size_t)i * rcap + k] <= 0.f) {
+    for (int q = 0; q < n; ++q) z[q] = 0.0;
+    return;
+  }
+  const double* d = dd + (size_t)i * n;
+  const double* e = ee + (size_t)i * n;
+  const double lk = lamtop[(size_t)i * rcap + k];
+  double tn = 0.0;
+#pragma unroll 8
+  for (int q = 0; q < n; ++q) {
+    const double dq = d[q], eq = q < n - 1 ? e[q] : 0.0;
+    ds[q][t] = dq - lk;
+    es[q][t] = eq;
+    tn = fmax(tn, fabs(dq) + 2.0 * fabs(eq));
+    y[q][t] = 1.0 + 0.01 * ((q * 37 + k * 11) % 7);
+  }
+  const double eps = 1e-14 * tn + 1e-300;
+  double scale = 1.0;
+  for (int sweep = 0; sweep < 3; ++sweep) {
+    // factor and eliminate: the partly reduced row q is (dcur, ecur) at columns (q, q + 1)
+    double dcur = ds[0][t], ecur = es[0][t];
+    double yc = y[0][t] * scale;
+    for (int q = 0; q < n - 1; ++q) {
+      const double sub = es[q][t];
+      const double nd = ds[q + 1][t], ne = es[q + 1][t];
+      const double yn = y[q + 1][t] * scale;
+      if (fabs(dcur) >= fabs(sub)) {
+        const double piv = fabs(dcur) < eps ? eps : dcur;
+        const double rp = 1.0 / piv, ml = sub * rp;
+        ui[q][t] = rp; u1[q][t] = ecur; u2[q][t] = 0.0;
+        y[q][t] = yc;
+        yc = yn - ml * yc;
+        dcur = nd - ml * ecur;
+        ecur = ne;
+      } else {
+        const double rp = 1.0 / sub, ml = dcur * rp;
+        ui[q][t] = rp; u1[q][t] = nd; u2[q][t] = ne;
+        y[q][t] = yn;
+        yc = yc - ml * yn;
+        dcur = ecur - ml * nd;
+        ecur = -ml * ne;
+      }
+    }
+    ui[n - 1][t] = 1.0 / (fabs(dcur) < eps ? eps : dcur);
+    y[n - 1][t] = yc;
+    // back substitution
+    double y1 = 0.0, y2 = 0.0, nr = 0.0;
+    for (int q = n - 1; q >= 0; --q) {
+      const double v = (y[q][t] - u1[q][t] * y1 - u2[q][t] * y2) * ui[q][t];
+      y[q][t] = v;
+      nr += v * v;
+      y2 = y1;
+      y1 = v;
+    }
+    scale = 1.0 / sqrt(fmax(nr, 1e-300));
+  }
+  for (int q = 0; q < n; ++q) z[q] = y[q][t] * scale;
+}
+
+// u_k = H_0 H_1 ... H_{n-3} D z_k for the rcap vectors; one wave per patch, lane = row. Vectors
+// whose eigenvalues agree to 1e-6 of the largest are first orthogonalised against the earlier
+// ones of their cluster (modified Gram-Schmidt in the tridiagonal basis). Stores U[i][k][a] (FP32).
+__global__ __launch_bounds__(64) void k_backxf(const double* __restrict__ zvec, const double* __restrict__ lamtop,
+                                              const dcplx* __restrict__ refl, const double* __restrict__ rtau,
+                                              const dcplx* __restrict__ phase, int Np, int n, int rcap,
+                                              cf* __restrict__ U) {
+  __shared__ double zs[kMaxRllr][kMaxPP];
   const int i = patch_of_block(Np);
   if (i < 0) return;
   const int r = threadIdx.x;
   const dcplx* Ri = refl + (size_t)i * n * n;
+  const double* lt = lamtop + (size_t)i * rcap;
+  const double ctol = 1e-6 * fmax(fabs(lt[0]), 1e-300);
   for (int k = 0; k < rcap && k < n; ++k) {
-    const double z = r < n ? zvec[((size_t)i * rcap + k) * n + r] : 0.0;
+    double z = r < n ? zvec[((size_t)i * rcap + k) * n + r] : 0.0;
+    if (wave_sum(z * z) == 0.0) {   // component with f = 0
+      if (r < n) U[((size_t)i * rcap + k) * n + r] = cf{0.f, 0.f};
+      zs[k][r] = 0.0;
+      continue;
+    }
+    bool moved = false;
+    for (int j = 0; j < k; ++j) {
+      if (fabs(lt[k] - lt[j]) > ctol) continue;
+      const double zj = zs[j][r];
+      const double dot = wave_sum(zj * z);
+      z -= dot * zj;
+      moved = true;
+    }
+    if (moved) z *= 1.0 / sqrt(fmax(wave_sum(z * z), 1e-300));
+    zs[k][r] = z;
     dcplx u = r < n ? dscale(phase[(size_t)i * n + r], z) : dcplx{0.0, 0.0};
     for (int j = n - 3; j >= 0; --j) {
       const double tau = rtau[(size_t)i * n + j];
@@ -535,6 +616,7 @@ struct LlrWs {
   dcplx* ph;    // [Np][PP]
   double* nuc;  // [Np]
   double* z;    // [Np][rcap][PP]
+  double* lam;  // [Np][rcap]
   size_t bytes;
 };
 
@@ -558,6 +640,7 @@ LlrWs llr_ws_layout(const PatchGeom& g, int rcap, void* base) {
   w.ph = (dcplx*)take(Np * PP * sizeof(dcplx));
   w.nuc = (double*)take(Np * 8);
   w.z = (double*)take(Np * rcap * PP * 8);
+  w.lam = (double*)take(Np * rcap * 8);
   w.bytes = off;
   return w;
 }
@@ -574,9 +657,11 @@ mrf_status llr_analyse(const cf* X, const PatchGeom& g, int L, double tau, int r
   else if (PP == 32 || PP == 48) return fail(MRF_SHAPE, "llr: p^2 must be 16 or 64 (or < 16)");
   else if (PP < 16) MRF_LAUNCH("llr_gram", s, k_gram_small<<<nb, 256, 0, s>>>(X, g, L, w.G));
   else return fail(MRF_SHAPE, "llr: p^2 must be 16 or 64 (or < 16)");
-  MRF_LAUNCH("llr_tridiag", s, k_tridiag<<<nb, 64, 0, s>>>(w.G, g.Np, PP, w.dd, w.ee, w.refl, w.rtau, w.ph));
-  MRF_LAUNCH("llr_eig", s, k_eig_tri<<<nb, 64, 0, s>>>(w.dd, w.ee, g.Np, PP, tau, rcap, w.nuc, w.z, f, lam_out));
-  MRF_LAUNCH("llr_backxf", s, k_backxf<<<nb, 64, 0, s>>>(w.z, w.refl, w.rtau, w.ph, g.Np, PP, rcap, U));
+  MRF_LAUNCH("llr_tridiag", s, k_tridiag<<<nb, 256, 0, s>>>(w.G, g.Np, PP, w.dd, w.ee, w.refl, w.rtau, w.ph));
+  MRF_LAUNCH("llr_eig", s, k_eig_val<<<nb, 64, 0, s>>>(w.dd, w.ee, g.Np, PP, tau, rcap, w.nuc, w.lam, f, lam_out));
+  const int nv = (int)ceil_div((long)g.Np * rcap, (long)kEvT);
+  MRF_LAUNCH("llr_eigvec", s, k_eig_vec<<<nv, kEvT, 0, s>>>(w.dd, w.ee, w.lam, f, g.Np, PP, rcap, w.z));
+  MRF_LAUNCH("llr_backxf", s, k_backxf<<<nb, 64, 0, s>>>(w.z, w.lam, w.refl, w.rtau, w.ph, g.Np, PP, rcap, U));
   MRF_LAUNCH("llr_nuc_sum", s, k_sum_d<<<1, 256, 0, s>>>(w.nuc, g.Np, nuc_out));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
