@@ -395,64 +395,113 @@ __global__ __launch_bounds__(256) void k_lap_full(const cf* __restrict__ X, cf* 
 }
 
 // Tr(Q(X) L Q(X)^H) = sum_i L_ii ||q_i||^2 + 2 sum_{i<j} L_ij Re<q_i, q_j> (L symmetric), with
-// q_i the patch i block of X over all frames. Block: patch i and a chunk of frames; thread =
-// (pixel of the patch, frame lane), holding q_i in registers while it streams the neighbours
-// j > i. XCD x takes the frame chunks c = x (mod 8), so each XCD's L2 holds its own frames.
-template <int PP, int FPT>
+// q_i the patch i block of X over all frames. One wave per (patch i, chunk of 8 frames): lane =
+// (pixel of the patch, frame lane), FPT frames each; the row's neighbours j > i are compacted
+// into LDS (64 entries at a time), then streamed two at a time so that 2 FPT loads per lane are
+// in flight.
+// Blocks hold 4 patches of one chunk; XCD x takes the chunks c = x (mod 8), so each XCD's L2
+// holds its 8 frames (4 MB at 256 x 256) while it runs over all patches.
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+constexpr int kQuadFch = 8;
+// PV adjacent pixels per lane (PV = 2: one 16-byte load; needs an even stride and patch size)
+template <int PV>
+struct PixVec;
+template <>
+struct PixVec<1> {
+  typedef cf T;
+  __device__ static float dot(const T& a, const T& b) { return a.x * b.x + a.y * b.y; }
+};
+template <>
+struct PixVec<2> {
+  typedef float4 T;
+  __device__ static float dot(const T& a, const T& b) { return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w; }
+};
+template <int PP, int PV>
 __global__ __launch_bounds__(256) void k_lap_quad_edges(const cf* __restrict__ X, const int* __restrict__ rowptr,
                                                         const int* __restrict__ col, const float* __restrict__ val,
                                                         PatchGeom g, int L, int nchunk, double* __restrict__ part) {
-  constexpr int NSUB = 256 / PP;
-  constexpr int FCH = NSUB * FPT;
-  __shared__ double red[256];
+  typedef typename PixVec<PV>::T VT;
+  constexpr int NPL = PP / PV;             // lanes per frame
+  constexpr int NSUB = 64 / NPL;           // frame lanes per wave
+  constexpr int FPT = kQuadFch / NSUB;     // frames per lane
+  static_assert(FPT >= 1, "chunk too small for the patch");
+  __shared__ int sj[4][64];
+  __shared__ float sw[4][64];
   const int b = blockIdx.x;
   const int q = b >> 3;
-  const int i = q % g.Np;
-  const int c = (q / g.Np) * 8 + (b & 7);
-  if (c >= nchunk) return;
-  const int t = threadIdx.x;
-  const int r = t % PP, fsub = t / PP;
+  const int ngrp = (g.Np + 3) / 4;
+  const int c = (q / ngrp) * 8 + (b & 7);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = (q % ngrp) * 4 + w;
+  if (c >= nchunk || i >= g.Np) return;    // whole waves only; no block barrier below
+  const int r = (lane % NPL) * PV, fsub = lane / NPL;
   const int off = (r / g.p) * g.N + r % g.p;
   const size_t NN = (size_t)g.N * g.N;
   const int oi = (i / g.n1) * g.s * g.N + (i % g.n1) * g.s;
-  cf qi[FPT];
+  const int fbase = c * kQuadFch + fsub;
+  auto ld = [&](int f, int o) -> VT {
+    VT v{};
+    if (f < L) v = *reinterpret_cast<const VT*>(X + (size_t)f * NN + o);
+    return v;
+  };
+  VT qi[FPT];
+#pragma unroll
+  for (int k = 0; k < FPT; ++k) qi[k] = ld(fbase + k * NSUB, oi + off);
+  float s0 = 0.f;
+#pragma unroll
+  for (int k = 0; k < FPT; ++k) s0 += PixVec<PV>::dot(qi[k], qi[k]);
   double acc = 0.0;
-#pragma unroll
-  for (int k = 0; k < FPT; ++k) {
-    const int f = c * FCH + fsub + k * NSUB;
-    qi[k] = f < L ? X[(size_t)f * NN + oi + off] : cf{0.f, 0.f};
-  }
+  auto pix = [&](int j) { return (j / g.n1) * g.s * g.N + (j % g.n1) * g.s + off; };
+  // the row in windows of 64 entries (a hub node's row can be longer than 2 K + 1)
   const int e0 = rowptr[i], e1 = rowptr[i + 1];
-  for (int e = e0; e < e1; ++e) {
-    const int j = col[e];
-    if (j < i) continue;
-    const float w = val[e];
-    if (j == i) {
-      float s = 0.f;
-#pragma unroll
-      for (int k = 0; k < FPT; ++k) s += qi[k].x * qi[k].x + qi[k].y * qi[k].y;
-      acc += (double)w * s;
-      continue;
+  for (int base = e0; base < e1; base += 64) {
+    const bool has = base + lane < e1;
+    const int cj = has ? col[base + lane] : -1;
+    const float wj = has ? val[base + lane] : 0.f;
+    const unsigned long long up = __ballot(cj > i);
+    const unsigned long long dg = __ballot(cj == i);
+    const int nup = __popcll(up);
+    if (dg) acc += (double)__shfl(wj, __ffsll((long long)dg) - 1) * s0;
+    if (cj > i) {
+      const int pos = __popcll(up & ((1ull << lane) - 1ull));
+      sj[w][pos] = cj;
+      sw[w][pos] = wj;
     }
-    const int oj = (j / g.n1) * g.s * g.N + (j % g.n1) * g.s;
-    float s = 0.f;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    int m = 0;
+    for (; m + 1 < nup; m += 2) {
+      const int oa = pix(sj[w][m]), ob = pix(sj[w][m + 1]);
+      VT xa[FPT], xb[FPT];
 #pragma unroll
-    for (int k = 0; k < FPT; ++k) {
-      const int f = c * FCH + fsub + k * NSUB;
-      if (f < L) {
-        const cf qj = X[(size_t)f * NN + oj + off];
-        s += qi[k].x * qj.x + qi[k].y * qj.y;
+      for (int k = 0; k < FPT; ++k) {
+        xa[k] = ld(fbase + k * NSUB, oa);
+        xb[k] = ld(fbase + k * NSUB, ob);
       }
+      float sa = 0.f, sb = 0.f;
+#pragma unroll
+      for (int k = 0; k < FPT; ++k) {
+        sa += PixVec<PV>::dot(qi[k], xa[k]);
+        sb += PixVec<PV>::dot(qi[k], xb[k]);
+      }
+      acc += 2.0 * ((double)sw[w][m] * sa + (double)sw[w][m + 1] * sb);
     }
-    acc += 2.0 * (double)w * s;
+    if (m < nup) {
+      const int oa = pix(sj[w][m]);
+      float sa = 0.f;
+#pragma unroll
+      for (int k = 0; k < FPT; ++k) sa += PixVec<PV>::dot(qi[k], ld(fbase + k * NSUB, oa));
+      acc += 2.0 * (double)sw[w][m] * sa;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();   // the window's list is read before the next one is written
   }
-  red[t] = acc;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (t < o) red[t] += red[t + o];
-    __syncthreads();
-  }
-  if (t == 0) part[(size_t)c * g.Np + i] = red[0];
+  acc = wave_sum_d(acc);
+  if (lane == 0) part[(size_t)c * g.Np + i] = acc;
 }
 
 // S_L applied to per-voxel subspace coefficients A[v][k] (k < r), voxel-major. One thread per voxel.
@@ -560,18 +609,19 @@ mrf_status lap_apply_full(const mrf_graph_s* G, const cf* X, cf* Y, int L, hipSt
 mrf_status lap_quad(mrf_graph_s* G, const cf* X, int L, double* out, hipStream_t s) {
   const PatchGeom& g = G->g;
   const int PP = g.p * g.p;
-  int fch = 0;
-  if (PP == 64) fch = 4 * 2;
-  else if (PP == 16) fch = 16 * 2;
-  if (fch) {
-    const int nchunk = ceil_div(L, fch);
+  if (PP == 64 || PP == 16) {
+    const int nchunk = ceil_div(L, kQuadFch);
     const size_t nb = (size_t)nchunk * g.Np;
     if (nb > G->npart) return fail(MRF_SHAPE, "laplacian quad: too many frames for the partial-sum buffer");
-    const int grid = 8 * g.Np * ceil_div(nchunk, 8);
-    if (PP == 64)
-      MRF_LAUNCH("lap_quad", s, k_lap_quad_edges<64, 2><<<grid, 256, 0, s>>>(X, G->rowptr, G->col, G->val, g, L, nchunk, G->part));
-    else
-      MRF_LAUNCH("lap_quad", s, k_lap_quad_edges<16, 2><<<grid, 256, 0, s>>>(X, G->rowptr, G->col, G->val, g, L, nchunk, G->part));
+    const int grid = 8 * ceil_div(g.Np, 4) * ceil_div(nchunk, 8);
+    const bool vec = g.s % 2 == 0 && g.N % 2 == 0;   // 16-byte aligned pixel pairs
+#define MRF_QUAD(PPv, PVv) \
+  MRF_LAUNCH("lap_quad", s, k_lap_quad_edges<PPv, PVv><<<grid, 256, 0, s>>>(X, G->rowptr, G->col, G->val, g, L, nchunk, G->part))
+    if (PP == 64 && vec) MRF_QUAD(64, 2);
+    else if (PP == 64) MRF_QUAD(64, 1);
+    else if (vec) MRF_QUAD(16, 2);
+    else MRF_QUAD(16, 1);
+#undef MRF_QUAD
     MRF_CHECK_LAUNCH();
     return sum_partials2(G->part, (long)nb, G->part + G->npart, out, s);
   }
