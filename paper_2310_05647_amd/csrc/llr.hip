@@ -55,70 +55,82 @@ inline int patch_blocks(int Np) { return 8 * ((Np + 7) / 8); }
 // ------------------------------------------------------------------ Gram on MFMA
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// G_i = P_i P_i^H, p^2 = PP. Re G = A1 A1^T, Im G = A2 A1^T with A1 = [Re P | Im P],
-// A2 = [Im P | -Re P] over the interleaved K index k = 2 l + {0: re, 1: im}. Only the upper
-// 16 x 16 tiles are computed; the kernel writes both triangles.
+// G_i = P_i P_i^H, p^2 = PP, on the real parts: with P = Pr + i Pi,
+//   Re G = Pr Pr^T + Pi Pi^T,   Im G = Pi Pr^T - Pr Pi^T.
+// The 16 x 16 tiles (a, b) of the upper triangle are shared out over the block's waves; per
+// group of 4 frames a lane reads one complex value of each operand from LDS and issues the four
+// MFMAs of the tile's real and imaginary parts. The kernel writes both triangles.
 template <int PP>
-__global__ __launch_bounds__(256) void k_gram(const cf* __restrict__ X, PatchGeom g, int L, cf* __restrict__ G) {
-  constexpr int NT = PP / 16;                   // tiles per side
-  constexpr int NUP = NT * (NT + 1) / 2;        // upper tiles
-  constexpr int FCH = 64;                       // frames per LDS chunk
-  constexpr int TPW = (2 * NUP + 3) / 4;        // accumulators per wave (re and im tiles)
-  constexpr int PER = FCH * PP / 256;           // chunk elements per thread
+struct GramCfg {
+  static constexpr int NT = PP / 16;                 // tiles per side
+  static constexpr int NUP = NT * (NT + 1) / 2;      // upper tiles
+  static constexpr int NW = NUP >= 5 ? 5 : NUP;      // waves per block
+  static constexpr int TPW = (NUP + NW - 1) / NW;    // tiles per wave
+  static constexpr int NTHR = 64 * NW;
+  static constexpr int FCH = 64;                     // frames per LDS chunk
+  static constexpr int PER = (FCH * PP + NTHR - 1) / NTHR;
+};
+template <int PP>
+__global__ __launch_bounds__(GramCfg<PP>::NTHR) void k_gram(const cf* __restrict__ X, PatchGeom g, int L,
+                                                            cf* __restrict__ G) {
+  typedef GramCfg<PP> C;
+  constexpr int FCH = C::FCH, TPW = C::TPW, PER = C::PER, NTHR = C::NTHR;
   __shared__ cf P[FCH][PP];
   const int i = patch_of_block(g.Np);
   if (i < 0) return;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int oy = (i / g.n1) * g.s, ox = (i % g.n1) * g.s;
   const size_t NN = (size_t)g.N * g.N;
-  // job q of this wave: tile (ta, tb) of the upper triangle, real (A1) or imaginary (A2) part
   int ta[TPW], tb[TPW];
-  bool im[TPW], on[TPW];
+  bool on[TPW];
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
-    const int j = w * TPW + q;
-    on[q] = j < 2 * NUP;
-    im[q] = j >= NUP;
-    int u = j % NUP, a = 0;
-    while (u >= NT - a) {
-      u -= NT - a;
+    const int j = w + q * C::NW;
+    on[q] = j < C::NUP;
+    int u = on[q] ? j : 0, a = 0;
+    while (u >= C::NT - a) {
+      u -= C::NT - a;
       ++a;
     }
     ta[q] = a;
     tb[q] = a + u;
   }
-  f32x4 acc[TPW];
+  f32x4 accr[TPW], acci[TPW];
 #pragma unroll
-  for (int q = 0; q < TPW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < TPW; ++q) {
+    accr[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    acci[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
   cf nxt[PER];
   auto load = [&](int l0) {
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int idx = tid + k * 256, f = idx / PP, a = idx % PP;
-      nxt[k] = l0 + f < L ? X[(size_t)(l0 + f) * NN + (size_t)(oy + a / g.p) * g.N + ox + a % g.p] : cf{0.f, 0.f};
+      const int idx = tid + k * NTHR, f = idx / PP, a = idx % PP;
+      nxt[k] = idx < FCH * PP && l0 + f < L
+                   ? X[(size_t)(l0 + f) * NN + (size_t)(oy + a / g.p) * g.N + ox + a % g.p]
+                   : cf{0.f, 0.f};
     }
   };
   load(0);
   for (int l0 = 0; l0 < L; l0 += FCH) {
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int idx = tid + k * 256;
-      P[idx / PP][idx % PP] = nxt[k];
+      const int idx = tid + k * NTHR;
+      if (idx < FCH * PP) P[idx / PP][idx % PP] = nxt[k];
     }
     lds_sync();
     if (l0 + FCH < L) load(l0 + FCH);   // in flight during this chunk's MFMAs
-    for (int k0 = 0; k0 < 2 * FCH; k0 += 4) {
-      const int k = k0 + lane / 16;
-      const int f = k >> 1, part = k & 1;
+    for (int f0 = 0; f0 < FCH; f0 += 4) {
+      const int f = f0 + lane / 16;
 #pragma unroll
       for (int q = 0; q < TPW; ++q) {
         if (on[q]) {
           const cf pa = P[f][ta[q] * 16 + lane % 16];
-          const cf pb = P[f][tb[q] * 16 + lane % 16];
-          const float bval = part ? pb.y : pb.x;                  // A1[b][k]
-          const float aval = !im[q] ? (part ? pa.y : pa.x)        // A1[a][k]
-                                    : (part ? -pa.x : pa.y);      // A2[a][k]
-          acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(aval, bval, acc[q], 0, 0, 0);
+          const cf pb = ta[q] == tb[q] ? pa : P[f][tb[q] * 16 + lane % 16];
+          accr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa.x, pb.x, accr[q], 0, 0, 0);
+          accr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa.y, pb.y, accr[q], 0, 0, 0);
+          acci[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa.y, pb.x, acci[q], 0, 0, 0);
+          acci[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(-pa.x, pb.y, acci[q], 0, 0, 0);
         }
       }
     }
@@ -132,22 +144,13 @@ __global__ __launch_bounds__(256) void k_gram(const cf* __restrict__ X, PatchGeo
       for (int e = 0; e < 4; ++e) {
         const int a = ta[q] * 16 + 4 * (lane / 16) + e, b = tb[q] * 16 + lane % 16;
         if (ta[q] == tb[q] && a > b) continue;   // diagonal tiles: the upper half writes both halves
-        float* ga = (float*)&Gi[(size_t)a * PP + b];
-        float* gb = (float*)&Gi[(size_t)b * PP + a];
-        if (!im[q]) {
-          ga[0] = acc[q][e];
-          gb[0] = acc[q][e];
-        } else {
-          const float vi = a == b ? 0.f : acc[q][e];
-          ga[1] = vi;
-          gb[1] = -vi;
-        }
+        const float vi = a == b ? 0.f : acci[q][e];
+        Gi[(size_t)a * PP + b] = cf{accr[q][e], vi};
+        Gi[(size_t)b * PP + a] = cf{accr[q][e], -vi};
       }
     }
   }
 }
-
-// Small patches (p^2 < 16): plain FP32 accumulation, one thread per matrix entry.
 __global__ __launch_bounds__(256) void k_gram_small(const cf* __restrict__ X, PatchGeom g, int L, cf* __restrict__ G) {
   const int i = patch_of_block(g.Np);
   if (i < 0) return;
@@ -168,89 +171,118 @@ __global__ __launch_bounds__(256) void k_gram_small(const cf* __restrict__ X, Pa
 }
 
 // ------------------------------------------------------------------ FP64 Householder
-// One 4-wave block per patch; A (n x n, Hermitian, FP64) in LDS. Lanes are rows; wave w takes
-// the columns c = w (mod 4) of the matrix-vector product and of the rank-2 update. For k = 0 .. n-3:
+// One 4-wave block per patch; A (n x n, Hermitian, FP64) lives in registers: lane r of wave w
+// holds A[r][c] for the 16 columns c = w (mod 4). For k = 0 .. n-3:
 //   x = A[k+1:, k], alpha = ||x||, phase = x0/|x0|, beta = -phase alpha, v = x - beta e1,
 //   tau = 1 / (alpha (alpha + |x0|)) so that H = I - tau v v^H maps x to beta e1;
 //   p = tau A22 v, K = tau/2 v^H p, w = p - K v, A22 -= v w^H + w v^H.
-// The reflectors are written out (v, tau); T has diagonal d and sub-diagonal e (complex), then
-// the phases D make it real: D_0 = 1, D_{k+1} = D_k e_k / |e_k|, e_k -> |e_k|.
+// Each wave forms its part of A22 v, the parts meet in LDS, and every wave then computes p, K
+// and w itself and updates its columns; the wave that owns column k+1 forms the next reflector.
+// Two block barriers per column. The reflectors are written out (v, tau); T has diagonal d and
+// sub-diagonal e (complex), then the phases D make it real: D_0 = 1, D_{k+1} = D_k e_k / |e_k|,
+// e_k -> |e_k|.
+constexpr int kTdJ = kMaxPP / 4;   // columns per thread
+// a[j] for a run-time j, as a masked sum so that the array stays in registers
+__device__ inline dcplx pick(const dcplx (&a)[kTdJ], int j) {
+  double xr = 0.0, xi = 0.0;
+#pragma unroll
+  for (int q = 0; q < kTdJ; ++q) {
+    const double m = q == j ? 1.0 : 0.0;
+    xr = fma(m, a[q].x, xr);
+    xi = fma(m, a[q].y, xi);
+  }
+  return dcplx{xr, xi};
+}
 __global__ __launch_bounds__(256) void k_tridiag(const cf* __restrict__ G, int Np, int n, double* __restrict__ dd,
                                                 double* __restrict__ ee, dcplx* __restrict__ refl,
                                                 double* __restrict__ rtau, dcplx* __restrict__ phase) {
-  __shared__ dcplx A[kMaxPP][kMaxPP + 1];
-  __shared__ dcplx vs[kMaxPP], ws[kMaxPP], es[kMaxPP];
-  __shared__ dcplx pw[4][kMaxPP];
-  __shared__ double tau_s;
+  __shared__ dcplx vs[2][kMaxPP];    // reflector of the step, double-buffered by step parity
+  __shared__ dcplx pw[4][kMaxPP];    // per-wave parts of A22 v
+  __shared__ dcplx wsw[4][kMaxPP];   // each wave's copy of w
+  __shared__ dcplx es[kMaxPP];
+  __shared__ double taus[2];
   const int i = patch_of_block(Np);
   if (i < 0) return;
-  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int t = threadIdx.x, w = t >> 6, r = t & 63;
   const cf* Gi = G + (size_t)i * n * n;
-  for (int idx = t; idx < n * n; idx += 256) {
-    const cf x = Gi[idx];
-    A[idx / n][idx % n] = dcplx{x.x, x.y};
-  }
-  __syncthreads();
   dcplx* Ri = refl + (size_t)i * n * n;     // reflector k stored in row k (entries k+1 .. n-1)
-  for (int k = 0; k < n - 2; ++k) {
-    if (w == 0) {
-      const int r = lane;
-      const bool below = r > k && r < n;
-      const dcplx x = below ? A[r][k] : dcplx{0.0, 0.0};
-      const double alpha = sqrt(wave_sum(below ? x.x * x.x + x.y * x.y : 0.0));
-      const dcplx x0 = A[k + 1][k];
-      const double ax0 = sqrt(x0.x * x0.x + x0.y * x0.y);
-      const dcplx ph = ax0 > 0 ? dcplx{x0.x / ax0, x0.y / ax0} : dcplx{1.0, 0.0};
-      double tau = 0.0;
-      dcplx v{0.0, 0.0}, beta{0.0, 0.0};
-      if (alpha > 0.0) {
-        beta = dscale(ph, -alpha);
-        tau = 1.0 / (alpha * (alpha + ax0));
-        if (below) v = (r == k + 1) ? dsub(x, beta) : x;
-      }
-      vs[r] = v;
-      if (r < n) Ri[(size_t)k * n + r] = below ? v : dcplx{0.0, 0.0};
-      if (r == 0) {
-        rtau[(size_t)i * n + k] = tau;
-        tau_s = tau;
-        es[k] = alpha > 0.0 ? beta : x0;
-      }
+  dcplx a[kTdJ];
+#pragma unroll
+  for (int j = 0; j < kTdJ; ++j) {
+    const int c = 4 * j + w;
+    cf x = cf{0.f, 0.f};
+    if (r < n && c < n) x = Gi[(size_t)c * n + r];   // A[r][c] = conj(G[c][r])
+    a[j] = dcplx{x.x, -(double)x.y};
+  }
+  // reflector of column k from this wave's lanes x = A[r][k]
+  auto reflector = [&](int k, dcplx x, int buf) {
+    const bool below = r > k && r < n;
+    const double alpha = sqrt(wave_sum(below ? x.x * x.x + x.y * x.y : 0.0));
+    const double x0r = __shfl(x.x, k + 1), x0i = __shfl(x.y, k + 1);
+    const double ax0 = sqrt(x0r * x0r + x0i * x0i);
+    const double phr = ax0 > 0 ? x0r / ax0 : 1.0, phi = ax0 > 0 ? x0i / ax0 : 0.0;
+    const bool live = alpha > 0.0;
+    const double tau = live ? 1.0 / (alpha * (alpha + ax0)) : 0.0;
+    const double br = -alpha * phr, bi = -alpha * phi;   // beta
+    const bool head = r == k + 1, keep = live && below;
+    const double vr = keep ? (head ? x.x - br : x.x) : 0.0;
+    const double vi = keep ? (head ? x.y - bi : x.y) : 0.0;
+    vs[buf][r] = dcplx{vr, vi};
+    if (r < n) Ri[(size_t)k * n + r] = dcplx{vr, vi};
+    if (r == 0) {
+      rtau[(size_t)i * n + k] = tau;
+      taus[buf] = tau;
+      es[k] = dcplx{live ? br : x0r, live ? bi : x0i};
     }
-    __syncthreads();
-    const double tau = tau_s;
-    if (tau != 0.0) {
-      // p = tau A22 v: lane = row, wave w sums the columns c = w (mod 4); partials in LDS
-      const int r = lane;
+  };
+  if (n > 2 && w == 0) reflector(0, a[0], 0);
+  __syncthreads();
+  for (int k = 0; k < n - 2; ++k) {
+    const int buf = k & 1;
+    const double tau = taus[buf];
+    const bool below = r > k && r < n;
+    if (tau != 0.0) {   // uniform over the block
       dcplx pp{0.0, 0.0};
-      if (r > k && r < n)
-        for (int c = k + 1 + ((w - (k + 1)) % 4 + 4) % 4; c < n; c += 4) pp = dadd(pp, dmul(A[r][c], vs[c]));
-      pw[w][r] = pp;
-      __syncthreads();
-      if (w == 0) {
-        const bool below = r > k && r < n;
-        const dcplx v = vs[r];
-        const dcplx pv = below ? dscale(dadd(dadd(pw[0][r], pw[1][r]), dadd(pw[2][r], pw[3][r])), tau)
-                               : dcplx{0.0, 0.0};
-        const double kr = wave_sum(below ? v.x * pv.x + v.y * pv.y : 0.0);
-        const double ki = wave_sum(below ? v.x * pv.y - v.y * pv.x : 0.0);
-        const dcplx K = dscale(dcplx{kr, ki}, 0.5 * tau);
-        ws[r] = below ? dsub(pv, dmul(K, v)) : dcplx{0.0, 0.0};
+#pragma unroll
+      for (int j = 0; j < kTdJ; ++j) {
+        const int c = 4 * j + w;
+        if (c > k && c < n) pp = dadd(pp, dmul(a[j], vs[buf][c]));
       }
+      pw[w][r] = below ? pp : dcplx{0.0, 0.0};
       __syncthreads();
-      // A22 -= v w^H + w v^H: lane = row, wave w updates the columns c = w (mod 4)
-      if (r > k && r < n) {
-        const dcplx vr = vs[r], wr = ws[r];
-        for (int c = k + 1 + ((w - (k + 1)) % 4 + 4) % 4; c < n; c += 4) {
-          const dcplx t1 = dmul(vr, dcplx{ws[c].x, -ws[c].y});
-          const dcplx t2 = dmul(wr, dcplx{vs[c].x, -vs[c].y});
-          A[r][c] = dsub(A[r][c], dadd(t1, t2));
+      const dcplx v = vs[buf][r];
+      const dcplx pv = dscale(dadd(dadd(pw[0][r], pw[1][r]), dadd(pw[2][r], pw[3][r])), tau);
+      const double kr = wave_sum(below ? v.x * pv.x + v.y * pv.y : 0.0);
+      const double ki = wave_sum(below ? v.x * pv.y - v.y * pv.x : 0.0);
+      const dcplx K = dscale(dcplx{kr, ki}, 0.5 * tau);
+      const dcplx wr = below ? dsub(pv, dmul(K, v)) : dcplx{0.0, 0.0};
+      wsw[w][r] = wr;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (below) {
+#pragma unroll
+        for (int j = 0; j < kTdJ; ++j) {
+          const int c = 4 * j + w;
+          if (c > k && c < n) {
+            const dcplx wc = wsw[w][c], vc = vs[buf][c];
+            const dcplx t1 = dmul(v, dcplx{wc.x, -wc.y});
+            const dcplx t2 = dmul(wr, dcplx{vc.x, -vc.y});
+            a[j] = dsub(a[j], dadd(t1, t2));
+          }
         }
       }
+    }
+    if (k + 1 < n - 2) {
+      if (w == (k + 1) % 4) reflector(k + 1, pick(a, (k + 1) / 4), buf ^ 1);
       __syncthreads();
     }
   }
-  if (t == 0) es[n - 2] = A[n - 1][n - 2];
-  if (t < n) dd[(size_t)i * n + t] = A[t][t].x;
+  if (n >= 2 && w == (n - 2) % 4) {   // e_{n-2} = A[n-1][n-2]
+    const dcplx x = pick(a, (n - 2) / 4);
+    const dcplx y = dcplx{__shfl(x.x, n - 1), __shfl(x.y, n - 1)};
+    if (r == 0) es[n - 2] = y;
+  }
+  if (r < n && w == r % 4) dd[(size_t)i * n + r] = pick(a, r / 4).x;
   __syncthreads();
   if (t == 0) {
     dcplx D{1.0, 0.0};
@@ -491,10 +523,75 @@ __global__ __launch_bounds__(64) void k_backxf(const double* __restrict__ zvec, 
   }
 }
 
-// C[i][k][l] = f_k sum_a conj(U[i][k][a]) X[l][pixel a of patch i]; block per patch, thread per frame.
+// C[i][k][l] = f_k sum_a conj(U[i][k][a]) X[l][pixel a of patch i] on MFMA: D (k x frames) =
+// A (k x pixels) B (pixels x frames) with A = U^H held in registers (rows k >= rcap are zero) and
+// B staged in LDS per chunk of 64 frames, read by the 4 waves one 16-frame tile each. Rows of the
+// LDS chunk are padded by 4 values so that the column reads of B spread over the banks.
+template <int PP>
 __global__ __launch_bounds__(256) void k_coef(const cf* __restrict__ X, const cf* __restrict__ U,
                                               const float* __restrict__ fk, PatchGeom g, int L, int rcap,
                                               cf* __restrict__ C) {
+  constexpr int FCH = 64, PER = FCH * PP / 256, NA = PP / 4;
+  __shared__ cf P[FCH][PP + 4];
+  const int i = patch_of_block(g.Np);
+  if (i < 0) return;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int oy = (i / g.n1) * g.s, ox = (i % g.n1) * g.s;
+  const size_t NN = (size_t)g.N * g.N;
+  // A[m][kk] = conj(U[k = m][a0 + kk]): lane supplies m = lane % 16, kk = lane / 16
+  cf ua[NA];
+  {
+    const int k = lane % 16;
+#pragma unroll
+    for (int s = 0; s < NA; ++s)
+      ua[s] = k < rcap ? U[((size_t)i * rcap + k) * PP + s * 4 + lane / 16] : cf{0.f, 0.f};
+  }
+  float fo[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int k = 4 * (lane / 16) + e;
+    fo[e] = k < rcap ? fk[(size_t)i * rcap + k] : 0.f;
+  }
+  cf nxt[PER];
+  auto load = [&](int l0) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = tid + k * 256, f = idx / PP, a = idx % PP;
+      nxt[k] = l0 + f < L ? X[(size_t)(l0 + f) * NN + (size_t)(oy + a / g.p) * g.N + ox + a % g.p] : cf{0.f, 0.f};
+    }
+  };
+  load(0);
+  for (int l0 = 0; l0 < L; l0 += FCH) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = tid + k * 256;
+      P[idx / PP][idx % PP] = nxt[k];
+    }
+    lds_sync();
+    if (l0 + FCH < L) load(l0 + FCH);
+    f32x4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < NA; ++s) {
+      const cf bv = P[w * 16 + lane % 16][s * 4 + lane / 16];
+      dr = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[s].x, bv.x, dr, 0, 0, 0);
+      dr = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[s].y, bv.y, dr, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[s].x, bv.y, di, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_16x16x4f32(-ua[s].y, bv.x, di, 0, 0, 0);
+    }
+    const int f = l0 + w * 16 + lane % 16;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = 4 * (lane / 16) + e;
+      if (k < rcap && f < L) C[((size_t)i * rcap + k) * L + f] = cf{dr[e] * fo[e], di[e] * fo[e]};
+    }
+    lds_sync();
+  }
+}
+
+// Any p^2 <= 64: block per patch, thread per frame.
+__global__ __launch_bounds__(256) void k_coef_any(const cf* __restrict__ X, const cf* __restrict__ U,
+                                                  const float* __restrict__ fk, PatchGeom g, int L, int rcap,
+                                                  cf* __restrict__ C) {
   __shared__ cf Us[kMaxRllr][kMaxPP];
   __shared__ float fs[kMaxRllr];
   const int i = patch_of_block(g.Np);
@@ -530,7 +627,6 @@ __global__ __launch_bounds__(256) void k_coef(const cf* __restrict__ X, const cf
 // that cover the tile are staged in LDS for FCH frames at a time.
 constexpr int kTile = 16;
 constexpr int kXuFch = 8;
-
 template <bool WITHZ>
 __global__ __launch_bounds__(256) void k_xupdate(const cf* __restrict__ Z, const cf* __restrict__ U,
                                                  const cf* __restrict__ C, PatchGeom g, int L, int rcap,
@@ -652,8 +748,8 @@ mrf_status llr_analyse(const cf* X, const PatchGeom& g, int L, double tau, int r
   const int PP = g.p * g.p;
   LlrWs w = llr_ws_layout(g, rcap, ws);
   const int nb = patch_blocks(g.Np);
-  if (PP == 64) MRF_LAUNCH("llr_gram", s, k_gram<64><<<nb, 256, 0, s>>>(X, g, L, w.G));
-  else if (PP == 16) MRF_LAUNCH("llr_gram", s, k_gram<16><<<nb, 256, 0, s>>>(X, g, L, w.G));
+  if (PP == 64) MRF_LAUNCH("llr_gram", s, k_gram<64><<<nb, GramCfg<64>::NTHR, 0, s>>>(X, g, L, w.G));
+  else if (PP == 16) MRF_LAUNCH("llr_gram", s, k_gram<16><<<nb, GramCfg<16>::NTHR, 0, s>>>(X, g, L, w.G));
   else if (PP == 32 || PP == 48) return fail(MRF_SHAPE, "llr: p^2 must be 16 or 64 (or < 16)");
   else if (PP < 16) MRF_LAUNCH("llr_gram", s, k_gram_small<<<nb, 256, 0, s>>>(X, g, L, w.G));
   else return fail(MRF_SHAPE, "llr: p^2 must be 16 or 64 (or < 16)");
@@ -669,7 +765,10 @@ mrf_status llr_analyse(const cf* X, const PatchGeom& g, int L, double tau, int r
 
 mrf_status llr_coef(const cf* X, const PatchGeom& g, int L, int rcap, const cf* U, const float* f, cf* C,
                     hipStream_t s) {
-  MRF_LAUNCH("llr_coef", s, k_coef<<<patch_blocks(g.Np), 256, 0, s>>>(X, U, f, g, L, rcap, C));
+  const int PP = g.p * g.p, nb = patch_blocks(g.Np);
+  if (PP == 64) MRF_LAUNCH("llr_coef", s, k_coef<64><<<nb, 256, 0, s>>>(X, U, f, g, L, rcap, C));
+  else if (PP == 16) MRF_LAUNCH("llr_coef", s, k_coef<16><<<nb, 256, 0, s>>>(X, U, f, g, L, rcap, C));
+  else MRF_LAUNCH("llr_coef", s, k_coef_any<<<nb, 256, 0, s>>>(X, U, f, g, L, rcap, C));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
 }
