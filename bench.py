@@ -59,11 +59,12 @@ def algorithmic_work(name, cfg, E, Np):
         "nufft_col_fwd": ("hbm", T + E * 64 + E * 8),
         "nufft_col_adj": ("hbm", E * 64 + E * 8 + T),
         "llr_gram": ("mfma", 4.0 * pp * (pp + 1) * L * Np),          # Hermitian half, 8 flops / complex MAC
+        "llr_tridiag": ("fp64", 16.0 / 3.0 * pp ** 3 * Np),          # complex Hermitian tridiagonalisation
         "match_subspace": ("mfma", 8.0 * N * N * M * r),
         "subspace_reduce": ("hbm", 2 * img),
         "subspace_expand": ("hbm", img),
-        "llr_coef": ("hbm", img),
-        "llr_xupdate": ("hbm", 2 * img),
+        "llr_coef": ("hbm", img + Np * cfg["r_llr"] * L * 8),
+        "llr_xupdate": ("hbm", 2 * img + Np * cfg["r_llr"] * L * 8),
         "lap_quad": ("hbm", img),
     }
     if name not in table:
@@ -167,25 +168,28 @@ def main():
     torch.cuda.synchronize()
     match_ms = e0.elapsed_time(e1) / 5
 
-    # roofline of the kernel that takes the most time per step
+    # a plain streaming kernel of known size (256 MiB read, 256 MiB written): the reference that
+    # scales the FETCH_SIZE / WRITE_SIZE counters of a profiled run of this same command
+    cal = torch.zeros(1 << 26, dtype=torch.float32, device=dev)
+    cal_out = torch.empty_like(cal)
+    torch.neg(cal, out=cal_out)
+    torch.cuda.synchronize()
+    del cal, cal_out
+
+    # roofline of the kernels that take the most time per step
     inf = _plan_entries(plan)
     Np = ((N - cfg["p"]) // cfg["s"] + 1) ** 2
-    dom = max(per_kernel.items(), key=lambda kv: kv[1]["ms_per_step"])[0]
-    roof = None
+    rows = []
     for name in sorted(per_kernel, key=lambda k: -per_kernel[k]["ms_per_step"]):
         w = algorithmic_work(name, cfg, inf, Np)
         if w is None:
             continue
-        bound, amount = w
-        avg_s = per_kernel[name]["avg_ms"] * 1e-3
-        if bound == "hbm":
-            ach, peak, unit = amount / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
-        else:
-            ach, peak, unit = amount / avg_s / 1e12, FP32_MFMA_TFLOPS, "TFLOP/s"
-        roof = dict(kernel=name, bound=bound, achieved=round(ach, 2), peak=peak, unit=unit, frac=round(ach / peak, 4),
-                    traffic=None, algorithmic_per_launch=amount, avg_launch_ms=round(per_kernel[name]["avg_ms"], 4),
-                    dominant_kernel=dom)
-        break
+        rows.append(_roof_row(name, w, per_kernel[name]["avg_ms"]))
+    dom = max(per_kernel.items(), key=lambda kv: kv[1]["ms_per_step"])[0]
+    roof = dict(rows[0]) if rows else None
+    if roof is not None:
+        roof["dominant_kernel"] = dom
+        roof["traffic"] = _counter_traffic(roof["kernel"])
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -220,9 +224,31 @@ def main():
             "fingerprints_matched_per_s_subspace_fp32": round(N * N / (match_ms * 1e-3), 1),
             "per_kernel_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in
                                        sorted(per_kernel.items(), key=lambda kv: -kv[1]["ms_per_step"])},
+            "roofline_by_kernel": {r["kernel"]: {"bound": r["bound"], "frac": r["frac"], "achieved": r["achieved"],
+                                                 "unit": r["unit"]} for r in rows},
         },
     }
     print(json.dumps(out), flush=True)
+
+
+def _roof_row(name, work, avg_ms):
+    bound, amount = work
+    avg_s = avg_ms * 1e-3
+    if bound == "hbm":
+        ach, peak, unit = amount / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
+    elif bound == "fp64":
+        ach, peak, unit = amount / avg_s / 1e12, FP64_VECTOR_TFLOPS, "TFLOP/s"
+    else:
+        ach, peak, unit = amount / avg_s / 1e12, FP32_MFMA_TFLOPS, "TFLOP/s"
+    return dict(kernel=name, bound="alu" if bound == "fp64" else bound, achieved=round(ach, 2), peak=peak, unit=unit,
+                frac=round(ach / peak, 4), traffic=None, algorithmic_per_launch=amount, avg_launch_ms=round(avg_ms, 4))
+
+
+def _counter_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary of this kernel, or None when there is
+    none or the kernel's source file has changed since the counters were taken."""
+    from paper_2310_05647_amd import profiling
+    return profiling.traffic_bytes(os.path.join(ROOT, "profiles"), kernel)
 
 
 def _plan_entries(plan):

@@ -1,0 +1,171 @@
+"""Text summaries of rocprofv3 output, and the reader that turns a counter summary into HBM bytes.
+
+rocprofv3 writes its results as an SQLite database (``<dir>/<host>/<pid>_results.db`` or
+``<dir>/<prefix>_results.db``); the tables used here are ``kernels`` (one row per dispatch, with its
+duration in ns) and ``counters_collection`` (one row per dispatch and counter).
+
+    python -m paper_2310_05647_amd.profiling stats --db DIR --out FILE --command "..."
+    python -m paper_2310_05647_amd.profiling traffic --fetch DIR --write DIR --kernel LABEL \\
+        --out FILE --command-fetch "..." --command-write "..."
+
+The traffic summary scales each counter by what it reads for a plain streaming kernel of known
+size in the same run (bench.py launches one: 256 MiB read, 256 MiB written), and records the
+SHA-256 of the kernel's source file so that a reader can tell when the counters have gone stale.
+"""
+import argparse
+import glob
+import hashlib
+import os
+import sqlite3
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+# launch label (as timed by the library) -> (kernel symbol substring, source file in csrc/)
+KERNELS = {
+    "llr_gram": ("k_gram<64>", "llr.hip"),
+    "llr_tridiag": ("k_tridiag", "llr.hip"),
+    "llr_coef": ("k_coef<64>", "llr.hip"),
+    "llr_xupdate": ("k_xupdate<true>", "llr.hip"),
+    "llr_backxf": ("k_backxf", "llr.hip"),
+    "lap_quad": ("k_lap_quad_edges<64, 2>", "graph.hip"),
+    "nufft_col_adj": ("k_col_adj", "nufft.hip"),
+    "nufft_col_fwd": ("k_col_fwd", "nufft.hip"),
+    "nufft_row_fwd": ("k_row_fwd", "nufft.hip"),
+    "nufft_row_adj": ("k_row_adj", "nufft.hip"),
+    "match_subspace": ("k_match_sub", "subspace.hip"),
+    "graph_knn": ("k_knn", "graph.hip"),
+}
+CALIBRATION = "neg_kernel"          # the streaming kernel's symbol substring
+CALIBRATION_BYTES = 1 << 28         # read, and the same written
+
+
+def _db(path):
+    if os.path.isfile(path):
+        return sqlite3.connect(path)
+    hits = sorted(glob.glob(os.path.join(path, "**", "*_results.db"), recursive=True))
+    if not hits:
+        raise FileNotFoundError("no rocprofv3 *_results.db under " + path)
+    return sqlite3.connect(hits[0])
+
+
+def _short(name, n=70):
+    name = name.split("(")[0]
+    for pre in ("void ", "mrf::"):
+        name = name.replace(pre, "")
+    return name if len(name) <= n else name[:n - 3] + "..."
+
+
+def kernel_stats(db):
+    """[(name, calls, total_ms, avg_us, min_us, max_us)] by total time, descending."""
+    c = _db(db)
+    rows = c.execute("select name, count(*), sum(duration), avg(duration), min(duration), max(duration) "
+                     "from kernels group by name").fetchall()
+    out = [(n, k, t / 1e6, a / 1e3, lo / 1e3, hi / 1e3) for n, k, t, a, lo, hi in rows]
+    return sorted(out, key=lambda r: -r[2])
+
+
+def counter_per_dispatch(db, counter):
+    """{kernel name: (mean value per dispatch, dispatches)} for one counter."""
+    c = _db(db)
+    rows = c.execute("select kernel_name, avg(value), count(*) from counters_collection where counter_name = ? "
+                     "group by kernel_name", (counter,)).fetchall()
+    return {n: (v, k) for n, v, k in rows}
+
+
+def _match(table, sub):
+    hits = [(n, v) for n, v in table.items() if sub in n]
+    if not hits:
+        raise KeyError("no kernel matching %r" % sub)
+    if len(hits) > 1:
+        hits.sort(key=lambda nv: len(nv[0]))
+    return hits[0]
+
+
+def source_sha(src):
+    with open(os.path.join(CSRC, src), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def write_stats(db, out, command, top=30):
+    rows = kernel_stats(db)
+    total = sum(r[2] for r in rows)
+    lines = ["# rocprofv3 kernel trace statistics", "command: " + command, "",
+             "%-72s %7s %10s %10s %10s %10s %6s" % ("kernel", "calls", "total_ms", "avg_us", "min_us", "max_us", "pct")]
+    for n, k, t, a, lo, hi in rows[:top]:
+        lines.append("%-72s %7d %10.3f %10.2f %10.2f %10.2f %6.2f" % (_short(n), k, t, a, lo, hi, 100.0 * t / total))
+    lines.append("")
+    with open(out, "w") as f:
+        f.write("\n".join(lines))
+
+
+def write_traffic(fetch_db, write_db, label, out, command_fetch, command_write):
+    sym, src = KERNELS[label]
+    fetch = counter_per_dispatch(fetch_db, "FETCH_SIZE")
+    write = counter_per_dispatch(write_db, "WRITE_SIZE")
+    kname, (fk, nd) = _match(fetch, sym)
+    _, (wk, _) = _match(write, sym)
+    _, (cfk, _) = _match(fetch, CALIBRATION)
+    _, (cwk, _) = _match(write, CALIBRATION)
+    fscale = CALIBRATION_BYTES / (cfk * 1024.0)
+    wscale = CALIBRATION_BYTES / (cwk * 1024.0)
+    hbm = fk * 1024.0 * fscale + wk * 1024.0 * wscale
+    lines = ["# HBM traffic of one launch from rocprofv3 counters (KiB per dispatch)",
+             "kernel: " + label, "symbol: " + _short(kname, 120), "source: csrc/" + src,
+             "source_sha256: " + source_sha(src), "dispatches: %d" % nd,
+             "fetch_kib_per_dispatch: %.1f" % fk, "write_kib_per_dispatch: %.1f" % wk,
+             "calibration_kernel: torch neg (%d bytes read, %d written)" % (CALIBRATION_BYTES, CALIBRATION_BYTES),
+             "calibration_fetch_kib: %.1f" % cfk, "calibration_write_kib: %.1f" % cwk,
+             "fetch_scale: %.4f" % fscale, "write_scale: %.4f" % wscale,
+             "hbm_bytes_per_launch: %.0f" % hbm,
+             "command_fetch: " + command_fetch, "command_write: " + command_write, ""]
+    with open(out, "w") as f:
+        f.write("\n".join(lines))
+
+
+def read_summary(path):
+    d = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                d[k.strip()] = v.strip()
+    return d
+
+
+def traffic_bytes(profiles_dir, label):
+    """HBM bytes per launch of `label` from profiles/<label>__*_traffic.txt, or None if absent or
+    if the kernel's source has changed since the counters were taken."""
+    if label not in KERNELS:
+        return None
+    hits = sorted(glob.glob(os.path.join(profiles_dir, label + "__*_traffic.txt")))
+    if not hits:
+        return None
+    d = read_summary(hits[0])
+    if d.get("source_sha256") != source_sha(KERNELS[label][1]):
+        return None
+    return float(d["hbm_bytes_per_launch"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("--db", required=True)
+    a.add_argument("--out", required=True)
+    a.add_argument("--command", required=True)
+    b = sub.add_parser("traffic")
+    b.add_argument("--fetch", required=True)
+    b.add_argument("--write", required=True)
+    b.add_argument("--kernel", required=True)
+    b.add_argument("--out", required=True)
+    b.add_argument("--command-fetch", required=True)
+    b.add_argument("--command-write", required=True)
+    args = ap.parse_args()
+    if args.cmd == "stats":
+        write_stats(args.db, args.out, args.command)
+    else:
+        write_traffic(args.fetch, args.write, args.kernel, args.out, args.command_fetch, args.command_write)
+
+
+if __name__ == "__main__":
+    main()
