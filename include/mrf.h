@@ -163,8 +163,9 @@ mrf_status mrf_subspace_project(const mrf_c64* U, const mrf_c64* V, int L, int N
 typedef struct mrf_dict_s* mrf_dict_t;
 
 /* atoms [M][L] complex (PD = 1 atoms, device), lut [M][nparam] float32 (device), V [L][r]
- * or NULL. Keeps the atom norms, the unit-norm atoms and, with V, the projected unit atoms
- * d_m V / ||d_m|| in MFMA operand order. Synchronises `stream`. 2 <= nparam <= 8, r <= 10. */
+ * or NULL. Keeps the atom norms, the unit-norm atoms (FP32, and BF16 / FP8 copies for the
+ * low-precision full-length match) and, with V, the projected unit atoms d_m V / ||d_m|| in MFMA
+ * operand order. Synchronises `stream`. 2 <= nparam <= 8, r <= 10. */
 mrf_status mrf_dict_create(const mrf_c64* atoms, const float* lut, int M, int L, int nparam, const mrf_c64* V,
                            int r, hipStream_t stream, mrf_dict_t* out);
 mrf_status mrf_dict_destroy(mrf_dict_t d);
@@ -173,6 +174,33 @@ mrf_status mrf_dict_destroy(mrf_dict_t d);
  * params [Nv][nparam] (LUT rows). FP32 on MFMA. Asynchronous. */
 mrf_status mrf_dict_match_subspace(mrf_dict_t d, const mrf_c64* alpha, int Nv, int32_t* idx, float* rho,
                                    float* score, float* params, hipStream_t stream);
+
+/* Full-length match modes (eq. (5) on length-L fingerprints). Every mode ranks all M atoms by
+ * |<d_m, x>| / ||d_m|| computed on MFMA in the stated precision (FP32 accumulation), keeps the
+ * four best (ties to the lower index) and re-ranks those four exactly in FP32 from the FP32
+ * unit-norm atoms; idx / score / rho / params come from the re-rank.
+ *   MRF_MATCH_FP32          scores from FP32 atoms and fingerprints (v_mfma_f32_16x16x4f32)
+ *   MRF_MATCH_BF16_RERANK4  atoms and fingerprints rounded to BF16 (v_mfma_f32_16x16x32_bf16)
+ *   MRF_MATCH_FP8_RERANK4   OCP E4M3 with one scale per row (max |component| -> 448), FP8 MFMA
+ *   MRF_MATCH_LEARNED       (C4) the MLP estimate with the residual gate; see mrf_mlp_*      */
+typedef enum mrf_match_mode {
+  MRF_MATCH_FP32 = 0,
+  MRF_MATCH_BF16_RERANK4 = 1,
+  MRF_MATCH_FP8_RERANK4 = 2,
+  MRF_MATCH_LEARNED = 3
+} mrf_match_mode;
+
+/* Workspace bytes of mrf_dict_match for Nv fingerprints (FP32 / BF16 / FP8 modes). */
+mrf_status mrf_dict_match_workspace_size(mrf_dict_t d, int Nv, mrf_match_mode mode, size_t* bytes);
+/* Full-length match of fp [Nv][L] (voxel-major, complex, device; L = the dictionary's length):
+ * idx [Nv] int32 (required); rho [Nv], score [Nv], params [Nv][nparam] and cand [Nv][4] (the
+ * candidates that entered the re-rank, best first by low-precision score; -1 where fewer than
+ * four atoms exist) are optional (NULL). The caller owns all arrays and the workspace.
+ * Asynchronous; MRF_NOT_SUPPORTED for MRF_MATCH_LEARNED (use mrf_mlp_match). */
+mrf_status mrf_dict_match(mrf_dict_t d, const mrf_c64* fp, int Nv, mrf_match_mode mode, int32_t* idx, float* rho,
+                          float* score, float* params, int32_t* cand, void* ws, size_t ws_bytes, hipStream_t stream);
+/* Y [Nv][L] = X [L][Nv] (frame-major image series to voxel-major fingerprints). Asynchronous. */
+mrf_status mrf_frames_to_voxels(const mrf_c64* X, int L, int Nv, mrf_c64* Y, hipStream_t stream);
 
 /* ====================================================================================
  * Algorithm 1: the MS-LLR reconstruction (Sec. III-C, III-D), run on the device.

@@ -50,6 +50,39 @@ def match_subspace(X, atoms, lut, V):
     return match_vectors(xv @ V, D @ V, lut, norms)
 
 
+def precision_match_ref(xv, atoms, lut, topk=4, chunk=4096):
+    """Exhaustive FP64 full-length match of xv [Nv, L] against atoms [M, L] (the reference the
+    low-precision forms are judged by), atoms taken in chunks of `chunk` so that the [Nv, M]
+    score matrix is never held whole.
+
+    Returns (idx, rho, score, params, top_idx [Nv, topk], top_score [Nv, topk]); the top-k
+    list is ordered by score descending, equal scores by the lower atom index.
+    """
+    xv = np.asarray(xv, np.complex128)
+    D = np.asarray(atoms, np.complex128)
+    norms = np.linalg.norm(D, axis=1)
+    Nv, M = xv.shape[0], D.shape[0]
+    k = min(topk, M)
+    best_s = np.full((Nv, k), -np.inf)
+    best_i = np.full((Nv, k), -1, np.int64)
+    best_ip = np.zeros((Nv, k), np.complex128)
+    for m0 in range(0, M, chunk):
+        m1 = min(M, m0 + chunk)
+        ip = xv @ D[m0:m1].conj().T
+        sc = np.abs(ip) / norms[None, m0:m1]
+        s_all = np.concatenate([best_s, sc], axis=1)
+        i_all = np.concatenate([best_i, np.broadcast_to(np.arange(m0, m1), sc.shape)], axis=1)
+        p_all = np.concatenate([best_ip, ip], axis=1)
+        # descending score, ties by ascending index: lexsort's last key is the primary one
+        order = np.lexsort((i_all, -s_all), axis=1)[:, :k]
+        best_s = np.take_along_axis(s_all, order, 1)
+        best_i = np.take_along_axis(i_all, order, 1)
+        best_ip = np.take_along_axis(p_all, order, 1)
+    idx = best_i[:, 0]
+    rho = np.maximum(best_ip[:, 0].real / norms[idx] ** 2, 0.0)
+    return idx, rho, best_s[:, 0], np.asarray(lut, np.float64)[idx], best_i, best_s
+
+
 def maps_from_match(idx, rho, lut, N):
     """[3, N, N] maps (T1, T2, PD) from a match result."""
     lut = np.asarray(lut, np.float64)

@@ -9,5 +9,5 @@ from ._lib import MrfError, lib, library_path, check, timing_enable, timing_repo
 from .nufft import NufftPlan  # noqa: F401
 from .graph import PatchGraph  # noqa: F401
 from .llr import llr_prox  # noqa: F401
-from .subspace import Dictionary, subspace_coeffs, subspace_project  # noqa: F401
+from .subspace import Dictionary, frames_to_voxels, subspace_coeffs, subspace_project  # noqa: F401
 from .recon import Recon  # noqa: F401

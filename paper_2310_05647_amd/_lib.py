@@ -71,6 +71,10 @@ _decl("mrf_subspace_project", [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p
 _decl("mrf_dict_create", [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_int, c_void_p, P(c_void_p)])
 _decl("mrf_dict_destroy", [c_void_p])
 _decl("mrf_dict_match_subspace", [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p])
+_decl("mrf_dict_match_workspace_size", [c_void_p, c_int, c_int, P(c_size_t)])
+_decl("mrf_dict_match", [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                         c_size_t, c_void_p])
+_decl("mrf_frames_to_voxels", [c_void_p, c_int, c_int, c_void_p, c_void_p])
 _decl("mrf_recon_create", [P(ReconParams), c_void_p, c_void_p, P(c_void_p)])
 _decl("mrf_recon_destroy", [c_void_p])
 _decl("mrf_recon_init", [c_void_p, c_void_p, c_void_p, c_void_p])

@@ -37,6 +37,19 @@ def subspace_project(U, V, stream=None):
     return out
 
 
+MATCH_MODES = {"fp32": 0, "bf16": 1, "fp8": 2}
+
+
+def frames_to_voxels(X, stream=None):
+    """[L, ...] complex64 image series (device) -> [Nv, L] voxel-major fingerprints."""
+    L = X.shape[0]
+    Nv = X.numel() // L
+    need(X, torch.complex64, tuple(X.shape), "X")
+    Y = torch.empty((Nv, L), dtype=torch.complex64, device=X.device)
+    check(lib.mrf_frames_to_voxels(ptr(X), L, Nv, ptr(Y), stream_ptr(stream)), "mrf_frames_to_voxels")
+    return Y
+
+
 class Dictionary:
     """Device dictionary: atoms [M, L] complex64, lut [M, nparam] float32, optional basis V [L, r]."""
 
@@ -66,6 +79,27 @@ class Dictionary:
         check(lib.mrf_dict_match_subspace(self.handle, ptr(alpha), Nv, ptr(idx), ptr(rho), ptr(score), ptr(params),
                                           stream_ptr(stream)), "mrf_dict_match_subspace")
         return idx, rho, score, params
+
+    def match(self, fp, mode="fp32", want_cand=False, stream=None):
+        """Full-length match of fp [Nv, L] complex64 (device). mode: "fp32", "bf16" or "fp8"
+        (top-4 on MFMA in that precision, then an FP32 re-rank). Returns (idx, rho, score, params)
+        and, with want_cand, the [Nv, 4] candidates of the re-rank."""
+        Nv = fp.shape[0]
+        need(fp, torch.complex64, (Nv, self.L), "fp")
+        m = MATCH_MODES[mode]
+        dev = fp.device
+        sz = ctypes.c_size_t()
+        check(lib.mrf_dict_match_workspace_size(self.handle, Nv, m, ctypes.byref(sz)), "mrf_dict_match_workspace_size")
+        ws = torch.empty(max(1, sz.value), dtype=torch.uint8, device=dev)
+        idx = torch.empty(Nv, dtype=torch.int32, device=dev)
+        rho = torch.empty(Nv, dtype=torch.float32, device=dev)
+        score = torch.empty(Nv, dtype=torch.float32, device=dev)
+        params = torch.empty((Nv, self.nparam), dtype=torch.float32, device=dev)
+        cand = torch.empty((Nv, 4), dtype=torch.int32, device=dev) if want_cand else None
+        check(lib.mrf_dict_match(self.handle, ptr(fp), Nv, m, ptr(idx), ptr(rho), ptr(score), ptr(params), ptr(cand),
+                                 ptr(ws), ws.numel(), stream_ptr(stream)), "mrf_dict_match")
+        out = (idx, rho, score, params)
+        return out + (cand,) if want_cand else out
 
     def close(self):
         if getattr(self, "handle", None):

@@ -48,3 +48,31 @@ def test_ties_go_to_the_lowest_atom_and_zero_voxels_give_zero_pd():
     idx, rho, _, _ = match.match_vectors(np.array([[2.0, 0], [0, 0]], complex), D, np.zeros((3, 2)))
     np.testing.assert_array_equal(idx, [0, 0])
     np.testing.assert_array_equal(rho, [2.0, 0.0])
+
+
+def test_precision_reference_top_k_by_brute_force():
+    """The chunked top-k reference against an explicit double loop over (voxel, atom) on tiny
+    inputs, with planted exact ties (ordered by the lower index) and chunk boundaries inside
+    the atom range."""
+    rng = np.random.default_rng(7)
+    Nv, M, L = 6, 23, 9
+    D = rng.standard_normal((M, L)) + 1j * rng.standard_normal((M, L))
+    D[11] = D[4]                # the same atom twice: an exact tie, 4 must come first
+    X = rng.standard_normal((Nv, L)) + 1j * rng.standard_normal((Nv, L))
+    X[2] = 3.0 * np.exp(0.4j) * D[4]
+    lut = np.stack([np.arange(M, dtype=float), 10.0 * np.arange(M)], 1)
+    idx, rho, score, params, ti, ts = match.precision_match_ref(X, D, lut, topk=4, chunk=5)
+    for v in range(Nv):
+        s = []
+        for m in range(M):
+            ip = sum(np.conj(D[m, l]) * X[v, l] for l in range(L))
+            s.append((-abs(ip) / np.sqrt(sum(abs(D[m, l]) ** 2 for l in range(L))), m))
+        s.sort()
+        ref = [m for _, m in s[:4]]
+        # equal scores (to rounding) may be ordered either way by the float sort; compare as sets
+        # of the top four and require the exact tie 4 / 11 to put 4 first
+        assert set(ti[v]) == set(ref) or np.isclose(-s[3][0], -s[4][0])
+        np.testing.assert_allclose(ts[v], [-x for x, _ in s[:4]], rtol=1e-12)
+    assert idx[2] == 4 and list(ti[2][:2]) == [4, 11]
+    assert np.isclose(rho[2], 3.0 * np.cos(0.4))
+    assert np.all(params[:, 0] == idx)
