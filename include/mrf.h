@@ -203,6 +203,76 @@ mrf_status mrf_dict_match(mrf_dict_t d, const mrf_c64* fp, int Nv, mrf_match_mod
 mrf_status mrf_frames_to_voxels(const mrf_c64* X, int L, int Nv, mrf_c64* Y, hipStream_t stream);
 
 /* ====================================================================================
+ * Learned matching (the library's own addition beside eq. (5); the paper cites learned
+ * signal-to-parameter mappings as related work, Sec. I). An MLP maps the features of the
+ * subspace coefficients alpha = x V (r complex values, normalised, phase-rotated so alpha_0 is
+ * real >= 0: 2 r reals) to the standardised (log T1, log T2); ReLU hidden layers.
+ * Training batches are drawn on the device: sample i of step s uses Philox4x32-10 with key
+ * `seed` and counter (i, s, c, 0) for the atom, the phase, the SNR in [snr_lo, snr_hi] dB and the
+ * Box-Muller noise (variance 10^(-SNR/10) / L per coefficient) added to d_m V / ||d_m||. Loss:
+ * mean squared error; Adam with bias correction; optional cosine decay of lr over total_steps.
+ * GEMMs on MFMA in FP32 or BF16 (operands rounded to nearest even), FP32 accumulation and
+ * FP32 master weights. Parameters are one flat FP32 array [W1 b1 W2 b2 ...], W_l [out][in].
+ * The gate: k* = the grid atom nearest to the prediction in (log T1, log T2); residual =
+ * 1 - |<d_k* V / ||d_k*||, alpha / ||alpha||>|; voxels with residual > theta take the exhaustive
+ * subspace match (mrf_dict_match_subspace) instead.
+ * ==================================================================================== */
+typedef struct mrf_mlp_s* mrf_mlp_t;
+
+typedef struct mrf_mlp_train_cfg {
+  int batch;          /* samples per step                                                  */
+  int steps;          /* steps run by this call                                            */
+  int first_step;     /* step index of the first one (the counter of the batch generator)   */
+  int total_steps;    /* length of the cosine schedule (<= 0: first_step + steps)           */
+  float lr, beta1, beta2, eps;
+  int cosine;         /* 1: lr_s = lr (1 + cos(pi s / total_steps)) / 2; 0: constant lr      */
+  float snr_lo, snr_hi;
+  uint64_t seed;
+  int bf16;           /* 1: BF16 GEMM operands, 0: FP32                                     */
+} mrf_mlp_train_cfg;
+
+/* n_in = 2 r inputs, n_hidden_layers layers of `hidden` units, n_out = 2 outputs; weights
+ * He-normal from Philox (key seed, counter (index, layer, 0x48e, 0)), biases 0. Synchronises. */
+mrf_status mrf_mlp_create(int n_in, int hidden, int n_hidden_layers, int n_out, uint64_t seed, hipStream_t stream,
+                          mrf_mlp_t* out);
+mrf_status mrf_mlp_destroy(mrf_mlp_t mlp);
+mrf_status mrf_mlp_param_count(mrf_mlp_t mlp, size_t* n);
+/* Device pointers to the library-owned flat parameter and gradient arrays (FP32, param_count
+ * values each); the caller may read or overwrite them between calls on the same stream. */
+mrf_status mrf_mlp_params(mrf_mlp_t mlp, float** params, float** grads);
+mrf_status mrf_mlp_reset_optimizer(mrf_mlp_t mlp, hipStream_t stream);
+/* The (T1, T2) grid of the gate: n1 T1 values log_t1_0 + i dlog_t1, n2 T2 values likewise;
+ * grid_index [n1][n2] (device int32) the atom of each point or -1. Synchronises. */
+mrf_status mrf_mlp_set_grid(mrf_mlp_t mlp, int n1, double log_t1_0, double dlog_t1, int n2, double log_t2_0,
+                            double dlog_t2, const int32_t* grid_index, hipStream_t stream);
+/* Mean and standard deviation of log T1, log T2 over the dictionary (the target scaling);
+ * stats_host [4] = (mean1, mean2, std1, std2) if not NULL (synchronises then). */
+mrf_status mrf_mlp_target_stats(mrf_mlp_t mlp, mrf_dict_t d, double* stats_host, hipStream_t stream);
+mrf_status mrf_mlp_train_workspace_size(mrf_mlp_t mlp, int batch, size_t* bytes);
+/* One synthetic batch: z [batch][n_in], t [batch][2] (standardised targets), m [batch] or NULL. */
+mrf_status mrf_mlp_synth(mrf_mlp_t mlp, mrf_dict_t d, uint64_t seed, int step, int batch, float snr_lo, float snr_hi,
+                         float* z, float* t, int32_t* m, hipStream_t stream);
+/* y [batch][2] = network(z [batch][n_in]); workspace of mrf_mlp_train_workspace_size(batch). */
+mrf_status mrf_mlp_forward(mrf_mlp_t mlp, const float* z, int batch, int bf16, float* y, void* ws, size_t ws_bytes,
+                           hipStream_t stream);
+/* Loss (device float, may be NULL) and gradients (into the library's gradient array) of a batch. */
+mrf_status mrf_mlp_grads(mrf_mlp_t mlp, const float* z, const float* t, int batch, int bf16, float* loss, void* ws,
+                         size_t ws_bytes, hipStream_t stream);
+/* One Adam update of the parameters from the current gradients. */
+mrf_status mrf_mlp_adam_step(mrf_mlp_t mlp, float lr, float beta1, float beta2, float eps, hipStream_t stream);
+/* cfg->steps steps of synthesis, forward, backward and Adam; losses [steps] (device) or NULL. */
+mrf_status mrf_mlp_train(mrf_mlp_t mlp, mrf_dict_t d, const mrf_mlp_train_cfg* cfg, float* losses, void* ws,
+                         size_t ws_bytes, hipStream_t stream);
+mrf_status mrf_mlp_match_workspace_size(mrf_mlp_t mlp, int Nv, size_t* bytes);
+/* Learned match of alpha [Nv][r]: idx [Nv] (k*, or the exhaustive match's atom where gated out),
+ * t12 [Nv][2] (the network's T1, T2, or the exhaustive match's LUT values), rho [Nv], resid [Nv],
+ * fallback [Nv] (1 where gated out) optional; n_fallback (host) optional. Synchronises once
+ * (the fallback count). */
+mrf_status mrf_mlp_match(mrf_mlp_t mlp, mrf_dict_t d, const mrf_c64* alpha, int Nv, int bf16, float theta, int32_t* idx,
+                         float* t12, float* rho, float* resid, int32_t* fallback, int* n_fallback, void* ws,
+                         size_t ws_bytes, hipStream_t stream);
+
+/* ====================================================================================
  * Algorithm 1: the MS-LLR reconstruction (Sec. III-C, III-D), run on the device.
  *   X^0 = A^H b (or a given X0), M^0 = Phi_D(X^0), L^0 = mrf_knn_laplacian(M^0),
  *   lambda1 = lambda1^0 max(L); per iteration the gradient step of eq. (15) with the

@@ -11,3 +11,4 @@ from .graph import PatchGraph  # noqa: F401
 from .llr import llr_prox  # noqa: F401
 from .subspace import Dictionary, frames_to_voxels, subspace_coeffs, subspace_project  # noqa: F401
 from .recon import Recon  # noqa: F401
+from .mlp import MLP  # noqa: F401

@@ -28,6 +28,12 @@ class ReconParams(ctypes.Structure):
                 ("sigma2", c_float), ("n_max", c_int), ("tol", ctypes.c_double)]
 
 
+class MlpTrainCfg(ctypes.Structure):
+    _fields_ = [("batch", c_int), ("steps", c_int), ("first_step", c_int), ("total_steps", c_int), ("lr", c_float),
+                ("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("cosine", c_int), ("snr_lo", c_float),
+                ("snr_hi", c_float), ("seed", ctypes.c_uint64), ("bf16", c_int)]
+
+
 MAX_ITERS = 512
 _D = ctypes.c_double * (MAX_ITERS + 1)
 
@@ -75,6 +81,24 @@ _decl("mrf_dict_match_workspace_size", [c_void_p, c_int, c_int, P(c_size_t)])
 _decl("mrf_dict_match", [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                          c_size_t, c_void_p])
 _decl("mrf_frames_to_voxels", [c_void_p, c_int, c_int, c_void_p, c_void_p])
+_u64 = ctypes.c_uint64
+_decl("mrf_mlp_create", [c_int, c_int, c_int, c_int, _u64, c_void_p, P(c_void_p)])
+_decl("mrf_mlp_destroy", [c_void_p])
+_decl("mrf_mlp_param_count", [c_void_p, P(c_size_t)])
+_decl("mrf_mlp_params", [c_void_p, P(c_void_p), P(c_void_p)])
+_decl("mrf_mlp_reset_optimizer", [c_void_p, c_void_p])
+_decl("mrf_mlp_set_grid", [c_void_p, c_int, ctypes.c_double, ctypes.c_double, c_int, ctypes.c_double, ctypes.c_double,
+                           c_void_p, c_void_p])
+_decl("mrf_mlp_target_stats", [c_void_p, c_void_p, c_void_p, c_void_p])
+_decl("mrf_mlp_train_workspace_size", [c_void_p, c_int, P(c_size_t)])
+_decl("mrf_mlp_synth", [c_void_p, c_void_p, _u64, c_int, c_int, c_float, c_float, c_void_p, c_void_p, c_void_p, c_void_p])
+_decl("mrf_mlp_forward", [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_size_t, c_void_p])
+_decl("mrf_mlp_grads", [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_size_t, c_void_p])
+_decl("mrf_mlp_adam_step", [c_void_p, c_float, c_float, c_float, c_float, c_void_p])
+_decl("mrf_mlp_train", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p])
+_decl("mrf_mlp_match_workspace_size", [c_void_p, c_int, P(c_size_t)])
+_decl("mrf_mlp_match", [c_void_p, c_void_p, c_void_p, c_int, c_int, c_float, c_void_p, c_void_p, c_void_p, c_void_p,
+                        c_void_p, P(c_int), c_void_p, c_size_t, c_void_p])
 _decl("mrf_recon_create", [P(ReconParams), c_void_p, c_void_p, P(c_void_p)])
 _decl("mrf_recon_destroy", [c_void_p])
 _decl("mrf_recon_init", [c_void_p, c_void_p, c_void_p, c_void_p])

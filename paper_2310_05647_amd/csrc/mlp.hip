@@ -1,0 +1,768 @@
+// Learned matching: an MLP from subspace coefficients to (log T1, log T2), trained and run on the
+// GPU, with a residual gate that sends poorly explained voxels to the exhaustive match.
+//
+// The paper's matching is the exhaustive search of eq. (5) (Sec. II-B); it cites learned
+// signal-to-parameter mappings as related work. This form of it is the library's own:
+//   features  alpha = x V (r complex), alpha / ||alpha||, rotated so that alpha_0 is real >= 0,
+//             z = (Re alpha, Im alpha) in R^{2r}
+//   network   h_l = relu(W_l h_{l-1} + b_l) (hidden layers), y = W_L h_{L-1} + b_L, y the
+//             standardised (log T1, log T2): (log T - mean) / std over the dictionary atoms
+//   loss      mean over batch and outputs of (y - t)^2; Adam with bias correction, cosine lr
+//   batches   sample i of step s: Philox4x32-10 with key = seed and counter (i, s, c, 0) gives the
+//             atom m = mulhi32(u0, M), the phase 2 pi (u1 + 1/2) 2^-32, the SNR uniform in
+//             [snr_lo, snr_hi] dB from u2, and (c = 1, 2, ...) Box-Muller normals for complex noise
+//             of variance 10^(-SNR/10) / L per coefficient (exact in distribution in the subspace:
+//             the columns of V are orthonormal); alpha = exp(i phase) d_m V / ||d_m|| + noise
+//   gate      k* = the grid atom nearest to the prediction in (log T1, log T2); residual =
+//             1 - |<d_k* V / ||d_k*||, alpha / ||alpha||>|; residual > theta -> exhaustive match.
+//
+// GEMMs: one MFMA kernel with 64 x 64 output tiles (4 waves of 32 x 32), K staged through LDS in
+// chunks of 32 from either operand layout (K-contiguous or K-strided), in FP32
+// (v_mfma_f32_16x16x4f32) or BF16 (operands rounded to nearest-even in registers,
+// v_mfma_f32_16x16x32_bf16), FP32 accumulation; epilogues for bias, ReLU and the ReLU mask of the
+// backward pass; split-K with a fixed-order reduction for the weight gradients (K = batch).
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.hpp"
+#include "dict.hpp"
+
+struct mrf_mlp_s {
+  int nin, hid, nhl, nout;      // input width, hidden width, hidden layers, outputs
+  int nl;                       // layers = nhl + 1
+  std::vector<size_t> offW, offb;
+  std::vector<int> lin, lout;
+  size_t np;                    // parameter count
+  float *p, *g, *m, *v;         // parameters, gradients, Adam moments (flat, FP32)
+  int t;                        // Adam step count
+  double *stats;                // device [4]: mean(log T1), mean(log T2), std(log T1), std(log T2)
+  bool have_stats;
+  // log-spaced (T1, T2) grid for the gate
+  int n1, n2;
+  double l1_0, dl1, l2_0, dl2;
+  int *gidx, *i2max;            // [n1][n2] atom index (or -1), [n1] largest kept T2 index
+};
+
+namespace mrf {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------------------ Philox4x32-10
+// Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3" (SC'11): ten rounds
+// of two 32x32 -> 64-bit multiplies with the Weyl key schedule.
+struct u4 {
+  unsigned x, y, z, w;
+};
+__device__ inline u4 philox(u4 c, unsigned k0, unsigned k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const unsigned long long p0 = (unsigned long long)0xD2511F53u * c.x;
+    const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * c.z;
+    const unsigned hi0 = (unsigned)(p0 >> 32), lo0 = (unsigned)p0;
+    const unsigned hi1 = (unsigned)(p1 >> 32), lo1 = (unsigned)p1;
+    c = u4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+__device__ inline float u01(unsigned u) { return ((float)u + 0.5f) * 2.3283064365386963e-10f; }
+
+constexpr int kMaxR = 16;
+
+// z [B][2r] features and t [B][2] standardised targets of a synthetic training batch; m [B].
+__global__ __launch_bounds__(256) void k_synth(const cf* __restrict__ dhr, int M, int r, const float* __restrict__ lut,
+                                               int nparam, const double* __restrict__ stats, unsigned k0, unsigned k1,
+                                               unsigned step, int B, float snr_lo, float snr_hi, float L,
+                                               float* __restrict__ z, float* __restrict__ t, int* __restrict__ mo) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= B) return;
+  const u4 u = philox(u4{(unsigned)i, step, 0u, 0u}, k0, k1);
+  const int m = (int)(((unsigned long long)u.x * (unsigned)M) >> 32);
+  const float phi = 6.283185307179586f * u01(u.y);
+  const float snr = snr_lo + (snr_hi - snr_lo) * u01(u.z);
+  const float sig = sqrtf(powf(10.f, -snr / 10.f) / L) * 0.70710678118654752f;
+  float gs[2 * kMaxR + 4];
+  const int nc = (2 * r + 3) / 4;
+  for (int c = 1; c <= nc; ++c) {
+    const u4 v = philox(u4{(unsigned)i, step, (unsigned)c, 0u}, k0, k1);
+    const float r0 = sqrtf(-2.f * logf(u01(v.x))), a0 = 6.283185307179586f * u01(v.y);
+    const float r1 = sqrtf(-2.f * logf(u01(v.z))), a1 = 6.283185307179586f * u01(v.w);
+    gs[4 * (c - 1) + 0] = r0 * cosf(a0);
+    gs[4 * (c - 1) + 1] = r0 * sinf(a0);
+    gs[4 * (c - 1) + 2] = r1 * cosf(a1);
+    gs[4 * (c - 1) + 3] = r1 * sinf(a1);
+  }
+  const float cp = cosf(phi), sp = sinf(phi);
+  float ar[kMaxR], ai[kMaxR], nrm = 0.f;
+  for (int k = 0; k < r; ++k) {
+    const cf d = dhr[(size_t)m * r + k];
+    ar[k] = cp * d.x - sp * d.y + gs[k] * sig;
+    ai[k] = sp * d.x + cp * d.y + gs[r + k] * sig;
+    nrm += ar[k] * ar[k] + ai[k] * ai[k];
+  }
+  nrm = sqrtf(nrm);
+  const float a0m = sqrtf(ar[0] * ar[0] + ai[0] * ai[0]);
+  const float c0 = a0m > 0.f ? ar[0] / a0m : 1.f, s0 = a0m > 0.f ? -ai[0] / a0m : 0.f;   // exp(-i angle)
+  const float inv = nrm > 0.f ? 1.f / nrm : 0.f;
+  for (int k = 0; k < r; ++k) {
+    z[(size_t)i * 2 * r + k] = (ar[k] * c0 - ai[k] * s0) * inv;
+    z[(size_t)i * 2 * r + r + k] = (ar[k] * s0 + ai[k] * c0) * inv;
+  }
+  t[(size_t)i * 2 + 0] = (float)((log((double)lut[(size_t)m * nparam + 0]) - stats[0]) / stats[2]);
+  t[(size_t)i * 2 + 1] = (float)((log((double)lut[(size_t)m * nparam + 1]) - stats[1]) / stats[3]);
+  if (mo) mo[i] = m;
+}
+
+// features of measured coefficients alpha [Nv][r]
+__global__ __launch_bounds__(256) void k_features(const cf* __restrict__ alpha, int Nv, int r, float* __restrict__ z) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= Nv) return;
+  const cf* a = alpha + (size_t)i * r;
+  float nrm = 0.f;
+  for (int k = 0; k < r; ++k) nrm += a[k].x * a[k].x + a[k].y * a[k].y;
+  nrm = sqrtf(nrm);
+  const float a0m = sqrtf(a[0].x * a[0].x + a[0].y * a[0].y);
+  const float c0 = a0m > 0.f ? a[0].x / a0m : 1.f, s0 = a0m > 0.f ? -a[0].y / a0m : 0.f;
+  const float inv = nrm > 0.f ? 1.f / nrm : 0.f;
+  for (int k = 0; k < r; ++k) {
+    z[(size_t)i * 2 * r + k] = (a[k].x * c0 - a[k].y * s0) * inv;
+    z[(size_t)i * 2 * r + r + k] = (a[k].x * s0 + a[k].y * c0) * inv;
+  }
+}
+
+// mean and standard deviation of log T1, log T2 over the atoms (one block, fixed order)
+__global__ __launch_bounds__(256) void k_target_stats(const float* __restrict__ lut, int M, int nparam,
+                                                      double* __restrict__ stats) {
+  __shared__ double red[4][256];
+  const int t = threadIdx.x;
+  double s1 = 0, s2 = 0, q1 = 0, q2 = 0;
+  for (int m = t; m < M; m += 256) {
+    const double a = log((double)lut[(size_t)m * nparam]), b = log((double)lut[(size_t)m * nparam + 1]);
+    s1 += a; s2 += b; q1 += a * a; q2 += b * b;
+  }
+  red[0][t] = s1; red[1][t] = s2; red[2][t] = q1; red[3][t] = q2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o)
+      for (int k = 0; k < 4; ++k) red[k][t] += red[k][t + o];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double m1 = red[0][0] / M, m2 = red[1][0] / M;
+    stats[0] = m1;
+    stats[1] = m2;
+    stats[2] = sqrt(fmax(red[2][0] / M - m1 * m1, 1e-300));
+    stats[3] = sqrt(fmax(red[3][0] / M - m2 * m2, 1e-300));
+  }
+}
+
+// ------------------------------------------------------------------ GEMM
+// C[m][n] (+)= sum_k A(m, k) B(k, n);  A(m, k) = A[m lda + k] (AK) or A[k lda + m] (AM);
+// B(k, n) = B[n ldb + k] (BK) or B[k ldb + n] (BN). Split-K slice z covers k in
+// [z ks, (z + 1) ks) and writes C + z M ldc.
+enum { LAY_K = 0, LAY_MN = 1 };
+enum { EPI_STORE = 0, EPI_BIAS_RELU = 1, EPI_BIAS = 2, EPI_MASK = 3 };
+constexpr int kG = 64, kGK = 32;
+
+__device__ inline unsigned bf16pair(float a, float b) {
+  const unsigned ua = __float_as_uint(a), ub = __float_as_uint(b);
+  const unsigned ra = (ua + 0x7fffu + ((ua >> 16) & 1u)) >> 16, rb = (ub + 0x7fffu + ((ub >> 16) & 1u)) >> 16;
+  return ra | (rb << 16);
+}
+
+template <bool BF16, int ALAY, int BLAY, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* __restrict__ A, int lda,
+                                              const float* __restrict__ B, int ldb, float* __restrict__ C, int ldc,
+                                              const float* __restrict__ bias, const float* __restrict__ mask, int mld,
+                                              int ks) {
+  __shared__ float As[kG][kGK + 1], Bs[kG][kGK + 1];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int wm = w >> 1, wn = w & 1, q = lane >> 4, n16 = lane & 15;
+  const int n0 = blockIdx.x * kG, m0 = blockIdx.y * kG;
+  const int kb = blockIdx.z * ks, ke = min(K, kb + ks);
+  C += (size_t)blockIdx.z * M * ldc;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = kb; k0 < ke; k0 += kGK) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kG * kGK / 256; ++j) {
+      const int idx = tid + 256 * j;
+      int r, c;
+      if (ALAY == LAY_K) { r = idx / kGK; c = idx % kGK; }
+      else { c = idx / kG; r = idx % kG; }
+      const int m = m0 + r, k = k0 + c;
+      As[r][c] = (m < M && k < ke) ? (ALAY == LAY_K ? A[(size_t)m * lda + k] : A[(size_t)k * lda + m]) : 0.f;
+      if (BLAY == LAY_K) { r = idx / kGK; c = idx % kGK; }
+      else { c = idx / kG; r = idx % kG; }
+      const int n = n0 + r, k2 = k0 + c;
+      Bs[r][c] = (n < N && k2 < ke) ? (BLAY == LAY_K ? B[(size_t)n * ldb + k2] : B[(size_t)k2 * ldb + n]) : 0.f;
+    }
+    __syncthreads();
+    if constexpr (BF16) {
+      bf16x8 av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const float* s = &As[wm * 32 + a * 16 + n16][8 * q];
+        const unsigned u[4] = {bf16pair(s[0], s[1]), bf16pair(s[2], s[3]), bf16pair(s[4], s[5]), bf16pair(s[6], s[7])};
+        av[a] = __builtin_bit_cast(bf16x8, make_uint4(u[0], u[1], u[2], u[3]));
+        const float* t = &Bs[wn * 32 + a * 16 + n16][8 * q];
+        const unsigned v[4] = {bf16pair(t[0], t[1]), bf16pair(t[2], t[3]), bf16pair(t[4], t[5]), bf16pair(t[6], t[7])};
+        bv[a] = __builtin_bit_cast(bf16x8, make_uint4(v[0], v[1], v[2], v[3]));
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int s = 0; s < kGK / 4; ++s) {
+        float av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          av[a] = As[wm * 32 + a * 16 + n16][4 * s + q];
+          bv[a] = Bs[wn * 32 + a * 16 + n16][4 * s + q];
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = m0 + wm * 32 + a * 16 + 4 * q + i, n = n0 + wn * 32 + b * 16 + n16;
+        if (m < M && n < N) {
+          float v = acc[a][b][i];
+          if (EPI == EPI_BIAS_RELU) v = fmaxf(v + bias[n], 0.f);
+          else if (EPI == EPI_BIAS) v += bias[n];
+          else if (EPI == EPI_MASK) v = mask[(size_t)m * mld + n] > 0.f ? v : 0.f;
+          C[(size_t)m * ldc + n] = v;
+        }
+      }
+}
+
+// out[i] = sum_s part[s n + i] (fixed order)
+__global__ __launch_bounds__(256) void k_reduce_slices(const float* __restrict__ part, int S, long n,
+                                                       float* __restrict__ out) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int k = 0; k < S; ++k) s += part[(size_t)k * n + i];
+  out[i] = s;
+}
+
+// db[n] = sum_b G[b][n]: block per 64 columns, 4 row phases, fixed-order tree
+__global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ G, int Bn, int N, float* __restrict__ db) {
+  __shared__ float red[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63), ph = threadIdx.x >> 6;
+  float s = 0.f;
+  if (c < N)
+    for (int b = ph; b < Bn; b += 4) s += G[(size_t)b * N + c];
+  red[ph][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (ph == 0 && c < N) db[c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+// g = 2 (y - t) / (B nout); per-block partial sums of (y - t)^2 into lpart
+__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const float* __restrict__ t, int n, float scale,
+                                              float* __restrict__ g, float* __restrict__ lpart) {
+  __shared__ float red[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  float d = 0.f;
+  if (i < n) {
+    d = y[i] - t[i];
+    g[i] = 2.f * d * scale;
+  }
+  red[threadIdx.x] = d * d;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
+}
+__global__ __launch_bounds__(256) void k_loss_final(const float* __restrict__ lpart, int nb, float scale,
+                                                    float* __restrict__ loss) {
+  __shared__ float red[256];
+  float s = 0.f;
+  for (int i = threadIdx.x; i < nb; i += 256) s += lpart[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[0] = red[0] * scale;
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                                              float* __restrict__ v, long n, float lr, float b1, float b2, float eps,
+                                              float c1, float c2) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// He-normal initialisation from Philox (counter (index, layer, 0x48e, 0)), zero biases
+__global__ __launch_bounds__(256) void k_init(float* __restrict__ W, long n, float sd, unsigned layer, unsigned k0,
+                                              unsigned k1) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const u4 u = philox(u4{(unsigned)i, layer, 0x48eu, 0u}, k0, k1);
+  W[i] = sd * sqrtf(-2.f * logf(u01(u.x))) * cosf(6.283185307179586f * u01(u.y));
+}
+
+// Gate: k* nearest grid atom to exp(y * std + mean), residual, rho; flags voxels above theta.
+__global__ __launch_bounds__(256) void k_gate(const float* __restrict__ y, const double* __restrict__ stats, int n1,
+                                              int n2, double l1_0, double dl1, double l2_0, double dl2,
+                                              const int* __restrict__ gidx, const int* __restrict__ i2max,
+                                              const cf* __restrict__ dhr, const float* __restrict__ norms,
+                                              const cf* __restrict__ alpha, int Nv, int r, float theta,
+                                              int* __restrict__ idx, float* __restrict__ t12, float* __restrict__ rho,
+                                              float* __restrict__ resid, int* __restrict__ fb, int* __restrict__ nfb,
+                                              int* __restrict__ fblist) {
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v >= Nv) return;
+  const double lt1 = (double)y[(size_t)v * 2] * stats[2] + stats[0];
+  const double lt2 = (double)y[(size_t)v * 2 + 1] * stats[3] + stats[1];
+  int i1 = (int)rint((lt1 - l1_0) / dl1), i2 = (int)rint((lt2 - l2_0) / dl2);
+  i1 = min(max(i1, 0), n1 - 1);
+  i2 = min(max(i2, 0), n2 - 1);
+  i2 = min(i2, i2max[i1]);
+  const int k = gidx[(size_t)i1 * n2 + i2];
+  const cf* a = alpha + (size_t)v * r;
+  const cf* d = dhr + (size_t)k * r;
+  float nr = 0.f, ipr = 0.f, ipi = 0.f;
+  for (int j = 0; j < r; ++j) {
+    nr += a[j].x * a[j].x + a[j].y * a[j].y;
+    ipr += d[j].x * a[j].x + d[j].y * a[j].y;
+    ipi += d[j].x * a[j].y - d[j].y * a[j].x;
+  }
+  nr = sqrtf(nr);
+  const float res = 1.f - sqrtf(ipr * ipr + ipi * ipi) / (nr > 0.f ? nr : 1.f);
+  idx[v] = k;
+  t12[(size_t)v * 2] = (float)exp(lt1);
+  t12[(size_t)v * 2 + 1] = (float)exp(lt2);
+  if (rho) rho[v] = fmaxf(ipr / norms[k], 0.f);
+  if (resid) resid[v] = res;
+  const int f = res > theta;
+  fb[v] = f;
+  if (f) fblist[atomicAdd(nfb, 1)] = v;
+}
+
+__global__ __launch_bounds__(256) void k_gather_alpha(const cf* __restrict__ alpha, const int* __restrict__ list,
+                                                      const int* __restrict__ nfb, int r, cf* __restrict__ out) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= nfb[0]) return;
+  const int v = list[j];
+  for (int k = 0; k < r; ++k) out[(size_t)j * r + k] = alpha[(size_t)v * r + k];
+}
+
+__global__ __launch_bounds__(256) void k_scatter_fb(const int* __restrict__ list, const int* __restrict__ nfb,
+                                                    const int* __restrict__ fidx, const float* __restrict__ frho,
+                                                    const float* __restrict__ lut, int nparam, int* __restrict__ idx,
+                                                    float* __restrict__ t12, float* __restrict__ rho) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= nfb[0]) return;
+  const int v = list[j], k = fidx[j];
+  idx[v] = k;
+  t12[(size_t)v * 2] = lut[(size_t)k * nparam];
+  t12[(size_t)v * 2 + 1] = lut[(size_t)k * nparam + 1];
+  if (rho) rho[v] = frho[j];
+}
+
+__global__ void k_zero_int(int* p) { p[0] = 0; }
+
+// ------------------------------------------------------------------ host side
+template <bool BF16, int AL, int BL, int EPI>
+mrf_status gemm(int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C, int ldc, const float* bias,
+                const float* mask, int mld, int S, hipStream_t s, const char* name) {
+  const int ks = (K + S - 1) / S;
+  dim3 grid(ceil_div(N, kG), ceil_div(M, kG), S);
+  MRF_LAUNCH(name, s, k_gemm<BF16, AL, BL, EPI><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, mask, mld, ks));
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+
+// forward pass: acts[l] = [B][width_l]; acts[0] = z; returns y in acts[nl]
+mrf_status mlp_forward(const mrf_mlp_s* P, bool bf16, int B, std::vector<float*>& acts, hipStream_t s) {
+  mrf_status e;
+  for (int l = 0; l < P->nl; ++l) {
+    const float* W = P->p + P->offW[l];
+    const float* b = P->p + P->offb[l];
+    const bool last = l == P->nl - 1;
+    const int in = P->lin[l], out = P->lout[l];
+    if (bf16) {
+      e = last ? gemm<true, LAY_K, LAY_K, EPI_BIAS>(B, out, in, acts[l], in, W, in, acts[l + 1], out, b, nullptr, 0, 1, s, "mlp_fwd")
+               : gemm<true, LAY_K, LAY_K, EPI_BIAS_RELU>(B, out, in, acts[l], in, W, in, acts[l + 1], out, b, nullptr, 0, 1, s, "mlp_fwd");
+    } else {
+      e = last ? gemm<false, LAY_K, LAY_K, EPI_BIAS>(B, out, in, acts[l], in, W, in, acts[l + 1], out, b, nullptr, 0, 1, s, "mlp_fwd")
+               : gemm<false, LAY_K, LAY_K, EPI_BIAS_RELU>(B, out, in, acts[l], in, W, in, acts[l + 1], out, b, nullptr, 0, 1, s, "mlp_fwd");
+    }
+    if (e) return e;
+  }
+  return MRF_OK;
+}
+
+struct TrainWs {
+  float* z;                 // [B][nin]
+  float* t;                 // [B][nout]
+  std::vector<float*> acts; // nl + 1 activations (acts[0] = z)
+  float *g0, *g1;           // [B][max width] gradient ping-pong
+  float* part;              // split-K partials
+  float* lpart;             // loss partials
+  float* loss;              // [1]
+  size_t bytes;
+};
+constexpr int kSplitK = 16;
+static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+TrainWs train_ws(const mrf_mlp_s* P, int B, void* base) {
+  TrainWs w{};
+  char* p = (char*)base;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    char* q = p ? p + off : nullptr;
+    off += al(b);
+    return (float*)q;
+  };
+  const int wmax = std::max(P->hid, std::max(P->nin, P->nout));
+  w.z = take((size_t)B * P->nin * 4);
+  w.t = take((size_t)B * P->nout * 4);
+  w.acts.push_back(w.z);
+  for (int l = 0; l < P->nl; ++l) w.acts.push_back(take((size_t)B * P->lout[l] * 4));
+  w.g0 = take((size_t)B * wmax * 4);
+  w.g1 = take((size_t)B * wmax * 4);
+  w.part = take((size_t)kSplitK * wmax * wmax * 4);
+  w.lpart = take((size_t)ceil_div((long)B * P->nout, 256) * 4);
+  w.loss = take(4);
+  w.bytes = off;
+  return w;
+}
+
+// loss and gradients of a batch (z, t already in the workspace); grads into P->g
+mrf_status mlp_backward(mrf_mlp_s* P, bool bf16, int B, TrainWs& w, hipStream_t s) {
+  mrf_status e;
+  if ((e = mlp_forward(P, bf16, B, w.acts, s))) return e;
+  const int n = B * P->nout;
+  const int nb = ceil_div(n, 256);
+  MRF_LAUNCH("mlp_loss", s, k_loss<<<nb, 256, 0, s>>>(w.acts[P->nl], w.t, n, 1.f / (float)n, w.g0, w.lpart));
+  MRF_LAUNCH("mlp_loss", s, k_loss_final<<<1, 256, 0, s>>>(w.lpart, nb, 1.f / (float)n, w.loss));
+  float* gout = w.g0;   // dL/d(output of layer l), [B][lout[l]]
+  float* gin = w.g1;
+  for (int l = P->nl - 1; l >= 0; --l) {
+    const int in = P->lin[l], out = P->lout[l];
+    float* dW = P->g + P->offW[l];
+    float* db = P->g + P->offb[l];
+    // dW[out][in] = sum_b gout[b][out] h[b][in]: split over the batch, fixed-order reduction
+    if (bf16) e = gemm<true, LAY_MN, LAY_MN, EPI_STORE>(out, in, B, gout, out, w.acts[l], in, w.part, in, nullptr, nullptr, 0, kSplitK, s, "mlp_dw");
+    else e = gemm<false, LAY_MN, LAY_MN, EPI_STORE>(out, in, B, gout, out, w.acts[l], in, w.part, in, nullptr, nullptr, 0, kSplitK, s, "mlp_dw");
+    if (e) return e;
+    MRF_LAUNCH("mlp_dw_reduce", s, k_reduce_slices<<<ceil_div((long)out * in, 256), 256, 0, s>>>(w.part, kSplitK, (long)out * in, dW));
+    MRF_LAUNCH("mlp_db", s, k_colsum<<<ceil_div(out, 64), 256, 0, s>>>(gout, B, out, db));
+    if (l > 0) {
+      // gin[b][in] = (sum_o gout[b][o] W[o][in]) * (h[b][in] > 0)
+      const float* W = P->p + P->offW[l];
+      if (bf16) e = gemm<true, LAY_K, LAY_MN, EPI_MASK>(B, in, out, gout, out, W, in, gin, in, nullptr, w.acts[l], in, 1, s, "mlp_bwd");
+      else e = gemm<false, LAY_K, LAY_MN, EPI_MASK>(B, in, out, gout, out, W, in, gin, in, nullptr, w.acts[l], in, 1, s, "mlp_bwd");
+      if (e) return e;
+      std::swap(gout, gin);
+    }
+  }
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+
+mrf_status adam(mrf_mlp_s* P, float lr, float b1, float b2, float eps, hipStream_t s) {
+  P->t += 1;
+  const float c1 = (float)(1.0 / (1.0 - std::pow((double)b1, P->t)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow((double)b2, P->t)));
+  MRF_LAUNCH("mlp_adam", s, k_adam<<<ceil_div((long)P->np, 256), 256, 0, s>>>(P->p, P->g, P->m, P->v, (long)P->np, lr, b1, b2, eps, c1, c2));
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+
+mrf_status ensure_stats(mrf_mlp_s* P, const mrf_dict_s* D, hipStream_t s) {
+  if (P->have_stats) return MRF_OK;
+  MRF_LAUNCH("mlp_stats", s, k_target_stats<<<1, 256, 0, s>>>(D->lut, D->M, D->nparam, P->stats));
+  MRF_CHECK_LAUNCH();
+  P->have_stats = true;
+  return MRF_OK;
+}
+
+}  // namespace mrf
+
+using namespace mrf;
+
+extern "C" mrf_status mrf_mlp_create(int n_in, int hidden, int n_hidden_layers, int n_out, uint64_t seed, hipStream_t s,
+                                     mrf_mlp_t* out) {
+  clear_error();
+  MRF_REQUIRE(out, MRF_INVALID_ARG, "mlp_create: null output");
+  *out = nullptr;
+  MRF_REQUIRE(n_in >= 1 && n_in <= 2 * kMaxR && hidden >= 1 && hidden <= 4096 && n_hidden_layers >= 1 &&
+                  n_hidden_layers <= 8 && n_out == 2,
+              MRF_INVALID_ARG, "mlp_create: need 1 <= n_in <= 32, 1 <= hidden <= 4096, 1..8 hidden layers, 2 outputs");
+  auto* P = new mrf_mlp_s{};
+  P->nin = n_in; P->hid = hidden; P->nhl = n_hidden_layers; P->nout = n_out; P->nl = n_hidden_layers + 1;
+  size_t off = 0;
+  for (int l = 0; l < P->nl; ++l) {
+    const int in = l == 0 ? n_in : hidden, o = l == P->nl - 1 ? n_out : hidden;
+    P->lin.push_back(in);
+    P->lout.push_back(o);
+    P->offW.push_back(off);
+    off += (size_t)in * o;
+    P->offb.push_back(off);
+    off += o;
+  }
+  P->np = off;
+  bool ok = hipMalloc(&P->p, off * 4) == hipSuccess && hipMalloc(&P->g, off * 4) == hipSuccess &&
+            hipMalloc(&P->m, off * 4) == hipSuccess && hipMalloc(&P->v, off * 4) == hipSuccess &&
+            hipMalloc(&P->stats, 4 * 8) == hipSuccess;
+  if (!ok) {
+    mrf_mlp_destroy(P);
+    return fail(MRF_OOM, "mlp_create: device allocation failed");
+  }
+  hipError_t e = hipMemsetAsync(P->p, 0, off * 4, s);
+  if (e == hipSuccess) e = hipMemsetAsync(P->m, 0, off * 4, s);
+  if (e == hipSuccess) e = hipMemsetAsync(P->v, 0, off * 4, s);
+  for (int l = 0; l < P->nl && e == hipSuccess; ++l) {
+    const long n = (long)P->lin[l] * P->lout[l];
+    k_init<<<ceil_div(n, 256), 256, 0, s>>>(P->p + P->offW[l], n, std::sqrt(2.f / P->lin[l]), (unsigned)l,
+                                             (unsigned)seed, (unsigned)(seed >> 32));
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    mrf_mlp_destroy(P);
+    return fail(MRF_DEVICE, std::string("mlp_create: ") + hipGetErrorString(e));
+  }
+  *out = P;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_mlp_destroy(mrf_mlp_t P) {
+  clear_error();
+  if (!P) return MRF_OK;
+  hipFree(P->p); hipFree(P->g); hipFree(P->m); hipFree(P->v); hipFree(P->stats);
+  hipFree(P->gidx); hipFree(P->i2max);
+  delete P;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_mlp_param_count(mrf_mlp_t P, size_t* n) {
+  clear_error();
+  MRF_REQUIRE(P && n, MRF_INVALID_ARG, "mlp_param_count: null argument");
+  *n = P->np;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_mlp_params(mrf_mlp_t P, float** params, float** grads) {
+  clear_error();
+  MRF_REQUIRE(P, MRF_INVALID_ARG, "mlp_params: null handle");
+  if (params) *params = P->p;
+  if (grads) *grads = P->g;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_mlp_reset_optimizer(mrf_mlp_t P, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(P, MRF_INVALID_ARG, "mlp_reset_optimizer: null handle");
+  P->t = 0;
+  MRF_CHECK_HIP(hipMemsetAsync(P->m, 0, P->np * 4, s));
+  MRF_CHECK_HIP(hipMemsetAsync(P->v, 0, P->np * 4, s));
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_mlp_set_grid(mrf_mlp_t P, int n1, double log_t1_0, double dlog_t1, int n2, double log_t2_0,
+                                       double dlog_t2, const int32_t* grid_index, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(P && grid_index && n1 >= 2 && n2 >= 2 && dlog_t1 > 0 && dlog_t2 > 0, MRF_INVALID_ARG,
+              "mlp_set_grid: bad argument");
+  std::vector<int> gi((size_t)n1 * n2), mx(n1, -1);
+  MRF_CHECK_HIP(hipMemcpyAsync(gi.data(), grid_index, gi.size() * 4, hipMemcpyDeviceToHost, s));
+  MRF_CHECK_HIP(hipStreamSynchronize(s));
+  for (int a = 0; a < n1; ++a)
+    for (int b = 0; b < n2; ++b)
+      if (gi[(size_t)a * n2 + b] >= 0) mx[a] = b;
+  for (int a = 0; a < n1; ++a) MRF_REQUIRE(mx[a] >= 0, MRF_INVALID_ARG, "mlp_set_grid: a T1 row without atoms");
+  hipFree(P->gidx);
+  hipFree(P->i2max);
+  P->gidx = nullptr;
+  P->i2max = nullptr;
+  MRF_CHECK_HIP(hipMalloc(&P->gidx, gi.size() * 4));
+  MRF_CHECK_HIP(hipMalloc(&P->i2max, (size_t)n1 * 4));
+  MRF_CHECK_HIP(hipMemcpyAsync(P->gidx, gi.data(), gi.size() * 4, hipMemcpyHostToDevice, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(P->i2max, mx.data(), (size_t)n1 * 4, hipMemcpyHostToDevice, s));
+  MRF_CHECK_HIP(hipStreamSynchronize(s));
+  P->n1 = n1; P->n2 = n2; P->l1_0 = log_t1_0; P->dl1 = dlog_t1; P->l2_0 = log_t2_0; P->dl2 = dlog_t2;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_mlp_target_stats(mrf_mlp_t P, mrf_dict_t D, double* stats_host, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(P && D, MRF_INVALID_ARG, "mlp_target_stats: null handle");
+  mrf_status e = ensure_stats(P, D, s);
+  if (e) return e;
+  if (stats_host) {
+    MRF_CHECK_HIP(hipMemcpyAsync(stats_host, P->stats, 32, hipMemcpyDeviceToHost, s));
+    MRF_CHECK_HIP(hipStreamSynchronize(s));
+  }
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_mlp_train_workspace_size(mrf_mlp_t P, int batch, size_t* bytes) {
+  clear_error();
+  MRF_REQUIRE(P && bytes && batch >= 1, MRF_INVALID_ARG, "mlp_train_workspace_size: bad argument");
+  *bytes = train_ws(P, batch, nullptr).bytes;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_mlp_synth(mrf_mlp_t P, mrf_dict_t D, uint64_t seed, int step, int batch, float snr_lo,
+                                    float snr_hi, float* z, float* t, int32_t* m, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(P && D && z && t && batch >= 1 && step >= 0, MRF_INVALID_ARG, "mlp_synth: bad argument");
+  MRF_REQUIRE(D->r >= 1 && 2 * D->r == P->nin, MRF_SHAPE, "mlp_synth: the dictionary needs a basis with 2 r = n_in");
+  mrf_status e = ensure_stats(P, D, s);
+  if (e) return e;
+  MRF_LAUNCH("mlp_synth", s,
+             k_synth<<<ceil_div(batch, 256), 256, 0, s>>>(D->dhr, D->M, D->r, D->lut, D->nparam, P->stats, (unsigned)seed,
+                                                         (unsigned)(seed >> 32), (unsigned)step, batch, snr_lo, snr_hi,
+                                                         (float)D->L, z, t, m));
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_mlp_forward(mrf_mlp_t P, const float* z, int batch, int bf16, float* y, void* ws,
+                                      size_t ws_bytes, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(P && z && y && batch >= 1, MRF_INVALID_ARG, "mlp_forward: bad argument");
+  TrainWs w = train_ws(P, batch, ws);
+  MRF_REQUIRE(ws && ws_bytes >= w.bytes, MRF_WORKSPACE, "mlp_forward: workspace too small");
+  w.acts[0] = (float*)z;
+  w.acts[P->nl] = y;
+  return mlp_forward(P, bf16 != 0, batch, w.acts, s);
+}
+
+extern "C" mrf_status mrf_mlp_grads(mrf_mlp_t P, const float* z, const float* t, int batch, int bf16, float* loss,
+                                    void* ws, size_t ws_bytes, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(P && z && t && batch >= 1, MRF_INVALID_ARG, "mlp_grads: bad argument");
+  TrainWs w = train_ws(P, batch, ws);
+  MRF_REQUIRE(ws && ws_bytes >= w.bytes, MRF_WORKSPACE, "mlp_grads: workspace too small");
+  MRF_CHECK_HIP(hipMemcpyAsync(w.z, z, (size_t)batch * P->nin * 4, hipMemcpyDeviceToDevice, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(w.t, t, (size_t)batch * P->nout * 4, hipMemcpyDeviceToDevice, s));
+  mrf_status e = mlp_backward(P, bf16 != 0, batch, w, s);
+  if (e) return e;
+  if (loss) MRF_CHECK_HIP(hipMemcpyAsync(loss, w.loss, 4, hipMemcpyDeviceToDevice, s));
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_mlp_adam_step(mrf_mlp_t P, float lr, float beta1, float beta2, float eps, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(P && lr >= 0.f && beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f,
+              MRF_INVALID_ARG, "mlp_adam_step: bad argument");
+  return adam(P, lr, beta1, beta2, eps, s);
+}
+
+extern "C" mrf_status mrf_mlp_train(mrf_mlp_t P, mrf_dict_t D, const mrf_mlp_train_cfg* cfg, float* losses,
+                                    void* ws, size_t ws_bytes, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(P && D && cfg, MRF_INVALID_ARG, "mlp_train: null argument");
+  MRF_REQUIRE(cfg->batch >= 1 && cfg->steps >= 0 && cfg->lr > 0.f && cfg->snr_hi >= cfg->snr_lo, MRF_INVALID_ARG,
+              "mlp_train: bad configuration");
+  MRF_REQUIRE(D->r >= 1 && 2 * D->r == P->nin, MRF_SHAPE, "mlp_train: the dictionary needs a basis with 2 r = n_in");
+  TrainWs w = train_ws(P, cfg->batch, ws);
+  MRF_REQUIRE(ws && ws_bytes >= w.bytes, MRF_WORKSPACE, "mlp_train: workspace too small");
+  mrf_status e = ensure_stats(P, D, s);
+  if (e) return e;
+  const int B = cfg->batch;
+  const double pi = 3.14159265358979323846;
+  for (int it = 0; it < cfg->steps; ++it) {
+    const int step = cfg->first_step + it;
+    MRF_LAUNCH("mlp_synth", s,
+               k_synth<<<ceil_div(B, 256), 256, 0, s>>>(D->dhr, D->M, D->r, D->lut, D->nparam, P->stats,
+                                                       (unsigned)cfg->seed, (unsigned)(cfg->seed >> 32), (unsigned)step, B,
+                                                       cfg->snr_lo, cfg->snr_hi, (float)D->L, w.z, w.t, nullptr));
+    if ((e = mlp_backward(P, cfg->bf16 != 0, B, w, s))) return e;
+    if (losses) MRF_CHECK_HIP(hipMemcpyAsync(losses + it, w.loss, 4, hipMemcpyDeviceToDevice, s));
+    const int T = cfg->total_steps > 0 ? cfg->total_steps : cfg->first_step + cfg->steps;
+    const float lr = cfg->cosine ? (float)(cfg->lr * 0.5 * (1.0 + std::cos(pi * step / (double)T))) : cfg->lr;
+    if ((e = adam(P, lr, cfg->beta1, cfg->beta2, cfg->eps, s))) return e;
+  }
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_mlp_match_workspace_size(mrf_mlp_t P, int Nv, size_t* bytes) {
+  clear_error();
+  MRF_REQUIRE(P && bytes && Nv >= 1, MRF_INVALID_ARG, "mlp_match_workspace_size: bad argument");
+  *bytes = train_ws(P, Nv, nullptr).bytes + al((size_t)Nv * 4) * 4 + al((size_t)Nv * 2 * 4) + al(256) +
+           al((size_t)Nv * kMaxR * sizeof(cf));
+  return MRF_OK;
+}
+
+namespace mrf {
+mrf_status match_subspace(const mrf_dict_s* D, const cf* alpha, int Nv, int* idx, float* rho, float* score,
+                          float* params, hipStream_t s);
+}
+
+extern "C" mrf_status mrf_mlp_match(mrf_mlp_t P, mrf_dict_t D, const mrf_c64* alpha, int Nv, int bf16, float theta,
+                                    int32_t* idx, float* t12, float* rho, float* resid, int32_t* fallback, int* n_fallback,
+                                    void* ws, size_t ws_bytes, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(P && D && alpha && idx && t12 && Nv >= 1, MRF_INVALID_ARG, "mlp_match: null argument");
+  MRF_REQUIRE(P->gidx, MRF_INVALID_ARG, "mlp_match: call mrf_mlp_set_grid first");
+  MRF_REQUIRE(D->r >= 1 && 2 * D->r == P->nin, MRF_SHAPE, "mlp_match: the dictionary needs a basis with 2 r = n_in");
+  size_t need = 0;
+  mrf_mlp_match_workspace_size(P, Nv, &need);
+  MRF_REQUIRE(ws && ws_bytes >= need, MRF_WORKSPACE, "mlp_match: workspace too small");
+  mrf_status e = ensure_stats(P, D, s);
+  if (e) return e;
+  TrainWs w = train_ws(P, Nv, ws);
+  char* base = (char*)ws + w.bytes;
+  int* fb = fallback ? fallback : (int*)base;
+  base += al((size_t)Nv * 4);
+  int* list = (int*)base; base += al((size_t)Nv * 4);
+  int* fidx = (int*)base; base += al((size_t)Nv * 4);
+  float* frho = (float*)base; base += al((size_t)Nv * 4);
+  float* yv = (float*)base; base += al((size_t)Nv * 2 * 4);
+  int* nfb = (int*)base; base += al(256);
+  cf* fa = (cf*)base;
+  MRF_LAUNCH("mlp_features", s, k_features<<<ceil_div(Nv, 256), 256, 0, s>>>((const cf*)alpha, Nv, D->r, w.z));
+  w.acts[P->nl] = yv;
+  if ((e = mlp_forward(P, bf16 != 0, Nv, w.acts, s))) return e;
+  MRF_LAUNCH("mlp_gate", s, k_zero_int<<<1, 1, 0, s>>>(nfb));
+  MRF_LAUNCH("mlp_gate", s,
+             k_gate<<<ceil_div(Nv, 256), 256, 0, s>>>(yv, P->stats, P->n1, P->n2, P->l1_0, P->dl1, P->l2_0, P->dl2, P->gidx,
+                                                     P->i2max, D->dhr, D->norms, (const cf*)alpha, Nv, D->r, theta, idx, t12,
+                                                     rho, resid, fb, nfb, list));
+  MRF_CHECK_LAUNCH();
+  int nf = 0;
+  MRF_CHECK_HIP(hipMemcpyAsync(&nf, nfb, 4, hipMemcpyDeviceToHost, s));
+  MRF_CHECK_HIP(hipStreamSynchronize(s));
+  if (n_fallback) *n_fallback = nf;
+  if (nf > 0) {
+    MRF_LAUNCH("mlp_fallback", s, k_gather_alpha<<<ceil_div(nf, 256), 256, 0, s>>>((const cf*)alpha, list, nfb, D->r, fa));
+    if ((e = match_subspace(D, fa, nf, fidx, frho, nullptr, nullptr, s))) return e;
+    MRF_LAUNCH("mlp_fallback", s,
+               k_scatter_fb<<<ceil_div(nf, 256), 256, 0, s>>>(list, nfb, fidx, frho, D->lut, D->nparam, idx, t12, rho));
+    MRF_CHECK_LAUNCH();
+  }
+  return MRF_OK;
+}
