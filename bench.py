@@ -73,6 +73,104 @@ def algorithmic_work(name, cfg, E, Np):
     return bound, amount
 
 
+def _nmse(est, tru, mask):
+    e, t = est[mask], tru[mask]
+    return float(np.sum((e - t) ** 2) / np.sum(t ** 2))
+
+
+def _time(torch, fn, reps):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_precision_match(torch, mrf, dev, fp, truth, mask, oracle_sample=256):
+    """Full-length match of the 65 536 fingerprints (the 256 x 256 truth series plus 40 dB noise)
+    against the 50 000-atom T1 x T2 x B1 dictionary in FP32, BF16 and FP8 (each with the FP32
+    top-4 re-rank): fingerprints/s, T1/T2 NMSE against the truth over the tissue, and index
+    agreement with the oracle's FP64 exhaustive match on a sample of tissue voxels."""
+    import mrfgen
+    from oracle import match as omatch
+    cfg3 = mrfgen.get_config("C3")
+    atoms, grid = mrfgen.make_dictionary(cfg3)
+    lut = grid["lut"]
+    d = mrf.Dictionary(torch.from_numpy(atoms).to(dev), torch.from_numpy(lut).to(dev))
+    Nv = fp.shape[0]
+    rng = np.random.default_rng(0)
+    sample = rng.choice(np.flatnonzero(mask.ravel()), oracle_sample, replace=False)
+    t0 = time.time()
+    ref_idx = omatch.precision_match_ref(fp[sample].cpu().numpy(), atoms, lut)[0]
+    log("C3 oracle sample (%d voxels) %.1f s" % (oracle_sample, time.time() - t0))
+    out = {"atoms": int(atoms.shape[0]), "fingerprints": int(Nv), "L": int(atoms.shape[1])}
+    for mode in ("fp32", "bf16", "fp8"):
+        ms = _time(torch, lambda: d.match(fp, mode=mode), 1 if mode == "fp32" else 3)
+        idx, rho, score, params = [t.cpu().numpy() for t in d.match(fp, mode=mode)]
+        out[mode] = dict(ms=round(ms, 3), fingerprints_per_s=round(Nv / ms * 1e3, 1),
+                         tflops=round(8.0 * Nv * atoms.shape[0] * atoms.shape[1] / ms / 1e9, 1),
+                         nmse_t1=_nmse(params[:, 0], truth[0].ravel(), mask.ravel()),
+                         nmse_t2=_nmse(params[:, 1], truth[1].ravel(), mask.ravel()),
+                         agree_fp64_sample=float(np.mean(idx[sample] == ref_idx)))
+        log("C3 %s: %.2f ms, %.3g fp/s, NMSE T1 %.2e T2 %.2e, agreement %.3f" % (
+            mode, ms, out[mode]["fingerprints_per_s"], out[mode]["nmse_t1"], out[mode]["nmse_t2"],
+            out[mode]["agree_fp64_sample"]))
+    d.close()
+    return out
+
+
+def bench_learned_match(torch, mrf, dev, d, V, Xn, truth, mask, grid, epochs=20, batch=4096, samples=2_000_000):
+    """MLP trained on the device (2 M noisy atoms per epoch, SNR 20-60 dB, BF16 GEMMs), then the
+    gated learned match on the 65 536 fingerprints against the plain FP32 exhaustive subspace
+    match: the smallest fallback threshold at which both learned NMSEs are <= the plain ones,
+    and fingerprints/s of both (each includes the projection alpha = x V)."""
+    net = mrf.MLP(n_in=2 * V.shape[1], hidden=256, layers=3, seed=1)
+    net.set_grid(grid)
+    steps_per_epoch = (samples + batch - 1) // batch
+    steps = epochs * steps_per_epoch
+    torch.cuda.synchronize()
+    t0 = time.time()
+    losses = net.train(d, steps=steps, batch=batch, lr=1e-3, total_steps=steps, seed=2, bf16=True)
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    lo = losses.cpu().numpy()
+    log("MLP training: %d steps in %.2f s, loss %.4f -> %.6f" % (steps, train_s, lo[:20].mean(), lo[-100:].mean()))
+    Vd = torch.from_numpy(V).to(dev)
+    Nv = Xn[0].numel()
+    alpha = mrf.subspace_coeffs(Xn, Vd)
+    plain = d.match_subspace(alpha)
+    pp = plain[3].cpu().numpy()
+    m = mask.ravel()
+    t1, t2 = truth[0].ravel(), truth[1].ravel()
+    plain_err = (_nmse(pp[:, 0], t1, m), _nmse(pp[:, 1], t2, m))
+    choice = None
+    sweep = {}
+    for theta in (1.0, 0.05, 0.02, 0.01, 0.005, 0.002, 0.001):
+        r = net.match(d, alpha, theta=theta, bf16=True)
+        t12 = r["t12"].cpu().numpy()
+        err = (_nmse(t12[:, 0], t1, m), _nmse(t12[:, 1], t2, m))
+        sweep[str(theta)] = dict(nmse_t1=err[0], nmse_t2=err[1], fallback=int(r["n_fallback"]))
+        if choice is None and err[0] <= plain_err[0] and err[1] <= plain_err[1]:
+            choice = theta
+    theta = choice if choice is not None else 0.0
+    ms_plain = _time(torch, lambda: d.match_subspace(mrf.subspace_coeffs(Xn, Vd)), 5)
+    ms_proj = _time(torch, lambda: mrf.subspace_coeffs(Xn, Vd), 5)
+    ms_learn = _time(torch, lambda: net.match(d, mrf.subspace_coeffs(Xn, Vd), theta=theta, bf16=True), 5)
+    out = dict(train_steps=steps, train_s=round(train_s, 3), train_ms_per_epoch=round(1e3 * train_s / epochs, 2),
+               final_loss=float(lo[-100:].mean()), plain_nmse_t1=plain_err[0], plain_nmse_t2=plain_err[1],
+               theta=theta, sweep=sweep, projection_ms=round(ms_proj, 4),
+               plain_ms=round(ms_plain, 4), learned_ms=round(ms_learn, 4),
+               plain_fingerprints_per_s=round(Nv / ms_plain * 1e3, 1),
+               learned_fingerprints_per_s=round(Nv / ms_learn * 1e3, 1))
+    log("learned at theta %s: %.3f ms vs plain %.3f ms; NMSE sweep %s" % (theta, ms_learn, ms_plain, sweep))
+    net.close()
+    return out
+
+
 def cpu_baseline(cfg, traj, frames=16):
     """The oracle's NUFFT pair (FP64 KB gridding) on a frame sample, scaled to the volume."""
     from oracle import nufft as onufft
@@ -95,6 +193,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-match-forms", action="store_true", help="skip the precision and learned match components")
+    ap.add_argument("--mlp-epochs", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (frames would shard "
@@ -191,12 +291,23 @@ def main():
         roof["dominant_kernel"] = dom
         roof["traffic"] = _counter_traffic(roof["kernel"])
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(cfg, traj)
+    # match forms on the truth fingerprints plus 40 dB noise (voxel-major)
+    comps_extra = {}
+    if not args.no_match_forms:
+        import mrfgen
+        rng_noise = 23
+        s2 = mrfgen.noise_sigma(np.mean(np.abs(Xtrue[:, ph["PD"] > 0]) ** 2), 40.0)
+        Xn = torch.from_numpy((Xtrue + mrfgen.complex_noise(Xtrue.shape, s2, rng_noise)).astype(np.complex64)).to(dev)
+        fpv = mrf.frames_to_voxels(Xn)
+        truth = np.stack([ph["T1"], ph["T2"]])
+        tmask = ph["mask"] & (ph["PD"] > 0)
+        comps_extra["precision_match"] = bench_precision_match(torch, mrf, dev, fpv, truth, tmask)
+        grid_c2 = mrfgen.param_grid(cfg)
+        comps_extra["learned_match"] = bench_learned_match(torch, mrf, dev, d, V, Xn, truth, tmask, grid_c2,
+                                                          epochs=args.mlp_epochs)
 
-    out = {
+    cpu = None
+    if not args.no_cpu_baseline:    out = {
         "metric": METRIC,
         "value": round(1000.0 / ms, 3),
         "unit": "NUFFT pairs/s",
@@ -226,6 +337,7 @@ def main():
                                        sorted(per_kernel.items(), key=lambda kv: -kv[1]["ms_per_step"])},
             "roofline_by_kernel": {r["kernel"]: {"bound": r["bound"], "frac": r["frac"], "achieved": r["achieved"],
                                                  "unit": r["unit"]} for r in rows},
+            **comps_extra,
         },
     }
     print(json.dumps(out), flush=True)

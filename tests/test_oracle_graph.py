@@ -7,12 +7,16 @@ from oracle import graph, ops, patches
 
 
 def test_three_node_example_eq11():
-    w12, w13, w23 = 0.3, 0.7, 0.11
-    W = np.array([[0, w12, w13], [w12, 0, w23], [w13, w23, 0]])
-    expect = np.array([[w12 + w13, -w12, -w13],
-                       [-w12, w12 + w23, -w23],
-                       [-w13, -w23, w13 + w23]])
-    np.testing.assert_array_equal(graph.laplacian_from_weights(W), expect)
+    """The symbolic three-node Laplacian of eq. (11), read from tests/golden, evaluated at
+    arbitrary weights."""
+    import os
+    rows = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "eq11_three_node_laplacian.txt"))
+    for w12, w13, w23 in ((0.3, 0.7, 0.11), (1.0, 0.0, 2.5)):
+        W = np.array([[0, w12, w13], [w12, 0, w23], [w13, w23, 0]])
+        expect = np.zeros((3, 3))
+        for i, j, c12, c13, c23 in rows:
+            expect[int(i), int(j)] = c12 * w12 + c13 * w13 + c23 * w23
+        np.testing.assert_array_equal(graph.laplacian_from_weights(W), expect)
 
 
 def _rand_maps(rng, N):
