@@ -171,6 +171,69 @@ def bench_learned_match(torch, mrf, dev, d, V, Xn, truth, mask, grid, epochs=20,
     return out
 
 
+def bench_batched(torch, mrf, dev, rounds=3):
+    """Eight uneven slices (N = 128, 192, 256, 320, each with L = 500 at 2 spiral interleaves per
+    frame and L = 1000 at 1), every slice's NUFFT strip width chosen by the autotuner; one round =
+    one iteration of every slice. Timed back to back on one stream and batched on 8 streams."""
+    import mrfgen
+    c5 = mrfgen.get_config("C5")
+    dicts = {}
+    slices = []
+    t0 = time.time()
+    for k, sl in enumerate(c5["slices"]):
+        N, L, ipf = sl["N"], sl["L"], sl["interleaves_per_frame"]
+        cfg = mrfgen.get_config("C5", N=N, L=L)
+        if L not in dicts:
+            atoms, grid = mrfgen.make_dictionary(cfg)
+            V, _ = mrfgen.subspace_basis(atoms, cfg["r"])
+            dicts[L] = (mrf.Dictionary(torch.from_numpy(atoms).to(dev), torch.from_numpy(grid["lut"]).to(dev),
+                                       torch.from_numpy(V).to(dev)), V)
+        ph = mrfgen.make_phantom(cfg, 100 + k)
+        X = torch.from_numpy(mrfgen.truth_fingerprints(cfg, ph)).to(dev)
+        traj = torch.from_numpy(mrfgen.vds_spiral(N, L, c5["Ns"], c5["n_interleaves"], interleaves_per_frame=ipf)).to(dev)
+        tx, times = mrf.autotune(N, traj, reps=2)
+        plan = mrf.NufftPlan(N, traj, tile_cols=tx)
+        b = plan.fwd(X)
+        bh = b.cpu().numpy()
+        b = torch.from_numpy(bh + mrfgen.complex_noise(bh.shape, mrfgen.noise_sigma(np.mean(np.abs(bh) ** 2), 40.0),
+                                                       200 + k)).to(dev)
+        lamA = plan.opnorm(30)
+        rc = mrf.Recon(plan, dicts[L][0], cfg["p"], cfg["s"], cfg["K"], cfg["r_llr"], lam1_0=cfg["lam1_0"],
+                       lam2=cfg["lam2"], beta=cfg["beta"], mu0=cfg["mu0"], lamA=lamA, n_max=100000, tol=-1.0)
+        rc.init(b)
+        slices.append(dict(N=N, L=L, Ns=int(traj.shape[1]), tile_cols=tx, autotune_ms={str(a): round(v, 3) for a, v in times.items()},
+                           rc=rc, plan=plan, b=b))
+        del X
+    torch.cuda.synchronize()
+    log("C5: 8 slices set up in %.1f s" % (time.time() - t0))
+    recons = [x["rc"] for x in slices]
+    for rc in recons:
+        rc.iterate(1)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(rounds):
+        for rc in recons:
+            rc.iterate(1)
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t) * 1e3 / rounds
+    streams = [torch.cuda.Stream() for _ in recons]
+    mrf.recon_batched(recons, streams, 1)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    mrf.recon_batched(recons, streams, rounds)
+    torch.cuda.synchronize()
+    bat_ms = (time.perf_counter() - t) * 1e3 / rounds
+    frames = sum(x["L"] for x in slices)
+    log("C5: round (one iteration of all 8 slices) %.2f ms back to back, %.2f ms batched" % (seq_ms, bat_ms))
+    out = dict(slices=[{k: v for k, v in x.items() if k not in ("rc", "plan", "b")} for x in slices],
+               round_ms_sequential=round(seq_ms, 3), round_ms_batched=round(bat_ms, 3),
+               frame_pairs_per_s_batched=round(frames / bat_ms * 1e3, 1),
+               frame_pairs_per_s_sequential=round(frames / seq_ms * 1e3, 1))
+    for x in slices:
+        x["rc"].close()
+    return out
+
+
 def cpu_baseline(cfg, traj, frames=16):
     """The oracle's NUFFT pair (FP64 KB gridding) on a frame sample, scaled to the volume."""
     from oracle import nufft as onufft
@@ -195,6 +258,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-match-forms", action="store_true", help="skip the precision and learned match components")
     ap.add_argument("--mlp-epochs", type=int, default=20)
+    ap.add_argument("--no-batched", action="store_true", help="skip the 8-slice batched component")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (frames would shard "
@@ -305,6 +369,10 @@ def main():
         grid_c2 = mrfgen.param_grid(cfg)
         comps_extra["learned_match"] = bench_learned_match(torch, mrf, dev, d, V, Xn, truth, tmask, grid_c2,
                                                           epochs=args.mlp_epochs)
+        del Xn, fpv
+    if not args.no_batched:
+        rc.close()
+        comps_extra["batched_c5"] = bench_batched(torch, mrf, dev)
 
     cpu = None
     if not args.no_cpu_baseline:    out = {

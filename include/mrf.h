@@ -67,7 +67,7 @@ mrf_status mrf_timing_report(char* buf, size_t buf_len);
 typedef struct mrf_nufft_plan_s* mrf_nufft_plan_t;
 
 typedef struct mrf_nufft_desc {
-  int n;          /* image side N; a power of two, 16 <= N <= 512                      */
+  int n;          /* image side N: 16, 32, 64, 128, 192, 256, 320 or 512 (G = 2N)      */
   int nframes;    /* L >= 1                                                            */
   int nsamp;      /* Ns >= 1 samples per frame                                         */
   int kb_width;   /* must be 6                                                         */
@@ -91,6 +91,13 @@ mrf_status mrf_nufft_fwd(mrf_nufft_plan_t plan, const mrf_c64* img, mrf_c64* ksp
 /* img [L][N][N] = A^H ksp, ksp [L][Ns]. */
 mrf_status mrf_nufft_adj(mrf_nufft_plan_t plan, const mrf_c64* ksp, mrf_c64* img,
                          void* ws, size_t ws_bytes, hipStream_t stream);
+/* Autotuner: for the trajectory traj (as in mrf_nufft_plan_create) times reps forward + adjoint
+ * pairs on a pseudo-random image for each strip width tile_cols in {8, 16, 32} that the grid
+ * allows, writes their mean pair times (ms; -1 where not allowed) to pair_ms [3] (optional) and
+ * the fastest width to best_tile_cols (use it as desc.tile_cols). Allocates and frees its own
+ * buffers; synchronises. */
+mrf_status mrf_nufft_autotune(const mrf_nufft_desc* desc, const float* traj, int reps, int* best_tile_cols,
+                              float* pair_ms, hipStream_t stream);
 /* lambda_max(A^H A) estimated by `iters` power iterations from a deterministic start vector
  * (seeded hash), written to *lam (host). Setup call: allocates temporary device memory and
  * synchronises. Algorithm 1's step-size rule takes this bound (see mrf_recon_params.lamA). */
@@ -323,6 +330,12 @@ mrf_status mrf_recon_init(mrf_recon_t r, const mrf_c64* b, const mrf_c64* X0, hi
 /* Runs up to n more iterations (stops early on the tolerance or at n_max). Synchronises once
  * per iteration to read the cost. *stopped (may be NULL) is set when no iteration is left. */
 mrf_status mrf_recon_iterate(mrf_recon_t r, int n, int* stopped, hipStream_t stream);
+/* C5: advances nslices independent reconstructions (each created and initialised on its own,
+ * with its own plan, dictionary and graph; slices may differ in n, L and Ns) by up to n
+ * iterations each. Per round, every active slice's iteration is enqueued on its own stream
+ * (streams[i], default priority), then each is waited for and its stopping rule applied, so the
+ * slices' kernels overlap on the device. n_active (host, optional): slices still running. */
+mrf_status mrf_recon_batched(int nslices, const mrf_recon_t* recons, const hipStream_t* streams, int n, int* n_active);
 /* Final match Phi_D(X): any of X_out [L][n][n], maps [3][n][n] (T1, T2, PD), idx [n*n],
  * rho [n*n] may be NULL. Asynchronous. */
 mrf_status mrf_recon_finish(mrf_recon_t r, mrf_c64* X_out, float* maps, int32_t* idx, float* rho, hipStream_t stream);

@@ -61,6 +61,7 @@ _decl("mrf_nufft_workspace_size", [c_void_p, P(c_size_t)])
 _decl("mrf_nufft_fwd", [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_nufft_adj", [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_nufft_opnorm", [c_void_p, c_int, ctypes.c_uint, P(ctypes.c_double), c_void_p])
+_decl("mrf_nufft_autotune", [P(NufftDesc), c_void_p, c_int, P(c_int), P(c_float), c_void_p])
 _decl("mrf_graph_create", [c_int, c_int, c_int, c_int, c_int, P(c_void_p)])
 _decl("mrf_graph_destroy", [c_void_p])
 _decl("mrf_knn_laplacian", [c_void_p, c_void_p, c_int, c_float, c_void_p])
@@ -101,6 +102,7 @@ _decl("mrf_mlp_match", [c_void_p, c_void_p, c_void_p, c_int, c_int, c_float, c_v
                         c_void_p, P(c_int), c_void_p, c_size_t, c_void_p])
 _decl("mrf_recon_create", [P(ReconParams), c_void_p, c_void_p, P(c_void_p)])
 _decl("mrf_recon_destroy", [c_void_p])
+_decl("mrf_recon_batched", [c_int, c_void_p, c_void_p, c_int, P(c_int)])
 _decl("mrf_recon_init", [c_void_p, c_void_p, c_void_p, c_void_p])
 _decl("mrf_recon_iterate", [c_void_p, c_int, P(c_int), c_void_p])
 _decl("mrf_recon_finish", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p])

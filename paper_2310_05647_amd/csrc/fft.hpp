@@ -1,4 +1,5 @@
-// Stockham auto-sort FFT on data resident in LDS, for power-of-two lengths 32..1024.
+// Stockham auto-sort FFT on data resident in LDS, for lengths 2^a 3^b 5^c (32 <= G <= 1024,
+// 2^a >= 4): radix-8 passes, one radix-4 or radix-2 pass, then the radix-3 and radix-5 passes.
 //
 // Pass with radix R over a length-G transform whose finished sub-transforms have span Ns:
 //   butterfly j (0 <= j < G/R): v[r] = in[j + r G/R] * w^(k r), k = j mod Ns,
@@ -22,16 +23,25 @@ __device__ inline void lds_sync() {
   asm volatile("" ::: "memory");
 }
 
-// Radix schedule: radix-8 passes, then one radix-4 or radix-2 pass when log2(G) % 3 != 0.
+// Radix schedule: radix-8 passes, one radix-4 or radix-2 pass when log2 of the power-of-two
+// part is not a multiple of 3, then one pass per factor 3 and per factor 5.
+constexpr int count_factor(int g, int f) { return g % f == 0 ? 1 + count_factor(g / f, f) : 0; }
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 template <int G>
 struct FftPlan {
-  static constexpr int log2g = (G == 32) ? 5 : (G == 64) ? 6 : (G == 128) ? 7 : (G == 256) ? 8
-                             : (G == 512) ? 9 : (G == 1024) ? 10 : -1;
-  static_assert(log2g > 0, "unsupported FFT length");
+  static constexpr int n3 = count_factor(G, 3);
+  static constexpr int n5 = count_factor(G, 5);
+  static constexpr int p2 = G / (ipow(3, n3) * ipow(5, n5));
+  static constexpr int log2g = ilog2(p2);
+  static_assert(p2 >= 4 && (1 << log2g) == p2 && G >= 32 && G <= 1024, "unsupported FFT length");
   static constexpr int n8 = log2g / 3;
   static constexpr int tail = 1 << (log2g % 3);   // 1, 2 or 4
-  static constexpr int npass = n8 + (tail > 1 ? 1 : 0);
-  __host__ __device__ static constexpr int radix(int p) { return p < n8 ? 8 : tail; }
+  static constexpr int ntail = tail > 1 ? 1 : 0;
+  static constexpr int npass = n8 + ntail + n3 + n5;
+  __host__ __device__ static constexpr int radix(int p) {
+    return p < n8 ? 8 : p < n8 + ntail ? tail : p < n8 + ntail + n3 ? 3 : 5;
+  }
 };
 
 template <bool INV>
@@ -41,7 +51,32 @@ __device__ inline cf mul_i(cf a) {  // a * (-i) forward, a * (+i) inverse
 
 template <int R, bool INV>
 __device__ inline void dft_regs(cf* v) {
-  if constexpr (R == 2) {
+  if constexpr (R == 3) {
+    // V_k = sum_n v_n w^{nk}, w = exp(-+ 2 pi i / 3): V_{1,2} = v0 - (v1 + v2)/2 -+ i (sqrt3/2)(v1 - v2)
+    constexpr float s3 = 0.86602540378443864676f;
+    const cf t1 = cadd(v[1], v[2]);
+    const cf t2 = cf{v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y};
+    const cf t3 = mul_i<INV>(cscale(csub(v[1], v[2]), s3));
+    v[0] = cadd(v[0], t1);
+    v[1] = cadd(t2, t3);
+    v[2] = csub(t2, t3);
+  } else if constexpr (R == 5) {
+    // a = v1 + v4, v2 + v3; b = v1 - v4, v2 - v3; V_{1,4} = t1 -+ i u1, V_{2,3} = t2 -+ i u2 with
+    // t1 = v0 + c1 a1 + c2 a2, t2 = v0 + c2 a1 + c1 a2, u1 = s1 b1 + s2 b2, u2 = s2 b1 - s1 b2
+    constexpr float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
+    constexpr float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;
+    const cf a1 = cadd(v[1], v[4]), a2 = cadd(v[2], v[3]);
+    const cf b1 = csub(v[1], v[4]), b2 = csub(v[2], v[3]);
+    const cf t1 = cf{v[0].x + c1 * a1.x + c2 * a2.x, v[0].y + c1 * a1.y + c2 * a2.y};
+    const cf t2 = cf{v[0].x + c2 * a1.x + c1 * a2.x, v[0].y + c2 * a1.y + c1 * a2.y};
+    const cf u1 = mul_i<INV>(cf{s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y});
+    const cf u2 = mul_i<INV>(cf{s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y});
+    v[0] = cadd(v[0], cadd(a1, a2));
+    v[1] = cadd(t1, u1);
+    v[4] = csub(t1, u1);
+    v[2] = cadd(t2, u2);
+    v[3] = csub(t2, u2);
+  } else if constexpr (R == 2) {
     cf a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
@@ -108,7 +143,7 @@ __device__ inline void stockham_pass(cf* buf, const cf* tw, int Ns) {
       if (Ns > 1) {   // the first pass has only unit twiddles
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cf t = tw[(k * r * step) & (G - 1)];
+          cf t = tw[k * r * step];   // k r step < G for every pass
           if (INV) t.y = -t.y;
           v[b][r] = cmul(v[b][r], t);
         }
@@ -131,7 +166,9 @@ __device__ inline void lds_fft(cf* buf, const cf* tw) {
   for (int p = 0; p < P::npass; ++p) {
     if (P::radix(p) == 8) stockham_pass<G, 8, NT, ES, TS, CFAST, INV>(buf, tw, Ns);
     else if (P::radix(p) == 4) stockham_pass<G, 4, NT, ES, TS, CFAST, INV>(buf, tw, Ns);
-    else stockham_pass<G, 2, NT, ES, TS, CFAST, INV>(buf, tw, Ns);
+    else if (P::radix(p) == 2) stockham_pass<G, 2, NT, ES, TS, CFAST, INV>(buf, tw, Ns);
+    else if (P::radix(p) == 3) stockham_pass<G, 3, NT, ES, TS, CFAST, INV>(buf, tw, Ns);
+    else stockham_pass<G, 5, NT, ES, TS, CFAST, INV>(buf, tw, Ns);
     Ns *= P::radix(p);
   }
 }

@@ -61,6 +61,10 @@ namespace mrf {
 // which share 128-byte lines of T, meet in the same L2.
 constexpr int kMaxFramesPerBlock = 1;
 
+// Rows per row-pass group: a radix-8 pass of the group then gives one butterfly per thread
+// (for G with factors 3 or 5 the count is rounded down).
+__host__ __device__ constexpr int row_rpb(int G) { return kBlock * 8 / G > 0 ? kBlock * 8 / G : 1; }
+
 __device__ inline bool strip_and_chunk(int nstrips, int nchunks, int& sx, int& c) {
   const int b = blockIdx.x;
   const int q = b >> 3;
@@ -76,7 +80,7 @@ __global__ __launch_bounds__(kBlock) void k_row_fwd(const cf* __restrict__ X, cf
                                                     const float* __restrict__ dinv,
                                                     const cf* __restrict__ twg, int nrows) {
   constexpr int N = G / 2;
-  constexpr int RPB = kBlock / (G / 8);   // rows per group
+  constexpr int RPB = row_rpb(G);          // rows per group
   constexpr int TS = G + 1;
   constexpr int PIN = (RPB * N + kBlock - 1) / kBlock;   // non-zero inputs per thread
   __shared__ cf buf[RPB * TS];
@@ -131,9 +135,9 @@ __global__ __launch_bounds__(kBlock) void k_row_adj(const cf* __restrict__ T, cf
                                                     const float* __restrict__ dinv,
                                                     const cf* __restrict__ twg, int nrows, float scale) {
   constexpr int N = G / 2;
-  constexpr int RPB = kBlock / (G / 8);
+  constexpr int RPB = row_rpb(G);
   constexpr int TS = G + 1;
-  constexpr int PIN = RPB * G / kBlock;
+  constexpr int PIN = (RPB * G + kBlock - 1) / kBlock;
   __shared__ cf buf[RPB * TS];
   __shared__ cf tw[G];
   const int tid = threadIdx.x;
@@ -145,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void k_row_adj(const cf* __restrict__ T, cf
     for (int i = 0; i < PIN; ++i) {
       const int idx = tid + i * kBlock;
       const long row = (long)g * RPB + idx / G;
-      pre[i] = row < nrows ? T[row * G + idx % G] : cf{0.f, 0.f};
+      pre[i] = (idx < RPB * G && row < nrows) ? T[row * G + idx % G] : cf{0.f, 0.f};
     }
   };
   int g = blockIdx.x;
@@ -154,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void k_row_adj(const cf* __restrict__ T, cf
 #pragma unroll
     for (int i = 0; i < PIN; ++i) {
       const int idx = tid + i * kBlock;
-      buf[(idx / G) * TS + idx % G] = pre[i];
+      if (idx < RPB * G) buf[(idx / G) * TS + idx % G] = pre[i];
     }
     lds_sync();
     if (g + (int)gridDim.x < ngroups) load(g + gridDim.x);
@@ -577,7 +581,9 @@ void parallel_for(int n, F fn) {
 
 }  // namespace
 
-static bool supported_g(int G) { return G == 32 || G == 64 || G == 128 || G == 256 || G == 512 || G == 1024; }
+static bool supported_g(int G) {
+  return G == 32 || G == 64 || G == 128 || G == 256 || G == 384 || G == 512 || G == 640 || G == 1024;
+}
 
 }  // namespace mrf
 
@@ -592,7 +598,8 @@ extern "C" mrf_status mrf_nufft_plan_create(const mrf_nufft_desc* d, const float
   MRF_REQUIRE(d->oversamp == 2, MRF_NOT_SUPPORTED, "nufft_plan_create: oversamp must be 2");
   MRF_REQUIRE(d->nframes >= 1 && d->nsamp >= 1, MRF_INVALID_ARG, "nufft_plan_create: nframes, nsamp must be >= 1");
   const int N = d->n, G = 2 * N;
-  MRF_REQUIRE(N >= 16 && N <= 512 && supported_g(G), MRF_SHAPE, "nufft_plan_create: n must be a power of two in [16, 512]");
+  MRF_REQUIRE(N >= 16 && N <= 512 && supported_g(G), MRF_SHAPE,
+              "nufft_plan_create: n must be 16, 32, 64, 128, 192, 256, 320 or 512");
   int TX = d->tile_cols ? d->tile_cols : (G <= 32 ? 16 : 8);
   MRF_REQUIRE(TX == 8 || TX == 16 || TX == 32, MRF_INVALID_ARG, "nufft_plan_create: tile_cols must be 0, 8, 16 or 32");
   MRF_REQUIRE(TX <= G / 2 && (long)G * TX <= 8192 && (TX < 32 || G <= 128), MRF_SHAPE,
@@ -710,7 +717,7 @@ static int row_blocks(long ngroups) { return (int)std::min<long>(ngroups, 2048);
 template <int G, int TX>
 static void launch_fwd_g(const mrf_nufft_plan_s* p, const cf* img, cf* T, cf* part, hipStream_t s) {
   const int nrows = p->L * p->N;
-  constexpr int RPB = kBlock / (G / 8);
+  constexpr int RPB = row_rpb(G);
   const int FC = frames_per_chunk(p);
   MRF_LAUNCH("nufft_row_fwd", s,
              k_row_fwd<G><<<row_blocks((nrows + RPB - 1) / RPB), kBlock, 0, s>>>(img, T, p->dinv, p->tw, nrows));
@@ -721,7 +728,7 @@ static void launch_fwd_g(const mrf_nufft_plan_s* p, const cf* img, cf* T, cf* pa
 template <int G, int TX>
 static void launch_adj_g(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, cf* T, cf* rg, hipStream_t s) {
   const int nrows = p->L * p->N;
-  constexpr int RPB = kBlock / (G / 8);
+  constexpr int RPB = row_rpb(G);
   const int FC = frames_per_chunk(p);
   const long total = (long)p->L * p->Ns;
   MRF_LAUNCH("nufft_gather_r", s,
@@ -745,7 +752,10 @@ static void launch_adj_g(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, cf* 
     case 128 * 100 + 32: FN<128, 32>(__VA_ARGS__); break;                            \
     case 256 * 100 + 8: FN<256, 8>(__VA_ARGS__); break;                              \
     case 256 * 100 + 16: FN<256, 16>(__VA_ARGS__); break;                            \
+    case 384 * 100 + 8: FN<384, 8>(__VA_ARGS__); break;                              \
+    case 384 * 100 + 16: FN<384, 16>(__VA_ARGS__); break;                            \
     case 512 * 100 + 8: FN<512, 8>(__VA_ARGS__); break;                              \
+    case 640 * 100 + 8: FN<640, 8>(__VA_ARGS__); break;                              \
     case 512 * 100 + 16: FN<512, 16>(__VA_ARGS__); break;                            \
     case 1024 * 100 + 8: FN<1024, 8>(__VA_ARGS__); break;                            \
     default: return fail(MRF_SHAPE, "nufft: unsupported grid / tile combination");  \
@@ -856,4 +866,98 @@ extern "C" mrf_status mrf_nufft_opnorm(mrf_nufft_plan_t p, int iters, unsigned s
   cleanup();
   if (st == MRF_OK) *lam = h[0];
   return st;
+}
+
+// Autotuner: times the forward + adjoint pair of the trajectory for every strip width the grid
+// allows (the spread tile is TX columns by G/4 rows) and returns the fastest. The entry order
+// inside a tile is fixed by the design: the atomics-free spread finds each row window's entries
+// with two ballots, which needs them sorted by footprint row.
+extern "C" mrf_status mrf_nufft_autotune(const mrf_nufft_desc* d, const float* traj, int reps, int* best_tile_cols,
+                                         float* pair_ms, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(d && traj && best_tile_cols && reps >= 1, MRF_INVALID_ARG, "nufft_autotune: bad argument");
+  const int cand[3] = {8, 16, 32};
+  const long nimg = (long)d->nframes * d->n * d->n, nksp = (long)d->nframes * d->nsamp;
+  cf *x = nullptr, *k = nullptr;
+  void* ws = nullptr;
+  size_t ws_have = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    hipFree(x); hipFree(k); hipFree(ws);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  };
+  if (hipMalloc(&x, nimg * 8) != hipSuccess || hipMalloc(&k, nksp * 8) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return fail(MRF_OOM, "nufft_autotune: device allocation failed");
+  }
+  k_hash_fill<<<1024, 256, 0, s>>>(x, nimg, 7u);
+  float best = -1.f;
+  int best_tx = 0;
+  for (int c = 0; c < 3; ++c) {
+    if (pair_ms) pair_ms[c] = -1.f;
+    const int G = 2 * d->n, TX = cand[c];
+    if (!(TX <= G / 2 && (long)G * TX <= 8192 && (TX < 32 || G <= 128))) continue;
+    bool dispatched = false;
+    switch (G * 100 + TX) {
+      case 32 * 100 + 8: case 32 * 100 + 16: case 64 * 100 + 8: case 64 * 100 + 16: case 64 * 100 + 32:
+      case 128 * 100 + 8: case 128 * 100 + 16: case 128 * 100 + 32: case 256 * 100 + 8: case 256 * 100 + 16:
+      case 384 * 100 + 8: case 384 * 100 + 16: case 512 * 100 + 8: case 512 * 100 + 16: case 640 * 100 + 8:
+      case 1024 * 100 + 8:
+        dispatched = true;
+        break;
+      default:
+        break;
+    }
+    if (!dispatched) continue;
+    mrf_nufft_desc dc = *d;
+    dc.tile_cols = TX;
+    mrf_nufft_plan_t p = nullptr;
+    mrf_status st = mrf_nufft_plan_create(&dc, traj, s, &p);
+    if (st != MRF_OK) {
+      cleanup();
+      return st;
+    }
+    if (p->ws_bytes > ws_have) {
+      hipFree(ws);
+      ws = nullptr;
+      if (hipMalloc(&ws, p->ws_bytes) != hipSuccess) {
+        mrf_nufft_plan_destroy(p);
+        cleanup();
+        return fail(MRF_OOM, "nufft_autotune: workspace allocation failed");
+      }
+      ws_have = p->ws_bytes;
+    }
+    st = mrf_nufft_fwd(p, (const mrf_c64*)x, (mrf_c64*)k, ws, ws_have, s);
+    if (st == MRF_OK) st = mrf_nufft_adj(p, (const mrf_c64*)k, (mrf_c64*)x, ws, ws_have, s);
+    hipEventRecord(e0, s);
+    for (int r = 0; r < reps && st == MRF_OK; ++r) {
+      st = mrf_nufft_fwd(p, (const mrf_c64*)x, (mrf_c64*)k, ws, ws_have, s);
+      if (st == MRF_OK) st = mrf_nufft_adj(p, (const mrf_c64*)k, (mrf_c64*)x, ws, ws_have, s);
+    }
+    hipEventRecord(e1, s);
+    float ms = 0.f;
+    hipError_t he = hipEventSynchronize(e1);
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    mrf_nufft_plan_destroy(p);
+    if (st != MRF_OK) {
+      cleanup();
+      return st;
+    }
+    if (he != hipSuccess) {
+      cleanup();
+      return fail(MRF_DEVICE, std::string("nufft_autotune: ") + hipGetErrorString(he));
+    }
+    ms /= reps;
+    if (pair_ms) pair_ms[c] = ms;
+    if (best < 0.f || ms < best) {
+      best = ms;
+      best_tx = TX;
+    }
+  }
+  cleanup();
+  MRF_REQUIRE(best_tx > 0, MRF_SHAPE, "nufft_autotune: no strip width fits this grid");
+  *best_tile_cols = best_tx;
+  return MRF_OK;
 }

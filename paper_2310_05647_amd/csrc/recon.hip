@@ -102,6 +102,8 @@ struct mrf_recon_s {
   void *nws, *rws, *lws;
   double *sc, *rpart;
   bool initialised;
+  bool pending_graph;   // a rebuilt graph whose scalars are not yet recorded
+  double* hsc;          // pinned host copy of the device scalars
   double c_prev;
   mrf_recon_stats st;
   std::vector<void*> allocs;
@@ -123,8 +125,8 @@ mrf_status rebuild(mrf_recon_s* R, hipStream_t s) {
   return MRF_OK;
 }
 
-// cost terms of the current X (with the current graph); reads them back (synchronises)
-mrf_status evaluate(mrf_recon_s* R, hipStream_t s, double* h) {
+// cost terms of the current X (with the current graph), copied to the pinned host scalars
+mrf_status evaluate_enqueue(mrf_recon_s* R, hipStream_t s) {
   mrf_status e;
   if ((e = nufft_residual(R->plan, R->X, R->b, R->res, R->nws, R->rpart, R->sc + SC_RN2, s))) return e;
   if ((e = llr_analyse(R->X, R->g, R->L, 1.0 / R->prm.beta, R->prm.rank_cap, R->lws, R->U, R->f, R->sc + SC_NUC,
@@ -133,8 +135,16 @@ mrf_status evaluate(mrf_recon_s* R, hipStream_t s, double* h) {
   if ((e = lap_quad(R->graph, R->X, R->L, R->sc + SC_QUAD, s))) return e;
   MRF_LAUNCH("recon_cost", s, k_cost<<<1, 1, 0, s>>>(R->sc, R->prm.lam2));
   MRF_CHECK_LAUNCH();
-  MRF_CHECK_HIP(hipMemcpyAsync(h, R->sc, SC_N * sizeof(double), hipMemcpyDeviceToHost, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(R->hsc, R->sc, SC_N * sizeof(double), hipMemcpyDeviceToHost, s));
+  return MRF_OK;
+}
+
+// the same, waiting for the result
+mrf_status evaluate(mrf_recon_s* R, hipStream_t s, double* h) {
+  mrf_status e = evaluate_enqueue(R, s);
+  if (e) return e;
   MRF_CHECK_HIP(hipStreamSynchronize(s));
+  std::copy(R->hsc, R->hsc + SC_N, h);
   if (!std::isfinite(h[SC_COST])) return fail(MRF_NONFINITE, "recon: cost is not finite");
   return MRF_OK;
 }
@@ -211,6 +221,7 @@ extern "C" mrf_status mrf_recon_create(const mrf_recon_params* prm, mrf_nufft_pl
             (R->idx = (int*)alloc(Nv * 4)) && (R->nws = alloc(nufft_ws_bytes(plan))) &&
             (R->rws = alloc(reduce_ws_bytes(L, (int)Nv, (int)rr))) && (R->lws = alloc(llr_ws_bytes(R->g, (int)rc))) &&
             (R->sc = (double*)alloc(SC_N * 8)) && (R->rpart = (double*)alloc(nufft_resid_blocks(plan) * 8));
+  if (ok) ok = hipHostMalloc((void**)&R->hsc, SC_N * sizeof(double), hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     mrf_recon_destroy(R);
     return fail(MRF_OOM, "recon_create: device allocation failed");
@@ -223,6 +234,7 @@ extern "C" mrf_status mrf_recon_destroy(mrf_recon_t R) {
   clear_error();
   if (!R) return MRF_OK;
   for (void* p : R->allocs) hipFree(p);
+  if (R->hsc) hipHostFree(R->hsc);
   mrf_graph_destroy(R->graph);
   delete R;
   return MRF_OK;
@@ -233,6 +245,7 @@ extern "C" mrf_status mrf_recon_init(mrf_recon_t R, const mrf_c64* b, const mrf_
   MRF_REQUIRE(R && b, MRF_INVALID_ARG, "recon_init: null argument");
   R->b = (const cf*)b;
   R->st = mrf_recon_stats{};
+  R->pending_graph = false;
   mrf_status e;
   if (X0) {
     MRF_LAUNCH("recon_copy", s, k_copy_c<<<1024, 256, 0, s>>>((const cf*)X0, R->X, (size_t)R->L * R->Nv));
@@ -250,44 +263,87 @@ extern "C" mrf_status mrf_recon_init(mrf_recon_t R, const mrf_c64* b, const mrf_
   return MRF_OK;
 }
 
+namespace {
+
+bool active(const mrf_recon_s* R) { return R->st.stop_reason == 0 && R->st.iters < R->prm.n_max; }
+
+// Enqueues one iteration: the graph rebuild left by the previous one (if any), the gradient step
+// with the projection (eqs. (15), (17)), the SVT of Q(X^n) from the previous eigen-analysis and
+// the X update (eq. (23)), and the cost of X^{n+1}, whose terms are copied to the host.
+mrf_status enqueue_step(mrf_recon_s* R, hipStream_t s) {
+  const int L = R->L, Nv = R->Nv, r = R->r, rc = R->prm.rank_cap;
+  const cf* V = dict_basis(R->dict);
+  mrf_status e;
+  if (R->pending_graph && (e = rebuild(R, s))) return e;
+  if ((e = nufft_adj_impl(R->plan, R->res, R->ZG, R->nws, s))) return e;                      // G = A^H r
+  if ((e = subspace_reduce(R->X, R->ZG, R->sc + SC_MU, V, L, Nv, r, R->aU, (cf*)R->rws, s))) return e;
+  if ((e = lap_apply_sub(R->graph, R->aX, R->Ya, r, s))) return e;                            // S_L(X V)
+  if ((e = axpy_scal(R->aU, R->Ya, R->sc + SC_MU, R->sc + SC_LAM1, 1.0, (long)Nv * r, R->beta, s))) return e;
+  if ((e = subspace_expand(R->beta, V, L, Nv, r, R->ZG, s))) return e;                        // Z
+  if ((e = llr_coef(R->X, R->g, L, rc, R->U, R->f, R->C, s))) return e;
+  if ((e = llr_xupdate(R->ZG, R->U, R->C, R->g, L, rc, R->sc + SC_KAP, 1.0, R->X, s))) return e;
+  return evaluate_enqueue(R, s);
+}
+
+// Waits for the step's cost terms, records them and applies the stopping rule; when another
+// iteration follows, the next graph rebuild is left to it (its scalars arrive with its cost).
+mrf_status complete_step(mrf_recon_s* R, hipStream_t s) {
+  MRF_CHECK_HIP(hipStreamSynchronize(s));
+  const double* h = R->hsc;
+  if (!std::isfinite(h[SC_COST])) return fail(MRF_NONFINITE, "recon: cost is not finite");
+  if (R->pending_graph) record_graph(R, h);
+  R->pending_graph = false;
+  R->st.iters += 1;
+  record(R, h, false);
+  const double c = h[SC_COST];
+  if (R->prm.tol >= 0.0 && R->c_prev / c - 1.0 < R->prm.tol) {
+    R->st.stop_reason = 1;
+    return MRF_OK;
+  }
+  R->c_prev = c;
+  R->pending_graph = R->st.iters < R->prm.n_max;   // M^{n+1}, L^{n+1}, lambda1 before the next step
+  return MRF_OK;
+}
+
+}  // namespace
+
 extern "C" mrf_status mrf_recon_iterate(mrf_recon_t R, int n, int* stopped, hipStream_t s) {
   clear_error();
   MRF_REQUIRE(R && R->initialised, MRF_INVALID_ARG, "recon_iterate: call mrf_recon_init first");
   MRF_REQUIRE(n >= 0, MRF_INVALID_ARG, "recon_iterate: n must be >= 0");
-  if (stopped) *stopped = R->st.stop_reason != 0;
-  const int L = R->L, Nv = R->Nv, r = R->r, rc = R->prm.rank_cap;
-  const cf* V = dict_basis(R->dict);
   mrf_status e;
-  for (int it = 0; it < n && R->st.stop_reason == 0 && R->st.iters < R->prm.n_max; ++it) {
-    // gradient step with the subspace projection (eqs. (15), (17))
-    if ((e = nufft_adj_impl(R->plan, R->res, R->ZG, R->nws, s))) return e;                      // G = A^H r
-    if ((e = subspace_reduce(R->X, R->ZG, R->sc + SC_MU, V, L, Nv, r, R->aU, (cf*)R->rws, s))) return e;
-    if ((e = lap_apply_sub(R->graph, R->aX, R->Ya, r, s))) return e;                            // S_L(X V)
-    if ((e = axpy_scal(R->aU, R->Ya, R->sc + SC_MU, R->sc + SC_LAM1, 1.0, (long)Nv * r, R->beta, s))) return e;
-    if ((e = subspace_expand(R->beta, V, L, Nv, r, R->ZG, s))) return e;                        // Z
-    // SVT of Q(X^n) (eigen-analysis from the previous evaluation) and the X update (eq. (23))
-    if ((e = llr_coef(R->X, R->g, L, rc, R->U, R->f, R->C, s))) return e;
-    if ((e = llr_xupdate(R->ZG, R->U, R->C, R->g, L, rc, R->sc + SC_KAP, 1.0, R->X, s))) return e;
-    // cost of X^{n+1} (also the next residual and eigen-analysis)
-    double h[SC_N];
-    if ((e = evaluate(R, s, h))) return e;
-    R->st.iters += 1;
-    record(R, h, false);
-    const double c = h[SC_COST];
-    if (R->prm.tol >= 0.0 && R->c_prev / c - 1.0 < R->prm.tol) {
-      R->st.stop_reason = 1;
-      break;
-    }
-    R->c_prev = c;
-    if (R->st.iters < R->prm.n_max) {
-      if ((e = rebuild(R, s))) return e;
-      double h2[SC_N];
-      MRF_CHECK_HIP(hipMemcpyAsync(h2, R->sc, SC_N * sizeof(double), hipMemcpyDeviceToHost, s));
-      MRF_CHECK_HIP(hipStreamSynchronize(s));
-      record_graph(R, h2);
-    }
+  for (int it = 0; it < n && active(R); ++it) {
+    if ((e = enqueue_step(R, s))) return e;
+    if ((e = complete_step(R, s))) return e;
   }
-  if (stopped) *stopped = R->st.stop_reason != 0 || R->st.iters >= R->prm.n_max;
+  if (stopped) *stopped = !active(R);
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_recon_batched(int nslices, const mrf_recon_t* Rs, const hipStream_t* streams, int n,
+                                        int* n_active) {
+  clear_error();
+  MRF_REQUIRE(nslices >= 1 && Rs && streams && n >= 0, MRF_INVALID_ARG, "recon_batched: bad argument");
+  for (int i = 0; i < nslices; ++i)
+    MRF_REQUIRE(Rs[i] && Rs[i]->initialised, MRF_INVALID_ARG, "recon_batched: every slice needs mrf_recon_init");
+  mrf_status e;
+  for (int it = 0; it < n; ++it) {
+    bool any = false;
+    for (int i = 0; i < nslices; ++i)
+      if (active(Rs[i])) {
+        if ((e = enqueue_step(Rs[i], streams[i]))) return e;
+        any = true;
+      }
+    if (!any) break;
+    for (int i = 0; i < nslices; ++i)
+      if (Rs[i]->st.iters < Rs[i]->prm.n_max && Rs[i]->st.stop_reason == 0 && (e = complete_step(Rs[i], streams[i])))
+        return e;
+  }
+  if (n_active) {
+    int k = 0;
+    for (int i = 0; i < nslices; ++i) k += active(Rs[i]);
+    *n_active = k;
+  }
   return MRF_OK;
 }
 

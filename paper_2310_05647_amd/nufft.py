@@ -20,6 +20,18 @@ def _need(t, dtype, shape, name):
         raise ValueError("%s must be a contiguous CUDA %s tensor of shape %s" % (name, dtype, tuple(shape)))
 
 
+def autotune(n, traj, reps=3, stream=None):
+    """Fastest strip width for this trajectory: returns (tile_cols, {tile_cols: mean pair ms})."""
+    L, Ns, _ = traj.shape
+    _need(traj, torch.float32, (L, Ns, 2), "traj")
+    desc = NufftDesc(int(n), int(L), int(Ns), 6, 2, 0)
+    best = ctypes.c_int()
+    times = (ctypes.c_float * 3)()
+    check(lib.mrf_nufft_autotune(ctypes.byref(desc), _ptr(traj), int(reps), ctypes.byref(best), times,
+                                 _stream(stream)), "mrf_nufft_autotune")
+    return best.value, {tx: t for tx, t in zip((8, 16, 32), times) if t >= 0}
+
+
 class NufftPlan:
     """Plan of A / A^H for a fixed trajectory traj [L, Ns, 2] (float32, rad/pixel, device)."""
 

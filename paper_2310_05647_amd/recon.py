@@ -69,3 +69,15 @@ class Recon:
             self.close()
         except Exception:
             pass
+
+
+def recon_batched(recons, streams, n):
+    """Advances several initialised Recon objects by up to n iterations each, every slice's work on
+    its own torch stream (mrf_recon_batched). Returns the number of slices still running."""
+    if len(recons) != len(streams) or not recons:
+        raise ValueError("need one stream per slice")
+    hs = (ctypes.c_void_p * len(recons))(*[r.handle.value for r in recons])
+    ss = (ctypes.c_void_p * len(streams))(*[s.cuda_stream for s in streams])
+    active = ctypes.c_int()
+    check(lib.mrf_recon_batched(len(recons), hs, ss, int(n), ctypes.byref(active)), "mrf_recon_batched")
+    return active.value

@@ -32,7 +32,8 @@ def _edge_traj(rng, L, Ns):
 
 
 @pytest.mark.parametrize("N,L,Ns,tx", [(16, 3, 37, 0), (32, 4, 200, 8), (32, 2, 1, 16), (64, 3, 333, 32),
-                                       (128, 2, 700, 0), (256, 2, 257, 0), (512, 1, 300, 0)])
+                                       (128, 2, 700, 0), (192, 2, 500, 0), (192, 3, 301, 16), (256, 2, 257, 0),
+                                       (320, 2, 600, 0), (512, 1, 300, 0)])
 def test_random_trajectory_parity(N, L, Ns, tx):
     from paper_2310_05647_amd import NufftPlan
     say(f"nufft parity N={N} L={L} Ns={Ns} tile_cols={tx}")
