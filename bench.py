@@ -234,7 +234,7 @@ def bench_batched(torch, mrf, dev, rounds=3):
     return out
 
 
-def cpu_baseline(cfg, traj, frames=16):
+def cpu_baseline(cfg, traj, frames=320):
     """The oracle's NUFFT pair (FP64 KB gridding) on a frame sample, scaled to the volume."""
     from oracle import nufft as onufft
     rng = np.random.default_rng(0)
@@ -375,7 +375,11 @@ def main():
         comps_extra["batched_c5"] = bench_batched(torch, mrf, dev)
 
     cpu = None
-    if not args.no_cpu_baseline:    out = {
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(cfg, traj)
+
+    out = {
         "metric": METRIC,
         "value": round(1000.0 / ms, 3),
         "unit": "NUFFT pairs/s",

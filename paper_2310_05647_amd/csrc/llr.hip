@@ -627,6 +627,90 @@ __global__ __launch_bounds__(256) void k_coef_any(const cf* __restrict__ X, cons
 // that cover the tile are staged in LDS for FCH frames at a time.
 constexpr int kTile = 16;
 constexpr int kXuFch = 8;
+
+// The same X update when every pixel has at most 4 covering patches (p <= 2 s) and rcap <= RC:
+// each thread keeps U[i][k][a_i(v)] of its covering patches in registers for the whole frame
+// range, and the covering patches' C rows are staged in LDS 16 frames at a time.
+constexpr int kXrFch = 16;
+template <int RC, bool WITHZ>
+__global__ __launch_bounds__(256) void k_xupdate_reg(const cf* __restrict__ Z, const cf* __restrict__ U,
+                                                     const cf* __restrict__ C, PatchGeom g, int L, int rcap,
+                                                     const double* __restrict__ kap_ptr, double kap_scale, int fpb,
+                                                     cf* __restrict__ Xout) {
+  extern __shared__ cf Cs[];   // [npt][rcap][kXrFch]
+  const int ntx = g.N / kTile;
+  const int ty = blockIdx.x / ntx, tx = blockIdx.x % ntx;
+  const int t = threadIdx.x;
+  const int py = ty * kTile + t / kTile, px = tx * kTile + t % kTile;
+  const int v = py * g.N + px;
+  const int cy0 = ty * kTile / g.s, cy1 = (ty * kTile + kTile - 1) / g.s;
+  const int cx0 = tx * kTile / g.s, cx1 = (tx * kTile + kTile - 1) / g.s;
+  const int alo = max(0, cy0 - g.ppc + 1), ahi = min(g.n1 - 1, cy1);
+  const int blo = max(0, cx0 - g.ppc + 1), bhi = min(g.n1 - 1, cx1);
+  const int nb = bhi - blo + 1, npt = (ahi - alo + 1) * nb;
+  int a0, a1, b0, b1;
+  cover_range(g, py / g.s, a0, a1);
+  cover_range(g, px / g.s, b0, b1);
+  const int na = a1 - a0 + 1, nbb = b1 - b0 + 1, ncov = na * nbb;
+  const int PP = g.p * g.p;
+  cf u[4][RC];
+  int qo[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int a = a0 + (c < ncov ? c / nbb : 0), b = b0 + (c < ncov ? c % nbb : 0);
+    const int i = a * g.n1 + b;
+    qo[c] = ((a - alo) * nb + (b - blo)) * rcap * kXrFch;
+    const int ap = (py - a * g.s) * g.p + (px - b * g.s);
+#pragma unroll
+    for (int k = 0; k < RC; ++k)
+      u[c][k] = (c < ncov && k < rcap) ? U[((size_t)i * rcap + k) * PP + ap] : cf{0.f, 0.f};
+  }
+  const float kap = WITHZ ? (float)(kap_ptr[0] * kap_scale) : 1.f;
+  const float den = WITHZ ? 1.f / (1.f + kap * ncov) : 1.f;
+  const int l0 = blockIdx.y * fpb, l1 = min(L, l0 + fpb);
+  for (int lc = l0; lc < l1; lc += kXrFch) {
+    const int nf = min(kXrFch, l1 - lc);
+    __syncthreads();
+    for (int idx = t; idx < npt * rcap * kXrFch; idx += 256) {
+      const int f = idx % kXrFch, k = (idx / kXrFch) % rcap, q = idx / (kXrFch * rcap);
+      const int i = (alo + q / nb) * g.n1 + blo + q % nb;
+      Cs[idx] = f < nf ? C[((size_t)i * rcap + k) * L + lc + f] : cf{0.f, 0.f};
+    }
+    __syncthreads();
+    cf acc[kXrFch];
+#pragma unroll
+    for (int f = 0; f < kXrFch; ++f) acc[f] = cf{0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (c < ncov) {
+#pragma unroll
+        for (int k = 0; k < RC; ++k) {
+          if (k < rcap) {
+            const float4* cs = (const float4*)(Cs + qo[c] + k * kXrFch);
+#pragma unroll
+            for (int f2 = 0; f2 < kXrFch / 2; ++f2) {
+              const float4 w = cs[f2];
+              acc[2 * f2] = cadd(acc[2 * f2], cmul(u[c][k], cf{w.x, w.y}));
+              acc[2 * f2 + 1] = cadd(acc[2 * f2 + 1], cmul(u[c][k], cf{w.z, w.w}));
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < kXrFch; ++f)
+      if (f < nf) {
+        const size_t o = (size_t)(lc + f) * g.N * g.N + v;
+        if (WITHZ) {
+          const cf zv = Z[o];
+          Xout[o] = cf{(zv.x + kap * acc[f].x) * den, (zv.y + kap * acc[f].y) * den};
+        } else {
+          Xout[o] = acc[f];
+        }
+      }
+  }
+}
+
 template <bool WITHZ>
 __global__ __launch_bounds__(256) void k_xupdate(const cf* __restrict__ Z, const cf* __restrict__ U,
                                                  const cf* __restrict__ C, PatchGeom g, int L, int rcap,
@@ -778,6 +862,26 @@ mrf_status llr_xupdate(const cf* Z, const cf* U, const cf* C, const PatchGeom& g
   if (g.N % kTile != 0) return fail(MRF_SHAPE, "x update: N must be a multiple of 16");
   const int ntile = (g.N / kTile) * (g.N / kTile);
   const int ca = kTile / g.s + g.ppc;   // covering patches per tile side (upper bound)
+  if (g.ppc <= 2 && rcap <= 16) {
+    const size_t lds = (size_t)ca * ca * rcap * kXrFch * sizeof(cf);
+    if (lds <= 64 * 1024) {
+      // frame groups: enough blocks to fill the chip, whole 16-frame chunks
+      const int fpb = std::max(kXrFch, ((L + 15) / 16 + kXrFch - 1) / kXrFch * kXrFch);
+      dim3 grid(ntile, (L + fpb - 1) / fpb);
+#define MRF_XR(RCv, W, NAME, ZP, KP, KS)                                                                  \
+  MRF_LAUNCH(NAME, s, k_xupdate_reg<RCv, W><<<grid, 256, lds, s>>>(ZP, U, C, g, L, rcap, KP, KS, fpb, Xout))
+      if (rcap <= 10) {
+        if (Z) MRF_XR(10, true, "llr_xupdate", Z, kap_dev, kap_scale);
+        else MRF_XR(10, false, "llr_qtp", nullptr, nullptr, 1.0);
+      } else {
+        if (Z) MRF_XR(16, true, "llr_xupdate", Z, kap_dev, kap_scale);
+        else MRF_XR(16, false, "llr_qtp", nullptr, nullptr, 1.0);
+      }
+#undef MRF_XR
+      MRF_CHECK_LAUNCH();
+      return MRF_OK;
+    }
+  }
   const size_t lds = (size_t)ca * ca * rcap * kXuFch * sizeof(cf);
   if (lds > 64 * 1024) return fail(MRF_SHAPE, "x update: too many patches per tile");
   const int fpb = std::max(kXuFch, ((L + 63) / 64 + kXuFch - 1) / kXuFch * kXuFch);

@@ -45,6 +45,8 @@ mrf_status subspace_reduce(const cf* X, const cf* Gd, const double* mu_dev, cons
 mrf_status subspace_expand(const cf* beta, const cf* V, int L, int Nv, int r, cf* Z, hipStream_t s);
 mrf_status axpy_scal(const cf* aU, const cf* Y, const double* s0, const double* s1, double scale, long n, cf* out,
                      hipStream_t s);
+mrf_status grad_coef(const cf* aX, const cf* aG, const cf* Y, const double* mu, const double* lam1, long n, cf* out,
+                     hipStream_t s);
 mrf_status match_subspace(const mrf_dict_s* D, const cf* alpha, int Nv, int* idx, float* rho, float* score,
                           float* params, hipStream_t s);
 mrf_status maps_from_match(const mrf_dict_s* D, const int* idx, const float* rho, int Nv, float* maps, hipStream_t s);
@@ -275,10 +277,11 @@ mrf_status enqueue_step(mrf_recon_s* R, hipStream_t s) {
   const cf* V = dict_basis(R->dict);
   mrf_status e;
   if (R->pending_graph && (e = rebuild(R, s))) return e;
+  // aX = X V is current: the graph rebuild (or the initialisation) computed it from this X
   if ((e = nufft_adj_impl(R->plan, R->res, R->ZG, R->nws, s))) return e;                      // G = A^H r
-  if ((e = subspace_reduce(R->X, R->ZG, R->sc + SC_MU, V, L, Nv, r, R->aU, (cf*)R->rws, s))) return e;
+  if ((e = subspace_reduce(R->ZG, nullptr, nullptr, V, L, Nv, r, R->aU, (cf*)R->rws, s))) return e;  // G V
   if ((e = lap_apply_sub(R->graph, R->aX, R->Ya, r, s))) return e;                            // S_L(X V)
-  if ((e = axpy_scal(R->aU, R->Ya, R->sc + SC_MU, R->sc + SC_LAM1, 1.0, (long)Nv * r, R->beta, s))) return e;
+  if ((e = grad_coef(R->aX, R->aU, R->Ya, R->sc + SC_MU, R->sc + SC_LAM1, (long)Nv * r, R->beta, s))) return e;
   if ((e = subspace_expand(R->beta, V, L, Nv, r, R->ZG, s))) return e;                        // Z
   if ((e = llr_coef(R->X, R->g, L, rc, R->U, R->f, R->C, s))) return e;
   if ((e = llr_xupdate(R->ZG, R->U, R->C, R->g, L, rc, R->sc + SC_KAP, 1.0, R->X, s))) return e;

@@ -159,6 +159,17 @@ __global__ void k_axpy_scal(const cf* __restrict__ aU, const cf* __restrict__ Y,
   out[i] = cf{aU[i].x - c * Y[i].x, aU[i].y - c * Y[i].y};
 }
 
+// beta = aX - mu (aG + lam1 Y): the projected gradient step in the coefficient space, with
+// aX = X V, aG = (A^H r) V, Y = S_L(X V) and mu, lam1 from device scalars
+__global__ void k_grad_coef(const cf* __restrict__ aX, const cf* __restrict__ aG, const cf* __restrict__ Y,
+                            const double* __restrict__ mu, const double* __restrict__ lam1, long n,
+                            cf* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float m = (float)mu[0], c = (float)(mu[0] * lam1[0]);
+  out[i] = cf{aX[i].x - m * aG[i].x - c * Y[i].x, aX[i].y - m * aG[i].y - c * Y[i].y};
+}
+
 // ---------------------------------------------------------------- subspace match (MFMA)
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -295,6 +306,13 @@ mrf_status subspace_expand(const cf* beta, const cf* V, int L, int Nv, int r, cf
 mrf_status axpy_scal(const cf* aU, const cf* Y, const double* s0, const double* s1, double scale, long n, cf* out,
                      hipStream_t s) {
   MRF_LAUNCH("subspace_axpy", s, k_axpy_scal<<<ceil_div(n, 256), 256, 0, s>>>(aU, Y, s0, s1, scale, n, out));
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+
+mrf_status grad_coef(const cf* aX, const cf* aG, const cf* Y, const double* mu, const double* lam1, long n, cf* out,
+                     hipStream_t s) {
+  MRF_LAUNCH("subspace_axpy", s, k_grad_coef<<<ceil_div(n, 256), 256, 0, s>>>(aX, aG, Y, mu, lam1, n, out));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
 }
