@@ -36,10 +36,29 @@ __device__ inline dcplx dmul(dcplx a, dcplx b) { return {a.x * b.x - a.y * b.y, 
 __device__ inline dcplx dconjmul(dcplx a, dcplx b) { return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x}; }
 __device__ inline dcplx dscale(dcplx a, double s) { return {a.x * s, a.y * s}; }
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+// Sum over the 64 lanes of a wave, returned in every lane; the whole wave must be active.
+// Within each 16-lane row by DPP (quad permutes for xor 1 and xor 2, then row rotations by 4
+// and 8), then the four row sums read with readlane, in a fixed order.
+template <int CTRL>
+__device__ inline double dpp64(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
+}
+__device__ inline double row_sum16(double v) {
+  v += dpp64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp64<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp64<0x124>(v);   // row_ror 4
+  v += dpp64<0x128>(v);   // row_ror 8
   return v;
+}
+__device__ inline double lane_value(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ inline double wave_sum(double v) {
+  v = row_sum16(v);
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
 // Patch index of the b-th block, XCD-aware: blocks go to the 8 XCDs round-robin, and each XCD
@@ -59,7 +78,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 //   Re G = Pr Pr^T + Pi Pi^T,   Im G = Pi Pr^T - Pr Pi^T.
 // The 16 x 16 tiles (a, b) of the upper triangle are shared out over the block's waves; per
 // group of 4 frames a lane reads one complex value of each operand from LDS and issues the four
-// MFMAs of the tile's real and imaginary parts. The kernel writes both triangles.
+// MFMAs of the tile's real and imaginary parts. The frame groups of a chunk are unrolled so that
+// the LDS reads run ahead of the MFMAs. The kernel writes both triangles.
 template <int PP>
 struct GramCfg {
   static constexpr int NT = PP / 16;                 // tiles per side
@@ -81,13 +101,11 @@ __global__ __launch_bounds__(GramCfg<PP>::NTHR) void k_gram(const cf* __restrict
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int oy = (i / g.n1) * g.s, ox = (i % g.n1) * g.s;
   const size_t NN = (size_t)g.N * g.N;
+  static_assert(C::NUP % C::NW == 0, "every wave takes the same number of tiles");
   int ta[TPW], tb[TPW];
-  bool on[TPW];
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
-    const int j = w + q * C::NW;
-    on[q] = j < C::NUP;
-    int u = on[q] ? j : 0, a = 0;
+    int u = w + q * C::NW, a = 0;
     while (u >= C::NT - a) {
       u -= C::NT - a;
       ++a;
@@ -120,17 +138,38 @@ __global__ __launch_bounds__(GramCfg<PP>::NTHR) void k_gram(const cf* __restrict
     }
     lds_sync();
     if (l0 + FCH < L) load(l0 + FCH);   // in flight during this chunk's MFMAs
+    // operands of frame group f0 + 4 are read while the MFMAs of group f0 run
+    cf pa[TPW], pb[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      pa[q] = P[lane / 16][ta[q] * 16 + lane % 16];
+      pb[q] = P[lane / 16][tb[q] * 16 + lane % 16];
+    }
+#pragma unroll
     for (int f0 = 0; f0 < FCH; f0 += 4) {
-      const int f = f0 + lane / 16;
+      cf na[TPW], nb[TPW];
+      if (f0 + 4 < FCH) {
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+          na[q] = P[f0 + 4 + lane / 16][ta[q] * 16 + lane % 16];
+          nb[q] = P[f0 + 4 + lane / 16][tb[q] * 16 + lane % 16];
+        }
+      }
 #pragma unroll
       for (int q = 0; q < TPW; ++q) {
-        if (on[q]) {
-          const cf pa = P[f][ta[q] * 16 + lane % 16];
-          const cf pb = ta[q] == tb[q] ? pa : P[f][tb[q] * 16 + lane % 16];
-          accr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa.x, pb.x, accr[q], 0, 0, 0);
-          accr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa.y, pb.y, accr[q], 0, 0, 0);
-          acci[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa.y, pb.x, acci[q], 0, 0, 0);
-          acci[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(-pa.x, pb.y, acci[q], 0, 0, 0);
+        accr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[q].x, pb[q].x, accr[q], 0, 0, 0);
+        acci[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[q].y, pb[q].x, acci[q], 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) {
+        accr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[q].y, pb[q].y, accr[q], 0, 0, 0);
+        acci[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(-pa[q].x, pb[q].y, acci[q], 0, 0, 0);
+      }
+      if (f0 + 4 < FCH) {
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+          pa[q] = na[q];
+          pb[q] = nb[q];
         }
       }
     }
@@ -139,15 +178,13 @@ __global__ __launch_bounds__(GramCfg<PP>::NTHR) void k_gram(const cf* __restrict
   cf* Gi = G + (size_t)i * PP * PP;
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
-    if (on[q]) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int a = ta[q] * 16 + 4 * (lane / 16) + e, b = tb[q] * 16 + lane % 16;
-        if (ta[q] == tb[q] && a > b) continue;   // diagonal tiles: the upper half writes both halves
-        const float vi = a == b ? 0.f : acci[q][e];
-        Gi[(size_t)a * PP + b] = cf{accr[q][e], vi};
-        Gi[(size_t)b * PP + a] = cf{accr[q][e], -vi};
-      }
+    for (int e = 0; e < 4; ++e) {
+      const int a = ta[q] * 16 + 4 * (lane / 16) + e, b = tb[q] * 16 + lane % 16;
+      if (ta[q] == tb[q] && a > b) continue;   // diagonal tiles: the upper half writes both halves
+      const float vi = a == b ? 0.f : acci[q][e];
+      Gi[(size_t)a * PP + b] = cf{accr[q][e], vi};
+      Gi[(size_t)b * PP + a] = cf{accr[q][e], -vi};
     }
   }
 }
@@ -477,50 +514,97 @@ __global__ __launch_bounds__(kEvT) void k_eig_vec(const double* __restrict__ dd,
   for (int q = 0; q < n; ++q) z[q] = y[q][t] * scale;
 }
 
-// u_k = H_0 H_1 ... H_{n-3} D z_k for the rcap vectors; one wave per patch, lane = row. Vectors
-// whose eigenvalues agree to 1e-6 of the largest are first orthogonalised against the earlier
-// ones of their cluster (modified Gram-Schmidt in the tridiagonal basis). Stores U[i][k][a] (FP32).
-__global__ __launch_bounds__(64) void k_backxf(const double* __restrict__ zvec, const double* __restrict__ lamtop,
-                                              const dcplx* __restrict__ refl, const double* __restrict__ rtau,
-                                              const dcplx* __restrict__ phase, int Np, int n, int rcap,
-                                              cf* __restrict__ U) {
+// u_k = H_0 H_1 ... H_{n-3} D z_k for the rcap vectors. One 4-wave block per patch: the patch's
+// reflectors (entries k+1 .. n-1 of row k) are staged once in LDS, packed by row. Wave 0 first
+// orthogonalises, in the tridiagonal basis, each vector against the earlier ones of its cluster
+// (eigenvalues within 1e-6 of the largest; modified Gram-Schmidt); then wave w back-transforms
+// the vectors k = w (mod 4), up to three at once so that their reductions overlap. Stores
+// U[i][k][a] (FP32); components with f_k = 0 (zero z) get zero vectors.
+constexpr int kBxPer = (kMaxRllr + 3) / 4;   // vectors per wave
+__global__ __launch_bounds__(256) void k_backxf(const double* __restrict__ zvec, const double* __restrict__ lamtop,
+                                               const dcplx* __restrict__ refl, const double* __restrict__ rtau,
+                                               const dcplx* __restrict__ phase, int Np, int n, int rcap,
+                                               cf* __restrict__ U) {
+  __shared__ dcplx R[kMaxPP * (kMaxPP - 1) / 2];   // row j at j (n - 1) - j (j - 1) / 2, entries j+1 .. n-1
   __shared__ double zs[kMaxRllr][kMaxPP];
+  __shared__ double tau[kMaxPP];
+  __shared__ int live[kMaxRllr];
   const int i = patch_of_block(Np);
   if (i < 0) return;
-  const int r = threadIdx.x;
+  const int t = threadIdx.x, w = t >> 6, r = t & 63;
   const dcplx* Ri = refl + (size_t)i * n * n;
-  const double* lt = lamtop + (size_t)i * rcap;
-  const double ctol = 1e-6 * fmax(fabs(lt[0]), 1e-300);
-  for (int k = 0; k < rcap && k < n; ++k) {
-    double z = r < n ? zvec[((size_t)i * rcap + k) * n + r] : 0.0;
-    if (wave_sum(z * z) == 0.0) {   // component with f = 0
-      if (r < n) U[((size_t)i * rcap + k) * n + r] = cf{0.f, 0.f};
-      zs[k][r] = 0.0;
-      continue;
-    }
-    bool moved = false;
-    for (int j = 0; j < k; ++j) {
-      if (fabs(lt[k] - lt[j]) > ctol) continue;
-      const double zj = zs[j][r];
-      const double dot = wave_sum(zj * z);
-      z -= dot * zj;
-      moved = true;
-    }
-    if (moved) z *= 1.0 / sqrt(fmax(wave_sum(z * z), 1e-300));
-    zs[k][r] = z;
-    dcplx u = r < n ? dscale(phase[(size_t)i * n + r], z) : dcplx{0.0, 0.0};
-    for (int j = n - 3; j >= 0; --j) {
-      const double tau = rtau[(size_t)i * n + j];
-      if (tau == 0.0) continue;
-      const dcplx v = r < n ? Ri[(size_t)j * n + r] : dcplx{0.0, 0.0};
-      // u -= tau v (v^H u)
-      const double dr = wave_sum(v.x * u.x + v.y * u.y);
-      const double di = wave_sum(v.x * u.y - v.y * u.x);
-      const dcplx c = dscale(dcplx{dr, di}, tau);
-      u = dsub(u, dmul(v, c));
-    }
-    if (r < n) U[((size_t)i * rcap + k) * n + r] = cf{(float)u.x, (float)u.y};
+  const int nref = n - 2 > 0 ? n - 2 : 0;
+  for (int idx = t; idx < nref * n; idx += 256) {
+    const int j = idx / n, c = idx % n;
+    if (c > j) R[j * (n - 1) - j * (j - 1) / 2 + c - j - 1] = Ri[idx];
   }
+  if (t < n) tau[t] = t < nref ? rtau[(size_t)i * n + t] : 0.0;
+  const int m = min(rcap, n);
+  for (int idx = t; idx < m * kMaxPP; idx += 256) {
+    const int k = idx / kMaxPP, q = idx % kMaxPP;
+    zs[k][q] = q < n ? zvec[((size_t)i * rcap + k) * n + q] : 0.0;
+  }
+  __syncthreads();
+  if (w == 0) {
+    const double* lt = lamtop + (size_t)i * rcap;
+    const double ctol = 1e-6 * fmax(fabs(lt[0]), 1e-300);
+    for (int k = 0; k < m; ++k) {
+      double z = zs[k][r];
+      const bool lv = wave_sum(z * z) != 0.0;
+      if (r == 0) live[k] = lv;
+      if (!lv) continue;
+      bool moved = false;
+      for (int j = 0; j < k; ++j) {
+        if (fabs(lt[k] - lt[j]) > ctol) continue;
+        const double zj = zs[j][r];
+        z -= wave_sum(zj * z) * zj;
+        moved = true;
+      }
+      if (moved) {
+        z *= 1.0 / sqrt(fmax(wave_sum(z * z), 1e-300));
+        zs[k][r] = z;
+      }
+    }
+  }
+  __syncthreads();
+  dcplx u[kBxPer];
+  const dcplx ph = r < n ? phase[(size_t)i * n + r] : dcplx{0.0, 0.0};
+#pragma unroll
+  for (int c = 0; c < kBxPer; ++c) {
+    const int k = w + 4 * c;
+    u[c] = k < m && live[k] ? dscale(ph, zs[k][r]) : dcplx{0.0, 0.0};
+  }
+  for (int j = nref - 1; j >= 0; --j) {
+    const double tj = tau[j];
+    if (tj == 0.0) continue;
+    const int off = j * (n - 1) - j * (j - 1) / 2;
+    const dcplx v = (r > j && r < n) ? R[off + r - j - 1] : dcplx{0.0, 0.0};
+    double dr[kBxPer], di[kBxPer];
+#pragma unroll
+    for (int c = 0; c < kBxPer; ++c) {
+      dr[c] = v.x * u[c].x + v.y * u[c].y;
+      di[c] = v.x * u[c].y - v.y * u[c].x;
+    }
+#pragma unroll
+    for (int c = 0; c < kBxPer; ++c) {
+      dr[c] = row_sum16(dr[c]);
+      di[c] = row_sum16(di[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < kBxPer; ++c) {
+      dr[c] = (lane_value(dr[c], 0) + lane_value(dr[c], 16)) + (lane_value(dr[c], 32) + lane_value(dr[c], 48));
+      di[c] = (lane_value(di[c], 0) + lane_value(di[c], 16)) + (lane_value(di[c], 32) + lane_value(di[c], 48));
+    }
+#pragma unroll
+    for (int c = 0; c < kBxPer; ++c) u[c] = dsub(u[c], dmul(v, dcplx{tj * dr[c], tj * di[c]}));
+  }
+#pragma unroll
+  for (int c = 0; c < kBxPer; ++c) {
+    const int k = w + 4 * c;
+    if (k < m && r < n) U[((size_t)i * rcap + k) * n + r] = cf{(float)u[c].x, (float)u[c].y};
+  }
+  for (int k = m; k < rcap; ++k)   // rank cap above the patch size: zero rows
+    if (w == 0 && r < n) U[((size_t)i * rcap + k) * n + r] = cf{0.f, 0.f};
 }
 
 // C[i][k][l] = f_k sum_a conj(U[i][k][a]) X[l][pixel a of patch i] on MFMA: D (k x frames) =
@@ -841,7 +925,7 @@ mrf_status llr_analyse(const cf* X, const PatchGeom& g, int L, double tau, int r
   MRF_LAUNCH("llr_eig", s, k_eig_val<<<nb, 64, 0, s>>>(w.dd, w.ee, g.Np, PP, tau, rcap, w.nuc, w.lam, f, lam_out));
   const int nv = (int)ceil_div((long)g.Np * rcap, (long)kEvT);
   MRF_LAUNCH("llr_eigvec", s, k_eig_vec<<<nv, kEvT, 0, s>>>(w.dd, w.ee, w.lam, f, g.Np, PP, rcap, w.z));
-  MRF_LAUNCH("llr_backxf", s, k_backxf<<<nb, 64, 0, s>>>(w.z, w.lam, w.refl, w.rtau, w.ph, g.Np, PP, rcap, U));
+  MRF_LAUNCH("llr_backxf", s, k_backxf<<<nb, 256, 0, s>>>(w.z, w.lam, w.refl, w.rtau, w.ph, g.Np, PP, rcap, U));
   MRF_LAUNCH("llr_nuc_sum", s, k_sum_d<<<1, 256, 0, s>>>(w.nuc, g.Np, nuc_out));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
