@@ -716,12 +716,13 @@ constexpr int kXuFch = 8;
 // each thread keeps U[i][k][a_i(v)] of its covering patches in registers for the whole frame
 // range, and the covering patches' C rows are staged in LDS 16 frames at a time.
 constexpr int kXrFch = 16;
+constexpr int kXrPad = 2;   // complex values of padding per patch block of Cs: its rows start on different banks
 template <int RC, bool WITHZ>
 __global__ __launch_bounds__(256) void k_xupdate_reg(const cf* __restrict__ Z, const cf* __restrict__ U,
                                                      const cf* __restrict__ C, PatchGeom g, int L, int rcap,
                                                      const double* __restrict__ kap_ptr, double kap_scale, int fpb,
                                                      cf* __restrict__ Xout) {
-  extern __shared__ cf Cs[];   // [npt][rcap][kXrFch]
+  extern __shared__ cf Cs[];   // [npt][rcap * kXrFch + kXrPad]
   const int ntx = g.N / kTile;
   const int ty = blockIdx.x / ntx, tx = blockIdx.x % ntx;
   const int t = threadIdx.x;
@@ -743,7 +744,7 @@ __global__ __launch_bounds__(256) void k_xupdate_reg(const cf* __restrict__ Z, c
   for (int c = 0; c < 4; ++c) {
     const int a = a0 + (c < ncov ? c / nbb : 0), b = b0 + (c < ncov ? c % nbb : 0);
     const int i = a * g.n1 + b;
-    qo[c] = ((a - alo) * nb + (b - blo)) * rcap * kXrFch;
+    qo[c] = ((a - alo) * nb + (b - blo)) * (rcap * kXrFch + kXrPad);
     const int ap = (py - a * g.s) * g.p + (px - b * g.s);
 #pragma unroll
     for (int k = 0; k < RC; ++k)
@@ -758,7 +759,7 @@ __global__ __launch_bounds__(256) void k_xupdate_reg(const cf* __restrict__ Z, c
     for (int idx = t; idx < npt * rcap * kXrFch; idx += 256) {
       const int f = idx % kXrFch, k = (idx / kXrFch) % rcap, q = idx / (kXrFch * rcap);
       const int i = (alo + q / nb) * g.n1 + blo + q % nb;
-      Cs[idx] = f < nf ? C[((size_t)i * rcap + k) * L + lc + f] : cf{0.f, 0.f};
+      Cs[q * (rcap * kXrFch + kXrPad) + k * kXrFch + f] = f < nf ? C[((size_t)i * rcap + k) * L + lc + f] : cf{0.f, 0.f};
     }
     __syncthreads();
     cf acc[kXrFch];
@@ -947,7 +948,7 @@ mrf_status llr_xupdate(const cf* Z, const cf* U, const cf* C, const PatchGeom& g
   const int ntile = (g.N / kTile) * (g.N / kTile);
   const int ca = kTile / g.s + g.ppc;   // covering patches per tile side (upper bound)
   if (g.ppc <= 2 && rcap <= 16) {
-    const size_t lds = (size_t)ca * ca * rcap * kXrFch * sizeof(cf);
+    const size_t lds = (size_t)ca * ca * (rcap * kXrFch + kXrPad) * sizeof(cf);
     if (lds <= 64 * 1024) {
       // frame groups: enough blocks to fill the chip, whole 16-frame chunks
       const int fpb = std::max(kXrFch, ((L + 15) / 16 + kXrFch - 1) / kXrFch * kXrFch);

@@ -223,20 +223,27 @@ __global__ __launch_bounds__(256) void k_match_sub(const cf* __restrict__ alpha,
       for (int q = 0; q < 10; ++q) bn[q] = bpk[((size_t)(t + 1) * 10 + q) * 64 + lane];
     }
     const int m = 16 * t + row;   // the atom (column) this lane's outputs belong to
+    // K-steps outer, row tiles inner: eight independent accumulation chains in flight
+    f32x4 cre[4], cim[4];
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt) {
-      f32x4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+      cre[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      cim[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
 #pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][q], b[q], cre, 0, 0, 0);
-        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][q], b[5 + q], cim, 0, 0, 0);
+    for (int q = 0; q < 5; ++q)
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) {
+        cre[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][q], b[q], cre[rt], 0, 0, 0);
+        cim[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][q], b[5 + q], cim[rt], 0, 0, 0);
       }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float s = m < M ? cre[i] * cre[i] + cim[i] * cim[i] : -1.f;
-        if (s > best[rt][i].s) best[rt][i] = Best{s, cre[i], m};
+        const float s = m < M ? cre[rt][i] * cre[rt][i] + cim[rt][i] * cim[rt][i] : -1.f;
+        if (s > best[rt][i].s) best[rt][i] = Best{s, cre[rt][i], m};
       }
-    }
 #pragma unroll
     for (int q = 0; q < 10; ++q) b[q] = bn[q];
   }
