@@ -112,10 +112,21 @@ __device__ inline void dft_regs(cf* v) {
   }
 }
 
+// Element n of a transform sits at padx<PS>(n) * ES: with PS > 0 one pad element follows every
+// 2^PS elements, so that the stride-R stores of the early passes spread over the LDS banks.
+template <int PS>
+__host__ __device__ constexpr int padx(int n) {
+  return PS ? n + (n >> PS) : n;
+}
+
 // One Stockham pass on NT transforms in LDS. CFAST: consecutive threads take consecutive
 // transforms (strip layout, ES > 1); otherwise consecutive butterflies (row layout, ES == 1).
-template <int G, int R, int NT, int ES, int TS, bool CFAST, bool INV>
+// ZIN: the inputs n in [G/4, 3G/4) are zero (zero-padded half of a 2x oversampled grid) and are
+// not read; only valid for a first pass (Ns = 1) of radix 8, whose butterflies then take r = 0, 1,
+// 6, 7. COUT: outputs n in [G/4, 3G/4) are not needed (cropped) and are not stored.
+template <int G, int R, int NT, int ES, int TS, bool CFAST, bool INV, int PS = 0, bool ZIN = false, bool COUT = false>
 __device__ inline void stockham_pass(cf* buf, const cf* tw, int Ns) {
+  static_assert(!ZIN || R == 8, "input pruning needs a radix-8 first pass");
   constexpr int NB = G / R;                 // butterflies per transform
   constexpr int TB = NB * NT;               // butterflies per pass
   constexpr int PER = (TB + kBlock - 1) / kBlock;
@@ -128,7 +139,8 @@ __device__ inline void stockham_pass(cf* buf, const cf* tw, int Ns) {
       const int c = CFAST ? id % NT : id / NB;
       const int j = CFAST ? id / NT : id % NB;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b][r] = buf[(j + r * NB) * ES + c * TS];
+      for (int r = 0; r < R; ++r)
+        v[b][r] = (ZIN && r >= 2 && r <= 5) ? cf{0.f, 0.f} : buf[padx<PS>(j + r * NB) * ES + c * TS];
     }
   }
   lds_sync();
@@ -151,24 +163,42 @@ __device__ inline void stockham_pass(cf* buf, const cf* tw, int Ns) {
       dft_regs<R, INV>(v[b]);
       const int d = (j / Ns) * Ns * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[(d + r * Ns) * ES + c * TS] = v[b][r];
+      for (int r = 0; r < R; ++r) {
+        const int o = d + r * Ns;
+        if (!COUT || o < G / 4 || o >= 3 * G / 4) buf[padx<PS>(o) * ES + c * TS] = v[b][r];
+      }
     }
   }
   lds_sync();
 }
 
 // Full in-LDS FFT of NT transforms of length G. tw[k] = exp(-2 pi i k / G) in LDS.
-template <int G, int NT, int ES, int TS, bool CFAST, bool INV>
+template <int G, int NT, int ES, int TS, bool CFAST, bool INV, int PS = 0, bool ZIN = false, bool COUT = false>
 __device__ inline void lds_fft(cf* buf, const cf* tw) {
   using P = FftPlan<G>;
+  static_assert(!ZIN || P::radix(0) == 8, "input pruning needs a radix-8 first pass");
   int Ns = 1;
 #pragma unroll
   for (int p = 0; p < P::npass; ++p) {
-    if (P::radix(p) == 8) stockham_pass<G, 8, NT, ES, TS, CFAST, INV>(buf, tw, Ns);
-    else if (P::radix(p) == 4) stockham_pass<G, 4, NT, ES, TS, CFAST, INV>(buf, tw, Ns);
-    else if (P::radix(p) == 2) stockham_pass<G, 2, NT, ES, TS, CFAST, INV>(buf, tw, Ns);
-    else if (P::radix(p) == 3) stockham_pass<G, 3, NT, ES, TS, CFAST, INV>(buf, tw, Ns);
-    else stockham_pass<G, 5, NT, ES, TS, CFAST, INV>(buf, tw, Ns);
+    const bool first = p == 0, last = p == P::npass - 1;
+    if (P::radix(p) == 8) {
+      if (first && last) stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS, ZIN, COUT>(buf, tw, Ns);
+      else if (first) stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS, ZIN, false>(buf, tw, Ns);
+      else if (last) stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS, false, COUT>(buf, tw, Ns);
+      else stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS>(buf, tw, Ns);
+    } else if (P::radix(p) == 4) {
+      if (last) stockham_pass<G, 4, NT, ES, TS, CFAST, INV, PS, false, COUT>(buf, tw, Ns);
+      else stockham_pass<G, 4, NT, ES, TS, CFAST, INV, PS>(buf, tw, Ns);
+    } else if (P::radix(p) == 2) {
+      if (last) stockham_pass<G, 2, NT, ES, TS, CFAST, INV, PS, false, COUT>(buf, tw, Ns);
+      else stockham_pass<G, 2, NT, ES, TS, CFAST, INV, PS>(buf, tw, Ns);
+    } else if (P::radix(p) == 3) {
+      if (last) stockham_pass<G, 3, NT, ES, TS, CFAST, INV, PS, false, COUT>(buf, tw, Ns);
+      else stockham_pass<G, 3, NT, ES, TS, CFAST, INV, PS>(buf, tw, Ns);
+    } else {
+      if (last) stockham_pass<G, 5, NT, ES, TS, CFAST, INV, PS, false, COUT>(buf, tw, Ns);
+      else stockham_pass<G, 5, NT, ES, TS, CFAST, INV, PS>(buf, tw, Ns);
+    }
     Ns *= P::radix(p);
   }
 }

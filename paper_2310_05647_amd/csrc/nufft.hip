@@ -81,7 +81,8 @@ __global__ __launch_bounds__(kBlock) void k_row_fwd(const cf* __restrict__ X, cf
                                                     const cf* __restrict__ twg, int nrows) {
   constexpr int N = G / 2;
   constexpr int RPB = row_rpb(G);          // rows per group
-  constexpr int TS = G + 1;
+  constexpr int PS = 3;                    // one pad element per 8 (LDS banks)
+  constexpr int TS = padx<PS>(G) + 1;
   constexpr int PIN = (RPB * N + kBlock - 1) / kBlock;   // non-zero inputs per thread
   __shared__ cf buf[RPB * TS];
   __shared__ cf tw[G];
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_row_fwd(const cf* __restrict__ X, cf
     // zero the padding, place the deapodised inputs at (x - N/2) mod G
     for (int idx = tid; idx < RPB * (G - N); idx += kBlock) {
       const int rr = idx / (G - N), n = N / 2 + idx % (G - N);
-      buf[rr * TS + n] = cf{0.f, 0.f};
+      buf[rr * TS + padx<PS>(n)] = cf{0.f, 0.f};
     }
 #pragma unroll
     for (int i = 0; i < PIN; ++i) {
@@ -114,16 +115,16 @@ __global__ __launch_bounds__(kBlock) void k_row_fwd(const cf* __restrict__ X, cf
         const int y = (int)(row % N);
         int n = x - N / 2;
         if (n < 0) n += G;
-        buf[rr * TS + n] = cscale(pre[i], dinv[x] * dinv[y]);
+        buf[rr * TS + padx<PS>(n)] = cscale(pre[i], dinv[x] * dinv[y]);
       }
     }
     lds_sync();
     if (g + (int)gridDim.x < ngroups) load(g + gridDim.x);
-    lds_fft<G, RPB, 1, TS, false, false>(buf, tw);
+    lds_fft<G, RPB, 1, TS, false, false, PS>(buf, tw);
     for (int idx = tid; idx < RPB * G; idx += kBlock) {
       const int rr = idx / G, n = idx % G;
       const long row = (long)g * RPB + rr;
-      if (row < nrows) T[row * G + n] = buf[rr * TS + n];
+      if (row < nrows) T[row * G + n] = buf[rr * TS + padx<PS>(n)];
     }
     lds_sync();
   }
@@ -136,7 +137,8 @@ __global__ __launch_bounds__(kBlock) void k_row_adj(const cf* __restrict__ T, cf
                                                     const cf* __restrict__ twg, int nrows, float scale) {
   constexpr int N = G / 2;
   constexpr int RPB = row_rpb(G);
-  constexpr int TS = G + 1;
+  constexpr int PS = 3;
+  constexpr int TS = padx<PS>(G) + 1;
   constexpr int PIN = (RPB * G + kBlock - 1) / kBlock;
   __shared__ cf buf[RPB * TS];
   __shared__ cf tw[G];
@@ -158,11 +160,11 @@ __global__ __launch_bounds__(kBlock) void k_row_adj(const cf* __restrict__ T, cf
 #pragma unroll
     for (int i = 0; i < PIN; ++i) {
       const int idx = tid + i * kBlock;
-      if (idx < RPB * G) buf[(idx / G) * TS + idx % G] = pre[i];
+      if (idx < RPB * G) buf[(idx / G) * TS + padx<PS>(idx % G)] = pre[i];
     }
     lds_sync();
     if (g + (int)gridDim.x < ngroups) load(g + gridDim.x);
-    lds_fft<G, RPB, 1, TS, false, true>(buf, tw);
+    lds_fft<G, RPB, 1, TS, false, true, PS>(buf, tw);
     for (int idx = tid; idx < RPB * N; idx += kBlock) {
       const int rr = idx / N, x = idx % N;
       const long row = (long)g * RPB + rr;
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_row_adj(const cf* __restrict__ T, cf
         int n = x - N / 2;
         if (n < 0) n += G;
         const int y = (int)(row % N);
-        X[row * N + x] = cscale(buf[rr * TS + n], dinv[x] * dinv[y] * scale);
+        X[row * N + x] = cscale(buf[rr * TS + padx<PS>(n)], dinv[x] * dinv[y] * scale);
       }
     }
     lds_sync();
@@ -216,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_col_fwd(const cf* __restrict__ T, co
   };
   load(fb);
   for (int f = fb; f < fe; ++f) {
-    for (int idx = tid; idx < (G - N) * TX; idx += kBlock) S[(N / 2 + idx / TX) * P + idx % TX] = cf{0.f, 0.f};
+    // rows [N/2, G - N/2) are the zero padding: the FFT's first pass does not read them
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
       const int idx = tid + i * kBlock;
@@ -229,7 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_col_fwd(const cf* __restrict__ T, co
     const Entry first = en_pre;
     lds_sync();
     if (f + 1 < fe) load(f + 1);
-    lds_fft<G, TX, P, 1, true, false>(S, tw);
+    lds_fft<G, TX, P, 1, true, false, 0, true, false>(S, tw);
     const int e0 = tp[f - fb][w], e1 = tp[f - fb][w + 1];
     const cf* Sw = S + w * TY * P;
     for (int e = e0 + lane; e < e1; e += 64) {
@@ -360,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_col_adj(const cf* __restrict__ rg, c
     if (f + 1 < fe) load(f + 1);
     spread_tile<G, TX>(ent, rg, tp[f - fb][w], tp[f - fb][w + 1], first, first_r, wst[w], S + w * TY * P, lane);
     lds_sync();
-    lds_fft<G, TX, P, 1, true, true>(S, tw);
+    lds_fft<G, TX, P, 1, true, true, 0, false, true>(S, tw);   // only the N cropped rows are stored
     cf* Tf = T + (size_t)f * N * G;
     for (int idx = tid; idx < N * TX; idx += kBlock) {
       const int y = idx / TX, cc = idx % TX;
