@@ -8,9 +8,9 @@
 // patches of the (T1, T2, PD) maps, each channel divided by its maximum over the map. sigma^2 is
 // the lower median of the positive directed K-NN squared distances unless given.
 //
-// Kernels: k_chan_max -> k_features -> k_knn (one block per patch: distances to all patches and a
-// deterministic block-wide K-way selection) -> k_sigma (radix select of the median) -> dense
-// symmetric W -> CSR rows with the diagonal D_ii (columns ascending) -> lmax = max_i D_ii.
+// Kernels: k_chan_max -> k_features -> k_knn_dist (distance tiles) -> k_knn_select (one wave per
+// patch: bitwise search of the K-th distance, ordered ballot compaction) -> k_sigma (radix select
+// of the median) -> dense symmetric W -> CSR rows with the diagonal D_ii (columns ascending) -> lmax = max_i D_ii.
 // Laplacian apply: one block per s x s pixel cell and a chunk of frames; every pixel of a cell
 // lies in the same patches, so the stencil (covering patch i, neighbour j, L_ij) is uniform
 // across the block and each source pixel is the output pixel shifted by q_j - q_i.
@@ -69,77 +69,135 @@ __global__ void k_features(const float* __restrict__ maps, const float* __restri
   F[t] = maps[((size_t)c * g.N + y) * g.N + x] / mx[c];
 }
 
-// One block per group of KR patches: squared distances to every other patch, then the K smallest
-// (distance, index) keys per patch. Each thread keeps its own sorted top-K per row in LDS; K
-// rounds of a block-wide minimum over the threads' heads produce each row's order. The KR rows
-// share every candidate row F[j] the thread loads.
-constexpr int kKnnRows = 2;
-__global__ __launch_bounds__(256) void k_knn(const float* __restrict__ F, int Np, int nf, int K,
-                                             int* __restrict__ knn, float* __restrict__ knd2, int kmax) {
-  __shared__ float Fi[kKnnRows][192];
-  __shared__ unsigned long long lst[kKnnRows][256][16];
-  __shared__ unsigned long long red[256];
-  __shared__ int redt[256];
-  const int i0 = blockIdx.x * kKnnRows, t = threadIdx.x;
-  for (int f = t; f < kKnnRows * nf; f += 256) {
-    const int rr = f / nf, ff = f % nf;
-    Fi[rr][ff] = i0 + rr < Np ? F[(size_t)(i0 + rr) * nf + ff] : 0.f;
+// K-NN search in two kernels. k_knn_dist: squared feature distances of every patch pair, one
+// 64 x 64 tile of pairs per block, only tiles on or above the diagonal; an off-diagonal tile is
+// also stored transposed. Each pair sums fmaf(d, d, .) over the features in ascending order with
+// d = F_i - F_j; (F_j - F_i)^2 is the same float, so the matrix is exactly symmetric and each
+// distance has a single value wherever it is used. The matrix is written into the W buffer (it is
+// cleared before W is filled). k_knn_select: one wave per patch; the row (self excluded) sits in
+// registers, a bitwise search finds the K-th smallest distance, and an ordered ballot pass over
+// the row takes every smaller one plus the lowest-index ties at that value, sorted by
+// (distance, index).
+constexpr int kKnnTile = 64;
+constexpr int kKnnFch = 32;               // features per LDS chunk
+constexpr int kKnnLd = kKnnTile + 4;      // LDS row stride (floats; keeps float4 rows aligned)
+
+__global__ __launch_bounds__(256) void k_knn_dist(const float* __restrict__ F, int Np, int nf, int nt,
+                                                  float* __restrict__ D) {
+  __shared__ __align__(16) float sm[2 * kKnnFch * kKnnLd > kKnnTile * (kKnnTile + 1) ? 2 * kKnnFch * kKnnLd
+                                                                                       : kKnnTile * (kKnnTile + 1)];
+  float* Fa = sm;                         // [kKnnFch][kKnnLd], patches of the row tile
+  float* Fb = sm + kKnnFch * kKnnLd;      // same for the column tile
+  // upper-triangular tile (bi <= bj) from the linear block index
+  int bi = 0, rem = blockIdx.x;
+  while (rem >= nt - bi) {
+    rem -= nt - bi;
+    ++bi;
+  }
+  const int bj = bi + rem;
+  const int i0 = bi * kKnnTile, j0 = bj * kKnnTile, t = threadIdx.x;
+  const int ti = t & 15, tj = t >> 4;     // this thread: rows i0 + 4 ti + a, columns j0 + 4 tj + b
+  float acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
+  for (int f0 = 0; f0 < nf; f0 += kKnnFch) {
+    __syncthreads();
+    for (int e = t; e < kKnnTile * kKnnFch; e += 256) {
+      const int r = e / kKnnFch, c = e % kKnnFch, f = f0 + c;
+      const int ia = i0 + r, jb = j0 + r;
+      Fa[c * kKnnLd + r] = ia < Np && f < nf ? F[(size_t)ia * nf + f] : 0.f;
+      Fb[c * kKnnLd + r] = jb < Np && f < nf ? F[(size_t)jb * nf + f] : 0.f;
+    }
+    __syncthreads();
+    // zero-padded features beyond nf add fmaf(0, 0, acc) = acc
+#pragma unroll 4
+    for (int c = 0; c < kKnnFch; ++c) {
+      const float4 x = *reinterpret_cast<const float4*>(Fa + c * kKnnLd + 4 * ti);
+      const float4 y = *reinterpret_cast<const float4*>(Fb + c * kKnnLd + 4 * tj);
+      const float xa[4] = {x.x, x.y, x.z, x.w}, yb[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const float d = xa[a] - yb[b];
+          acc[a][b] = fmaf(d, d, acc[a][b]);
+        }
+    }
   }
   __syncthreads();
-  int n[kKnnRows];
+  float* T = sm;                          // [kKnnTile][kKnnTile + 1] staged output tile
 #pragma unroll
-  for (int rr = 0; rr < kKnnRows; ++rr) n[rr] = 0;
-  for (int j = t; j < Np; j += 256) {
-    const float* Fj = F + (size_t)j * nf;
-    float d2[kKnnRows];
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int rr = 0; rr < kKnnRows; ++rr) d2[rr] = 0.f;
-    for (int f = 0; f < nf; ++f) {
-      const float x = Fj[f];
-#pragma unroll
-      for (int rr = 0; rr < kKnnRows; ++rr) {
-        const float d = Fi[rr][f] - x;
-        d2[rr] = fmaf(d, d, d2[rr]);
-      }
-    }
-#pragma unroll
-    for (int rr = 0; rr < kKnnRows; ++rr) {
-      if (j == i0 + rr) continue;
-      const unsigned long long key = ((unsigned long long)__float_as_uint(d2[rr]) << 32) | (unsigned)j;
-      unsigned long long* L = lst[rr][t];
-      if (n[rr] < K || key < L[K - 1]) {
-        int pos = n[rr] < K ? n[rr] : K - 1;
-        while (pos > 0 && L[pos - 1] > key) {
-          L[pos] = L[pos - 1];
-          --pos;
-        }
-        L[pos] = key;
-        if (n[rr] < K) ++n[rr];
-      }
+    for (int b = 0; b < 4; ++b) T[(4 * ti + a) * (kKnnTile + 1) + 4 * tj + b] = acc[a][b];
+  __syncthreads();
+  const int lane = t & 63, w = t >> 6;
+  for (int r = w; r < kKnnTile; r += 4) {
+    const int i = i0 + r, j = j0 + lane;
+    if (i < Np && j < Np) D[(size_t)i * Np + j] = T[r * (kKnnTile + 1) + lane];
+  }
+  if (bi != bj) {
+    for (int r = w; r < kKnnTile; r += 4) {
+      const int j = j0 + r, i = i0 + lane;
+      if (i < Np && j < Np) D[(size_t)j * Np + i] = T[lane * (kKnnTile + 1) + r];
     }
   }
-  for (int rr = 0; rr < kKnnRows; ++rr) {
-    const int i = i0 + rr;
-    int head = 0;
-    for (int k = 0; k < K; ++k) {
-      red[t] = head < n[rr] ? lst[rr][t][head] : ~0ull;
-      redt[t] = t;
-      __syncthreads();
-      for (int o = 128; o > 0; o >>= 1) {
-        if (t < o && red[t + o] < red[t]) {
-          red[t] = red[t + o];
-          redt[t] = redt[t + o];
-        }
-        __syncthreads();
-      }
-      const unsigned long long best = red[0];
-      if (t == redt[0]) ++head;
-      if (t == 0 && i < Np) {
-        knn[(size_t)i * kmax + k] = (int)(best & 0xffffffffu);
-        knd2[(size_t)i * kmax + k] = __uint_as_float((unsigned)(best >> 32));
-      }
-      __syncthreads();
-    }
+}
+
+__device__ inline int wave_count(bool p) { return __popcll(__ballot(p)); }
+
+// RC = values of the row per lane (Np <= 64 RC). Block: 4 waves, one row each.
+template <int RC>
+__global__ __launch_bounds__(256) void k_knn_select(const float* __restrict__ D, int Np, int K,
+                                                    int* __restrict__ knn, float* __restrict__ knd2, int kmax) {
+  __shared__ unsigned long long sel[4][16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 4 + w;
+  const bool valid = i < Np;              // no early exit: the block meets at a barrier below
+  const float* row = D + (size_t)(valid ? i : 0) * Np;
+  unsigned u[RC];
+#pragma unroll
+  for (int c = 0; c < RC; ++c) {
+    const int j = lane + 64 * c;
+    // self and the padding past Np get the largest key; they are never among the K (K <= Np - 1)
+    u[c] = valid && j < Np && j != i ? __float_as_uint(row[j]) : 0xffffffffu;
+  }
+  // v = the largest x with #{u < x} <= K - 1, i.e. the K-th smallest value (distances are
+  // non-negative, so their bit patterns order like the values)
+  unsigned v = 0u;
+  for (int bit = 31; bit >= 0; --bit) {
+    const unsigned cand = v | (1u << bit);
+    int cnt = 0;
+#pragma unroll
+    for (int c = 0; c < RC; ++c) cnt += wave_count(u[c] < cand);
+    if (cnt <= K - 1) v = cand;
+  }
+  int nless = 0;
+#pragma unroll
+  for (int c = 0; c < RC; ++c) nless += wave_count(u[c] < v);
+  const int neq_take = K - nless;         // ties at v taken in index order
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int taken = 0, eq_seen = 0;
+#pragma unroll
+  for (int c = 0; c < RC; ++c) {
+    const int j = lane + 64 * c;
+    const unsigned long long eqm = __ballot(u[c] == v && j < Np && j != i);
+    const bool is_eq = (eqm >> lane) & 1ull;
+    const bool take = u[c] < v || (is_eq && eq_seen + __popcll(eqm & below) < neq_take);
+    const unsigned long long tm = __ballot(take);
+    if (take && valid) sel[w][taken + __popcll(tm & below)] = ((unsigned long long)u[c] << 32) | (unsigned)j;
+    taken += __popcll(tm);
+    eq_seen += __popcll(eqm);
+  }
+  __syncthreads();
+  if (valid && lane < K) {
+    const unsigned long long key = sel[w][lane];
+    int rank = 0;
+    for (int k = 0; k < K; ++k) rank += sel[w][k] < key;
+    knn[(size_t)i * kmax + rank] = (int)(key & 0xffffffffu);
+    knd2[(size_t)i * kmax + rank] = __uint_as_float((unsigned)(key >> 32));
   }
 }
 
@@ -578,8 +636,18 @@ mrf_status graph_build(mrf_graph_s* G, const float* maps, int K, float sigma2, h
   MRF_LAUNCH("graph_chan_max", s, k_chan_max<<<1, 1024, 0, s>>>(maps, g.N * g.N, G->mx));
   const long nfeat = (long)g.Np * nf;
   MRF_LAUNCH("graph_features", s, k_features<<<ceil_div(nfeat, 256), 256, 0, s>>>(maps, G->mx, g, G->F));
-  MRF_LAUNCH("graph_knn", s,
-             k_knn<<<ceil_div(g.Np, kKnnRows), 256, 0, s>>>(G->F, g.Np, nf, K, G->knn, G->knd2, G->kmax));
+  const int nt = ceil_div(g.Np, kKnnTile);
+  MRF_LAUNCH("graph_knn_dist", s, k_knn_dist<<<nt * (nt + 1) / 2, 256, 0, s>>>(G->F, g.Np, nf, nt, G->W));
+  const int rc = ceil_div(g.Np, 64);
+  const dim3 sg(ceil_div(g.Np, 4));
+  if (rc <= 16)
+    MRF_LAUNCH("graph_knn_select", s, k_knn_select<16><<<sg, 256, 0, s>>>(G->W, g.Np, K, G->knn, G->knd2, G->kmax));
+  else if (rc <= 32)
+    MRF_LAUNCH("graph_knn_select", s, k_knn_select<32><<<sg, 256, 0, s>>>(G->W, g.Np, K, G->knn, G->knd2, G->kmax));
+  else if (rc <= 64)
+    MRF_LAUNCH("graph_knn_select", s, k_knn_select<64><<<sg, 256, 0, s>>>(G->W, g.Np, K, G->knn, G->knd2, G->kmax));
+  else
+    MRF_LAUNCH("graph_knn_select", s, k_knn_select<128><<<sg, 256, 0, s>>>(G->W, g.Np, K, G->knn, G->knd2, G->kmax));
   MRF_LAUNCH("graph_sigma", s, k_sigma<<<1, 1024, 0, s>>>(G->knd2, g.Np, K, G->kmax, sigma2, G->scal));
   const size_t nw = (size_t)g.Np * g.Np;
   MRF_LAUNCH("graph_zero_w", s, k_fill_f<<<1024, 256, 0, s>>>(G->W, nw, 0.f));

@@ -25,7 +25,7 @@ KERNELS = {
     "llr_gram": ("k_gram<64>", "llr.hip"),
     "llr_tridiag": ("k_tridiag", "llr.hip"),
     "llr_coef": ("k_coef<64>", "llr.hip"),
-    "llr_xupdate": ("k_xupdate<true>", "llr.hip"),
+    "llr_xupdate": ("k_xupdate_reg", "llr.hip"),
     "llr_backxf": ("k_backxf", "llr.hip"),
     "lap_quad": ("k_lap_quad_edges<64, 2>", "graph.hip"),
     "nufft_col_adj": ("k_col_adj", "nufft.hip"),
@@ -33,7 +33,8 @@ KERNELS = {
     "nufft_row_fwd": ("k_row_fwd", "nufft.hip"),
     "nufft_row_adj": ("k_row_adj", "nufft.hip"),
     "match_subspace": ("k_match_sub", "subspace.hip"),
-    "graph_knn": ("k_knn", "graph.hip"),
+    "graph_knn_dist": ("k_knn_dist", "graph.hip"),
+    "graph_knn_select": ("k_knn_select", "graph.hip"),
 }
 CALIBRATION = "neg_kernel"          # the streaming kernel's symbol substring
 CALIBRATION_BYTES = 1 << 28         # read, and the same written
