@@ -464,7 +464,8 @@ __device__ inline double wave_sum_d(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
 }
-constexpr int kQuadFch = 8;
+constexpr int kQuadFch64 = 8;             // frames per chunk for 8 x 8 patches
+constexpr int kQuadFch16 = 8;             // and for 4 x 4 patches
 // PV adjacent pixels per lane (PV = 2: one 16-byte load; needs an even stride and patch size)
 template <int PV>
 struct PixVec;
@@ -478,14 +479,14 @@ struct PixVec<2> {
   typedef float4 T;
   __device__ static float dot(const T& a, const T& b) { return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w; }
 };
-template <int PP, int PV>
+template <int PP, int PV, int FCH>
 __global__ __launch_bounds__(256) void k_lap_quad_edges(const cf* __restrict__ X, const int* __restrict__ rowptr,
                                                         const int* __restrict__ col, const float* __restrict__ val,
                                                         PatchGeom g, int L, int nchunk, double* __restrict__ part) {
   typedef typename PixVec<PV>::T VT;
   constexpr int NPL = PP / PV;             // lanes per frame
   constexpr int NSUB = 64 / NPL;           // frame lanes per wave
-  constexpr int FPT = kQuadFch / NSUB;     // frames per lane
+  constexpr int FPT = FCH / NSUB;          // frames per lane
   static_assert(FPT >= 1, "chunk too small for the patch");
   __shared__ int sj[4][64];
   __shared__ float sw[4][64];
@@ -500,7 +501,7 @@ __global__ __launch_bounds__(256) void k_lap_quad_edges(const cf* __restrict__ X
   const int off = (r / g.p) * g.N + r % g.p;
   const size_t NN = (size_t)g.N * g.N;
   const int oi = (i / g.n1) * g.s * g.N + (i % g.n1) * g.s;
-  const int fbase = c * kQuadFch + fsub;
+  const int fbase = c * FCH + fsub;
   auto ld = [&](int f, int o) -> VT {
     VT v{};
     if (f < L) v = *reinterpret_cast<const VT*>(X + (size_t)f * NN + o);
@@ -678,17 +679,19 @@ mrf_status lap_quad(mrf_graph_s* G, const cf* X, int L, double* out, hipStream_t
   const PatchGeom& g = G->g;
   const int PP = g.p * g.p;
   if (PP == 64 || PP == 16) {
-    const int nchunk = ceil_div(L, kQuadFch);
+    const int fch = PP == 64 ? kQuadFch64 : kQuadFch16;
+    const int nchunk = ceil_div(L, fch);
     const size_t nb = (size_t)nchunk * g.Np;
     if (nb > G->npart) return fail(MRF_SHAPE, "laplacian quad: too many frames for the partial-sum buffer");
     const int grid = 8 * ceil_div(g.Np, 4) * ceil_div(nchunk, 8);
     const bool vec = g.s % 2 == 0 && g.N % 2 == 0;   // 16-byte aligned pixel pairs
-#define MRF_QUAD(PPv, PVv) \
-  MRF_LAUNCH("lap_quad", s, k_lap_quad_edges<PPv, PVv><<<grid, 256, 0, s>>>(X, G->rowptr, G->col, G->val, g, L, nchunk, G->part))
-    if (PP == 64 && vec) MRF_QUAD(64, 2);
-    else if (PP == 64) MRF_QUAD(64, 1);
-    else if (vec) MRF_QUAD(16, 2);
-    else MRF_QUAD(16, 1);
+#define MRF_QUAD(PPv, PVv, FCHv) \
+  MRF_LAUNCH("lap_quad", s,                                                                                    \
+             k_lap_quad_edges<PPv, PVv, FCHv><<<grid, 256, 0, s>>>(X, G->rowptr, G->col, G->val, g, L, nchunk, G->part))
+    if (PP == 64 && vec) MRF_QUAD(64, 2, kQuadFch64);
+    else if (PP == 64) MRF_QUAD(64, 1, kQuadFch64);
+    else if (vec) MRF_QUAD(16, 2, kQuadFch16);
+    else MRF_QUAD(16, 1, kQuadFch16);
 #undef MRF_QUAD
     MRF_CHECK_LAUNCH();
     return sum_partials2(G->part, (long)nb, G->part + G->npart, out, s);

@@ -514,13 +514,99 @@ __global__ __launch_bounds__(kEvT) void k_eig_vec(const double* __restrict__ dd,
   for (int q = 0; q < n; ++q) z[q] = y[q][t] * scale;
 }
 
-// u_k = H_0 H_1 ... H_{n-3} D z_k for the rcap vectors. One 4-wave block per patch: the patch's
-// reflectors (entries k+1 .. n-1 of row k) are staged once in LDS, packed by row. Wave 0 first
-// orthogonalises, in the tridiagonal basis, each vector against the earlier ones of its cluster
-// (eigenvalues within 1e-6 of the largest; modified Gram-Schmidt); then wave w back-transforms
-// the vectors k = w (mod 4), up to three at once so that their reductions overlap. Stores
-// U[i][k][a] (FP32); components with f_k = 0 (zero z) get zero vectors.
-constexpr int kBxPer = (kMaxRllr + 3) / 4;   // vectors per wave
+// The same inverse iteration for n = N known at compile time, with the thread's LU factors and
+// right-hand side in registers (no LDS, so many threads per CU): the pivoting choice is a select
+// rather than a branch, and the second superdiagonal of U is non-zero only where rows were
+// swapped, where it equals the next off-diagonal of T (one bit per row records the swap). Same
+// arithmetic as k_eig_vec.
+template <int N>
+__global__ __launch_bounds__(64) void k_eig_vec_reg(const double* __restrict__ dd, const double* __restrict__ ee,
+                                                    const double* __restrict__ lamtop, const float* __restrict__ fk,
+                                                    int Np, int rcap, double* __restrict__ zvec) {
+  static_assert(N >= 3 && N <= 64, "register inverse iteration needs 3 <= n <= 64");
+  const long gid = (long)blockIdx.x * 64 + threadIdx.x;
+  if (gid >= (long)Np * rcap) return;
+  const int i = (int)(gid / rcap), k = (int)(gid % rcap);
+  double* z = zvec + ((size_t)i * rcap + k) * N;
+  if (k >= N || fk[(size_t)i * rcap + k] <= 0.f) {
+    for (int q = 0; q < N; ++q) z[q] = 0.0;
+    return;
+  }
+  const double* d = dd + (size_t)i * N;
+  const double* e = ee + (size_t)i * N;
+  const double lk = lamtop[(size_t)i * rcap + k];
+  double tn = 0.0;
+#pragma unroll
+  for (int q = 0; q < N; ++q) tn = fmax(tn, fabs(d[q]) + 2.0 * fabs(q < N - 1 ? e[q] : 0.0));
+  const double eps = 1e-14 * tn + 1e-300;
+  // T is re-read (from cache) one step ahead inside the sweeps: the empty asm statements with a
+  // memory clobber keep the compiler from holding all of d and e in registers next to the three
+  // n-long arrays below.
+  asm volatile("" ::: "memory");
+  double y[N], ui[N], u1[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) y[q] = 1.0 + 0.01 * ((q * 37 + k * 11) % 7);
+  double scale = 1.0;
+  for (int sweep = 0; sweep < 3; ++sweep) {
+    unsigned long long swp = 0ull;
+    double dcur = d[0] - lk, ecur = e[0];
+    double yc = y[0] * scale;
+    double eq = e[0], dq1 = d[1], eq1 = e[1];   // e[q], d[q+1], e[q+1] of step q
+#pragma unroll
+    for (int q = 0; q < N - 1; ++q) {
+      const double dq2 = q + 2 < N ? d[q + 2] : 0.0, eq2 = q + 2 < N - 1 ? e[q + 2] : 0.0;
+      asm volatile("" ::: "memory");
+      const double sub = eq;
+      const double nd = dq1 - lk, ne = q + 1 < N - 1 ? eq1 : 0.0;
+      const double yn = y[q + 1] * scale;
+      const bool sw = !(fabs(dcur) >= fabs(sub));
+      const double piv = fabs(dcur) < eps ? eps : dcur;
+      const double rp = 1.0 / (sw ? sub : piv);
+      const double ml = (sw ? dcur : sub) * rp;
+      ui[q] = rp;
+      u1[q] = sw ? nd : ecur;
+      const double ya = sw ? yc : yn, yb = sw ? yn : yc;
+      y[q] = yb;
+      yc = ya - ml * yb;
+      const double da = sw ? ecur : nd, db = sw ? nd : ecur;
+      dcur = da - ml * db;
+      ecur = sw ? -ml * ne : ne;
+      swp |= (unsigned long long)sw << q;
+      eq = eq1;
+      dq1 = dq2;
+      eq1 = eq2;
+    }
+    ui[N - 1] = 1.0 / (fabs(dcur) < eps ? eps : dcur);
+    double y1 = yc * ui[N - 1], y2 = 0.0;
+    y[N - 1] = y1;
+    double nr = y1 * y1;
+    double en = 0.0;                              // e[q+1] of step q (0 for q = n - 2)
+#pragma unroll
+    for (int q = N - 2; q >= 0; --q) {
+      const double ep = q >= 1 ? e[q] : 0.0;      // for step q - 1
+      asm volatile("" ::: "memory");
+      const double u2 = (swp >> q) & 1ull ? en : 0.0;
+      const double v = (y[q] - u1[q] * y1 - u2 * y2) * ui[q];
+      y[q] = v;
+      nr += v * v;
+      y2 = y1;
+      y1 = v;
+      en = ep;
+    }
+    scale = 1.0 / sqrt(fmax(nr, 1e-300));
+  }
+#pragma unroll
+  for (int q = 0; q < N; ++q) z[q] = y[q] * scale;
+}
+
+// u_k = H_0 H_1 ... H_{n-3} D z_k for the rcap vectors. One block per patch with one wave per four
+// vectors: the patch's reflectors (entries k+1 .. n-1 of row k) are staged once in LDS, packed by
+// row. Wave 0 first orthogonalises, in the tridiagonal basis, each vector against the earlier
+// ones of its cluster (eigenvalues within 1e-6 of the largest; modified Gram-Schmidt). Then wave
+// w back-transforms vectors k = 4 w + s, s = lane / 16: each vector lives in one 16-lane DPP row,
+// lane l of the row holding rows l, l + 16, l + 32, l + 48, so the reflector's inner product with
+// the vector is a 16-lane row sum. Stores U[i][k][a] (FP32); components with f_k = 0 (zero z) get
+// zero vectors.
 __global__ __launch_bounds__(256) void k_backxf(const double* __restrict__ zvec, const double* __restrict__ lamtop,
                                                const dcplx* __restrict__ refl, const double* __restrict__ rtau,
                                                const dcplx* __restrict__ phase, int Np, int n, int rcap,
@@ -531,16 +617,16 @@ __global__ __launch_bounds__(256) void k_backxf(const double* __restrict__ zvec,
   __shared__ int live[kMaxRllr];
   const int i = patch_of_block(Np);
   if (i < 0) return;
-  const int t = threadIdx.x, w = t >> 6, r = t & 63;
+  const int nt = blockDim.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
   const dcplx* Ri = refl + (size_t)i * n * n;
   const int nref = n - 2 > 0 ? n - 2 : 0;
-  for (int idx = t; idx < nref * n; idx += 256) {
+  for (int idx = t; idx < nref * n; idx += nt) {
     const int j = idx / n, c = idx % n;
     if (c > j) R[j * (n - 1) - j * (j - 1) / 2 + c - j - 1] = Ri[idx];
   }
   if (t < n) tau[t] = t < nref ? rtau[(size_t)i * n + t] : 0.0;
   const int m = min(rcap, n);
-  for (int idx = t; idx < m * kMaxPP; idx += 256) {
+  for (int idx = t; idx < m * kMaxPP; idx += nt) {
     const int k = idx / kMaxPP, q = idx % kMaxPP;
     zs[k][q] = q < n ? zvec[((size_t)i * rcap + k) * n + q] : 0.0;
   }
@@ -549,62 +635,63 @@ __global__ __launch_bounds__(256) void k_backxf(const double* __restrict__ zvec,
     const double* lt = lamtop + (size_t)i * rcap;
     const double ctol = 1e-6 * fmax(fabs(lt[0]), 1e-300);
     for (int k = 0; k < m; ++k) {
-      double z = zs[k][r];
+      double z = zs[k][lane];
       const bool lv = wave_sum(z * z) != 0.0;
-      if (r == 0) live[k] = lv;
+      if (lane == 0) live[k] = lv;
       if (!lv) continue;
       bool moved = false;
       for (int j = 0; j < k; ++j) {
         if (fabs(lt[k] - lt[j]) > ctol) continue;
-        const double zj = zs[j][r];
+        const double zj = zs[j][lane];
         z -= wave_sum(zj * z) * zj;
         moved = true;
       }
       if (moved) {
         z *= 1.0 / sqrt(fmax(wave_sum(z * z), 1e-300));
-        zs[k][r] = z;
+        zs[k][lane] = z;
       }
     }
   }
   __syncthreads();
-  dcplx u[kBxPer];
-  const dcplx ph = r < n ? phase[(size_t)i * n + r] : dcplx{0.0, 0.0};
+  const int t16 = lane & 15, k = 4 * w + (lane >> 4);
+  const bool on = k < m && live[k];
+  dcplx u[4];
 #pragma unroll
-  for (int c = 0; c < kBxPer; ++c) {
-    const int k = w + 4 * c;
-    u[c] = k < m && live[k] ? dscale(ph, zs[k][r]) : dcplx{0.0, 0.0};
+  for (int a = 0; a < 4; ++a) {
+    const int r = t16 + 16 * a;
+    u[a] = on && r < n ? dscale(phase[(size_t)i * n + r], zs[k][r]) : dcplx{0.0, 0.0};
   }
-  for (int j = nref - 1; j >= 0; --j) {
-    const double tj = tau[j];
-    if (tj == 0.0) continue;
-    const int off = j * (n - 1) - j * (j - 1) / 2;
-    const dcplx v = (r > j && r < n) ? R[off + r - j - 1] : dcplx{0.0, 0.0};
-    double dr[kBxPer], di[kBxPer];
+  if (__ballot(on) != 0ull) {
+    for (int j = nref - 1; j >= 0; --j) {
+      const double tj = tau[j];
+      if (tj == 0.0) continue;
+      const int off = j * (n - 1) - j * (j - 1) / 2;
+      dcplx v[4];
+      double dr = 0.0, di = 0.0;
 #pragma unroll
-    for (int c = 0; c < kBxPer; ++c) {
-      dr[c] = v.x * u[c].x + v.y * u[c].y;
-      di[c] = v.x * u[c].y - v.y * u[c].x;
+      for (int a = 0; a < 4; ++a) {
+        const int r = t16 + 16 * a;
+        v[a] = r > j && r < n ? R[off + r - j - 1] : dcplx{0.0, 0.0};
+        dr += v[a].x * u[a].x + v[a].y * u[a].y;
+        di += v[a].x * u[a].y - v[a].y * u[a].x;
+      }
+      dr = row_sum16(dr);
+      di = row_sum16(di);
+      const dcplx gk = {tj * dr, tj * di};
+#pragma unroll
+      for (int a = 0; a < 4; ++a) u[a] = dsub(u[a], dmul(v[a], gk));
     }
-#pragma unroll
-    for (int c = 0; c < kBxPer; ++c) {
-      dr[c] = row_sum16(dr[c]);
-      di[c] = row_sum16(di[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < kBxPer; ++c) {
-      dr[c] = (lane_value(dr[c], 0) + lane_value(dr[c], 16)) + (lane_value(dr[c], 32) + lane_value(dr[c], 48));
-      di[c] = (lane_value(di[c], 0) + lane_value(di[c], 16)) + (lane_value(di[c], 32) + lane_value(di[c], 48));
-    }
-#pragma unroll
-    for (int c = 0; c < kBxPer; ++c) u[c] = dsub(u[c], dmul(v, dcplx{tj * dr[c], tj * di[c]}));
   }
+  if (k < m) {
 #pragma unroll
-  for (int c = 0; c < kBxPer; ++c) {
-    const int k = w + 4 * c;
-    if (k < m && r < n) U[((size_t)i * rcap + k) * n + r] = cf{(float)u[c].x, (float)u[c].y};
+    for (int a = 0; a < 4; ++a) {
+      const int r = t16 + 16 * a;
+      if (r < n) U[((size_t)i * rcap + k) * n + r] = cf{(float)u[a].x, (float)u[a].y};
+    }
   }
-  for (int k = m; k < rcap; ++k)   // rank cap above the patch size: zero rows
-    if (w == 0 && r < n) U[((size_t)i * rcap + k) * n + r] = cf{0.f, 0.f};
+  if (w == 0)   // rank cap above the patch size: zero rows
+    for (int kk = m; kk < rcap; ++kk)
+      for (int r = lane; r < n; r += 64) U[((size_t)i * rcap + kk) * n + r] = cf{0.f, 0.f};
 }
 
 // C[i][k][l] = f_k sum_a conj(U[i][k][a]) X[l][pixel a of patch i] on MFMA: D (k x frames) =
@@ -924,9 +1011,17 @@ mrf_status llr_analyse(const cf* X, const PatchGeom& g, int L, double tau, int r
   else return fail(MRF_SHAPE, "llr: p^2 must be 16 or 64 (or < 16)");
   MRF_LAUNCH("llr_tridiag", s, k_tridiag<<<nb, 256, 0, s>>>(w.G, g.Np, PP, w.dd, w.ee, w.refl, w.rtau, w.ph));
   MRF_LAUNCH("llr_eig", s, k_eig_val<<<nb, 64, 0, s>>>(w.dd, w.ee, g.Np, PP, tau, rcap, w.nuc, w.lam, f, lam_out));
-  const int nv = (int)ceil_div((long)g.Np * rcap, (long)kEvT);
-  MRF_LAUNCH("llr_eigvec", s, k_eig_vec<<<nv, kEvT, 0, s>>>(w.dd, w.ee, w.lam, f, g.Np, PP, rcap, w.z));
-  MRF_LAUNCH("llr_backxf", s, k_backxf<<<nb, 256, 0, s>>>(w.z, w.lam, w.refl, w.rtau, w.ph, g.Np, PP, rcap, U));
+  const int nv64 = (int)ceil_div((long)g.Np * rcap, 64L);
+  if (PP == 64)
+    MRF_LAUNCH("llr_eigvec", s, k_eig_vec_reg<64><<<nv64, 64, 0, s>>>(w.dd, w.ee, w.lam, f, g.Np, rcap, w.z));
+  else if (PP == 16)
+    MRF_LAUNCH("llr_eigvec", s, k_eig_vec_reg<16><<<nv64, 64, 0, s>>>(w.dd, w.ee, w.lam, f, g.Np, rcap, w.z));
+  else
+    MRF_LAUNCH("llr_eigvec", s,
+               k_eig_vec<<<(int)ceil_div((long)g.Np * rcap, (long)kEvT), kEvT, 0, s>>>(w.dd, w.ee, w.lam, f, g.Np, PP,
+                                                                                     rcap, w.z));
+  const int nbw = std::max(1, (std::min(rcap, PP) + 3) / 4);   // waves: four vectors each
+  MRF_LAUNCH("llr_backxf", s, k_backxf<<<nb, 64 * nbw, 0, s>>>(w.z, w.lam, w.refl, w.rtau, w.ph, g.Np, PP, rcap, U));
   MRF_LAUNCH("llr_nuc_sum", s, k_sum_d<<<1, 256, 0, s>>>(w.nuc, g.Np, nuc_out));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
