@@ -188,6 +188,105 @@ __global__ __launch_bounds__(GramCfg<PP>::NTHR) void k_gram(const cf* __restrict
     }
   }
 }
+// Cell-pair form for 8 x 8 patches at stride 4 (each patch = 2 x 2 cells of 4 x 4 pixels). Every
+// 16 x 16 block of a patch Gram is a cell-pair product C(a, b) = sum_f x_a(f) x_b(f)^H of the
+// two cells' pixels, and neighbouring patches share these blocks, so each distinct pair is formed
+// once: per cell a, the five blocks D = C(a, a), H = C(a, a + (0, 1)), V = C(a, a + (1, 0)),
+// DR = C(a, a + (1, 1)), DL = C(a, a + (1, -1)); every other pair inside a patch is the
+// conjugate transpose of one of these. Cb[cell][type][u][v] with u, v the raster index inside the
+// 4 x 4 cell. A block takes kGcW consecutive cells of one cell row, one wave per cell; the
+// block's frames are staged in LDS as the 2 cell rows x (kGcW + 2) cells that its five
+// products touch.
+constexpr int kGcW = 4;    // cells per block
+constexpr int kGcF = 16;   // frames per LDS chunk
+constexpr int kGcPer = kGcF * 2 * (kGcW + 2) * 16 / (64 * kGcW);   // staged values per thread
+static_assert(kGcF * 2 * (kGcW + 2) * 16 % (64 * kGcW) == 0, "whole chunks per thread");
+__global__ __launch_bounds__(64 * kGcW) void k_gram_cells(const cf* __restrict__ X, int N, int nc, int L,
+                                                          cf* __restrict__ Cb) {
+  constexpr int SW = kGcW + 2, RW = 4 * SW;   // cells per staged row, pixels per staged image row
+  __shared__ cf S[kGcF][2][SW][16];
+  const int nstrip = (nc + kGcW - 1) / kGcW, nblk = nc * nstrip;
+  const int per = (nblk + 7) / 8;
+  const int q = (blockIdx.x & 7) * per + (blockIdx.x >> 3);   // XCD x: a band of cell rows
+  if (q >= nblk) return;
+  const int cy = q / nstrip, cx0 = (q % nstrip) * kGcW;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int cx = cx0 + w;
+  const bool vD = cx < nc, vH = vD && cx + 1 < nc, vV = vD && cy + 1 < nc, vDR = vH && vV, vDL = vV && cx >= 1;
+  const size_t NN = (size_t)N * N;
+  f32x4 accr[5], acci[5];
+#pragma unroll
+  for (int t = 0; t < 5; ++t) {
+    accr[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    acci[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  // element k of this thread: frame f = e / (8 RW) of the chunk, staged image row r8, column xr;
+  // its offset inside a frame-chunk of X (32-bit: < kGcF N^2), or -1 outside the image
+  int off[kGcPer];
+#pragma unroll
+  for (int k = 0; k < kGcPer; ++k) {
+    const int e = tid + k * 64 * kGcW;
+    const int f = e / (8 * RW), rem = e % (8 * RW), r8 = rem / RW, xr = rem % RW;
+    const int y = 4 * cy + r8, x = 4 * (cx0 - 1) + xr;
+    off[k] = y < N && x >= 0 && x < N ? f * N * N + y * N + x : -1;
+  }
+  cf nxt[kGcPer];
+  auto load = [&](int l0) {
+    const cf* Xc = X + (size_t)l0 * NN;
+#pragma unroll
+    for (int k = 0; k < kGcPer; ++k) {
+      const int f = (tid + k * 64 * kGcW) / (8 * RW);
+      nxt[k] = off[k] >= 0 && l0 + f < L ? Xc[off[k]] : cf{0.f, 0.f};
+    }
+  };
+  load(0);
+  for (int l0 = 0; l0 < L; l0 += kGcF) {
+#pragma unroll
+    for (int k = 0; k < kGcPer; ++k) {
+      const int e = tid + k * 64 * kGcW;
+      const int f = e / (8 * RW), rem = e % (8 * RW), r8 = rem / RW, xr = rem % RW;
+      S[f][r8 >> 2][xr >> 2][(r8 & 3) * 4 + (xr & 3)] = nxt[k];
+    }
+    lds_sync();
+    if (l0 + kGcF < L) load(l0 + kGcF);   // in flight during this chunk's MFMAs
+    if (vD) {
+#pragma unroll 2
+      for (int f0 = 0; f0 < kGcF; f0 += 4) {
+        const int fr = f0 + (lane >> 4), px = lane & 15;
+        const cf pa = S[fr][0][w + 1][px];
+        const cf pb[5] = {pa, S[fr][0][w + 2][px], S[fr][1][w + 1][px], S[fr][1][w + 2][px], S[fr][1][w][px]};
+        const bool on[5] = {true, vH, vV, vDR, vDL};
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+          if (!on[t]) continue;
+          accr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa.x, pb[t].x, accr[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa.y, pb[t].x, acci[t], 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+          if (!on[t]) continue;
+          accr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa.y, pb[t].y, accr[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-pa.x, pb[t].y, acci[t], 0, 0, 0);
+        }
+      }
+    }
+    lds_sync();
+  }
+  const bool on[5] = {vD, vH, vV, vDR, vDL};
+#pragma unroll
+  for (int t = 0; t < 5; ++t) {
+    if (!on[t]) continue;
+    cf* o = Cb + ((size_t)(cy * nc + cx) * 5 + t) * 256;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o[(4 * (lane >> 4) + e) * 16 + (lane & 15)] = cf{accr[t][e], acci[t][e]};
+  }
+}
+inline bool gram_cells_ok(const PatchGeom& g) { return g.p == 8 && g.s == 4 && g.nc >= 2; }
+inline int gram_cells_blocks(const PatchGeom& g) {
+  const int nblk = g.nc * ((g.nc + kGcW - 1) / kGcW);
+  return 8 * ((nblk + 7) / 8);
+}
+
 __global__ __launch_bounds__(256) void k_gram_small(const cf* __restrict__ X, PatchGeom g, int L, cf* __restrict__ G) {
   const int i = patch_of_block(g.Np);
   if (i < 0) return;
@@ -230,9 +329,10 @@ __device__ inline dcplx pick(const dcplx (&a)[kTdJ], int j) {
   }
   return dcplx{xr, xi};
 }
-__global__ __launch_bounds__(256) void k_tridiag(const cf* __restrict__ G, int Np, int n, double* __restrict__ dd,
-                                                double* __restrict__ ee, dcplx* __restrict__ refl,
-                                                double* __restrict__ rtau, dcplx* __restrict__ phase) {
+__global__ __launch_bounds__(256) void k_tridiag(const cf* __restrict__ G, const cf* __restrict__ Cb, PatchGeom g,
+                                                int Np, int n, double* __restrict__ dd, double* __restrict__ ee,
+                                                dcplx* __restrict__ refl, double* __restrict__ rtau,
+                                                dcplx* __restrict__ phase) {
   __shared__ dcplx vs[2][kMaxPP];    // reflector of the step, double-buffered by step parity
   __shared__ dcplx pw[4][kMaxPP];    // per-wave parts of A22 v
   __shared__ dcplx wsw[4][kMaxPP];   // each wave's copy of w
@@ -244,12 +344,45 @@ __global__ __launch_bounds__(256) void k_tridiag(const cf* __restrict__ G, int N
   const cf* Gi = G + (size_t)i * n * n;
   dcplx* Ri = refl + (size_t)i * n * n;     // reflector k stored in row k (entries k+1 .. n-1)
   dcplx a[kTdJ];
+  if (Cb) {
+    // Gram from cell-pair blocks (8 x 8 patch = cells 0 1 / 2 3): slots 0-3 the diagonal blocks
+    // of cells 0-3, then H of cells 0 and 2, V of cells 0 and 1, DR of cell 0, DL of cell 1. A pair
+    // (alpha, beta) with alpha < beta is stored as is, the reverse pair as its conjugate transpose;
+    // inside a diagonal block only u <= v is read, so A is exactly Hermitian.
+    __shared__ cf cblk[10][256];
+    const int py = i / g.n1, px = i % g.n1, nc = g.nc;
+    for (int e = t; e < 10 * 256; e += 256) {
+      const int sl = e >> 8, o = e & 255;
+      int cell, ty;
+      if (sl < 4) { cell = sl; ty = 0; }
+      else if (sl < 6) { cell = 2 * (sl - 4); ty = 1; }
+      else if (sl < 8) { cell = sl - 6; ty = 2; }
+      else if (sl == 8) { cell = 0; ty = 3; }
+      else { cell = 1; ty = 4; }
+      const int gc = (py + (cell >> 1)) * nc + px + (cell & 1);
+      cblk[sl][o] = Cb[((size_t)gc * 5 + ty) * 256 + o];
+    }
+    __syncthreads();
+    constexpr int kSlot[4][4] = {{0, 4, 6, 8}, {4, 1, 9, 7}, {6, 9, 2, 5}, {8, 7, 5, 3}};
+    const int ca = ((r >> 3) >> 2) * 2 + ((r & 7) >> 2), u = ((r >> 3) & 3) * 4 + (r & 3);
 #pragma unroll
-  for (int j = 0; j < kTdJ; ++j) {
-    const int c = 4 * j + w;
-    cf x = cf{0.f, 0.f};
-    if (r < n && c < n) x = Gi[(size_t)c * n + r];   // A[r][c] = conj(G[c][r])
-    a[j] = dcplx{x.x, -(double)x.y};
+    for (int j = 0; j < kTdJ; ++j) {
+      const int c = 4 * j + w;
+      const int cbt = ((c >> 3) >> 2) * 2 + ((c & 7) >> 2), v = ((c >> 3) & 3) * 4 + (c & 3);
+      const int sl = kSlot[ca][cbt];
+      const bool direct = ca < cbt || (ca == cbt && u <= v);
+      const cf x = direct ? cblk[sl][u * 16 + v] : cblk[sl][v * 16 + u];
+      a[j] = dcplx{x.x, direct ? (double)x.y : -(double)x.y};
+      if (ca == cbt && u == v) a[j].y = 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kTdJ; ++j) {
+      const int c = 4 * j + w;
+      cf x = cf{0.f, 0.f};
+      if (r < n && c < n) x = Gi[(size_t)c * n + r];   // A[r][c] = conj(G[c][r])
+      a[j] = dcplx{x.x, -(double)x.y};
+    }
   }
   // reflector of column k from this wave's lanes x = A[r][k]
   auto reflector = [&](int k, dcplx x, int buf) {
@@ -984,7 +1117,7 @@ LlrWs llr_ws_layout(const PatchGeom& g, int rcap, void* base) {
     off += al(b);
     return q;
   };
-  w.G = (cf*)take(Np * PP * PP * sizeof(cf));
+  w.G = (cf*)take(std::max(Np * PP * PP, (size_t)g.nc * g.nc * 5 * 256) * sizeof(cf));   // dense or cell-pair Grams
   w.dd = (double*)take(Np * PP * 8);
   w.ee = (double*)take(Np * PP * 8);
   w.refl = (dcplx*)take(Np * PP * PP * sizeof(dcplx));
@@ -1004,12 +1137,17 @@ mrf_status llr_analyse(const cf* X, const PatchGeom& g, int L, double tau, int r
   const int PP = g.p * g.p;
   LlrWs w = llr_ws_layout(g, rcap, ws);
   const int nb = patch_blocks(g.Np);
-  if (PP == 64) MRF_LAUNCH("llr_gram", s, k_gram<64><<<nb, GramCfg<64>::NTHR, 0, s>>>(X, g, L, w.G));
+  const bool cells = gram_cells_ok(g);
+  if (cells)
+    MRF_LAUNCH("llr_gram", s, k_gram_cells<<<gram_cells_blocks(g), 64 * kGcW, 0, s>>>(X, g.N, g.nc, L, w.G));
+  else if (PP == 64) MRF_LAUNCH("llr_gram", s, k_gram<64><<<nb, GramCfg<64>::NTHR, 0, s>>>(X, g, L, w.G));
   else if (PP == 16) MRF_LAUNCH("llr_gram", s, k_gram<16><<<nb, GramCfg<16>::NTHR, 0, s>>>(X, g, L, w.G));
   else if (PP == 32 || PP == 48) return fail(MRF_SHAPE, "llr: p^2 must be 16 or 64 (or < 16)");
   else if (PP < 16) MRF_LAUNCH("llr_gram", s, k_gram_small<<<nb, 256, 0, s>>>(X, g, L, w.G));
   else return fail(MRF_SHAPE, "llr: p^2 must be 16 or 64 (or < 16)");
-  MRF_LAUNCH("llr_tridiag", s, k_tridiag<<<nb, 256, 0, s>>>(w.G, g.Np, PP, w.dd, w.ee, w.refl, w.rtau, w.ph));
+  MRF_LAUNCH("llr_tridiag", s,
+             k_tridiag<<<nb, 256, 0, s>>>(cells ? nullptr : w.G, cells ? w.G : nullptr, g, g.Np, PP, w.dd, w.ee, w.refl,
+                                          w.rtau, w.ph));
   MRF_LAUNCH("llr_eig", s, k_eig_val<<<nb, 64, 0, s>>>(w.dd, w.ee, g.Np, PP, tau, rcap, w.nuc, w.lam, f, lam_out));
   const int nv64 = (int)ceil_div((long)g.Np * rcap, 64L);
   if (PP == 64)

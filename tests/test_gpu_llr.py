@@ -25,7 +25,8 @@ def _lowrank_series(rng, L, N, rank, noise):
 
 
 @pytest.mark.parametrize("N,L,p,s,tau,cap", [(32, 100, 4, 2, 3.0, 8), (32, 60, 8, 4, 5.0, 10),
-                                             (64, 100, 4, 2, 5.0, 8), (16, 1000, 8, 4, 20.0, 10)])
+                                             (64, 100, 4, 2, 5.0, 8), (16, 1000, 8, 4, 20.0, 10),
+                                             (48, 101, 8, 4, 4.0, 10)])
 def test_llr_prox_matches_oracle(N, L, p, s, tau, cap):
     from paper_2310_05647_amd import llr_prox
     say(f"llr N={N} L={L} p={p} tau={tau} cap={cap}")
