@@ -1016,6 +1016,87 @@ __global__ __launch_bounds__(256) void k_xupdate_reg(const cf* __restrict__ Z, c
   }
 }
 
+// The same update on MFMA for 8 x 8 patches at stride 4. The 16 pixels of a 4 x 4 cell share
+// their (up to) 4 covering patches, so a cell's frames are one complex product
+//   X_cell[px][f] = sum_{k < rcap} sum_{c < 4} U_{i_c}[k][a_c(px)] C_{i_c}[k][f],
+// a 16 x (4 rcap) by (4 rcap) x F matrix product. One wave per cell and 16-frame tile: the
+// K-step k takes component k of the 4 patches (lane l: patch c = l / 16), so the A operands
+// (U, kept in registers for all frames) and B operands (C, 16 consecutive frames per patch row)
+// are plain loads; Re and Im come from four real 16x16x4 products. A block = 4 cells of one cell
+// row and a range of frames; the 4 waves' tiles meet in LDS and leave as 128-byte rows.
+template <int RC, bool WITHZ>
+__global__ __launch_bounds__(256) void k_xupdate_mfma(const cf* __restrict__ Z, const cf* __restrict__ U,
+                                                      const cf* __restrict__ C, PatchGeom g, int L, int rcap,
+                                                      const double* __restrict__ kap_ptr, double kap_scale, int fpb,
+                                                      cf* __restrict__ Xout) {
+  __shared__ cf T[16][4][16];
+  const int nq = g.nc / 4;
+  const int w = threadIdx.x >> 6;
+  const int cy = blockIdx.x / nq, cxb = (blockIdx.x % nq) * 4, cx = cxb + w;
+  const int lane = threadIdx.x & 63, c = lane >> 4, px = lane & 15;
+  const int a = cy - 1 + (c >> 1), b = cx - 1 + (c & 1);   // covering patch c of this cell
+  const bool pv = a >= 0 && a < g.n1 && b >= 0 && b < g.n1;
+  const int i = pv ? a * g.n1 + b : 0;
+  const int ap = (4 * (cy - a) + (px >> 2)) * 8 + 4 * (cx - b) + (px & 3);   // pixel px inside patch c
+  int ncov = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int qa = cy - 1 + (q >> 1), qb = cx - 1 + (q & 1);
+    ncov += qa >= 0 && qa < g.n1 && qb >= 0 && qb < g.n1;
+  }
+  float ur[RC], ui[RC], un[RC];
+#pragma unroll
+  for (int k = 0; k < RC; ++k) {
+    const cf x = pv && k < rcap ? U[((size_t)i * rcap + k) * 64 + ap] : cf{0.f, 0.f};
+    ur[k] = x.x;
+    ui[k] = x.y;
+    un[k] = -x.y;
+  }
+  const float kap = WITHZ ? (float)(kap_ptr[0] * kap_scale) : 1.f;
+  const float den = WITHZ ? 1.f / (1.f + kap * ncov) : 1.f;
+  const int l0 = blockIdx.y * fpb, l1 = min(L, l0 + fpb);
+  const cf* Ci = C + (size_t)i * rcap * L;
+  const size_t NN = (size_t)g.N * g.N;
+  for (int f0 = l0; f0 < l1; f0 += 16) {
+    const int f = f0 + px;
+    const bool fv = pv && f < l1;
+    cf bv[RC];
+#pragma unroll
+    for (int k = 0; k < RC; ++k) bv[k] = fv && k < rcap ? Ci[(size_t)k * L + f] : cf{0.f, 0.f};
+    f32x4 accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < RC; ++k) {
+      if (k < rcap) {   // uniform
+        accr = __builtin_amdgcn_mfma_f32_16x16x4f32(ur[k], bv[k].x, accr, 0, 0, 0);
+        acci = __builtin_amdgcn_mfma_f32_16x16x4f32(ur[k], bv[k].y, acci, 0, 0, 0);
+        accr = __builtin_amdgcn_mfma_f32_16x16x4f32(un[k], bv[k].y, accr, 0, 0, 0);
+        acci = __builtin_amdgcn_mfma_f32_16x16x4f32(ui[k], bv[k].x, acci, 0, 0, 0);
+      }
+    }
+    // accumulator element e: cell pixel 4 (lane / 16) + e (row lane / 16, column e), frame
+    // f0 + lane % 16; staged as T[frame][cell row][16 pixels of the 4 cells] so that the block
+    // reads Z and writes X in 128-byte rows
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) T[px][c][4 * w + e] = cf{accr[e], acci[e]};
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int fr = (threadIdx.x >> 6) + 4 * q, row = (threadIdx.x >> 4) & 3, x16 = threadIdx.x & 15;
+      if (f0 + fr < l1) {
+        const size_t o = (size_t)(f0 + fr) * NN + (size_t)(4 * cy + row) * g.N + 4 * cxb + x16;
+        const cf acc = T[fr][row][x16];
+        if (WITHZ) {
+          const cf zv = Z[o];
+          Xout[o] = cf{(zv.x + kap * acc.x) * den, (zv.y + kap * acc.y) * den};
+        } else {
+          Xout[o] = acc;
+        }
+      }
+    }
+  }
+}
+
 template <bool WITHZ>
 __global__ __launch_bounds__(256) void k_xupdate(const cf* __restrict__ Z, const cf* __restrict__ U,
                                                  const cf* __restrict__ C, PatchGeom g, int L, int rcap,
@@ -1180,6 +1261,22 @@ mrf_status llr_xupdate(const cf* Z, const cf* U, const cf* C, const PatchGeom& g
   if (g.N % kTile != 0) return fail(MRF_SHAPE, "x update: N must be a multiple of 16");
   const int ntile = (g.N / kTile) * (g.N / kTile);
   const int ca = kTile / g.s + g.ppc;   // covering patches per tile side (upper bound)
+  if (g.p == 8 && g.s == 4 && rcap <= 16) {
+    const int fpb = 64;
+    dim3 grid(g.nc / 4 * g.nc, (L + fpb - 1) / fpb);
+#define MRF_XM(RCv, W, NAME, ZP, KP, KS)                                                                  \
+  MRF_LAUNCH(NAME, s, k_xupdate_mfma<RCv, W><<<grid, 256, 0, s>>>(ZP, U, C, g, L, rcap, KP, KS, fpb, Xout))
+    if (rcap <= 10) {
+      if (Z) MRF_XM(10, true, "llr_xupdate", Z, kap_dev, kap_scale);
+      else MRF_XM(10, false, "llr_qtp", nullptr, nullptr, 1.0);
+    } else {
+      if (Z) MRF_XM(16, true, "llr_xupdate", Z, kap_dev, kap_scale);
+      else MRF_XM(16, false, "llr_qtp", nullptr, nullptr, 1.0);
+    }
+#undef MRF_XM
+    MRF_CHECK_LAUNCH();
+    return MRF_OK;
+  }
   if (g.ppc <= 2 && rcap <= 16) {
     const size_t lds = (size_t)ca * ca * (rcap * kXrFch + kXrPad) * sizeof(cf);
     if (lds <= 64 * 1024) {
