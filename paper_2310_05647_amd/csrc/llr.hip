@@ -830,13 +830,14 @@ __global__ __launch_bounds__(256) void k_backxf(const double* __restrict__ zvec,
 // C[i][k][l] = f_k sum_a conj(U[i][k][a]) X[l][pixel a of patch i] on MFMA: D (k x frames) =
 // A (k x pixels) B (pixels x frames) with A = U^H held in registers (rows k >= rcap are zero) and
 // B staged in LDS per chunk of 64 frames, read by the 4 waves one 16-frame tile each. Rows of the
-// LDS chunk are padded by 4 values so that the column reads of B spread over the banks.
+// LDS chunk are padded by one value (row stride = 2 mod 32 banks), so the 16 frames read by a
+// quarter-wave fall on distinct bank pairs.
 template <int PP>
 __global__ __launch_bounds__(256) void k_coef(const cf* __restrict__ X, const cf* __restrict__ U,
                                               const float* __restrict__ fk, PatchGeom g, int L, int rcap,
                                               cf* __restrict__ C) {
   constexpr int FCH = 64, PER = FCH * PP / 256, NA = PP / 4;
-  __shared__ cf P[FCH][PP + 4];
+  __shared__ cf P[FCH][PP + 1];
   const int i = patch_of_block(g.Np);
   if (i < 0) return;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;

@@ -118,14 +118,16 @@ __global__ __launch_bounds__(256) void k_reduce(const cf* __restrict__ X, const 
   }
 }
 
-// alpha[v][k] = sum_c part[c][k][v] (fixed order)
+// alpha[v][k] = sum_c part[c][k][v] (fixed order). One thread per voxel: the reads of part are
+// coalesced over v, and the thread writes its r contiguous values.
 __global__ void k_reduce_finish(const cf* __restrict__ part, int nch, int Nv, int r, cf* __restrict__ alpha) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)Nv * r) return;
-  const int v = (int)(idx / r), k = (int)(idx % r);
-  cf s = {0.f, 0.f};
-  for (int c = 0; c < nch; ++c) s = cadd(s, part[((size_t)c * r + k) * Nv + v]);
-  alpha[idx] = s;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= Nv) return;
+  for (int k = 0; k < r; ++k) {
+    cf s = {0.f, 0.f};
+    for (int c = 0; c < nch; ++c) s = cadd(s, part[((size_t)c * r + k) * Nv + v]);
+    alpha[(size_t)v * r + k] = s;
+  }
 }
 
 // Z[l][v] = sum_k beta[v][k] conj(V[l][k])
@@ -285,19 +287,24 @@ __global__ void k_maps(const int* __restrict__ idx, const float* __restrict__ rh
 }
 
 // ---------------------------------------------------------------- internal API
-int reduce_chunks(int L) { return std::max(1, std::min(64, (L + 15) / 16)); }
+// frame chunks of the reduction: enough blocks to fill the chip (about 2048 of 256 voxels), each
+// chunk at least 16 frames; fewer chunks keep the partial sums (chunks x r x Nv) small
+int reduce_chunks(int L, int Nv) {
+  const int vblk = (Nv + 255) / 256;
+  const int want = (2048 + vblk - 1) / vblk;
+  return std::max(1, std::min(std::min(64, (L + 15) / 16), want));
+}
 
-size_t reduce_ws_bytes(int L, int Nv, int r) { return (size_t)reduce_chunks(L) * r * Nv * sizeof(cf); }
+size_t reduce_ws_bytes(int L, int Nv, int r) { return (size_t)reduce_chunks(L, Nv) * r * Nv * sizeof(cf); }
 
 // alpha [Nv][r] = (X - mu G) V, with mu from a device scalar (G may be null)
 mrf_status subspace_reduce(const cf* X, const cf* Gd, const double* mu_dev, const cf* V, int L, int Nv, int r,
                            cf* alpha, cf* part, hipStream_t s) {
-  const int nch = reduce_chunks(L);
+  const int nch = reduce_chunks(L, Nv);
   const int fch = (L + nch - 1) / nch;
   MRF_LAUNCH("subspace_reduce", s,
              k_reduce<<<dim3(ceil_div(Nv, 256), nch), 256, 0, s>>>(X, Gd, mu_dev, 1.0f, V, L, Nv, r, fch, part));
-  MRF_LAUNCH("subspace_reduce_finish", s,
-             k_reduce_finish<<<ceil_div((long)Nv * r, 256), 256, 0, s>>>(part, nch, Nv, r, alpha));
+  MRF_LAUNCH("subspace_reduce_finish", s, k_reduce_finish<<<ceil_div(Nv, 256), 256, 0, s>>>(part, nch, Nv, r, alpha));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
 }
