@@ -183,17 +183,21 @@ struct Best {
 
 __device__ inline bool better(float s, int m, float bs, int bm) { return s > bs || (s == bs && m < bm); }
 
-// Block: 4 waves x 64 voxels. Each wave keeps 4 row tiles of 16 voxels; per atom tile of 16 it
-// issues 4 x (5 + 5) MFMAs (real and imaginary parts of the complex products) and folds the
-// squared magnitudes into per-lane running maxima; a final butterfly over the 16 lanes that
-// share a row produces the arg-max (ties to the lowest atom).
+// Block: 64 voxels, 4 waves. Each wave keeps the 4 row tiles of 16 voxels and takes the atom
+// tiles t = w (mod 4); per atom tile of 16 it issues 4 x (5 + 5) MFMAs (real and imaginary parts
+// of the complex products) and folds the squared magnitudes into per-lane running maxima. A
+// butterfly over the 16 lanes that share a row gives each wave's arg-max, and the four waves'
+// results meet in LDS (ties to the lowest atom throughout). Four waves per SIMD let one wave's
+// score updates run under another's MFMAs.
 __global__ __launch_bounds__(256) void k_match_sub(const cf* __restrict__ alpha, int Nv, int r,
                                                    const float* __restrict__ bpk, int ntile, int M,
                                                    const float* __restrict__ norms, const float* __restrict__ lut,
                                                    int nparam, int* __restrict__ idx_out, float* __restrict__ rho_out,
                                                    float* __restrict__ score_out, float* __restrict__ params_out) {
+  __shared__ float ws_s[4][64], ws_re[4][64];
+  __shared__ int ws_m[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int vbase = (blockIdx.x * 4 + w) * 64;
+  const int vbase = blockIdx.x * 64;
   const int row = lane % 16, kq = lane / 16;
   // A operands: a[rt][q] = A[v = vbase + 16 rt + row][k = 4q + kq], A row = [Re alpha, Im alpha]
   float a[4][5];
@@ -217,12 +221,14 @@ __global__ __launch_bounds__(256) void k_match_sub(const cf* __restrict__ alpha,
 #pragma unroll
     for (int i = 0; i < 4; ++i) best[rt][i] = Best{-1.f, 0.f, 0x7fffffff};
   float b[10], bn[10];
+  if (w < ntile) {
 #pragma unroll
-  for (int q = 0; q < 10; ++q) b[q] = bpk[q * 64 + lane];
-  for (int t = 0; t < ntile; ++t) {
-    if (t + 1 < ntile) {
+    for (int q = 0; q < 10; ++q) b[q] = bpk[((size_t)w * 10 + q) * 64 + lane];
+  }
+  for (int t = w; t < ntile; t += 4) {
+    if (t + 4 < ntile) {
 #pragma unroll
-      for (int q = 0; q < 10; ++q) bn[q] = bpk[((size_t)(t + 1) * 10 + q) * 64 + lane];
+      for (int q = 0; q < 10; ++q) bn[q] = bpk[((size_t)(t + 4) * 10 + q) * 64 + lane];
     }
     const int m = 16 * t + row;   // the atom (column) this lane's outputs belong to
     // K-steps outer, row tiles inner: eight independent accumulation chains in flight
@@ -262,17 +268,30 @@ __global__ __launch_bounds__(256) void k_match_sub(const cf* __restrict__ alpha,
         const int om = __shfl_xor(bb.m, off);
         if (better(os, om, bb.s, bb.m)) bb = Best{os, ore, om};
       }
-      const int v = vbase + 16 * rt + 4 * kq + i;   // output row of value i
-      if (row == 0 && v < Nv) {
-        const int m = bb.m;
-        idx_out[v] = m;
-        const float nrm = norms[m];
-        if (rho_out) rho_out[v] = nrm > 0.f ? fmaxf(bb.re / nrm, 0.f) : 0.f;
-        if (score_out) score_out[v] = sqrtf(fmaxf(bb.s, 0.f));
-        if (params_out)
-          for (int p = 0; p < nparam; ++p) params_out[(size_t)v * nparam + p] = lut[(size_t)m * nparam + p];
+      if (row == 0) {
+        const int vl = 16 * rt + 4 * kq + i;   // output row of value i
+        ws_s[w][vl] = bb.s;
+        ws_re[w][vl] = bb.re;
+        ws_m[w][vl] = bb.m;
       }
     }
+  __syncthreads();
+  if (w == 0) {
+    Best bb{ws_s[0][lane], ws_re[0][lane], ws_m[0][lane]};
+#pragma unroll
+    for (int q = 1; q < 4; ++q)
+      if (better(ws_s[q][lane], ws_m[q][lane], bb.s, bb.m)) bb = Best{ws_s[q][lane], ws_re[q][lane], ws_m[q][lane]};
+    const int v = vbase + lane;
+    if (v < Nv) {
+      const int m = bb.m;
+      idx_out[v] = m;
+      const float nrm = norms[m];
+      if (rho_out) rho_out[v] = nrm > 0.f ? fmaxf(bb.re / nrm, 0.f) : 0.f;
+      if (score_out) score_out[v] = sqrtf(fmaxf(bb.s, 0.f));
+      if (params_out)
+        for (int p = 0; p < nparam; ++p) params_out[(size_t)v * nparam + p] = lut[(size_t)m * nparam + p];
+    }
+  }
 }
 
 // maps[3][N][N] = (T1, T2, PD) from a match result
@@ -334,7 +353,7 @@ mrf_status grad_coef(const cf* aX, const cf* aG, const cf* Y, const double* mu, 
 mrf_status match_subspace(const mrf_dict_s* D, const cf* alpha, int Nv, int* idx, float* rho, float* score,
                           float* params, hipStream_t s) {
   MRF_LAUNCH("match_subspace", s,
-             k_match_sub<<<ceil_div(Nv, 256), 256, 0, s>>>(alpha, Nv, D->r, D->bpk, D->ntile, D->M, D->norms, D->lut,
+             k_match_sub<<<ceil_div(Nv, 64), 256, 0, s>>>(alpha, Nv, D->r, D->bpk, D->ntile, D->M, D->norms, D->lut,
                                                           D->nparam, idx, rho, score, params));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
