@@ -73,7 +73,9 @@ __device__ inline float u01(unsigned u) { return ((float)u + 0.5f) * 2.328306436
 constexpr int kMaxR = 16;
 
 // z [B][2r] features and t [B][2] standardised targets of a synthetic training batch; m [B].
-__global__ __launch_bounds__(256) void k_synth(const cf* __restrict__ dhr, int M, int r, const float* __restrict__ lut,
+// The rank R is a template parameter so that the noise and coefficient arrays stay in registers.
+template <int R>
+__global__ __launch_bounds__(256) void k_synth(const cf* __restrict__ dhr, int M, const float* __restrict__ lut,
                                                int nparam, const double* __restrict__ stats, unsigned k0, unsigned k1,
                                                unsigned step, int B, float snr_lo, float snr_hi, float L,
                                                float* __restrict__ z, float* __restrict__ t, int* __restrict__ mo) {
@@ -84,9 +86,10 @@ __global__ __launch_bounds__(256) void k_synth(const cf* __restrict__ dhr, int M
   const float phi = 6.283185307179586f * u01(u.y);
   const float snr = snr_lo + (snr_hi - snr_lo) * u01(u.z);
   const float sig = sqrtf(powf(10.f, -snr / 10.f) / L) * 0.70710678118654752f;
-  float gs[2 * kMaxR + 4];
-  const int nc = (2 * r + 3) / 4;
-  for (int c = 1; c <= nc; ++c) {
+  constexpr int NC = (2 * R + 3) / 4;
+  float gs[4 * NC];
+#pragma unroll
+  for (int c = 1; c <= NC; ++c) {
     const u4 v = philox(u4{(unsigned)i, step, (unsigned)c, 0u}, k0, k1);
     const float r0 = sqrtf(-2.f * logf(u01(v.x))), a0 = 6.283185307179586f * u01(v.y);
     const float r1 = sqrtf(-2.f * logf(u01(v.z))), a1 = 6.283185307179586f * u01(v.w);
@@ -96,24 +99,39 @@ __global__ __launch_bounds__(256) void k_synth(const cf* __restrict__ dhr, int M
     gs[4 * (c - 1) + 3] = r1 * sinf(a1);
   }
   const float cp = cosf(phi), sp = sinf(phi);
-  float ar[kMaxR], ai[kMaxR], nrm = 0.f;
-  for (int k = 0; k < r; ++k) {
-    const cf d = dhr[(size_t)m * r + k];
+  float ar[R], ai[R], nrm = 0.f;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const cf d = dhr[(size_t)m * R + k];
     ar[k] = cp * d.x - sp * d.y + gs[k] * sig;
-    ai[k] = sp * d.x + cp * d.y + gs[r + k] * sig;
+    ai[k] = sp * d.x + cp * d.y + gs[R + k] * sig;
     nrm += ar[k] * ar[k] + ai[k] * ai[k];
   }
   nrm = sqrtf(nrm);
   const float a0m = sqrtf(ar[0] * ar[0] + ai[0] * ai[0]);
   const float c0 = a0m > 0.f ? ar[0] / a0m : 1.f, s0 = a0m > 0.f ? -ai[0] / a0m : 0.f;   // exp(-i angle)
   const float inv = nrm > 0.f ? 1.f / nrm : 0.f;
-  for (int k = 0; k < r; ++k) {
-    z[(size_t)i * 2 * r + k] = (ar[k] * c0 - ai[k] * s0) * inv;
-    z[(size_t)i * 2 * r + r + k] = (ar[k] * s0 + ai[k] * c0) * inv;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    z[(size_t)i * 2 * R + k] = (ar[k] * c0 - ai[k] * s0) * inv;
+    z[(size_t)i * 2 * R + R + k] = (ar[k] * s0 + ai[k] * c0) * inv;
   }
   t[(size_t)i * 2 + 0] = (float)((log((double)lut[(size_t)m * nparam + 0]) - stats[0]) / stats[2]);
   t[(size_t)i * 2 + 1] = (float)((log((double)lut[(size_t)m * nparam + 1]) - stats[1]) / stats[3]);
   if (mo) mo[i] = m;
+}
+
+// launches k_synth<r> for the dictionary's rank (1 .. kMaxR)
+template <int R = 1>
+static void launch_synth(int r, dim3 grid, hipStream_t s, const cf* dhr, int M, const float* lut, int nparam,
+                         const double* stats, unsigned k0, unsigned k1, unsigned step, int B, float snr_lo,
+                         float snr_hi, float L, float* z, float* t, int* mo) {
+  if constexpr (R <= kMaxR) {
+    if (r == R)
+      k_synth<R><<<grid, 256, 0, s>>>(dhr, M, lut, nparam, stats, k0, k1, step, B, snr_lo, snr_hi, L, z, t, mo);
+    else
+      launch_synth<R + 1>(r, grid, s, dhr, M, lut, nparam, stats, k0, k1, step, B, snr_lo, snr_hi, L, z, t, mo);
+  }
 }
 
 // features of measured coefficients alpha [Nv][r]
@@ -642,9 +660,8 @@ extern "C" mrf_status mrf_mlp_synth(mrf_mlp_t P, mrf_dict_t D, uint64_t seed, in
   mrf_status e = ensure_stats(P, D, s);
   if (e) return e;
   MRF_LAUNCH("mlp_synth", s,
-             k_synth<<<ceil_div(batch, 256), 256, 0, s>>>(D->dhr, D->M, D->r, D->lut, D->nparam, P->stats, (unsigned)seed,
-                                                         (unsigned)(seed >> 32), (unsigned)step, batch, snr_lo, snr_hi,
-                                                         (float)D->L, z, t, m));
+             launch_synth(D->r, dim3(ceil_div(batch, 256)), s, D->dhr, D->M, D->lut, D->nparam, P->stats, (unsigned)seed,
+                          (unsigned)(seed >> 32), (unsigned)step, batch, snr_lo, snr_hi, (float)D->L, z, t, m));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
 }
@@ -697,9 +714,9 @@ extern "C" mrf_status mrf_mlp_train(mrf_mlp_t P, mrf_dict_t D, const mrf_mlp_tra
   for (int it = 0; it < cfg->steps; ++it) {
     const int step = cfg->first_step + it;
     MRF_LAUNCH("mlp_synth", s,
-               k_synth<<<ceil_div(B, 256), 256, 0, s>>>(D->dhr, D->M, D->r, D->lut, D->nparam, P->stats,
-                                                       (unsigned)cfg->seed, (unsigned)(cfg->seed >> 32), (unsigned)step, B,
-                                                       cfg->snr_lo, cfg->snr_hi, (float)D->L, w.z, w.t, nullptr));
+               launch_synth(D->r, dim3(ceil_div(B, 256)), s, D->dhr, D->M, D->lut, D->nparam, P->stats,
+                            (unsigned)cfg->seed, (unsigned)(cfg->seed >> 32), (unsigned)step, B, cfg->snr_lo,
+                            cfg->snr_hi, (float)D->L, w.z, w.t, nullptr));
     if ((e = mlp_backward(P, cfg->bf16 != 0, B, w, s))) return e;
     if (losses) MRF_CHECK_HIP(hipMemcpyAsync(losses + it, w.loss, 4, hipMemcpyDeviceToDevice, s));
     const int T = cfg->total_steps > 0 ? cfg->total_steps : cfg->first_step + cfg->steps;

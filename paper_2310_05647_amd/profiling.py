@@ -22,12 +22,12 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
 # launch label (as timed by the library) -> (kernel symbol substring, source file in csrc/)
 KERNELS = {
-    "llr_gram": ("k_gram<64>", "llr.hip"),
+    "llr_gram": ("k_gram_cells", "llr.hip"),
     "llr_tridiag": ("k_tridiag", "llr.hip"),
     "llr_coef": ("k_coef<64>", "llr.hip"),
-    "llr_xupdate": ("k_xupdate_reg", "llr.hip"),
+    "llr_xupdate": ("k_xupdate_mfma<10, true>", "llr.hip"),
     "llr_backxf": ("k_backxf", "llr.hip"),
-    "lap_quad": ("k_lap_quad_edges<64, 2>", "graph.hip"),
+    "lap_quad": ("k_lap_quad_edges<64, 2, 8>", "graph.hip"),
     "nufft_col_adj": ("k_col_adj", "nufft.hip"),
     "nufft_col_fwd": ("k_col_fwd", "nufft.hip"),
     "nufft_row_fwd": ("k_row_fwd", "nufft.hip"),
