@@ -894,6 +894,97 @@ __global__ __launch_bounds__(256) void k_coef(const cf* __restrict__ X, const cf
 }
 
 // Any p^2 <= 64: block per patch, thread per frame.
+// The same coefficients for 8 x 8 patches at stride 4, organised for reuse of X: a block takes 4
+// neighbouring patches of one patch row (one wave each) and a chunk of 64 frames. Per 16 frames
+// the block stages the 8 x 20 pixels its patches cover in LDS (frame stride 161 values: the 16
+// frames read by a quarter-wave fall on distinct bank pairs) and each wave forms its 16 x 16 tile
+// on MFMA. Blocks are numbered chunk-major and dealt to the XCDs in contiguous ranges, so each
+// XCD runs through all patch rows of its frames and consecutive rows find their shared pixels in
+// its L2.
+constexpr int kCsF = 16, kCsChunk = 64, kCsW = 20, kCsFS = 8 * kCsW + 1;
+constexpr int kCsPer = kCsF * 8 * kCsW / 256;   // staged values per thread
+static_assert(kCsF * 8 * kCsW % 256 == 0, "whole stage per thread");
+__global__ __launch_bounds__(256) void k_coef_strip(const cf* __restrict__ X, const cf* __restrict__ U,
+                                                    const float* __restrict__ fk, PatchGeom g, int L, int rcap,
+                                                    cf* __restrict__ C) {
+  __shared__ cf S[kCsF * kCsFS];
+  const int nstrip = (g.n1 + 3) / 4, nchunk = (L + kCsChunk - 1) / kCsChunk;
+  const int nblk = nchunk * g.n1 * nstrip, per = (nblk + 7) / 8;
+  const int q = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (q >= nblk) return;
+  const int ch = q / (g.n1 * nstrip), rem = q % (g.n1 * nstrip);
+  const int pa = rem / nstrip, b0 = (rem % nstrip) * 4;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int pb = b0 + w;
+  const bool pv = pb < g.n1;
+  const int i = pa * g.n1 + (pv ? pb : 0);
+  // A[m][kk] = conj(U[k = m][pixel 4 s + kk]): lane supplies m = lane % 16, kk = lane / 16
+  float ur[16], ui[16];
+  {
+    const int k = lane % 16;
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+      const cf x = pv && k < rcap ? U[((size_t)i * rcap + k) * 64 + st * 4 + lane / 16] : cf{0.f, 0.f};
+      ur[st] = x.x;
+      ui[st] = x.y;
+    }
+  }
+  float fo[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int k = 4 * (lane / 16) + e;
+    fo[e] = pv && k < rcap ? fk[(size_t)i * rcap + k] : 0.f;
+  }
+  const size_t NN = (size_t)g.N * g.N;
+  const int x0 = 4 * b0, y0 = 4 * pa;
+  const int lc0 = ch * kCsChunk, lc1 = min(L, lc0 + kCsChunk);
+  cf nxt[kCsPer];
+  auto load = [&](int l0) {
+#pragma unroll
+    for (int j = 0; j < kCsPer; ++j) {
+      const int e = tid + 256 * j, f = e / (8 * kCsW), r2 = e % (8 * kCsW), y = r2 / kCsW, x = r2 % kCsW;
+      nxt[j] = l0 + f < lc1 && x0 + x < g.N ? X[(size_t)(l0 + f) * NN + (size_t)(y0 + y) * g.N + x0 + x]
+                                             : cf{0.f, 0.f};
+    }
+  };
+  load(lc0);
+  for (int l0 = lc0; l0 < lc1; l0 += kCsF) {
+#pragma unroll
+    for (int j = 0; j < kCsPer; ++j) {
+      const int e = tid + 256 * j, f = e / (8 * kCsW), r2 = e % (8 * kCsW);
+      S[f * kCsFS + r2] = nxt[j];
+    }
+    lds_sync();
+    if (l0 + kCsF < lc1) load(l0 + kCsF);
+    if (pv) {
+      // four accumulation chains (Re, Im x even, odd pixel steps) keep the MFMA pipe busy
+      f32x4 dr[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}}, di[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+      const cf* Sb = S + (lane % 16) * kCsFS + 4 * w;
+#pragma unroll
+      for (int st = 0; st < 16; ++st) {
+        const int a = 4 * st + lane / 16, h = st & 1;
+        const cf bv = Sb[(a >> 3) * kCsW + (a & 7)];
+        dr[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(ur[st], bv.x, dr[h], 0, 0, 0);
+        di[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(ur[st], bv.y, di[h], 0, 0, 0);
+        dr[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(ui[st], bv.y, dr[h], 0, 0, 0);
+        di[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ui[st], bv.x, di[h], 0, 0, 0);
+      }
+      const int f = l0 + lane % 16;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = 4 * (lane / 16) + e;
+        if (k < rcap && f < lc1)
+          C[((size_t)i * rcap + k) * L + f] = cf{(dr[0][e] + dr[1][e]) * fo[e], (di[0][e] + di[1][e]) * fo[e]};
+      }
+    }
+    lds_sync();
+  }
+}
+inline int coef_strip_blocks(const PatchGeom& g, int L) {
+  const int nblk = ((L + kCsChunk - 1) / kCsChunk) * g.n1 * ((g.n1 + 3) / 4);
+  return 8 * ((nblk + 7) / 8);
+}
+
 __global__ __launch_bounds__(256) void k_coef_any(const cf* __restrict__ X, const cf* __restrict__ U,
                                                   const float* __restrict__ fk, PatchGeom g, int L, int rcap,
                                                   cf* __restrict__ C) {
@@ -1250,7 +1341,9 @@ mrf_status llr_analyse(const cf* X, const PatchGeom& g, int L, double tau, int r
 mrf_status llr_coef(const cf* X, const PatchGeom& g, int L, int rcap, const cf* U, const float* f, cf* C,
                     hipStream_t s) {
   const int PP = g.p * g.p, nb = patch_blocks(g.Np);
-  if (PP == 64) MRF_LAUNCH("llr_coef", s, k_coef<64><<<nb, 256, 0, s>>>(X, U, f, g, L, rcap, C));
+  if (g.p == 8 && g.s == 4 && rcap <= 16)
+    MRF_LAUNCH("llr_coef", s, k_coef_strip<<<coef_strip_blocks(g, L), 256, 0, s>>>(X, U, f, g, L, rcap, C));
+  else if (PP == 64) MRF_LAUNCH("llr_coef", s, k_coef<64><<<nb, 256, 0, s>>>(X, U, f, g, L, rcap, C));
   else if (PP == 16) MRF_LAUNCH("llr_coef", s, k_coef<16><<<nb, 256, 0, s>>>(X, U, f, g, L, rcap, C));
   else MRF_LAUNCH("llr_coef", s, k_coef_any<<<nb, 256, 0, s>>>(X, U, f, g, L, rcap, C));
   MRF_CHECK_LAUNCH();
