@@ -23,6 +23,15 @@ __device__ inline void lds_sync() {
   asm volatile("" ::: "memory");
 }
 
+// Ordering of one wave's LDS accesses (a wave's LDS operations execute in order): the wave waits
+// for its outstanding LDS reads, and the compiler may not move memory operations across.
+__device__ inline void wave_lds_sync() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Radix schedule: radix-8 passes, one radix-4 or radix-2 pass when log2 of the power-of-two
 // part is not a multiple of 3, then one pass per factor 3 and per factor 5.
 constexpr int count_factor(int g, int f) { return g % f == 0 ? 1 + count_factor(g / f, f) : 0; }
@@ -124,18 +133,23 @@ __host__ __device__ constexpr int padx(int n) {
 // ZIN: the inputs n in [G/4, 3G/4) are zero (zero-padded half of a 2x oversampled grid) and are
 // not read; only valid for a first pass (Ns = 1) of radix 8, whose butterflies then take r = 0, 1,
 // 6, 7. COUT: outputs n in [G/4, 3G/4) are not needed (cropped) and are not stored.
-template <int G, int R, int NT, int ES, int TS, bool CFAST, bool INV, int PS = 0, bool ZIN = false, bool COUT = false>
+// WAVE: every wave transforms its own NT transforms (wave w: transforms w NT .. w NT + NT - 1)
+// and orders its LDS accesses itself, with no workgroup barrier.
+template <int G, int R, int NT, int ES, int TS, bool CFAST, bool INV, int PS = 0, bool ZIN = false, bool COUT = false,
+          bool WAVE = false>
 __device__ inline void stockham_pass(cf* buf, const cf* tw, int Ns) {
   static_assert(!ZIN || R == 8, "input pruning needs a radix-8 first pass");
   constexpr int NB = G / R;                 // butterflies per transform
   constexpr int TB = NB * NT;               // butterflies per pass
-  constexpr int PER = (TB + kBlock - 1) / kBlock;
-  const int tid = threadIdx.x;
+  constexpr int NTH = WAVE ? 64 : kBlock;   // threads sharing the pass
+  constexpr int PER = (TB + NTH - 1) / NTH;
+  const int tid = WAVE ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
+  if (WAVE) buf += (threadIdx.x >> 6) * NT * TS;
   cf v[PER][R];
 #pragma unroll
   for (int b = 0; b < PER; ++b) {
-    const int id = tid + b * kBlock;
-    if (TB % kBlock == 0 || id < TB) {
+    const int id = tid + b * NTH;
+    if (TB % NTH == 0 || id < TB) {
       const int c = CFAST ? id % NT : id / NB;
       const int j = CFAST ? id / NT : id % NB;
 #pragma unroll
@@ -143,11 +157,12 @@ __device__ inline void stockham_pass(cf* buf, const cf* tw, int Ns) {
         v[b][r] = (ZIN && r >= 2 && r <= 5) ? cf{0.f, 0.f} : buf[padx<PS>(j + r * NB) * ES + c * TS];
     }
   }
-  lds_sync();
+  if (WAVE) wave_lds_sync();
+  else lds_sync();
 #pragma unroll
   for (int b = 0; b < PER; ++b) {
-    const int id = tid + b * kBlock;
-    if (TB % kBlock == 0 || id < TB) {
+    const int id = tid + b * NTH;
+    if (TB % NTH == 0 || id < TB) {
       const int c = CFAST ? id % NT : id / NB;
       const int j = CFAST ? id / NT : id % NB;
       const int k = j % Ns;
@@ -169,11 +184,13 @@ __device__ inline void stockham_pass(cf* buf, const cf* tw, int Ns) {
       }
     }
   }
-  lds_sync();
+  if (WAVE) wave_lds_sync();
+  else lds_sync();
 }
 
 // Full in-LDS FFT of NT transforms of length G. tw[k] = exp(-2 pi i k / G) in LDS.
-template <int G, int NT, int ES, int TS, bool CFAST, bool INV, int PS = 0, bool ZIN = false, bool COUT = false>
+template <int G, int NT, int ES, int TS, bool CFAST, bool INV, int PS = 0, bool ZIN = false, bool COUT = false,
+          bool WAVE = false>
 __device__ inline void lds_fft(cf* buf, const cf* tw) {
   using P = FftPlan<G>;
   static_assert(!ZIN || P::radix(0) == 8, "input pruning needs a radix-8 first pass");
@@ -182,22 +199,22 @@ __device__ inline void lds_fft(cf* buf, const cf* tw) {
   for (int p = 0; p < P::npass; ++p) {
     const bool first = p == 0, last = p == P::npass - 1;
     if (P::radix(p) == 8) {
-      if (first && last) stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS, ZIN, COUT>(buf, tw, Ns);
-      else if (first) stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS, ZIN, false>(buf, tw, Ns);
-      else if (last) stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS, false, COUT>(buf, tw, Ns);
-      else stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS>(buf, tw, Ns);
+      if (first && last) stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS, ZIN, COUT, WAVE>(buf, tw, Ns);
+      else if (first) stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS, ZIN, false, WAVE>(buf, tw, Ns);
+      else if (last) stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS, false, COUT, WAVE>(buf, tw, Ns);
+      else stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS, false, false, WAVE>(buf, tw, Ns);
     } else if (P::radix(p) == 4) {
-      if (last) stockham_pass<G, 4, NT, ES, TS, CFAST, INV, PS, false, COUT>(buf, tw, Ns);
-      else stockham_pass<G, 4, NT, ES, TS, CFAST, INV, PS>(buf, tw, Ns);
+      if (last) stockham_pass<G, 4, NT, ES, TS, CFAST, INV, PS, false, COUT, WAVE>(buf, tw, Ns);
+      else stockham_pass<G, 4, NT, ES, TS, CFAST, INV, PS, false, false, WAVE>(buf, tw, Ns);
     } else if (P::radix(p) == 2) {
-      if (last) stockham_pass<G, 2, NT, ES, TS, CFAST, INV, PS, false, COUT>(buf, tw, Ns);
-      else stockham_pass<G, 2, NT, ES, TS, CFAST, INV, PS>(buf, tw, Ns);
+      if (last) stockham_pass<G, 2, NT, ES, TS, CFAST, INV, PS, false, COUT, WAVE>(buf, tw, Ns);
+      else stockham_pass<G, 2, NT, ES, TS, CFAST, INV, PS, false, false, WAVE>(buf, tw, Ns);
     } else if (P::radix(p) == 3) {
-      if (last) stockham_pass<G, 3, NT, ES, TS, CFAST, INV, PS, false, COUT>(buf, tw, Ns);
-      else stockham_pass<G, 3, NT, ES, TS, CFAST, INV, PS>(buf, tw, Ns);
+      if (last) stockham_pass<G, 3, NT, ES, TS, CFAST, INV, PS, false, COUT, WAVE>(buf, tw, Ns);
+      else stockham_pass<G, 3, NT, ES, TS, CFAST, INV, PS, false, false, WAVE>(buf, tw, Ns);
     } else {
-      if (last) stockham_pass<G, 5, NT, ES, TS, CFAST, INV, PS, false, COUT>(buf, tw, Ns);
-      else stockham_pass<G, 5, NT, ES, TS, CFAST, INV, PS>(buf, tw, Ns);
+      if (last) stockham_pass<G, 5, NT, ES, TS, CFAST, INV, PS, false, COUT, WAVE>(buf, tw, Ns);
+      else stockham_pass<G, 5, NT, ES, TS, CFAST, INV, PS, false, false, WAVE>(buf, tw, Ns);
     }
     Ns *= P::radix(p);
   }

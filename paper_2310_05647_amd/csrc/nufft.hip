@@ -29,6 +29,8 @@
 
 namespace mrf {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 struct alignas(16) Entry {
   int j;        // sample index inside the frame
   int lb;       // tile-local footprint origin: low 16 bits column (signed), high 16 bits row
@@ -231,7 +233,8 @@ __global__ __launch_bounds__(kBlock) void k_col_fwd(const cf* __restrict__ T, co
     const Entry first = en_pre;
     lds_sync();
     if (f + 1 < fe) load(f + 1);
-    lds_fft<G, TX, P, 1, true, false, 0, true, false>(S, tw);
+    lds_fft<G, TX / 4, P, 1, true, false, 0, true, false, true>(S, tw);   // per-wave columns, as in k_col_adj
+    lds_sync();
     const int e0 = tp[f - fb][w], e1 = tp[f - fb][w + 1];
     const cf* Sw = S + w * TY * P;
     for (int e = e0 + lane; e < e1; e += 64) {
@@ -321,11 +324,78 @@ __device__ inline void spread_tile(const Entry* __restrict__ ent, const cf* __re
   for (int w = 0; w < NW; ++w) Sw[(w * R + rsub) * P + col] = acc[w];
 }
 
+// The same spread for TX = 8 as small dense products on MFMA. The kernel is separable, so a window
+// of 16 rows of the wave's quarter strip is S_win = A B with A[row][e] = wy_e(row) (zero outside
+// entry e's six rows) and B[e][2 c + part] = wx_e(c) (Re, Im)(r_e)[part]: one 16x16x4 MFMA per
+// four entries gives the 16 rows x 8 complex columns. Entries are taken in list order, so the
+// sums have a fixed order. Lane l of a K-step reads entry 4 s + l / 16 of the batch: origin and
+// value by ds_bpermute from the lane that loaded it, weights from LDS.
+template <int G>
+__device__ inline void spread_tile_mfma(const Entry* __restrict__ ent, const cf* __restrict__ rg, int e0, int e1,
+                                        const Entry& first, cf first_r, float (*wst)[12], cf* __restrict__ Sw,
+                                        int lane) {
+  constexpr int TY = G / 4, NWIN = TY / 16, P = 9;
+  static_assert(NWIN >= 1 && TY % 16 == 0, "16-row windows");
+  f32x4 acc[NWIN];
+#pragma unroll
+  for (int wi = 0; wi < NWIN; ++wi) acc[wi] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int m = lane & 15, kk = lane >> 4;
+  const int c = m >> 1, part = m & 1;
+  for (int base = e0; base < e1; base += 64) {
+    const int cnt = min(64, e1 - base);
+    int lb = 0x7fff0000;       // rows beyond every window for idle lanes
+    cf rv{0.f, 0.f};
+    if (lane < cnt) {
+      const Entry en = base == e0 ? first : ent[base + lane];
+      lb = en.lb;
+      rv = base == e0 ? first_r : rg[base + lane];
+#pragma unroll
+      for (int d = 0; d < 6; ++d) {
+        wst[lane][d] = en.wx[d];
+        wst[lane][6 + d] = en.wy[d];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int lby = lb >> 16;
+#pragma unroll
+    for (int wi = 0; wi < NWIN; ++wi) {
+      const int r0 = 16 * wi;
+      const int a = __popcll(__ballot(lby < r0 - 5));
+      const int b = __popcll(__ballot(lby <= r0 + 15));
+      for (int k0 = a; k0 < b; k0 += 4) {
+        const int k = k0 + kk;
+        const bool valid = k < b;
+        const int kc = valid ? k : a;   // an entry of the batch, for in-range reads
+        const int lbk = __builtin_amdgcn_ds_bpermute(kc << 2, lb);
+        const float rx = __int_as_float(__builtin_amdgcn_ds_bpermute(kc << 2, __float_as_int(rv.x)));
+        const float ry = __int_as_float(__builtin_amdgcn_ds_bpermute(kc << 2, __float_as_int(rv.y)));
+        const int dy = r0 + m - (lbk >> 16), dx = c - (short)(lbk & 0xffff);
+        const bool iny = valid && (unsigned)dy < 6u, inx = valid && (unsigned)dx < 6u;
+        const float wy = wst[kc][6 + (iny ? dy : 0)];
+        const float wx = wst[kc][inx ? dx : 0];
+        const float av = iny ? wy : 0.f;
+        const float bv = inx ? wx * (part ? ry : rx) : 0.f;
+        acc[wi] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[wi], 0, 0, 0);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  float* Sf = reinterpret_cast<float*>(Sw);
+#pragma unroll
+  for (int wi = 0; wi < NWIN; ++wi)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Sf[((16 * wi + 4 * kk + e) * P + c) * 2 + part] = acc[wi][e];
+}
+
 // Column pass, adjoint: per (strip, frame) spread the tile entries into the strip (each wave one
 // tile), inverse transform along y, write the N crop rows of the strip to T. The next frame's
 // first 64 entries per wave and their residual values are prefetched during the transform.
 template <int G, int TX>
-__global__ __launch_bounds__(kBlock) void k_col_adj(const cf* __restrict__ rg, const Entry* __restrict__ ent,
+__global__ __launch_bounds__(kBlock, 3) void k_col_adj(const cf* __restrict__ rg, const Entry* __restrict__ ent,
                                                     const int* __restrict__ tile_ptr,
                                                     const cf* __restrict__ twg, cf* __restrict__ T,
                                                     int L, int FC) {
@@ -360,9 +430,15 @@ __global__ __launch_bounds__(kBlock) void k_col_adj(const cf* __restrict__ rg, c
     const Entry first = en_pre;
     const cf first_r = r_pre;
     if (f + 1 < fe) load(f + 1);
-    spread_tile<G, TX>(ent, rg, tp[f - fb][w], tp[f - fb][w + 1], first, first_r, wst[w], S + w * TY * P, lane);
+    if constexpr (TX == 8 && (G / 4) % 16 == 0)
+      spread_tile_mfma<G>(ent, rg, tp[f - fb][w], tp[f - fb][w + 1], first, first_r, wst[w], S + w * TY * P, lane);
+    else
+      spread_tile<G, TX>(ent, rg, tp[f - fb][w], tp[f - fb][w + 1], first, first_r, wst[w], S + w * TY * P, lane);
     lds_sync();
-    lds_fft<G, TX, P, 1, true, true, 0, false, true>(S, tw);   // only the N cropped rows are stored
+    // each wave transforms its TX/4 columns on its own (no workgroup barrier inside), then the
+    // block meets before the cropped rows are stored
+    lds_fft<G, TX / 4, P, 1, true, true, 0, false, true, true>(S, tw);   // only the N cropped rows are stored
+    lds_sync();
     cf* Tf = T + (size_t)f * N * G;
     for (int idx = tid; idx < N * TX; idx += kBlock) {
       const int y = idx / TX, cc = idx % TX;
