@@ -136,7 +136,7 @@ __host__ __device__ constexpr int padx(int n) {
 // WAVE: every wave transforms its own NT transforms (wave w: transforms w NT .. w NT + NT - 1)
 // and orders its LDS accesses itself, with no workgroup barrier.
 template <int G, int R, int NT, int ES, int TS, bool CFAST, bool INV, int PS = 0, bool ZIN = false, bool COUT = false,
-          bool WAVE = false>
+          bool WAVE = false, int TWS = 1>
 __device__ inline void stockham_pass(cf* buf, const cf* tw, int Ns) {
   static_assert(!ZIN || R == 8, "input pruning needs a radix-8 first pass");
   constexpr int NB = G / R;                 // butterflies per transform
@@ -170,7 +170,7 @@ __device__ inline void stockham_pass(cf* buf, const cf* tw, int Ns) {
       if (Ns > 1) {   // the first pass has only unit twiddles
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cf t = tw[k * r * step];   // k r step < G for every pass
+          cf t = tw[k * r * step * TWS];   // k r step < G for every pass
           if (INV) t.y = -t.y;
           v[b][r] = cmul(v[b][r], t);
         }
@@ -188,9 +188,9 @@ __device__ inline void stockham_pass(cf* buf, const cf* tw, int Ns) {
   else lds_sync();
 }
 
-// Full in-LDS FFT of NT transforms of length G. tw[k] = exp(-2 pi i k / G) in LDS.
+// Full in-LDS FFT of NT transforms of length G. tw[k TWS] = exp(-2 pi i k / G) in LDS.
 template <int G, int NT, int ES, int TS, bool CFAST, bool INV, int PS = 0, bool ZIN = false, bool COUT = false,
-          bool WAVE = false>
+          bool WAVE = false, int TWS = 1>
 __device__ inline void lds_fft(cf* buf, const cf* tw) {
   using P = FftPlan<G>;
   static_assert(!ZIN || P::radix(0) == 8, "input pruning needs a radix-8 first pass");
@@ -199,22 +199,22 @@ __device__ inline void lds_fft(cf* buf, const cf* tw) {
   for (int p = 0; p < P::npass; ++p) {
     const bool first = p == 0, last = p == P::npass - 1;
     if (P::radix(p) == 8) {
-      if (first && last) stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS, ZIN, COUT, WAVE>(buf, tw, Ns);
-      else if (first) stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS, ZIN, false, WAVE>(buf, tw, Ns);
-      else if (last) stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS, false, COUT, WAVE>(buf, tw, Ns);
-      else stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS, false, false, WAVE>(buf, tw, Ns);
+      if (first && last) stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS, ZIN, COUT, WAVE, TWS>(buf, tw, Ns);
+      else if (first) stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS, ZIN, false, WAVE, TWS>(buf, tw, Ns);
+      else if (last) stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS, false, COUT, WAVE, TWS>(buf, tw, Ns);
+      else stockham_pass<G, 8, NT, ES, TS, CFAST, INV, PS, false, false, WAVE, TWS>(buf, tw, Ns);
     } else if (P::radix(p) == 4) {
-      if (last) stockham_pass<G, 4, NT, ES, TS, CFAST, INV, PS, false, COUT, WAVE>(buf, tw, Ns);
-      else stockham_pass<G, 4, NT, ES, TS, CFAST, INV, PS, false, false, WAVE>(buf, tw, Ns);
+      if (last) stockham_pass<G, 4, NT, ES, TS, CFAST, INV, PS, false, COUT, WAVE, TWS>(buf, tw, Ns);
+      else stockham_pass<G, 4, NT, ES, TS, CFAST, INV, PS, false, false, WAVE, TWS>(buf, tw, Ns);
     } else if (P::radix(p) == 2) {
-      if (last) stockham_pass<G, 2, NT, ES, TS, CFAST, INV, PS, false, COUT, WAVE>(buf, tw, Ns);
-      else stockham_pass<G, 2, NT, ES, TS, CFAST, INV, PS, false, false, WAVE>(buf, tw, Ns);
+      if (last) stockham_pass<G, 2, NT, ES, TS, CFAST, INV, PS, false, COUT, WAVE, TWS>(buf, tw, Ns);
+      else stockham_pass<G, 2, NT, ES, TS, CFAST, INV, PS, false, false, WAVE, TWS>(buf, tw, Ns);
     } else if (P::radix(p) == 3) {
-      if (last) stockham_pass<G, 3, NT, ES, TS, CFAST, INV, PS, false, COUT, WAVE>(buf, tw, Ns);
-      else stockham_pass<G, 3, NT, ES, TS, CFAST, INV, PS, false, false, WAVE>(buf, tw, Ns);
+      if (last) stockham_pass<G, 3, NT, ES, TS, CFAST, INV, PS, false, COUT, WAVE, TWS>(buf, tw, Ns);
+      else stockham_pass<G, 3, NT, ES, TS, CFAST, INV, PS, false, false, WAVE, TWS>(buf, tw, Ns);
     } else {
-      if (last) stockham_pass<G, 5, NT, ES, TS, CFAST, INV, PS, false, COUT, WAVE>(buf, tw, Ns);
-      else stockham_pass<G, 5, NT, ES, TS, CFAST, INV, PS, false, false, WAVE>(buf, tw, Ns);
+      if (last) stockham_pass<G, 5, NT, ES, TS, CFAST, INV, PS, false, COUT, WAVE, TWS>(buf, tw, Ns);
+      else stockham_pass<G, 5, NT, ES, TS, CFAST, INV, PS, false, false, WAVE, TWS>(buf, tw, Ns);
     }
     Ns *= P::radix(p);
   }

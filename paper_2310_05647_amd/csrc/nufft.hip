@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_row_adj(const cf* __restrict__ T, cf
 // Each wave interpolates the entries of its tile (the strip's rows [w G/4, (w+1) G/4)), lane per
 // entry, with the taps that fall inside the tile; the sum over a sample's tiles is k_combine.
 template <int G, int TX>
-__global__ __launch_bounds__(kBlock) void k_col_fwd(const cf* __restrict__ T, const Entry* __restrict__ ent,
+__global__ __launch_bounds__(kBlock, 4) void k_col_fwd(const cf* __restrict__ T, const Entry* __restrict__ ent,
                                                     const int* __restrict__ tile_ptr,
                                                     const cf* __restrict__ twg,
                                                     cf* __restrict__ partial, int L, int FC) {
@@ -194,15 +194,14 @@ __global__ __launch_bounds__(kBlock) void k_col_fwd(const cf* __restrict__ T, co
   constexpr int TY = G / 4;
   constexpr int NSTRIP = G / TX;
   constexpr int PT = (N * TX + kBlock - 1) / kBlock;
-  __shared__ cf S[G * P];
-  __shared__ cf tw[G];
+  __shared__ cf S[G * P];   // column TX (the row padding) holds the twiddles tw[k] = S[k P + TX]
   __shared__ int tp[kMaxFramesPerBlock][5];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   int sx, c;
   if (!strip_and_chunk(NSTRIP, (L + FC - 1) / FC, sx, c)) return;
   const int fb = c * FC, fe = min(L, fb + FC);
   const int c0 = sx * TX;
-  for (int i = tid; i < G; i += kBlock) tw[i] = twg[i];
+  for (int i = tid; i < G; i += kBlock) S[i * P + TX] = twg[i];
   for (int i = tid; i < (fe - fb) * 5; i += kBlock)
     tp[i / 5][i % 5] = tile_ptr[(size_t)(fb + i / 5) * NSTRIP * 4 + sx * 4 + i % 5];
   lds_sync();
@@ -233,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_col_fwd(const cf* __restrict__ T, co
     const Entry first = en_pre;
     lds_sync();
     if (f + 1 < fe) load(f + 1);
-    lds_fft<G, TX / 4, P, 1, true, false, 0, true, false, true>(S, tw);   // per-wave columns, as in k_col_adj
+    lds_fft<G, TX / 4, P, 1, true, false, 0, true, false, true, P>(S, S + TX);   // per-wave columns, as in k_col_adj
     lds_sync();
     const int e0 = tp[f - fb][w], e1 = tp[f - fb][w + 1];
     const cf* Sw = S + w * TY * P;
