@@ -514,7 +514,7 @@ __global__ __launch_bounds__(256) void k_lap_quad_edges(const cf* __restrict__ X
 #pragma unroll
   for (int k = 0; k < FPT; ++k) s0 += PixVec<PV>::dot(qi[k], qi[k]);
   double acc = 0.0;
-  auto pix = [&](int j) { return (j / g.n1) * g.s * g.N + (j % g.n1) * g.s + off; };
+  // sj holds each neighbour's patch origin offset (formed once per edge by the lane that read it)
   // the row in windows of 64 entries (a hub node's row can be longer than 2 K + 1)
   const int e0 = rowptr[i], e1 = rowptr[i + 1];
   for (int base = e0; base < e1; base += 64) {
@@ -527,14 +527,14 @@ __global__ __launch_bounds__(256) void k_lap_quad_edges(const cf* __restrict__ X
     if (dg) acc += (double)__shfl(wj, __ffsll((long long)dg) - 1) * s0;
     if (cj > i) {
       const int pos = __popcll(up & ((1ull << lane) - 1ull));
-      sj[w][pos] = cj;
+      sj[w][pos] = (cj / g.n1) * g.s * g.N + (cj % g.n1) * g.s;
       sw[w][pos] = wj;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     int m = 0;
     for (; m + 1 < nup; m += 2) {
-      const int oa = pix(sj[w][m]), ob = pix(sj[w][m + 1]);
+      const int oa = sj[w][m] + off, ob = sj[w][m + 1] + off;
       VT xa[FPT], xb[FPT];
 #pragma unroll
       for (int k = 0; k < FPT; ++k) {
@@ -550,7 +550,7 @@ __global__ __launch_bounds__(256) void k_lap_quad_edges(const cf* __restrict__ X
       acc += 2.0 * ((double)sw[w][m] * sa + (double)sw[w][m + 1] * sb);
     }
     if (m < nup) {
-      const int oa = pix(sj[w][m]);
+      const int oa = sj[w][m] + off;
       float sa = 0.f;
 #pragma unroll
       for (int k = 0; k < FPT; ++k) sa += PixVec<PV>::dot(qi[k], ld(fbase + k * NSUB, oa));
