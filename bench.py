@@ -61,7 +61,7 @@ def algorithmic_work(name, cfg, E, Np):
         "llr_gram": ("mfma", 4.0 * pp * (pp + 1) * L * Np),          # Hermitian half, 8 flops / complex MAC
         "llr_tridiag": ("fp64", 16.0 / 3.0 * pp ** 3 * Np),          # complex Hermitian tridiagonalisation
         "match_subspace": ("mfma", 8.0 * N * N * M * r),
-        "subspace_reduce": ("hbm", 2 * img),
+        "subspace_reduce": ("hbm", img),                            # one series per call (X V, then (A^H r) V)
         "subspace_expand": ("hbm", img),
         "llr_coef": ("hbm", img + Np * cfg["r_llr"] * L * 8),
         "llr_xupdate": ("hbm", 2 * img + Np * cfg["r_llr"] * L * 8),
