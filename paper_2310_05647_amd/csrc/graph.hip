@@ -457,7 +457,7 @@ __global__ __launch_bounds__(256) void k_lap_full(const cf* __restrict__ X, cf* 
 // (pixel of the patch, frame lane), FPT frames each; the row's neighbours j > i are compacted
 // into LDS (64 entries at a time), then streamed two at a time so that 2 FPT loads per lane are
 // in flight.
-// Blocks hold 4 patches of one chunk; XCD x takes the chunks c = x (mod 8), so each XCD's L2
+// Blocks hold 8 patches of one chunk; XCD x takes the chunks c = x (mod 8), so each XCD's L2
 // holds its 8 frames (4 MB at 256 x 256) while it runs over all patches.
 __device__ inline double wave_sum_d(double v) {
 #pragma unroll
@@ -479,8 +479,9 @@ struct PixVec<2> {
   typedef float4 T;
   __device__ static float dot(const T& a, const T& b) { return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w; }
 };
+constexpr int kQuadWpb = 8;   // waves (patches) per block
 template <int PP, int PV, int FCH>
-__global__ __launch_bounds__(256) void k_lap_quad_edges(const cf* __restrict__ X, const int* __restrict__ rowptr,
+__global__ __launch_bounds__(64 * kQuadWpb) void k_lap_quad_edges(const cf* __restrict__ X, const int* __restrict__ rowptr,
                                                         const int* __restrict__ col, const float* __restrict__ val,
                                                         PatchGeom g, int L, int nchunk, double* __restrict__ part) {
   typedef typename PixVec<PV>::T VT;
@@ -488,14 +489,14 @@ __global__ __launch_bounds__(256) void k_lap_quad_edges(const cf* __restrict__ X
   constexpr int NSUB = 64 / NPL;           // frame lanes per wave
   constexpr int FPT = FCH / NSUB;          // frames per lane
   static_assert(FPT >= 1, "chunk too small for the patch");
-  __shared__ int sj[4][64];
-  __shared__ float sw[4][64];
+  __shared__ int sj[kQuadWpb][64];
+  __shared__ float sw[kQuadWpb][64];
   const int b = blockIdx.x;
   const int q = b >> 3;
-  const int ngrp = (g.Np + 3) / 4;
+  const int ngrp = (g.Np + kQuadWpb - 1) / kQuadWpb;
   const int c = (q / ngrp) * 8 + (b & 7);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = (q % ngrp) * 4 + w;
+  const int i = (q % ngrp) * kQuadWpb + w;
   if (c >= nchunk || i >= g.Np) return;    // whole waves only; no block barrier below
   const int r = (lane % NPL) * PV, fsub = lane / NPL;
   const int off = (r / g.p) * g.N + r % g.p;
@@ -683,11 +684,11 @@ mrf_status lap_quad(mrf_graph_s* G, const cf* X, int L, double* out, hipStream_t
     const int nchunk = ceil_div(L, fch);
     const size_t nb = (size_t)nchunk * g.Np;
     if (nb > G->npart) return fail(MRF_SHAPE, "laplacian quad: too many frames for the partial-sum buffer");
-    const int grid = 8 * ceil_div(g.Np, 4) * ceil_div(nchunk, 8);
+    const int grid = 8 * ceil_div(g.Np, kQuadWpb) * ceil_div(nchunk, 8);
     const bool vec = g.s % 2 == 0 && g.N % 2 == 0;   // 16-byte aligned pixel pairs
 #define MRF_QUAD(PPv, PVv, FCHv) \
   MRF_LAUNCH("lap_quad", s,                                                                                    \
-             k_lap_quad_edges<PPv, PVv, FCHv><<<grid, 256, 0, s>>>(X, G->rowptr, G->col, G->val, g, L, nchunk, G->part))
+             k_lap_quad_edges<PPv, PVv, FCHv><<<grid, 64 * kQuadWpb, 0, s>>>(X, G->rowptr, G->col, G->val, g, L, nchunk, G->part))
     if (PP == 64 && vec) MRF_QUAD(64, 2, kQuadFch64);
     else if (PP == 64) MRF_QUAD(64, 1, kQuadFch64);
     else if (vec) MRF_QUAD(16, 2, kQuadFch16);

@@ -118,3 +118,24 @@ def test_graph_from_c1_phantom_maps():
     n_flip = _check_pattern(Lg, ref["L"], ref["d2"], 8)
     say(f"  phantom graph: {n_flip} entries differ at exact-arithmetic ties")
     assert abs(inf["sigma2"] - ref["sigma2"]) <= 1e-5 * ref["sigma2"]
+
+
+@pytest.mark.parametrize("zero_rows", [24, 48])
+def test_quad_with_hub_rows_matches_oracle(zero_rows):
+    """8 x 8 patches at stride 4 on maps with a large all-zero region: exact-zero distances make the
+    lowest-index patches of the region everyone's nearest neighbours, so some rows hold far more
+    than 2K entries (the trace kernel walks a row in windows of 64 entries).
+    The trace against Re<X, Q*(Q(X) L)> formed by the oracle with the GPU's own L."""
+    rng = np.random.default_rng(zero_rows)
+    N, L = 64, 9
+    maps = random_maps(rng, N)
+    maps[:, :zero_rows, :] = 0.0
+    g, Lg, inf = _gpu_graph(maps, 8, 4, 16)
+    n = Lg.shape[0]
+    upper = max(int(np.count_nonzero(Lg[i, i + 1:])) for i in range(n))
+    X = (rng.standard_normal((L, N, N)) + 1j * rng.standard_normal((L, N, N))).astype(np.complex64)
+    q = float(g.quad(to_dev(X)).cpu().numpy()[0])
+    qref = float(np.vdot(X.astype(np.complex128), oops.laplacian_apply(X, Lg, 8, 4)).real)
+    say(f"  hub rows: longest upper row {upper}; quad rel {abs(q - qref) / abs(qref):.2e}")
+    assert upper > 64
+    assert abs(q - qref) <= 1e-5 * abs(qref)
