@@ -201,7 +201,7 @@ constexpr int kGcW = 4;    // cells per block
 constexpr int kGcF = 16;   // frames per LDS chunk
 constexpr int kGcPer = kGcF * 2 * (kGcW + 2) * 16 / (64 * kGcW);   // staged values per thread
 static_assert(kGcF * 2 * (kGcW + 2) * 16 % (64 * kGcW) == 0, "whole chunks per thread");
-__global__ __launch_bounds__(64 * kGcW) void k_gram_cells(const cf* __restrict__ X, int N, int nc, int L,
+__global__ __launch_bounds__(64 * kGcW, 3) void k_gram_cells(const cf* __restrict__ X, int N, int nc, int L,
                                                           cf* __restrict__ Cb) {
   constexpr int SW = kGcW + 2, RW = 4 * SW;   // cells per staged row, pixels per staged image row
   __shared__ cf S[kGcF][2][SW][16];
@@ -317,7 +317,8 @@ __global__ __launch_bounds__(256) void k_gram_small(const cf* __restrict__ X, Pa
 // Two block barriers per column. The reflectors are written out (v, tau); T has diagonal d and
 // sub-diagonal e (complex), then the phases D make it real: D_0 = 1, D_{k+1} = D_k e_k / |e_k|,
 // e_k -> |e_k|.
-constexpr int kTdJ = kMaxPP / 4;   // columns per thread
+constexpr int kTdW = 4;            // waves per patch (measured faster than 2 or 8)
+constexpr int kTdJ = kMaxPP / kTdW;   // columns per thread
 // a[j] for a run-time j, as a masked sum so that the array stays in registers
 __device__ inline dcplx pick(const dcplx (&a)[kTdJ], int j) {
   double xr = 0.0, xi = 0.0;
@@ -329,13 +330,13 @@ __device__ inline dcplx pick(const dcplx (&a)[kTdJ], int j) {
   }
   return dcplx{xr, xi};
 }
-__global__ __launch_bounds__(256) void k_tridiag(const cf* __restrict__ G, const cf* __restrict__ Cb, PatchGeom g,
+__global__ __launch_bounds__(64 * kTdW) void k_tridiag(const cf* __restrict__ G, const cf* __restrict__ Cb, PatchGeom g,
                                                 int Np, int n, double* __restrict__ dd, double* __restrict__ ee,
                                                 dcplx* __restrict__ refl, double* __restrict__ rtau,
                                                 dcplx* __restrict__ phase) {
   __shared__ dcplx vs[2][kMaxPP];    // reflector of the step, double-buffered by step parity
-  __shared__ dcplx pw[4][kMaxPP];    // per-wave parts of A22 v
-  __shared__ dcplx wsw[4][kMaxPP];   // each wave's copy of w
+  __shared__ dcplx pw[kTdW][kMaxPP];    // per-wave parts of A22 v
+  __shared__ dcplx wsw[kTdW][kMaxPP];   // each wave's copy of w
   __shared__ dcplx es[kMaxPP];
   __shared__ double taus[2];
   const int i = patch_of_block(Np);
@@ -351,7 +352,7 @@ __global__ __launch_bounds__(256) void k_tridiag(const cf* __restrict__ G, const
     // inside a diagonal block only u <= v is read, so A is exactly Hermitian.
     __shared__ cf cblk[10][256];
     const int py = i / g.n1, px = i % g.n1, nc = g.nc;
-    for (int e = t; e < 10 * 256; e += 256) {
+    for (int e = t; e < 10 * 256; e += 64 * kTdW) {
       const int sl = e >> 8, o = e & 255;
       int cell, ty;
       if (sl < 4) { cell = sl; ty = 0; }
@@ -367,7 +368,7 @@ __global__ __launch_bounds__(256) void k_tridiag(const cf* __restrict__ G, const
     const int ca = ((r >> 3) >> 2) * 2 + ((r & 7) >> 2), u = ((r >> 3) & 3) * 4 + (r & 3);
 #pragma unroll
     for (int j = 0; j < kTdJ; ++j) {
-      const int c = 4 * j + w;
+      const int c = kTdW * j + w;
       const int cbt = ((c >> 3) >> 2) * 2 + ((c & 7) >> 2), v = ((c >> 3) & 3) * 4 + (c & 3);
       const int sl = kSlot[ca][cbt];
       const bool direct = ca < cbt || (ca == cbt && u <= v);
@@ -378,7 +379,7 @@ __global__ __launch_bounds__(256) void k_tridiag(const cf* __restrict__ G, const
   } else {
 #pragma unroll
     for (int j = 0; j < kTdJ; ++j) {
-      const int c = 4 * j + w;
+      const int c = kTdW * j + w;
       cf x = cf{0.f, 0.f};
       if (r < n && c < n) x = Gi[(size_t)c * n + r];   // A[r][c] = conj(G[c][r])
       a[j] = dcplx{x.x, -(double)x.y};
@@ -415,13 +416,20 @@ __global__ __launch_bounds__(256) void k_tridiag(const cf* __restrict__ G, const
       dcplx pp{0.0, 0.0};
 #pragma unroll
       for (int j = 0; j < kTdJ; ++j) {
-        const int c = 4 * j + w;
+        const int c = kTdW * j + w;
         if (c > k && c < n) pp = dadd(pp, dmul(a[j], vs[buf][c]));
       }
       pw[w][r] = below ? pp : dcplx{0.0, 0.0};
       __syncthreads();
       const dcplx v = vs[buf][r];
-      const dcplx pv = dscale(dadd(dadd(pw[0][r], pw[1][r]), dadd(pw[2][r], pw[3][r])), tau);
+      dcplx ps;
+      if constexpr (kTdW == 4) ps = dadd(dadd(pw[0][r], pw[1][r]), dadd(pw[2][r], pw[3][r]));
+      else if constexpr (kTdW == 2) ps = dadd(pw[0][r], pw[1][r]);
+      else if constexpr (kTdW == 8)
+        ps = dadd(dadd(dadd(pw[0][r], pw[1][r]), dadd(pw[2][r], pw[3][r])),
+                  dadd(dadd(pw[4][r], pw[5][r]), dadd(pw[6][r], pw[7][r])));
+      else ps = pw[0][r];
+      const dcplx pv = dscale(ps, tau);
       const double kr = wave_sum(below ? v.x * pv.x + v.y * pv.y : 0.0);
       const double ki = wave_sum(below ? v.x * pv.y - v.y * pv.x : 0.0);
       const dcplx K = dscale(dcplx{kr, ki}, 0.5 * tau);
@@ -432,7 +440,7 @@ __global__ __launch_bounds__(256) void k_tridiag(const cf* __restrict__ G, const
       if (below) {
 #pragma unroll
         for (int j = 0; j < kTdJ; ++j) {
-          const int c = 4 * j + w;
+          const int c = kTdW * j + w;
           if (c > k && c < n) {
             const dcplx wc = wsw[w][c], vc = vs[buf][c];
             const dcplx t1 = dmul(v, dcplx{wc.x, -wc.y});
@@ -443,16 +451,16 @@ __global__ __launch_bounds__(256) void k_tridiag(const cf* __restrict__ G, const
       }
     }
     if (k + 1 < n - 2) {
-      if (w == (k + 1) % 4) reflector(k + 1, pick(a, (k + 1) / 4), buf ^ 1);
+      if (w == (k + 1) % kTdW) reflector(k + 1, pick(a, (k + 1) / kTdW), buf ^ 1);
       __syncthreads();
     }
   }
-  if (n >= 2 && w == (n - 2) % 4) {   // e_{n-2} = A[n-1][n-2]
-    const dcplx x = pick(a, (n - 2) / 4);
+  if (n >= 2 && w == (n - 2) % kTdW) {   // e_{n-2} = A[n-1][n-2]
+    const dcplx x = pick(a, (n - 2) / kTdW);
     const dcplx y = dcplx{__shfl(x.x, n - 1), __shfl(x.y, n - 1)};
     if (r == 0) es[n - 2] = y;
   }
-  if (r < n && w == r % 4) dd[(size_t)i * n + r] = pick(a, r / 4).x;
+  if (r < n && w == r % kTdW) dd[(size_t)i * n + r] = pick(a, r / kTdW).x;
   __syncthreads();
   if (t == 0) {
     dcplx D{1.0, 0.0};
@@ -1319,7 +1327,7 @@ mrf_status llr_analyse(const cf* X, const PatchGeom& g, int L, double tau, int r
   else if (PP < 16) MRF_LAUNCH("llr_gram", s, k_gram_small<<<nb, 256, 0, s>>>(X, g, L, w.G));
   else return fail(MRF_SHAPE, "llr: p^2 must be 16 or 64 (or < 16)");
   MRF_LAUNCH("llr_tridiag", s,
-             k_tridiag<<<nb, 256, 0, s>>>(cells ? nullptr : w.G, cells ? w.G : nullptr, g, g.Np, PP, w.dd, w.ee, w.refl,
+             k_tridiag<<<nb, 64 * kTdW, 0, s>>>(cells ? nullptr : w.G, cells ? w.G : nullptr, g, g.Np, PP, w.dd, w.ee, w.refl,
                                           w.rtau, w.ph));
   MRF_LAUNCH("llr_eig", s, k_eig_val<<<nb, 64, 0, s>>>(w.dd, w.ee, g.Np, PP, tau, rcap, w.nuc, w.lam, f, lam_out));
   const int nv64 = (int)ceil_div((long)g.Np * rcap, 64L);

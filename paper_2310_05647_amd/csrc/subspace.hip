@@ -189,7 +189,7 @@ __device__ inline bool better(float s, int m, float bs, int bm) { return s > bs 
 // butterfly over the 16 lanes that share a row gives each wave's arg-max, and the four waves'
 // results meet in LDS (ties to the lowest atom throughout). Four waves per SIMD let one wave's
 // score updates run under another's MFMAs.
-__global__ __launch_bounds__(256) void k_match_sub(const cf* __restrict__ alpha, int Nv, int r,
+__global__ __launch_bounds__(256, 4) void k_match_sub(const cf* __restrict__ alpha, int Nv, int r,
                                                    const float* __restrict__ bpk, int ntile, int M,
                                                    const float* __restrict__ norms, const float* __restrict__ lut,
                                                    int nparam, int* __restrict__ idx_out, float* __restrict__ rho_out,
