@@ -399,7 +399,7 @@ __global__ __launch_bounds__(64 * kTdW) void k_tridiag(const cf* __restrict__ G,
     const double vr = keep ? (head ? x.x - br : x.x) : 0.0;
     const double vi = keep ? (head ? x.y - bi : x.y) : 0.0;
     vs[buf][r] = dcplx{vr, vi};
-    if (r < n) Ri[(size_t)k * n + r] = dcplx{vr, vi};
+    if (r > k && r < n) Ri[(size_t)k * n + r] = dcplx{vr, vi};   // only the entries the back-transform reads
     if (r == 0) {
       rtau[(size_t)i * n + k] = tau;
       taus[buf] = tau;

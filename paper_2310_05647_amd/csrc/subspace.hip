@@ -118,6 +118,46 @@ __global__ __launch_bounds__(256) void k_reduce(const cf* __restrict__ X, const 
   }
 }
 
+// The same partial sums without G, on MFMA: D = V_c^T X_c per chunk c, with one wave per 16
+// voxels. K-step = 4 frames; lane l supplies A[k = l % 16][frame l / 16] = V[frame][k] and
+// B[frame l / 16][voxel l % 16] = X[frame][v0 + l % 16] (16 consecutive voxels of a frame per
+// quarter-wave), and ends with components 4 (l / 16) + e of voxel v0 + l % 16. Complex from four
+// real products: Re = Vr Xr - Vi Xi, Im = Vr Xi + Vi Xr.
+typedef float f32x4r __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_reduce_mfma(const cf* __restrict__ X, const cf* __restrict__ V, int L, int Nv,
+                                                     int r, int fch, cf* __restrict__ part) {
+  const int lane = threadIdx.x & 63, m = lane & 15, kk = lane >> 4;
+  const int v0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  const int c = blockIdx.y;
+  const int l0 = c * fch, l1 = min(L, l0 + fch);
+  const bool vv = v0 + m < Nv, kv = m < r;
+  f32x4r dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
+  for (int f = l0; f < l1; f += 32) {   // 8 K-steps: all loads issued before their MFMAs
+    cf x[8], vk[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int fr = f + 4 * q + kk;
+      const bool fv = fr < l1;
+      x[q] = fv && vv ? X[(size_t)fr * Nv + v0 + m] : cf{0.f, 0.f};
+      vk[q] = fv && kv ? V[(size_t)fr * r + m] : cf{0.f, 0.f};
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      dr = __builtin_amdgcn_mfma_f32_16x16x4f32(vk[q].x, x[q].x, dr, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_16x16x4f32(vk[q].x, x[q].y, di, 0, 0, 0);
+      dr = __builtin_amdgcn_mfma_f32_16x16x4f32(-vk[q].y, x[q].y, dr, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_16x16x4f32(vk[q].y, x[q].x, di, 0, 0, 0);
+    }
+  }
+  if (vv) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = 4 * kk + e;
+      if (k < r) part[((size_t)c * r + k) * Nv + v0 + m] = cf{dr[e], di[e]};
+    }
+  }
+}
+
 // alpha[v][k] = sum_c part[c][k][v] (fixed order). One thread per voxel: the reads of part are
 // coalesced over v, and the thread writes its r contiguous values.
 __global__ void k_reduce_finish(const cf* __restrict__ part, int nch, int Nv, int r, cf* __restrict__ alpha) {
@@ -321,8 +361,12 @@ mrf_status subspace_reduce(const cf* X, const cf* Gd, const double* mu_dev, cons
                            cf* alpha, cf* part, hipStream_t s) {
   const int nch = reduce_chunks(L, Nv);
   const int fch = (L + nch - 1) / nch;
-  MRF_LAUNCH("subspace_reduce", s,
-             k_reduce<<<dim3(ceil_div(Nv, 256), nch), 256, 0, s>>>(X, Gd, mu_dev, 1.0f, V, L, Nv, r, fch, part));
+  if (!Gd && r <= 16)
+    MRF_LAUNCH("subspace_reduce", s,
+               k_reduce_mfma<<<dim3(ceil_div(Nv, 64), nch), 256, 0, s>>>(X, V, L, Nv, r, fch, part));
+  else
+    MRF_LAUNCH("subspace_reduce", s,
+               k_reduce<<<dim3(ceil_div(Nv, 256), nch), 256, 0, s>>>(X, Gd, mu_dev, 1.0f, V, L, Nv, r, fch, part));
   MRF_LAUNCH("subspace_reduce_finish", s, k_reduce_finish<<<ceil_div(Nv, 256), 256, 0, s>>>(part, nch, Nv, r, alpha));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
