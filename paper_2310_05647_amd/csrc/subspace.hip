@@ -192,6 +192,51 @@ __global__ __launch_bounds__(256) void k_expand(const cf* __restrict__ beta, con
   }
 }
 
+// The same expansion on MFMA (r <= 16): per wave 16 voxels and a range of frames, each 16-frame
+// tile D[frame][voxel] = conj(V) beta^T with K = r in steps of 4. Lane l supplies
+// A[frame l % 16][k = 4 s + l / 16] = conj(V[frame][k]) and B[k][voxel l % 16] = beta[v0 + l % 16][k]
+// (held in registers for all frames), and ends with frames 4 (l / 16) + e of voxel v0 + l % 16: each
+// store instruction writes 16 consecutive voxels of 4 frames.
+// Re = Vr br + Vi bi, Im = Vr bi - Vi br.
+__global__ __launch_bounds__(256) void k_expand_mfma(const cf* __restrict__ beta, const cf* __restrict__ V, int L,
+                                                     int Nv, int r, int fch, cf* __restrict__ Z) {
+  const int lane = threadIdx.x & 63, m = lane & 15, kk = lane >> 4;
+  const int v0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  const bool vv = v0 + m < Nv;
+  float br[4], bi[4];
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int k = 4 * st + kk;
+    const cf b = vv && k < r ? beta[(size_t)(v0 + m) * r + k] : cf{0.f, 0.f};
+    br[st] = b.x;
+    bi[st] = b.y;
+  }
+  const int nst = (r + 3) / 4;
+  const int l0 = blockIdx.y * fch, l1 = min(L, l0 + fch);
+  for (int f0 = l0; f0 < l1; f0 += 16) {
+    const int fa = f0 + m;   // A row (frame) of this lane
+    f32x4r dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      if (st < nst) {   // uniform
+        const int k = 4 * st + kk;
+        const cf w = fa < l1 && k < r ? V[(size_t)fa * r + k] : cf{0.f, 0.f};
+        dr = __builtin_amdgcn_mfma_f32_16x16x4f32(w.x, br[st], dr, 0, 0, 0);
+        di = __builtin_amdgcn_mfma_f32_16x16x4f32(w.x, bi[st], di, 0, 0, 0);
+        dr = __builtin_amdgcn_mfma_f32_16x16x4f32(w.y, bi[st], dr, 0, 0, 0);
+        di = __builtin_amdgcn_mfma_f32_16x16x4f32(-w.y, br[st], di, 0, 0, 0);
+      }
+    }
+    if (vv) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int f = f0 + 4 * kk + e;
+        if (f < l1) Z[(size_t)f * Nv + v0 + m] = cf{dr[e], di[e]};
+      }
+    }
+  }
+}
+
 // beta = aU - c * Y  (c = mu * lam1 from device scalars: c = s[0] * s[1] * scale)
 __global__ void k_axpy_scal(const cf* __restrict__ aU, const cf* __restrict__ Y, const double* __restrict__ s0,
                             const double* __restrict__ s1, double scale, long n, cf* __restrict__ out) {
@@ -375,7 +420,11 @@ mrf_status subspace_reduce(const cf* X, const cf* Gd, const double* mu_dev, cons
 mrf_status subspace_expand(const cf* beta, const cf* V, int L, int Nv, int r, cf* Z, hipStream_t s) {
   const int nch = std::max(1, std::min(16, L / 32));
   const int fch = (L + nch - 1) / nch;
-  MRF_LAUNCH("subspace_expand", s, k_expand<<<dim3(ceil_div(Nv, 256), nch), 256, 0, s>>>(beta, V, L, Nv, r, fch, Z));
+  if (r <= 16)
+    MRF_LAUNCH("subspace_expand", s,
+               k_expand_mfma<<<dim3(ceil_div(Nv, 64), nch), 256, 0, s>>>(beta, V, L, Nv, r, fch, Z));
+  else
+    MRF_LAUNCH("subspace_expand", s, k_expand<<<dim3(ceil_div(Nv, 256), nch), 256, 0, s>>>(beta, V, L, Nv, r, fch, Z));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
 }
