@@ -42,20 +42,28 @@ struct mrf_graph_s {
 namespace mrf {
 
 
-__global__ __launch_bounds__(1024) void k_chan_max(const float* __restrict__ maps, int nn, float* __restrict__ mx) {
-  __shared__ float red[1024];
-  for (int c = 0; c < 3; ++c) {
-    float m = -3.4e38f;
-    for (int i = threadIdx.x; i < nn; i += 1024) m = fmaxf(m, maps[(size_t)c * nn + i]);
-    red[threadIdx.x] = m;
-    __syncthreads();
-    for (int o = 512; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) mx[c] = red[0] > 0.f ? red[0] : 1.f;
-    __syncthreads();
-  }
+// Channel maxima of the (T1, T2, PD) maps in two steps: 64 blocks per channel reduce slices into
+// pm[c][b], then one wave per channel takes the maximum of its 64 partials (1 if it is not
+// positive). The maximum does not depend on the order of the comparisons.
+constexpr int kCmBlocks = 64;
+__global__ __launch_bounds__(256) void k_chan_max_part(const float* __restrict__ maps, int nn, float* __restrict__ pm) {
+  __shared__ float red[4];
+  const int c = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
+  const int per = (nn + kCmBlocks - 1) / kCmBlocks, i0 = b * per, i1 = min(nn, i0 + per);
+  float m = -3.4e38f;
+  for (int i = i0 + t; i < i1; i += 256) m = fmaxf(m, maps[(size_t)c * nn + i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((t & 63) == 0) red[t >> 6] = m;
+  __syncthreads();
+  if (t == 0) pm[c * kCmBlocks + b] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+__global__ __launch_bounds__(64 * 3) void k_chan_max_final(const float* __restrict__ pm, float* __restrict__ mx) {
+  const int c = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float m = pm[c * kCmBlocks + lane];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if (lane == 0) mx[c] = m > 0.f ? m : 1.f;
 }
 
 __global__ void k_features(const float* __restrict__ maps, const float* __restrict__ mx, PatchGeom g,
@@ -201,9 +209,63 @@ __global__ __launch_bounds__(256) void k_knn_select(const float* __restrict__ D,
   }
 }
 
-// sigma^2: the lower median of the positive directed K-NN squared distances (radix select on the
-// float bit patterns, which order like the values for non-negative floats); 1 if there are none.
+// sigma^2: the lower median of the positive directed K-NN squared distances (1 if there are none).
+// One block of 1024 threads; for Np K <= 65536 thread t holds values e = t + 1024 j in registers
+// (at most 64 each), non-positive ones replaced by the largest key. The median's bit pattern (which
+// orders like the value for non-negative floats) is then found bit by bit: the largest x with
+// #{u < x} <= target, each count a block-wide sum.
 __global__ __launch_bounds__(1024) void k_sigma(const float* __restrict__ knd2, int Np, int K, int kmax,
+                                                float sigma2_user, double* __restrict__ scal) {
+  constexpr int kPer = 64;
+  __shared__ int wsum[16];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int total = Np * K;
+  unsigned u[kPer];
+  int c = 0;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int e = t + 1024 * j;
+    const float v = e < total ? knd2[(size_t)(e / K) * kmax + e % K] : 0.f;
+    const bool pos = v > 0.f;
+    u[j] = pos ? __float_as_uint(v) : 0xffffffffu;
+    c += pos;
+  }
+  auto block_sum = [&](int x) {   // every thread gets the block total
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    __syncthreads();
+    if (lane == 0) wsum[w] = x;
+    __syncthreads();
+    int tot = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) tot += wsum[q];
+    return tot;
+  };
+  const int npos = block_sum(c);
+  if (sigma2_user > 0.f || npos == 0) {
+    if (t == 0) {
+      scal[0] = sigma2_user > 0.f ? (double)sigma2_user : 1.0;
+      scal[3] = npos;
+    }
+    return;
+  }
+  const int target = (npos - 1) / 2;
+  unsigned x = 0u;
+  for (int bit = 31; bit >= 0; --bit) {
+    const unsigned cand = x | (1u << bit);
+    int cnt = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) cnt += u[j] < cand;
+    if (block_sum(cnt) <= target) x = cand;
+  }
+  if (t == 0) {
+    scal[0] = (double)__uint_as_float(x);
+    scal[3] = npos;
+  }
+}
+
+// The same by a 4-pass radix select from memory, for Np K > 65536.
+__global__ __launch_bounds__(1024) void k_sigma_radix(const float* __restrict__ knd2, int Np, int K, int kmax,
                                                 float sigma2_user, double* __restrict__ scal) {
   __shared__ int hist[256];
   __shared__ int cnt_s;
@@ -635,7 +697,9 @@ mrf_status sum_partials2(const double* part, long n, double* tmp, double* out, h
 mrf_status graph_build(mrf_graph_s* G, const float* maps, int K, float sigma2, hipStream_t s) {
   const PatchGeom& g = G->g;
   const int nf = 3 * g.p * g.p;
-  MRF_LAUNCH("graph_chan_max", s, k_chan_max<<<1, 1024, 0, s>>>(maps, g.N * g.N, G->mx));
+  float* pm = reinterpret_cast<float*>(G->part);   // 3 x kCmBlocks partial maxima (the buffer is free here)
+  MRF_LAUNCH("graph_chan_max", s, k_chan_max_part<<<dim3(kCmBlocks, 3), 256, 0, s>>>(maps, g.N * g.N, pm));
+  MRF_LAUNCH("graph_chan_max", s, k_chan_max_final<<<1, 64 * 3, 0, s>>>(pm, G->mx));
   const long nfeat = (long)g.Np * nf;
   MRF_LAUNCH("graph_features", s, k_features<<<ceil_div(nfeat, 256), 256, 0, s>>>(maps, G->mx, g, G->F));
   const int nt = ceil_div(g.Np, kKnnTile);
@@ -650,7 +714,10 @@ mrf_status graph_build(mrf_graph_s* G, const float* maps, int K, float sigma2, h
     MRF_LAUNCH("graph_knn_select", s, k_knn_select<64><<<sg, 256, 0, s>>>(G->W, g.Np, K, G->knn, G->knd2, G->kmax));
   else
     MRF_LAUNCH("graph_knn_select", s, k_knn_select<128><<<sg, 256, 0, s>>>(G->W, g.Np, K, G->knn, G->knd2, G->kmax));
-  MRF_LAUNCH("graph_sigma", s, k_sigma<<<1, 1024, 0, s>>>(G->knd2, g.Np, K, G->kmax, sigma2, G->scal));
+  if ((long)g.Np * K <= 65536)
+    MRF_LAUNCH("graph_sigma", s, k_sigma<<<1, 1024, 0, s>>>(G->knd2, g.Np, K, G->kmax, sigma2, G->scal));
+  else
+    MRF_LAUNCH("graph_sigma", s, k_sigma_radix<<<1, 1024, 0, s>>>(G->knd2, g.Np, K, G->kmax, sigma2, G->scal));
   const size_t nw = (size_t)g.Np * g.Np;
   MRF_LAUNCH("graph_zero_w", s, k_fill_f<<<1024, 256, 0, s>>>(G->W, nw, 0.f));
   MRF_LAUNCH("graph_scatter_w", s,
