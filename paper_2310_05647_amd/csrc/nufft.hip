@@ -103,11 +103,8 @@ __global__ __launch_bounds__(kBlock) void k_row_fwd(const cf* __restrict__ X, cf
   int g = blockIdx.x;
   if (g < ngroups) load(g);
   for (; g < ngroups; g += gridDim.x) {
-    // zero the padding, place the deapodised inputs at (x - N/2) mod G
-    for (int idx = tid; idx < RPB * (G - N); idx += kBlock) {
-      const int rr = idx / (G - N), n = N / 2 + idx % (G - N);
-      buf[rr * TS + padx<PS>(n)] = cf{0.f, 0.f};
-    }
+    // place the deapodised inputs at (x - N/2) mod G; the zero padding [N/2, G - N/2) is neither
+    // written nor read (the FFT's first pass skips those inputs)
 #pragma unroll
     for (int i = 0; i < PIN; ++i) {
       const int idx = tid + i * kBlock;
@@ -122,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_row_fwd(const cf* __restrict__ X, cf
     }
     lds_sync();
     if (g + (int)gridDim.x < ngroups) load(g + gridDim.x);
-    lds_fft<G, RPB, 1, TS, false, false, PS>(buf, tw);
+    lds_fft<G, RPB, 1, TS, false, false, PS, true, false>(buf, tw);
     for (int idx = tid; idx < RPB * G; idx += kBlock) {
       const int rr = idx / G, n = idx % G;
       const long row = (long)g * RPB + rr;
@@ -166,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_row_adj(const cf* __restrict__ T, cf
     }
     lds_sync();
     if (g + (int)gridDim.x < ngroups) load(g + gridDim.x);
-    lds_fft<G, RPB, 1, TS, false, true, PS>(buf, tw);
+    lds_fft<G, RPB, 1, TS, false, true, PS, false, true>(buf, tw);   // only the N cropped outputs are stored
     for (int idx = tid; idx < RPB * N; idx += kBlock) {
       const int rr = idx / N, x = idx % N;
       const long row = (long)g * RPB + rr;
