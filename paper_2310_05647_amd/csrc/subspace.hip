@@ -404,9 +404,12 @@ size_t reduce_ws_bytes(int L, int Nv, int r) { return (size_t)reduce_chunks(L, N
 // alpha [Nv][r] = (X - mu G) V, with mu from a device scalar (G may be null)
 mrf_status subspace_reduce(const cf* X, const cf* Gd, const double* mu_dev, const cf* V, int L, int Nv, int r,
                            cf* alpha, cf* part, hipStream_t s) {
-  const int nch = reduce_chunks(L, Nv);
+  const bool mf = !Gd && r <= 16;
+  // MFMA blocks take 64 voxels, so fewer chunks fill the chip (never more than the workspace holds)
+  const int nch = mf ? std::max(1, std::min(reduce_chunks(L, Nv), (int)ceil_div(2048, ceil_div(Nv, 64))))
+                     : reduce_chunks(L, Nv);
   const int fch = (L + nch - 1) / nch;
-  if (!Gd && r <= 16)
+  if (mf)
     MRF_LAUNCH("subspace_reduce", s,
                k_reduce_mfma<<<dim3(ceil_div(Nv, 64), nch), 256, 0, s>>>(X, V, L, Nv, r, fch, part));
   else
