@@ -741,10 +741,11 @@ __global__ __launch_bounds__(64) void k_eig_vec_reg(const double* __restrict__ d
 }
 
 // u_k = H_0 H_1 ... H_{n-3} D z_k for the rcap vectors. One block per patch with one wave per four
-// vectors: the patch's reflectors (entries k+1 .. n-1 of row k) are staged once in LDS, packed by
-// row. Wave 0 first orthogonalises, in the tridiagonal basis, each vector against the earlier
-// ones of its cluster (eigenvalues within 1e-6 of the largest; modified Gram-Schmidt). Then wave
-// w back-transforms vectors k = 4 w + s, s = lane / 16: each vector lives in one 16-lane DPP row,
+// vectors; the patch's reflectors (entries k+1 .. n-1 of row k) are read from cache, the next one
+// while the current one is applied. Wave 0 first orthogonalises, in the tridiagonal basis, each
+// vector against the earlier ones of its cluster (eigenvalues within 1e-6 of the largest; modified
+// Gram-Schmidt). Then wave w back-transforms vectors k = 4 w + s, s = lane / 16: each vector lives
+// in one 16-lane DPP row,
 // lane l of the row holding rows l, l + 16, l + 32, l + 48, so the reflector's inner product with
 // the vector is a 16-lane row sum. Stores U[i][k][a] (FP32); components with f_k = 0 (zero z) get
 // zero vectors.
@@ -752,19 +753,14 @@ __global__ __launch_bounds__(256) void k_backxf(const double* __restrict__ zvec,
                                                const dcplx* __restrict__ refl, const double* __restrict__ rtau,
                                                const dcplx* __restrict__ phase, int Np, int n, int rcap,
                                                cf* __restrict__ U) {
-  __shared__ dcplx R[kMaxPP * (kMaxPP - 1) / 2];   // row j at j (n - 1) - j (j - 1) / 2, entries j+1 .. n-1
   __shared__ double zs[kMaxRllr][kMaxPP];
   __shared__ double tau[kMaxPP];
   __shared__ int live[kMaxRllr];
   const int i = patch_of_block(Np);
   if (i < 0) return;
   const int nt = blockDim.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
-  const dcplx* Ri = refl + (size_t)i * n * n;
+  const dcplx* Ri = refl + (size_t)i * n * n;   // reflector j in row j, entries j+1 .. n-1 (read from cache)
   const int nref = n - 2 > 0 ? n - 2 : 0;
-  for (int idx = t; idx < nref * n; idx += nt) {
-    const int j = idx / n, c = idx % n;
-    if (c > j) R[j * (n - 1) - j * (j - 1) / 2 + c - j - 1] = Ri[idx];
-  }
   if (t < n) tau[t] = t < nref ? rtau[(size_t)i * n + t] : 0.0;
   const int m = min(rcap, n);
   for (int idx = t; idx < m * kMaxPP; idx += nt) {
@@ -803,16 +799,26 @@ __global__ __launch_bounds__(256) void k_backxf(const double* __restrict__ zvec,
     u[a] = on && r < n ? dscale(phase[(size_t)i * n + r], zs[k][r]) : dcplx{0.0, 0.0};
   }
   if (__ballot(on) != 0ull) {
-    for (int j = nref - 1; j >= 0; --j) {
-      const double tj = tau[j];
-      if (tj == 0.0) continue;
-      const int off = j * (n - 1) - j * (j - 1) / 2;
-      dcplx v[4];
-      double dr = 0.0, di = 0.0;
+    // the next reflector's entries are loaded while this one is applied
+    auto ldv = [&](int j, dcplx (&v)[4]) {
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const int r = t16 + 16 * a;
-        v[a] = r > j && r < n ? R[off + r - j - 1] : dcplx{0.0, 0.0};
+        v[a] = j >= 0 && r > j && r < n ? Ri[(size_t)j * n + r] : dcplx{0.0, 0.0};
+      }
+    };
+    dcplx vn[4];
+    ldv(nref - 1, vn);
+    for (int j = nref - 1; j >= 0; --j) {
+      dcplx v[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) v[a] = vn[a];
+      ldv(j - 1, vn);
+      const double tj = tau[j];
+      if (tj == 0.0) continue;
+      double dr = 0.0, di = 0.0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
         dr += v[a].x * u[a].x + v[a].y * u[a].y;
         di += v[a].x * u[a].y - v[a].y * u[a].x;
       }
