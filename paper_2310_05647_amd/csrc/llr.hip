@@ -479,15 +479,14 @@ __global__ __launch_bounds__(64 * kTdW) void k_tridiag(const cf* __restrict__ G,
 // Number of eigenvalues of the symmetric tridiagonal (d, e^2) smaller than x, from the signs of
 // the pivots q_k = (d_k - x) - e_{k-1}^2 / q_{k-1} of the LDL^T factorisation of T - x I. The
 // matrix is scaled so that |d|, e^2 <= 1; a pivot smaller than pmin in magnitude is replaced by
-// -pmin (a perturbation of d_k by at most pmin). 1/q comes from the hardware reciprocal refined by
-// two Newton steps, which is accurate to rounding whatever the initial approximation's bits.
+// -pmin (a perturbation of d_k by at most pmin). 1/q comes from the hardware reciprocal (about 24
+// correct bits) refined by one Newton step: measured on gfx950 within 11 ulp of the correctly
+// rounded value, a relative perturbation of the pivot of about 2e-15, far below the 1e-13 (of the
+// spectrum's span) resolution the bisection stops at.
 constexpr double kPivMin = 1e-280;
 __device__ inline double recip(double q) {
-  double r = __builtin_amdgcn_rcp(q);
-  double e = fma(-q, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-q, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(q);
+  return fma(r, fma(-q, r, 1.0), r);
 }
 __device__ inline int sturm_count(const double* d, const double* e2, int n, double x) {
   double q = d[0] - x;
