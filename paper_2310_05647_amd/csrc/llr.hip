@@ -412,14 +412,28 @@ __global__ __launch_bounds__(64 * kTdW) void k_tridiag(const cf* __restrict__ G,
     const int buf = k & 1;
     const double tau = taus[buf];
     const bool below = r > k && r < n;
+    // Columns are visited in pairs from the block-uniform bounds jlo = (k + 1) / 4 and
+    // jhi = (n - 1) / 4, which include every column k < c < n of every wave. A column c <= k or
+    // c >= n that a pair brings in adds exact zeros: v and w vanish outside (k, n).
+    const int jlo = (k + 1) >> 2, jhi = (n - 1) >> 2;
     if (tau != 0.0) {   // uniform over the block
-      dcplx pp{0.0, 0.0};
+      // (A22 v)_r over this wave's columns, accumulated by FMAs into two partial sums
+      dcplx pp[2] = {{0.0, 0.0}, {0.0, 0.0}};
 #pragma unroll
-      for (int j = 0; j < kTdJ; ++j) {
-        const int c = kTdW * j + w;
-        if (c > k && c < n) pp = dadd(pp, dmul(a[j], vs[buf][c]));
+      for (int j = 0; j < kTdJ; j += 2) {
+        if (j + 1 >= jlo && j <= jhi) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const dcplx vc = vs[buf][kTdW * (j + h) + w];
+            dcplx& q = pp[h];
+            q.x = fma(a[j + h].x, vc.x, q.x);
+            q.x = fma(-a[j + h].y, vc.y, q.x);
+            q.y = fma(a[j + h].x, vc.y, q.y);
+            q.y = fma(a[j + h].y, vc.x, q.y);
+          }
+        }
       }
-      pw[w][r] = below ? pp : dcplx{0.0, 0.0};
+      pw[w][r] = below ? dadd(pp[0], pp[1]) : dcplx{0.0, 0.0};
       __syncthreads();
       const dcplx v = vs[buf][r];
       dcplx ps;
@@ -438,14 +452,23 @@ __global__ __launch_bounds__(64 * kTdW) void k_tridiag(const cf* __restrict__ G,
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
       if (below) {
+        // A[r][c] -= v_r conj(w_c) + w_r conj(v_c), as four FMAs per component
 #pragma unroll
-        for (int j = 0; j < kTdJ; ++j) {
-          const int c = kTdW * j + w;
-          if (c > k && c < n) {
-            const dcplx wc = wsw[w][c], vc = vs[buf][c];
-            const dcplx t1 = dmul(v, dcplx{wc.x, -wc.y});
-            const dcplx t2 = dmul(wr, dcplx{vc.x, -vc.y});
-            a[j] = dsub(a[j], dadd(t1, t2));
+        for (int j = 0; j < kTdJ; j += 2) {
+          if (j + 1 >= jlo && j <= jhi) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int c = kTdW * (j + h) + w;
+              const dcplx wc = wsw[w][c], vc = vs[buf][c];
+              a[j + h].x = fma(-v.x, wc.x, a[j + h].x);
+              a[j + h].x = fma(-v.y, wc.y, a[j + h].x);
+              a[j + h].x = fma(-wr.x, vc.x, a[j + h].x);
+              a[j + h].x = fma(-wr.y, vc.y, a[j + h].x);
+              a[j + h].y = fma(-v.y, wc.x, a[j + h].y);
+              a[j + h].y = fma(v.x, wc.y, a[j + h].y);
+              a[j + h].y = fma(-wr.y, vc.x, a[j + h].y);
+              a[j + h].y = fma(wr.x, vc.y, a[j + h].y);
+            }
           }
         }
       }
