@@ -42,8 +42,9 @@ __device__ inline dcplx dscale(dcplx a, double s) { return {a.x * s, a.y * s}; }
 template <int CTRL>
 __device__ inline double dpp64(double v) {
   const int lo = __double2loint(v), hi = __double2hiint(v);
-  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false),
-                          __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
+  // every lane has a source lane under these controls, so no old value is needed
+  return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false),
+                          __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false));
 }
 __device__ inline double row_sum16(double v) {
   v += dpp64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
@@ -319,6 +320,7 @@ __global__ __launch_bounds__(256) void k_gram_small(const cf* __restrict__ X, Pa
 // e_k -> |e_k|.
 constexpr int kTdW = 4;            // waves per patch (measured faster than 2 or 8)
 constexpr int kTdJ = kMaxPP / kTdW;   // columns per thread
+constexpr int kTdG = 4;               // columns per guarded group of the update
 // a[j] for a run-time j, as a masked sum so that the array stays in registers
 __device__ inline dcplx pick(const dcplx (&a)[kTdJ], int j) {
   double xr = 0.0, xi = 0.0;
@@ -412,20 +414,20 @@ __global__ __launch_bounds__(64 * kTdW) void k_tridiag(const cf* __restrict__ G,
     const int buf = k & 1;
     const double tau = taus[buf];
     const bool below = r > k && r < n;
-    // Columns are visited in pairs from the block-uniform bounds jlo = (k + 1) / 4 and
+    // Columns are visited in groups of kTdG from the block-uniform bounds jlo = (k + 1) / 4 and
     // jhi = (n - 1) / 4, which include every column k < c < n of every wave. A column c <= k or
-    // c >= n that a pair brings in adds exact zeros: v and w vanish outside (k, n).
+    // c >= n that a group brings in adds exact zeros: v and w vanish outside (k, n).
     const int jlo = (k + 1) >> 2, jhi = (n - 1) >> 2;
     if (tau != 0.0) {   // uniform over the block
       // (A22 v)_r over this wave's columns, accumulated by FMAs into two partial sums
       dcplx pp[2] = {{0.0, 0.0}, {0.0, 0.0}};
 #pragma unroll
-      for (int j = 0; j < kTdJ; j += 2) {
-        if (j + 1 >= jlo && j <= jhi) {
+      for (int j = 0; j < kTdJ; j += kTdG) {
+        if (j + kTdG - 1 >= jlo && j <= jhi) {
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
+          for (int h = 0; h < kTdG; ++h) {
             const dcplx vc = vs[buf][kTdW * (j + h) + w];
-            dcplx& q = pp[h];
+            dcplx& q = pp[h & 1];
             q.x = fma(a[j + h].x, vc.x, q.x);
             q.x = fma(-a[j + h].y, vc.y, q.x);
             q.y = fma(a[j + h].x, vc.y, q.y);
@@ -454,10 +456,10 @@ __global__ __launch_bounds__(64 * kTdW) void k_tridiag(const cf* __restrict__ G,
       if (below) {
         // A[r][c] -= v_r conj(w_c) + w_r conj(v_c), as four FMAs per component
 #pragma unroll
-        for (int j = 0; j < kTdJ; j += 2) {
-          if (j + 1 >= jlo && j <= jhi) {
+        for (int j = 0; j < kTdJ; j += kTdG) {
+          if (j + kTdG - 1 >= jlo && j <= jhi) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < kTdG; ++h) {
               const int c = kTdW * (j + h) + w;
               const dcplx wc = wsw[w][c], vc = vs[buf][c];
               a[j + h].x = fma(-v.x, wc.x, a[j + h].x);
