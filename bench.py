@@ -259,6 +259,9 @@ def main():
     ap.add_argument("--no-match-forms", action="store_true", help="skip the precision and learned match components")
     ap.add_argument("--mlp-epochs", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true", help="skip the 8-slice batched component")
+    ap.add_argument("--serial", type=int, default=0,
+                    help="recon schedule mask: bit 0 runs the cost terms, bit 1 the rest of an iteration on one "
+                         "stream (default 0: independent parts overlap on the recon's two extra streams)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (frames would shard "
@@ -282,7 +285,7 @@ def main():
     sig2 = mrfgen.noise_sigma(np.mean(np.abs(bh) ** 2), cfg["snr_db"])
     b = torch.from_numpy(bh + mrfgen.complex_noise(bh.shape, sig2, 17)).to(dev)
     rc = mrf.Recon(plan, d, cfg["p"], cfg["s"], cfg["K"], cfg["r_llr"], lam1_0=cfg["lam1_0"], lam2=cfg["lam2"],
-                   beta=cfg["beta"], mu0=cfg["mu0"], lamA=lamA, n_max=100000, tol=-1.0)
+                   beta=cfg["beta"], mu0=cfg["mu0"], lamA=lamA, n_max=100000, tol=-1.0, serial=args.serial)
     t = time.time()
     rc.init(b)
     torch.cuda.synchronize()
@@ -302,13 +305,16 @@ def main():
     ms = e0.elapsed_time(e1) / args.steps
     log("timed %d iterations: %.3f ms / iteration" % (args.steps, ms))
 
-    # per-kernel times over two more iterations (HIP events on the launch stream)
+    # per-kernel times over two more iterations (HIP events on the launch stream), run with the
+    # iteration serialised so that no other kernel shares the device with the one being timed
+    rc.set_serial(3)
     mrf.timing_enable(True)
     nrep = 2
     for i in range(nrep):
         rc.iterate(1)
     rep = mrf.timing_report()
     mrf.timing_enable(False)
+    rc.set_serial(args.serial)
     per_kernel = {k: dict(launches_per_step=v[0] / nrep, ms_per_step=v[1] / nrep, avg_ms=v[1] / v[0])
                   for k, v in rep.items()}
 
@@ -405,6 +411,7 @@ def main():
             "nufft_frame_pairs_per_s": round(1000.0 * L / pair_ms, 1),
             "match_subspace_fp32_ms": round(match_ms, 4),
             "fingerprints_matched_per_s_subspace_fp32": round(N * N / (match_ms * 1e-3), 1),
+            "per_kernel_schedule": "serialised iterations after the timed region",
             "per_kernel_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in
                                        sorted(per_kernel.items(), key=lambda kv: -kv[1]["ms_per_step"])},
             "roofline_by_kernel": {r["kernel"]: {"bound": r["bound"], "frac": r["frac"], "achieved": r["achieved"],

@@ -301,6 +301,10 @@ typedef struct mrf_recon_params {
   float sigma2;      /* sigma^2 of eq. (8); <= 0 selects the median rule                           */
   int n_max;         /* maximum number of iterations                                              */
   double tol;        /* stopping tolerance; < 0 runs exactly n_max iterations                     */
+  int serial;        /* 0: independent parts of an iteration overlap on two streams the recon owns
+                        (the cost terms of X; the graph rebuild and the SVT coefficients beside the
+                        gradient). Bit 0 keeps the cost terms, bit 1 the rest on the caller's
+                        stream (per-kernel timings then carry no overlap). Results are identical.  */
 } mrf_recon_params;
 
 #define MRF_MAX_ITERS 512
@@ -330,6 +334,10 @@ mrf_status mrf_recon_init(mrf_recon_t r, const mrf_c64* b, const mrf_c64* X0, hi
 /* Runs up to n more iterations (stops early on the tolerance or at n_max). Synchronises once
  * per iteration to read the cost. *stopped (may be NULL) is set when no iteration is left. */
 mrf_status mrf_recon_iterate(mrf_recon_t r, int n, int* stopped, hipStream_t stream);
+/* Sets mrf_recon_params.serial for the iterations that follow (an iteration leaves no work
+ * on the recon's own streams once its cost has been read, so the schedule may change between
+ * calls). Host only; MRF_INVALID_ARG for a null handle. */
+mrf_status mrf_recon_set_serial(mrf_recon_t r, int serial);
 /* C5: advances nslices independent reconstructions (each created and initialised on its own,
  * with its own plan, dictionary and graph; slices may differ in n, L and Ns) by up to n
  * iterations each. Per round, every active slice's iteration is enqueued on its own stream

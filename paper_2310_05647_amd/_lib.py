@@ -25,7 +25,7 @@ class NufftDesc(ctypes.Structure):
 class ReconParams(ctypes.Structure):
     _fields_ = [("p", c_int), ("s", c_int), ("K", c_int), ("rank_cap", c_int), ("lam1_0", c_float),
                 ("lam2", c_float), ("beta", c_float), ("mu0", c_float), ("lamA", ctypes.c_double),
-                ("sigma2", c_float), ("n_max", c_int), ("tol", ctypes.c_double)]
+                ("sigma2", c_float), ("n_max", c_int), ("tol", ctypes.c_double), ("serial", c_int)]
 
 
 class MlpTrainCfg(ctypes.Structure):
@@ -105,6 +105,7 @@ _decl("mrf_recon_destroy", [c_void_p])
 _decl("mrf_recon_batched", [c_int, c_void_p, c_void_p, c_int, P(c_int)])
 _decl("mrf_recon_init", [c_void_p, c_void_p, c_void_p, c_void_p])
 _decl("mrf_recon_iterate", [c_void_p, c_int, P(c_int), c_void_p])
+_decl("mrf_recon_set_serial", [c_void_p, c_int])
 _decl("mrf_recon_finish", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p])
 _decl("mrf_recon_get_stats", [c_void_p, P(ReconStats)])
 _decl("mrf_recon", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, P(ReconStats), c_void_p])

@@ -101,8 +101,12 @@ struct mrf_recon_s {
   cf *X, *ZG, *res, *aX, *aU, *Ya, *beta, *U, *C;
   float *f, *maps, *rho;
   int* idx;
-  void *nws, *rws, *lws;
+  void *nws, *rws, *rws2, *lws;   // rws2: the graph rebuild's reduction, which overlaps the gradient's
   double *sc, *rpart;
+  // Independent parts of an iteration run on two streams of the recon beside the caller's stream
+  // (default priority), forked from and joined back into it by events.
+  hipStream_t aux[2];
+  hipEvent_t ev_fork, ev_aux[2];
   bool initialised;
   bool pending_graph;   // a rebuilt graph whose scalars are not yet recorded
   double* hsc;          // pinned host copy of the device scalars
@@ -113,9 +117,28 @@ struct mrf_recon_s {
 
 namespace {
 
+// Stream for aux part k of a phase (bit = the phase's bit of prm.serial): s when serial.
+hipStream_t aux_stream(const mrf_recon_s* R, int k, int bit, hipStream_t s) {
+  return (R->prm.serial & bit) ? s : R->aux[k];
+}
+// aux streams start after the work enqueued so far on s
+mrf_status fork(mrf_recon_s* R, int bit, hipStream_t s) {
+  if (R->prm.serial & bit) return MRF_OK;
+  MRF_CHECK_HIP(hipEventRecord(R->ev_fork, s));
+  for (int k = 0; k < 2; ++k) MRF_CHECK_HIP(hipStreamWaitEvent(R->aux[k], R->ev_fork, 0));
+  return MRF_OK;
+}
+// work enqueued later on s waits for what aux stream k holds so far
+mrf_status join(mrf_recon_s* R, int k, int bit, hipStream_t s) {
+  if (R->prm.serial & bit) return MRF_OK;
+  MRF_CHECK_HIP(hipEventRecord(R->ev_aux[k], R->aux[k]));
+  MRF_CHECK_HIP(hipStreamWaitEvent(s, R->ev_aux[k], 0));
+  return MRF_OK;
+}
+
 mrf_status rebuild(mrf_recon_s* R, hipStream_t s) {
   mrf_status e;
-  if ((e = subspace_reduce(R->X, nullptr, nullptr, dict_basis(R->dict), R->L, R->Nv, R->r, R->aX, (cf*)R->rws, s)))
+  if ((e = subspace_reduce(R->X, nullptr, nullptr, dict_basis(R->dict), R->L, R->Nv, R->r, R->aX, (cf*)R->rws2, s)))
     return e;
   if ((e = match_subspace(R->dict, R->aX, R->Nv, R->idx, R->rho, nullptr, nullptr, s))) return e;
   if ((e = maps_from_match(R->dict, R->idx, R->rho, R->Nv, R->maps, s))) return e;
@@ -127,14 +150,18 @@ mrf_status rebuild(mrf_recon_s* R, hipStream_t s) {
   return MRF_OK;
 }
 
-// cost terms of the current X (with the current graph), copied to the pinned host scalars
+// cost terms of the current X (with the current graph), copied to the pinned host scalars. The three
+// terms only read X: the residual runs on s, the eigen-analysis (which also gives the next SVT's U
+// and f) on aux[0] and the Laplacian trace on aux[1], each into buffers of its own.
 mrf_status evaluate_enqueue(mrf_recon_s* R, hipStream_t s) {
   mrf_status e;
-  if ((e = nufft_residual(R->plan, R->X, R->b, R->res, R->nws, R->rpart, R->sc + SC_RN2, s))) return e;
+  if ((e = fork(R, 1, s))) return e;
   if ((e = llr_analyse(R->X, R->g, R->L, 1.0 / R->prm.beta, R->prm.rank_cap, R->lws, R->U, R->f, R->sc + SC_NUC,
-                       nullptr, s)))
+                       nullptr, aux_stream(R, 0, 1, s))))
     return e;
-  if ((e = lap_quad(R->graph, R->X, R->L, R->sc + SC_QUAD, s))) return e;
+  if ((e = lap_quad(R->graph, R->X, R->L, R->sc + SC_QUAD, aux_stream(R, 1, 1, s)))) return e;
+  if ((e = nufft_residual(R->plan, R->X, R->b, R->res, R->nws, R->rpart, R->sc + SC_RN2, s))) return e;
+  if ((e = join(R, 0, 1, s)) || (e = join(R, 1, 1, s))) return e;
   MRF_LAUNCH("recon_cost", s, k_cost<<<1, 1, 0, s>>>(R->sc, R->prm.lam2));
   MRF_CHECK_LAUNCH();
   MRF_CHECK_HIP(hipMemcpyAsync(R->hsc, R->sc, SC_N * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -221,12 +248,21 @@ extern "C" mrf_status mrf_recon_create(const mrf_recon_params* prm, mrf_nufft_pl
             (R->C = (cf*)alloc(Np * rc * (size_t)L * 8)) && (R->f = (float*)alloc(Np * rc * 4)) &&
             (R->maps = (float*)alloc(3 * Nv * 4)) && (R->rho = (float*)alloc(Nv * 4)) &&
             (R->idx = (int*)alloc(Nv * 4)) && (R->nws = alloc(nufft_ws_bytes(plan))) &&
-            (R->rws = alloc(reduce_ws_bytes(L, (int)Nv, (int)rr))) && (R->lws = alloc(llr_ws_bytes(R->g, (int)rc))) &&
+            (R->rws = alloc(reduce_ws_bytes(L, (int)Nv, (int)rr))) &&
+            (R->rws2 = alloc(reduce_ws_bytes(L, (int)Nv, (int)rr))) && (R->lws = alloc(llr_ws_bytes(R->g, (int)rc))) &&
             (R->sc = (double*)alloc(SC_N * 8)) && (R->rpart = (double*)alloc(nufft_resid_blocks(plan) * 8));
   if (ok) ok = hipHostMalloc((void**)&R->hsc, SC_N * sizeof(double), hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     mrf_recon_destroy(R);
     return fail(MRF_OOM, "recon_create: device allocation failed");
+  }
+  for (int k = 0; k < 2 && ok; ++k)
+    ok = hipStreamCreateWithFlags(&R->aux[k], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&R->ev_aux[k], hipEventDisableTiming) == hipSuccess;
+  if (ok) ok = hipEventCreateWithFlags(&R->ev_fork, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    mrf_recon_destroy(R);
+    return fail(MRF_DEVICE, "recon_create: stream or event creation failed");
   }
   *out = R;
   return MRF_OK;
@@ -235,6 +271,13 @@ extern "C" mrf_status mrf_recon_create(const mrf_recon_params* prm, mrf_nufft_pl
 extern "C" mrf_status mrf_recon_destroy(mrf_recon_t R) {
   clear_error();
   if (!R) return MRF_OK;
+  for (int k = 0; k < 2; ++k)
+    if (R->aux[k]) hipStreamSynchronize(R->aux[k]);   // their work may still read the buffers
+  for (int k = 0; k < 2; ++k) {
+    if (R->aux[k]) hipStreamDestroy(R->aux[k]);
+    if (R->ev_aux[k]) hipEventDestroy(R->ev_aux[k]);
+  }
+  if (R->ev_fork) hipEventDestroy(R->ev_fork);
   for (void* p : R->allocs) hipFree(p);
   if (R->hsc) hipHostFree(R->hsc);
   mrf_graph_destroy(R->graph);
@@ -276,14 +319,20 @@ mrf_status enqueue_step(mrf_recon_s* R, hipStream_t s) {
   const int L = R->L, Nv = R->Nv, r = R->r, rc = R->prm.rank_cap;
   const cf* V = dict_basis(R->dict);
   mrf_status e;
-  if (R->pending_graph && (e = rebuild(R, s))) return e;
-  // aX = X V is current: the graph rebuild (or the initialisation) computed it from this X
+  // Three independent chains until the X update: the graph rebuild (aux[0]), the SVT coefficients
+  // of X (aux[1]) and the data-term gradient (s), which waits for the rebuild only where it needs
+  // the new graph, aX and the scalars.
+  if ((e = fork(R, 2, s))) return e;
+  if (R->pending_graph && (e = rebuild(R, aux_stream(R, 0, 2, s)))) return e;
+  if ((e = llr_coef(R->X, R->g, L, rc, R->U, R->f, R->C, aux_stream(R, 1, 2, s)))) return e;
   if ((e = nufft_adj_impl(R->plan, R->res, R->ZG, R->nws, s))) return e;                      // G = A^H r
   if ((e = subspace_reduce(R->ZG, nullptr, nullptr, V, L, Nv, r, R->aU, (cf*)R->rws, s))) return e;  // G V
+  // aX = X V is current: the graph rebuild (or the initialisation) computed it from this X
+  if ((e = join(R, 0, 2, s))) return e;
   if ((e = lap_apply_sub(R->graph, R->aX, R->Ya, r, s))) return e;                            // S_L(X V)
   if ((e = grad_coef(R->aX, R->aU, R->Ya, R->sc + SC_MU, R->sc + SC_LAM1, (long)Nv * r, R->beta, s))) return e;
   if ((e = subspace_expand(R->beta, V, L, Nv, r, R->ZG, s))) return e;                        // Z
-  if ((e = llr_coef(R->X, R->g, L, rc, R->U, R->f, R->C, s))) return e;
+  if ((e = join(R, 1, 2, s))) return e;
   if ((e = llr_xupdate(R->ZG, R->U, R->C, R->g, L, rc, R->sc + SC_KAP, 1.0, R->X, s))) return e;
   return evaluate_enqueue(R, s);
 }
@@ -320,6 +369,13 @@ extern "C" mrf_status mrf_recon_iterate(mrf_recon_t R, int n, int* stopped, hipS
     if ((e = complete_step(R, s))) return e;
   }
   if (stopped) *stopped = !active(R);
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_recon_set_serial(mrf_recon_t R, int serial) {
+  clear_error();
+  MRF_REQUIRE(R, MRF_INVALID_ARG, "recon_set_serial: null handle");
+  R->prm.serial = serial;
   return MRF_OK;
 }
 

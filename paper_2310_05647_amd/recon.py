@@ -11,10 +11,12 @@ class Recon:
     """MS-LLR solver state for a NUFFT plan and a dictionary with a basis."""
 
     def __init__(self, plan, dictionary, p, s, K, rank_cap, lam1_0=0.1, lam2=0.1, beta=0.2, mu0=1.0, lamA=0.0,
-                 sigma2=0.0, n_max=10, tol=-1.0):
+                 sigma2=0.0, n_max=10, tol=-1.0, serial=0):
+        """serial: bit 0 keeps the cost terms, bit 1 the rest of an iteration on the caller's stream
+        (0: independent parts overlap on the recon's own streams; the results are the same)."""
         self.plan, self.dict = plan, dictionary
         self.params = ReconParams(int(p), int(s), int(K), int(rank_cap), float(lam1_0), float(lam2), float(beta),
-                                  float(mu0), float(lamA), float(sigma2), int(n_max), float(tol))
+                                  float(mu0), float(lamA), float(sigma2), int(n_max), float(tol), int(serial))
         h = ctypes.c_void_p()
         check(lib.mrf_recon_create(ctypes.byref(self.params), plan.handle, dictionary.handle, ctypes.byref(h)),
               "mrf_recon_create")
@@ -31,6 +33,10 @@ class Recon:
         check(lib.mrf_recon_iterate(self.handle, int(n), ctypes.byref(stopped), stream_ptr(stream)),
               "mrf_recon_iterate")
         return bool(stopped.value)
+
+    def set_serial(self, serial):
+        """Schedule mask for later iterations (see the constructor's serial)."""
+        check(lib.mrf_recon_set_serial(self.handle, int(serial)), "mrf_recon_set_serial")
 
     def finish(self, stream=None):
         dev = self._b.device

@@ -86,3 +86,15 @@ def test_c1_recon_ten_iterations_quality():
         say(f"  {name} NMSE (tissue) gpu {eg:.4f} oracle {eo:.4f}")
         assert eg <= 1.5 * eo + 0.02
     say(f"  index agreement {np.mean(g['idx'] == o['idx']):.4f}")
+
+
+def test_overlapped_schedule_equals_serial():
+    """The two-stream schedule runs the same kernels on the same inputs as the serialised one:
+    X, the match and every cost agree bit for bit (a race between the overlapped parts would not)."""
+    w = c1_workload()
+    say("recon C1 n_max=3: overlapped vs serialised schedule")
+    a = _gpu_recon(w, 3, serial=3)
+    b = _gpu_recon(w, 3, serial=0)
+    assert np.array_equal(a["X"], b["X"])
+    assert np.array_equal(a["idx"], b["idx"])
+    assert a["stats"]["cost"] == b["stats"]["cost"]
