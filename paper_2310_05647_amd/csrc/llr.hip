@@ -506,23 +506,25 @@ __global__ __launch_bounds__(64 * kTdW) void k_tridiag(const cf* __restrict__ G,
 // matrix is scaled so that |d|, e^2 <= 1; a pivot smaller than pmin in magnitude is replaced by
 // -pmin (a perturbation of d_k by at most pmin). 1/q comes from the hardware reciprocal (about 24
 // correct bits) refined by one Newton step: measured on gfx950 within 11 ulp of the correctly
-// rounded value, a relative perturbation of the pivot of about 2e-15, far below the 1e-13 (of the
+// rounded value, a relative perturbation of the pivot of about 2e-15, far below the 1e-10 (of the
 // spectrum's span) resolution the bisection stops at.
 constexpr double kPivMin = 1e-280;
 __device__ inline double recip(double q) {
   const double r = __builtin_amdgcn_rcp(q);
   return fma(r, fma(-q, r, 1.0), r);
 }
+// After the guard a pivot is never zero or NaN, so q < 0 is its sign bit.
+__device__ inline unsigned neg_bit(double q) { return (unsigned)__double2hiint(q) >> 31; }
 __device__ inline int sturm_count(const double* d, const double* e2, int n, double x) {
   double q = d[0] - x;
   if (fabs(q) < kPivMin) q = -kPivMin;
-  int c = q < 0.0;
+  unsigned c = neg_bit(q);
   for (int k = 1; k < n; ++k) {
     q = (d[k] - x) - e2[k - 1] * recip(q);
     if (fabs(q) < kPivMin) q = -kPivMin;
-    c += q < 0.0;
+    c += neg_bit(q);
   }
-  return c;
+  return (int)c;
 }
 
 __device__ inline double wave_min(double v) {
@@ -578,8 +580,10 @@ __global__ __launch_bounds__(64) void k_eig_val(const double* __restrict__ dd, c
   while (j < 63 && cnt[j] <= t) ++j;
   double a = j == 0 ? lo : lo + j * h;
   double b = j == 63 ? hi : lo + (j + 1) * h;
-  // bisection to 1e-13 of the span: lambda_t (ascending) lies in (a, b]
-  const double tol = 1e-13 * span;
+  // bisection to 1e-10 of the span: lambda_t (ascending) lies in (a, b]. The Gram comes from FP32
+  // products over L frames, whose entries are off by about sqrt(2L) 2^-24 of the largest
+  // eigenvalue (3e-6 at L = 1000); a finer stop would resolve nothing of that matrix.
+  const double tol = 1e-10 * span;
   for (int it = 0; it < 48; ++it) {
     const double m = 0.5 * (a + b);
     const bool done = m <= a || m >= b || b - a <= tol;
