@@ -786,7 +786,22 @@ static int col_blocks(const mrf_nufft_plan_s* p, int FC) {
   return 8 * p->nstrips * ((nchunks + 7) / 8);
 }
 
-static int row_blocks(long ngroups) { return (int)std::min<long>(ngroups, 2048); }
+// Grid of a grid-stride row kernel: as many blocks as the device holds at once (CUs times the
+// kernel's resident blocks per CU), so that every block is resident from the start and all take
+// the same number of row groups; a larger grid leaves a second round of blocks that stretches the
+// kernel by their share of the groups. Queried once per kernel.
+template <auto kernel>
+static int row_blocks(long ngroups) {
+  static const int resident = [] {
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess)
+      return 2048;
+    return std::max(1, ncu) * std::max(1, per);
+  }();
+  return (int)std::min<long>(ngroups, resident);
+}
 
 template <int G, int TX>
 static void launch_fwd_g(const mrf_nufft_plan_s* p, const cf* img, cf* T, cf* part, hipStream_t s) {
@@ -794,7 +809,8 @@ static void launch_fwd_g(const mrf_nufft_plan_s* p, const cf* img, cf* T, cf* pa
   constexpr int RPB = row_rpb(G);
   const int FC = frames_per_chunk(p);
   MRF_LAUNCH("nufft_row_fwd", s,
-             k_row_fwd<G><<<row_blocks((nrows + RPB - 1) / RPB), kBlock, 0, s>>>(img, T, p->dinv, p->tw, nrows));
+             k_row_fwd<G><<<row_blocks<k_row_fwd<G>>((nrows + RPB - 1) / RPB), kBlock, 0, s>>>(img, T, p->dinv,
+                                                                                          p->tw, nrows));
   MRF_LAUNCH("nufft_col_fwd", s,
              k_col_fwd<G, TX><<<col_blocks(p, FC), kBlock, 0, s>>>(T, p->ent, p->tile_ptr, p->tw, part, p->L, FC));
 }
@@ -810,8 +826,9 @@ static void launch_adj_g(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, cf* 
   MRF_LAUNCH("nufft_col_adj", s,
              k_col_adj<G, TX><<<col_blocks(p, FC), kBlock, 0, s>>>(rg, p->ent, p->tile_ptr, p->tw, T, p->L, FC));
   MRF_LAUNCH("nufft_row_adj", s,
-             k_row_adj<G><<<row_blocks((nrows + RPB - 1) / RPB), kBlock, 0, s>>>(T, img, p->dinv, p->tw, nrows,
-                                                                                1.0f / p->N));
+             k_row_adj<G><<<row_blocks<k_row_adj<G>>((nrows + RPB - 1) / RPB), kBlock, 0, s>>>(T, img, p->dinv,
+                                                                                          p->tw, nrows,
+                                                                                          1.0f / p->N));
 }
 
 #define MRF_DISPATCH_G_TX(FN, ...)                                                   \
