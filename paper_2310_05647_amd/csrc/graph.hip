@@ -626,39 +626,72 @@ __global__ __launch_bounds__(64 * kQuadWpb) void k_lap_quad_edges(const cf* __re
   if (lane == 0) part[(size_t)c * g.Np + i] = acc;
 }
 
-// S_L applied to per-voxel subspace coefficients A[v][k] (k < r), voxel-major. One thread per voxel.
+// S_L applied to per-voxel subspace coefficients A[v][k] (k < r), voxel-major. Four threads per
+// voxel: thread q of a quad takes the covering patches q, q + 4, ... of the voxel's cell (in
+// raster order of (a, b)) and sums their rows of L; the quad's partial sums then meet by two
+// quad exchanges in a fixed order. For even r each neighbour's coefficients are read as 16-byte
+// pairs.
+__device__ inline float quad_xor_add(float x, int ctrl_xor1) {
+  return x + __int_as_float(ctrl_xor1 ? __builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false)
+                                      : __builtin_amdgcn_mov_dpp(__float_as_int(x), 0x4E, 0xF, 0xF, false));
+}
 __global__ __launch_bounds__(256) void k_lap_sub(const cf* __restrict__ A, cf* __restrict__ Y,
                                                  const int* __restrict__ rowptr, const int* __restrict__ col,
                                                  const float* __restrict__ val, PatchGeom g, int r) {
-  const int v = blockIdx.x * 256 + threadIdx.x;
-  if (v >= g.N * g.N) return;
-  const int py = v / g.N, px = v % g.N;
-  const int cy = py / g.s, cx = px / g.s;
+  const long t = (long)blockIdx.x * 256 + threadIdx.x;
+  const int v = (int)(t >> 2), q = (int)(t & 3);
+  const bool live = v < g.N * g.N;   // no early exit: the quad exchanges need all four lanes
   cf acc[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) acc[k] = cf{0.f, 0.f};
-  int alo, ahi, blo, bhi;
-  cover_range(g, cy, alo, ahi);
-  cover_range(g, cx, blo, bhi);
-  for (int a = alo; a <= ahi; ++a)
-    for (int b = blo; b <= bhi; ++b) {
+  if (live) {
+    const int py = v / g.N, px = v % g.N;
+    const int cy = py / g.s, cx = px / g.s;
+    int alo, ahi, blo, bhi;
+    cover_range(g, cy, alo, ahi);
+    cover_range(g, cx, blo, bhi);
+    const int nb = bhi - blo + 1, ncov = (ahi - alo + 1) * nb;
+    for (int c = q; c < ncov; c += 4) {
+      const int a = alo + c / nb, b = blo + c % nb;
       const int i = a * g.n1 + b;
       for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
         const int j = col[e];
         const float w = val[e];
         const int src = v + ((j / g.n1 - a) * g.N + (j % g.n1 - b)) * g.s;
+        if ((r & 1) == 0) {
+          const float4* Ap = reinterpret_cast<const float4*>(A + (size_t)src * r);
 #pragma unroll
-        for (int k = 0; k < 16; ++k)
-          if (k < r) {
-            const cf av = A[(size_t)src * r + k];
-            acc[k].x += w * av.x;
-            acc[k].y += w * av.y;
-          }
+          for (int k2 = 0; k2 < 8; ++k2)
+            if (2 * k2 < r) {
+              const float4 av = Ap[k2];
+              acc[2 * k2].x += w * av.x;
+              acc[2 * k2].y += w * av.y;
+              acc[2 * k2 + 1].x += w * av.z;
+              acc[2 * k2 + 1].y += w * av.w;
+            }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 16; ++k)
+            if (k < r) {
+              const cf av = A[(size_t)src * r + k];
+              acc[k].x += w * av.x;
+              acc[k].y += w * av.y;
+            }
+        }
       }
     }
+  }
 #pragma unroll
   for (int k = 0; k < 16; ++k)
-    if (k < r) Y[(size_t)v * r + k] = acc[k];
+    if (k < r) {
+      acc[k].x = quad_xor_add(quad_xor_add(acc[k].x, 1), 0);
+      acc[k].y = quad_xor_add(quad_xor_add(acc[k].y, 1), 0);
+    }
+  if (live && q == 0) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (k < r) Y[(size_t)v * r + k] = acc[k];
+  }
 }
 
 // First stage of a deterministic sum: block b adds the contiguous range [b*per, (b+1)*per).
@@ -775,7 +808,9 @@ mrf_status lap_quad(mrf_graph_s* G, const cf* X, int L, double* out, hipStream_t
 
 mrf_status lap_apply_sub(const mrf_graph_s* G, const cf* A, cf* Y, int r, hipStream_t s) {
   if (r > 16) return fail(MRF_SHAPE, "laplacian on subspace coefficients: r must be <= 16");
-  MRF_LAUNCH("lap_sub", s, k_lap_sub<<<ceil_div((long)G->g.N * G->g.N, 256), 256, 0, s>>>(A, Y, G->rowptr, G->col, G->val, G->g, r));
+  if (r % 2 == 0 && (reinterpret_cast<uintptr_t>(A) & 15))
+    return fail(MRF_INVALID_ARG, "laplacian on subspace coefficients: A must be 16-byte aligned for even r");
+  MRF_LAUNCH("lap_sub", s, k_lap_sub<<<ceil_div(4L * G->g.N * G->g.N, 256), 256, 0, s>>>(A, Y, G->rowptr, G->col, G->val, G->g, r));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
 }
