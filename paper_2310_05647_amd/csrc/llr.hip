@@ -1157,16 +1157,22 @@ __global__ __launch_bounds__(256) void k_xupdate_reg(const cf* __restrict__ Z, c
 // K-step k takes component k of the 4 patches (lane l: patch c = l / 16), so the A operands
 // (U, kept in registers for all frames) and B operands (C, 16 consecutive frames per patch row)
 // are plain loads; Re and Im come from four real 16x16x4 products. A block = 4 cells of one cell
-// row and a range of frames; the 4 waves' tiles meet in LDS and leave as 128-byte rows.
+// row and a range of frames; the 4 waves' tiles meet in LDS and leave as 128-byte rows. Blocks
+// are dealt to the 8 XCDs (XCD = block mod 8) so that each XCD takes a band of rows_per cell rows
+// for one frame chunk after another: cells of neighbouring rows and quads, which share covering
+// patches, then read those patches' C through the same L2.
 template <int RC, bool WITHZ>
 __global__ __launch_bounds__(256) void k_xupdate_mfma(const cf* __restrict__ Z, const cf* __restrict__ U,
                                                       const cf* __restrict__ C, PatchGeom g, int L, int rcap,
                                                       const double* __restrict__ kap_ptr, double kap_scale, int fpb,
-                                                      cf* __restrict__ Xout) {
+                                                      int rows_per, cf* __restrict__ Xout) {
   __shared__ cf T[16][4][16];
   const int nq = g.nc / 4;
   const int w = threadIdx.x >> 6;
-  const int cy = blockIdx.x / nq, cxb = (blockIdx.x % nq) * 4, cx = cxb + w;
+  const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3, per = rows_per * nq;
+  const int chunk = q / per, within = q % per;
+  const int cy = xcd * rows_per + within / nq, cxb = (within % nq) * 4, cx = cxb + w;
+  if (cy >= g.nc) return;   // the whole block: no barrier has been reached
   const int lane = threadIdx.x & 63, c = lane >> 4, px = lane & 15;
   const int a = cy - 1 + (c >> 1), b = cx - 1 + (c & 1);   // covering patch c of this cell
   const bool pv = a >= 0 && a < g.n1 && b >= 0 && b < g.n1;
@@ -1188,7 +1194,7 @@ __global__ __launch_bounds__(256) void k_xupdate_mfma(const cf* __restrict__ Z, 
   }
   const float kap = WITHZ ? (float)(kap_ptr[0] * kap_scale) : 1.f;
   const float den = WITHZ ? 1.f / (1.f + kap * ncov) : 1.f;
-  const int l0 = blockIdx.y * fpb, l1 = min(L, l0 + fpb);
+  const int l0 = chunk * fpb, l1 = min(L, l0 + fpb);
   const cf* Ci = C + (size_t)i * rcap * L;
   const size_t NN = (size_t)g.N * g.N;
   for (int f0 = l0; f0 < l1; f0 += 16) {
@@ -1399,9 +1405,10 @@ mrf_status llr_xupdate(const cf* Z, const cf* U, const cf* C, const PatchGeom& g
   const int ca = kTile / g.s + g.ppc;   // covering patches per tile side (upper bound)
   if (g.p == 8 && g.s == 4 && rcap <= 16) {
     const int fpb = 64;
-    dim3 grid(g.nc / 4 * g.nc, (L + fpb - 1) / fpb);
+    const int rows_per = (g.nc + 7) / 8;   // cell rows per XCD band
+    const int grid = 8 * rows_per * (g.nc / 4) * ((L + fpb - 1) / fpb);
 #define MRF_XM(RCv, W, NAME, ZP, KP, KS)                                                                  \
-  MRF_LAUNCH(NAME, s, k_xupdate_mfma<RCv, W><<<grid, 256, 0, s>>>(ZP, U, C, g, L, rcap, KP, KS, fpb, Xout))
+  MRF_LAUNCH(NAME, s, k_xupdate_mfma<RCv, W><<<grid, 256, 0, s>>>(ZP, U, C, g, L, rcap, KP, KS, fpb, rows_per, Xout))
     if (rcap <= 10) {
       if (Z) MRF_XM(10, true, "llr_xupdate", Z, kap_dev, kap_scale);
       else MRF_XM(10, false, "llr_qtp", nullptr, nullptr, 1.0);
