@@ -46,3 +46,35 @@ def test_nufft_plan_rejects_bad_descriptors_before_touching_the_device():
         assert st == expect, (desc.n, desc.kb_width, st, m.lib.mrf_last_error())
         assert m.lib.mrf_last_error() != b""
     assert m.lib.mrf_nufft_plan_create(None, fake, None, ctypes.byref(h)) == 1
+
+
+def test_ctypes_structs_match_the_header_layout(tmp_path):
+    """Each ctypes mirror in the binding has the size and field offsets of its C struct, as a host
+    C compiler lays out include/mrf.h."""
+    import shutil
+    import subprocess
+    from paper_2310_05647_amd import _lib
+    cc = shutil.which("gcc")
+    if cc is None or not os.path.isdir("/opt/rocm/include"):
+        pytest.skip("needs gcc and the ROCm headers")
+    pairs = [("mrf_nufft_desc", _lib.NufftDesc), ("mrf_recon_params", _lib.ReconParams),
+             ("mrf_mlp_train_cfg", _lib.MlpTrainCfg), ("mrf_recon_stats", _lib.ReconStats)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mrf.h"', "int main(void) {"]
+    for cname, py in pairs:
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+                    str(src), "-o", str(exe)], check=True, capture_output=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        a, b, v = ln.split()
+        got[(a, b)] = int(v)
+    for cname, py in pairs:
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
