@@ -262,7 +262,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct Best {
   float s;   // |<dhr_m, alpha>|^2
-  float re;  // Re<dhr_m, alpha>
   int m;
 };
 
@@ -273,13 +272,16 @@ __device__ inline bool better(float s, int m, float bs, int bm) { return s > bs 
 // of the complex products) and folds the squared magnitudes into per-lane running maxima. A
 // butterfly over the 16 lanes that share a row gives each wave's arg-max, and the four waves'
 // results meet in LDS (ties to the lowest atom throughout). Four waves per SIMD let one wave's
-// score updates run under another's MFMAs.
+// score updates run under another's MFMAs. Atoms past M in the last tile are zero in the packed
+// operands: they score 0 and lose every tie to a real atom of lower index, so they need no mask.
+// Re<dhr_m, alpha> of the winner alone is formed at the end from alpha and dhr_m.
 __global__ __launch_bounds__(256, 4) void k_match_sub(const cf* __restrict__ alpha, int Nv, int r,
-                                                   const float* __restrict__ bpk, int ntile, int M,
+                                                   const float* __restrict__ bpk, const cf* __restrict__ dhr,
+                                                   int ntile, int M,
                                                    const float* __restrict__ norms, const float* __restrict__ lut,
                                                    int nparam, int* __restrict__ idx_out, float* __restrict__ rho_out,
                                                    float* __restrict__ score_out, float* __restrict__ params_out) {
-  __shared__ float ws_s[4][64], ws_re[4][64];
+  __shared__ float ws_s[4][64];
   __shared__ int ws_m[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int vbase = blockIdx.x * 64;
@@ -304,7 +306,7 @@ __global__ __launch_bounds__(256, 4) void k_match_sub(const cf* __restrict__ alp
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) best[rt][i] = Best{-1.f, 0.f, 0x7fffffff};
+    for (int i = 0; i < 4; ++i) best[rt][i] = Best{-1.f, 0x7fffffff};
   float b[10], bn[10];
   if (w < ntile) {
 #pragma unroll
@@ -334,8 +336,8 @@ __global__ __launch_bounds__(256, 4) void k_match_sub(const cf* __restrict__ alp
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float s = m < M ? cre[rt][i] * cre[rt][i] + cim[rt][i] * cim[rt][i] : -1.f;
-        if (s > best[rt][i].s) best[rt][i] = Best{s, cre[rt][i], m};
+        const float s = cre[rt][i] * cre[rt][i] + cim[rt][i] * cim[rt][i];
+        if (s > best[rt][i].s) best[rt][i] = Best{s, m};
       }
 #pragma unroll
     for (int q = 0; q < 10; ++q) b[q] = bn[q];
@@ -349,29 +351,35 @@ __global__ __launch_bounds__(256, 4) void k_match_sub(const cf* __restrict__ alp
 #pragma unroll
       for (int off = 1; off < 16; off <<= 1) {
         const float os = __shfl_xor(bb.s, off);
-        const float ore = __shfl_xor(bb.re, off);
         const int om = __shfl_xor(bb.m, off);
-        if (better(os, om, bb.s, bb.m)) bb = Best{os, ore, om};
+        if (better(os, om, bb.s, bb.m)) bb = Best{os, om};
       }
       if (row == 0) {
         const int vl = 16 * rt + 4 * kq + i;   // output row of value i
         ws_s[w][vl] = bb.s;
-        ws_re[w][vl] = bb.re;
         ws_m[w][vl] = bb.m;
       }
     }
   __syncthreads();
   if (w == 0) {
-    Best bb{ws_s[0][lane], ws_re[0][lane], ws_m[0][lane]};
+    Best bb{ws_s[0][lane], ws_m[0][lane]};
 #pragma unroll
     for (int q = 1; q < 4; ++q)
-      if (better(ws_s[q][lane], ws_m[q][lane], bb.s, bb.m)) bb = Best{ws_s[q][lane], ws_re[q][lane], ws_m[q][lane]};
+      if (better(ws_s[q][lane], ws_m[q][lane], bb.s, bb.m)) bb = Best{ws_s[q][lane], ws_m[q][lane]};
     const int v = vbase + lane;
     if (v < Nv) {
       const int m = bb.m;
       idx_out[v] = m;
       const float nrm = norms[m];
-      if (rho_out) rho_out[v] = nrm > 0.f ? fmaxf(bb.re / nrm, 0.f) : 0.f;
+      if (rho_out) {
+        float re = 0.f;   // Re<dhr_m, alpha_v>
+        for (int k = 0; k < r; ++k) {
+          const cf d = dhr[(size_t)m * r + k], x = alpha[(size_t)v * r + k];
+          re = fmaf(d.x, x.x, re);
+          re = fmaf(d.y, x.y, re);
+        }
+        rho_out[v] = nrm > 0.f ? fmaxf(re / nrm, 0.f) : 0.f;
+      }
       if (score_out) score_out[v] = sqrtf(fmaxf(bb.s, 0.f));
       if (params_out)
         for (int p = 0; p < nparam; ++p) params_out[(size_t)v * nparam + p] = lut[(size_t)m * nparam + p];
@@ -449,7 +457,7 @@ mrf_status grad_coef(const cf* aX, const cf* aG, const cf* Y, const double* mu, 
 mrf_status match_subspace(const mrf_dict_s* D, const cf* alpha, int Nv, int* idx, float* rho, float* score,
                           float* params, hipStream_t s) {
   MRF_LAUNCH("match_subspace", s,
-             k_match_sub<<<ceil_div(Nv, 64), 256, 0, s>>>(alpha, Nv, D->r, D->bpk, D->ntile, D->M, D->norms, D->lut,
+             k_match_sub<<<ceil_div(Nv, 64), 256, 0, s>>>(alpha, Nv, D->r, D->bpk, D->dhr, D->ntile, D->M, D->norms, D->lut,
                                                           D->nparam, idx, rho, score, params));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
