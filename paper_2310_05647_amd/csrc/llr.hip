@@ -1178,12 +1178,6 @@ __global__ __launch_bounds__(256) void k_xupdate_mfma(const cf* __restrict__ Z, 
   const bool pv = a >= 0 && a < g.n1 && b >= 0 && b < g.n1;
   const int i = pv ? a * g.n1 + b : 0;
   const int ap = (4 * (cy - a) + (px >> 2)) * 8 + 4 * (cx - b) + (px & 3);   // pixel px inside patch c
-  int ncov = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int qa = cy - 1 + (q >> 1), qb = cx - 1 + (q & 1);
-    ncov += qa >= 0 && qa < g.n1 && qb >= 0 && qb < g.n1;
-  }
   float ur[RC], ui[RC], un[RC];
 #pragma unroll
   for (int k = 0; k < RC; ++k) {
@@ -1193,7 +1187,19 @@ __global__ __launch_bounds__(256) void k_xupdate_mfma(const cf* __restrict__ Z, 
     un[k] = -x.y;
   }
   const float kap = WITHZ ? (float)(kap_ptr[0] * kap_scale) : 1.f;
-  const float den = WITHZ ? 1.f / (1.f + kap * ncov) : 1.f;
+  // 1 / (1 + kap c(v)) of each of the block's 4 cells: a thread stores pixels of all four, and
+  // c(v) (the patches covering the cell) is smaller at the image's left and right edges
+  float den[4];
+#pragma unroll
+  for (int qc = 0; qc < 4; ++qc) {
+    int ncov = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int qa = cy - 1 + (q >> 1), qb = cxb + qc - 1 + (q & 1);
+      ncov += qa >= 0 && qa < g.n1 && qb >= 0 && qb < g.n1;
+    }
+    den[qc] = WITHZ ? 1.f / (1.f + kap * ncov) : 1.f;
+  }
   const int l0 = chunk * fpb, l1 = min(L, l0 + fpb);
   const cf* Ci = C + (size_t)i * rcap * L;
   const size_t NN = (size_t)g.N * g.N;
@@ -1228,7 +1234,8 @@ __global__ __launch_bounds__(256) void k_xupdate_mfma(const cf* __restrict__ Z, 
         const cf acc = T[fr][row][x16];
         if (WITHZ) {
           const cf zv = Z[o];
-          Xout[o] = cf{(zv.x + kap * acc.x) * den, (zv.y + kap * acc.y) * den};
+          const float dn = den[x16 >> 2];   // the cell of this column
+          Xout[o] = cf{(zv.x + kap * acc.x) * dn, (zv.y + kap * acc.y) * dn};
         } else {
           Xout[o] = acc;
         }

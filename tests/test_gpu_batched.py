@@ -131,3 +131,24 @@ def test_laplacian_term_with_8x8_patches_matches_oracle():
     assert abs(st["tr"][0] - tr_o[0]) <= 3e-3 * abs(tr_o[0])
     assert abs(st["tr"][1] - tr_o[1]) <= 3e-3 * abs(tr_o[1])
     assert ex <= 1e-3
+
+
+def test_x_update_at_the_left_and_right_edges_with_8x8_patches():
+    """8 x 8 patches at stride 4: the X update divides each pixel by 1 + kappa c(v), where c(v), the
+    number of patches covering the pixel, halves in the image's first and last four columns. With
+    lam2 raised 500-fold (kappa of order one) X^1 must match the oracle's in those columns as well
+    as over the whole image."""
+    w = _slice(64, 60, 1, 5, p=8, s=4, K=16, r_llr=10)
+    w["cfg"] = dict(w["cfg"], lam2=w["cfg"]["lam2"] * 500)
+    cfg = w["cfg"]
+    plan, d, rc = _make(w, 1)
+    g = rc.run(to_dev(w["b"]))
+    torch.cuda.synchronize()
+    o = orecon.recon(w["b"], w["traj"], w["atoms"], w["grid"]["lut"], w["V"], cfg["N"], cfg["p"], cfg["s"], cfg["K"],
+                     cfg["r_llr"], lam1_0=cfg["lam1_0"], lam2=cfg["lam2"], beta=cfg["beta"], mu0=cfg["mu0"],
+                     lamA=w["lamA"], n_max=1)
+    Xg, Xo = g["X"].cpu().numpy(), o["X"]
+    errs = {name: rel_l2(Xg[sl], Xo[sl]) for name, sl in
+            (("left", np.s_[:, :, :4]), ("right", np.s_[:, :, -4:]), ("all", np.s_[...]))}
+    say(f"N=64 p=8 s=4, lam2 x500: X^1 rel-L2 {errs}")
+    assert all(e <= 2e-3 for e in errs.values()), errs
