@@ -64,7 +64,9 @@ def algorithmic_work(name, cfg, E, Np):
         "subspace_reduce": ("hbm", img),                            # one series per call (X V, then (A^H r) V)
         "subspace_expand": ("hbm", img),
         "llr_coef": ("hbm", img + Np * cfg["r_llr"] * L * 8),
-        "llr_xupdate": ("hbm", 2 * img + Np * cfg["r_llr"] * L * 8),
+        # with 8 x 8 patches at stride 4 the update forms Z = beta V^H in its tiles: it reads C
+        # (and beta, V: a few MB) and writes X
+        "llr_xupdate": ("hbm", img + Np * cfg["r_llr"] * L * 8 + N * N * r * 8 + L * r * 8),
         "lap_quad": ("hbm", img),
     }
     if name not in table:

@@ -1161,9 +1161,13 @@ __global__ __launch_bounds__(256) void k_xupdate_reg(const cf* __restrict__ Z, c
 // are dealt to the 8 XCDs (XCD = block mod 8) so that each XCD takes a band of rows_per cell rows
 // for one frame chunk after another: cells of neighbouring rows and quads, which share covering
 // patches, then read those patches' C through the same L2.
-template <int RC, bool WITHZ>
+// ZB: Z is not read but formed here, Z = beta conj(V)^T (eq. (17)'s expansion; r <= 16) as four
+// more K-steps of the same tile: A[pixel][kq] = beta[v][4 s + kq] (registers, all frames),
+// B[kq][frame] = conj(V[frame][4 s + kq]); Re = br vr + bi vi, Im = bi vr - br vi.
+template <int RC, bool WITHZ, bool ZB>
 __global__ __launch_bounds__(256) void k_xupdate_mfma(const cf* __restrict__ Z, const cf* __restrict__ U,
-                                                      const cf* __restrict__ C, PatchGeom g, int L, int rcap,
+                                                      const cf* __restrict__ C, const cf* __restrict__ beta,
+                                                      const cf* __restrict__ Vb, int r, PatchGeom g, int L, int rcap,
                                                       const double* __restrict__ kap_ptr, double kap_scale, int fpb,
                                                       int rows_per, cf* __restrict__ Xout) {
   __shared__ cf T[16][4][16];
@@ -1203,6 +1207,19 @@ __global__ __launch_bounds__(256) void k_xupdate_mfma(const cf* __restrict__ Z, 
   const int l0 = chunk * fpb, l1 = min(L, l0 + fpb);
   const cf* Ci = C + (size_t)i * rcap * L;
   const size_t NN = (size_t)g.N * g.N;
+  float zbr[4], zbi[4], zbn[4];
+  const int nzs = (r + 3) / 4;
+  if constexpr (ZB) {
+    const size_t vpx = (size_t)(4 * cy + (px >> 2)) * g.N + 4 * cx + (px & 3);   // pixel px of this cell
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int k = 4 * st + c;
+      const cf bb = k < r ? beta[vpx * r + k] : cf{0.f, 0.f};
+      zbr[st] = bb.x;
+      zbi[st] = bb.y;
+      zbn[st] = -bb.x;
+    }
+  }
   for (int f0 = l0; f0 < l1; f0 += 16) {
     const int f = f0 + px;
     const bool fv = pv && f < l1;
@@ -1219,12 +1236,31 @@ __global__ __launch_bounds__(256) void k_xupdate_mfma(const cf* __restrict__ Z, 
         acci = __builtin_amdgcn_mfma_f32_16x16x4f32(ui[k], bv[k].x, acci, 0, 0, 0);
       }
     }
+    f32x4 zr = {0.f, 0.f, 0.f, 0.f}, zi = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (ZB) {
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        if (st < nzs) {   // uniform
+          const int k = 4 * st + c;
+          const cf vv = f < l1 && k < r ? Vb[(size_t)f * r + k] : cf{0.f, 0.f};
+          zr = __builtin_amdgcn_mfma_f32_16x16x4f32(zbr[st], vv.x, zr, 0, 0, 0);
+          zr = __builtin_amdgcn_mfma_f32_16x16x4f32(zbi[st], vv.y, zr, 0, 0, 0);
+          zi = __builtin_amdgcn_mfma_f32_16x16x4f32(zbi[st], vv.x, zi, 0, 0, 0);
+          zi = __builtin_amdgcn_mfma_f32_16x16x4f32(zbn[st], vv.y, zi, 0, 0, 0);
+        }
+      }
+    }
     // accumulator element e: cell pixel 4 (lane / 16) + e (row lane / 16, column e), frame
     // f0 + lane % 16; staged as T[frame][cell row][16 pixels of the 4 cells] so that the block
-    // reads Z and writes X in 128-byte rows
+    // reads Z and writes X in 128-byte rows (ZB: the finished X of this wave's cell)
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 4; ++e) T[px][c][4 * w + e] = cf{accr[e], acci[e]};
+    for (int e = 0; e < 4; ++e) {
+      if constexpr (ZB)
+        T[px][c][4 * w + e] = cf{(zr[e] + kap * accr[e]) * den[w], (zi[e] + kap * acci[e]) * den[w]};
+      else
+        T[px][c][4 * w + e] = cf{accr[e], acci[e]};
+    }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -1232,7 +1268,7 @@ __global__ __launch_bounds__(256) void k_xupdate_mfma(const cf* __restrict__ Z, 
       if (f0 + fr < l1) {
         const size_t o = (size_t)(f0 + fr) * NN + (size_t)(4 * cy + row) * g.N + 4 * cxb + x16;
         const cf acc = T[fr][row][x16];
-        if (WITHZ) {
+        if (WITHZ && !ZB) {
           const cf zv = Z[o];
           const float dn = den[x16 >> 2];   // the cell of this column
           Xout[o] = cf{(zv.x + kap * acc.x) * dn, (zv.y + kap * acc.y) * dn};
@@ -1405,6 +1441,29 @@ mrf_status llr_coef(const cf* X, const PatchGeom& g, int L, int rcap, const cf* 
   return MRF_OK;
 }
 
+// The X update with Z = beta conj(V)^T formed inside the kernel instead of read (the expansion of
+// eq. (17) fused into eq. (23)): for 8 x 8 patches at stride 4 with rcap, r <= 16.
+bool llr_xupdate_beta_ok(const PatchGeom& g, int rcap, int r) {
+  return g.p == 8 && g.s == 4 && g.N % kTile == 0 && rcap <= 16 && r >= 1 && r <= 16;
+}
+mrf_status llr_xupdate_beta(const cf* beta, const cf* V, int r, const cf* U, const cf* C, const PatchGeom& g, int L,
+                            int rcap, const double* kap_dev, double kap_scale, cf* Xout, hipStream_t s) {
+  if (!llr_xupdate_beta_ok(g, rcap, r)) return fail(MRF_NOT_SUPPORTED, "x update from beta: geometry not supported");
+  const int fpb = 64;
+  const int rows_per = (g.nc + 7) / 8;
+  const int grid = 8 * rows_per * (g.nc / 4) * ((L + fpb - 1) / fpb);
+  if (rcap <= 10)
+    MRF_LAUNCH("llr_xupdate", s, k_xupdate_mfma<10, true, true><<<grid, 256, 0, s>>>(nullptr, U, C, beta, V, r, g, L, rcap,
+                                                                                   kap_dev, kap_scale, fpb, rows_per,
+                                                                                   Xout));
+  else
+    MRF_LAUNCH("llr_xupdate", s, k_xupdate_mfma<16, true, true><<<grid, 256, 0, s>>>(nullptr, U, C, beta, V, r, g, L, rcap,
+                                                                                   kap_dev, kap_scale, fpb, rows_per,
+                                                                                   Xout));
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+
 mrf_status llr_xupdate(const cf* Z, const cf* U, const cf* C, const PatchGeom& g, int L, int rcap,
                        const double* kap_dev, double kap_scale, cf* Xout, hipStream_t s) {
   if (g.N % kTile != 0) return fail(MRF_SHAPE, "x update: N must be a multiple of 16");
@@ -1415,7 +1474,8 @@ mrf_status llr_xupdate(const cf* Z, const cf* U, const cf* C, const PatchGeom& g
     const int rows_per = (g.nc + 7) / 8;   // cell rows per XCD band
     const int grid = 8 * rows_per * (g.nc / 4) * ((L + fpb - 1) / fpb);
 #define MRF_XM(RCv, W, NAME, ZP, KP, KS)                                                                  \
-  MRF_LAUNCH(NAME, s, k_xupdate_mfma<RCv, W><<<grid, 256, 0, s>>>(ZP, U, C, g, L, rcap, KP, KS, fpb, rows_per, Xout))
+  MRF_LAUNCH(NAME, s, k_xupdate_mfma<RCv, W, false><<<grid, 256, 0, s>>>(ZP, U, C, nullptr, nullptr, 0, g, L, rcap, KP, \
+                                                                         KS, fpb, rows_per, Xout))
     if (rcap <= 10) {
       if (Z) MRF_XM(10, true, "llr_xupdate", Z, kap_dev, kap_scale);
       else MRF_XM(10, false, "llr_qtp", nullptr, nullptr, 1.0);

@@ -58,6 +58,9 @@ size_t llr_ws_bytes(const PatchGeom& g, int rcap);
 mrf_status llr_analyse(const cf* X, const PatchGeom& g, int L, double tau, int rcap, void* ws, cf* U, float* f,
                        double* nuc_out, double* lam_out, hipStream_t s);
 mrf_status llr_coef(const cf* X, const PatchGeom& g, int L, int rcap, const cf* U, const float* f, cf* C, hipStream_t s);
+bool llr_xupdate_beta_ok(const PatchGeom& g, int rcap, int r);
+mrf_status llr_xupdate_beta(const cf* beta, const cf* V, int r, const cf* U, const cf* C, const PatchGeom& g, int L,
+                            int rcap, const double* kap_dev, double kap_scale, cf* Xout, hipStream_t s);
 mrf_status llr_xupdate(const cf* Z, const cf* U, const cf* C, const PatchGeom& g, int L, int rcap,
                        const double* kap_dev, double kap_scale, cf* Xout, hipStream_t s);
 
@@ -331,6 +334,12 @@ mrf_status enqueue_step(mrf_recon_s* R, hipStream_t s) {
   if ((e = join(R, 0, 2, s))) return e;
   if ((e = lap_apply_sub(R->graph, R->aX, R->Ya, r, s))) return e;                            // S_L(X V)
   if ((e = grad_coef(R->aX, R->aU, R->Ya, R->sc + SC_MU, R->sc + SC_LAM1, (long)Nv * r, R->beta, s))) return e;
+  if (llr_xupdate_beta_ok(R->g, rc, r)) {
+    // Z = beta V^H is formed inside the X update's tiles and never stored
+    if ((e = join(R, 1, 2, s))) return e;
+    if ((e = llr_xupdate_beta(R->beta, V, r, R->U, R->C, R->g, L, rc, R->sc + SC_KAP, 1.0, R->X, s))) return e;
+    return evaluate_enqueue(R, s);
+  }
   if ((e = subspace_expand(R->beta, V, L, Nv, r, R->ZG, s))) return e;                        // Z
   if ((e = join(R, 1, 2, s))) return e;
   if ((e = llr_xupdate(R->ZG, R->U, R->C, R->g, L, rc, R->sc + SC_KAP, 1.0, R->X, s))) return e;

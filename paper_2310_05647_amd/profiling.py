@@ -25,7 +25,7 @@ KERNELS = {
     "llr_gram": ("k_gram_cells", "llr.hip"),
     "llr_tridiag": ("k_tridiag", "llr.hip"),
     "llr_coef": ("k_coef_strip", "llr.hip"),
-    "llr_xupdate": ("k_xupdate_mfma<10, true>", "llr.hip"),
+    "llr_xupdate": ("k_xupdate_mfma<10, true, true>", "llr.hip"),
     "llr_backxf": ("k_backxf", "llr.hip"),
     "lap_quad": ("k_lap_quad_edges<64, 2, 8>", "graph.hip"),
     "nufft_col_adj": ("k_col_adj", "nufft.hip"),
