@@ -58,7 +58,11 @@ def algorithmic_work(name, cfg, E, Np):
         "nufft_row_adj": ("hbm", T + img),
         "nufft_col_fwd": ("hbm", T + E * 64 + E * 8),
         "nufft_col_adj": ("hbm", E * 64 + E * 8 + T),
-        "llr_gram": ("mfma", 4.0 * pp * (pp + 1) * L * Np),          # Hermitian half, 8 flops / complex MAC
+        # 8 x 8 patches at stride 4: the five distinct 16 x 16 cell-pair blocks of each 4 x 4 cell
+        # (8 flops per complex MAC), of which every patch Gram is assembled; otherwise the Hermitian
+        # half of each patch Gram
+        "llr_gram": ("mfma", 8.0 * 256 * 5 * (N // 4) ** 2 * L if (cfg["p"], cfg["s"]) == (8, 4)
+                     else 4.0 * pp * (pp + 1) * L * Np),
         "llr_tridiag": ("fp64", 16.0 / 3.0 * pp ** 3 * Np),          # complex Hermitian tridiagonalisation
         "match_subspace": ("mfma", 8.0 * N * N * M * r),
         "subspace_reduce": ("hbm", img),                            # one series per call (X V, then (A^H r) V)
