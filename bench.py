@@ -270,8 +270,8 @@ def main():
                          "stream (default 0: independent parts overlap on the recon's two extra streams)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (frames would shard "
-              "across GPUs; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (frames would shard "
+              "across GPUs). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
