@@ -32,7 +32,7 @@ typedef enum mrf_status {
   MRF_DEVICE = 4,        /* a HIP runtime call or kernel launch failed              */
   MRF_OOM = 5,           /* device allocation of a handle's tables failed           */
   MRF_NONFINITE = 6,     /* a cost value became NaN or Inf                          */
-  MRF_NOT_SUPPORTED = 7  /* a valid request this build does not implement           */
+  MRF_NOT_SUPPORTED = 7  /* a valid request the library does not implement          */
 } mrf_status;
 
 typedef struct mrf_c64 {
