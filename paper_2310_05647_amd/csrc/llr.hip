@@ -61,6 +61,19 @@ __device__ inline double wave_sum(double v) {
   v = row_sum16(v);
   return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
+// Two independent wave sums with their DPP steps interleaved (each in the order of wave_sum).
+__device__ inline void wave_sum2(double& a, double& b) {
+  a += dpp64<0xB1>(a);
+  b += dpp64<0xB1>(b);
+  a += dpp64<0x4E>(a);
+  b += dpp64<0x4E>(b);
+  a += dpp64<0x124>(a);
+  b += dpp64<0x124>(b);
+  a += dpp64<0x128>(a);
+  b += dpp64<0x128>(b);
+  a = (lane_value(a, 0) + lane_value(a, 16)) + (lane_value(a, 32) + lane_value(a, 48));
+  b = (lane_value(b, 0) + lane_value(b, 16)) + (lane_value(b, 32) + lane_value(b, 48));
+}
 
 // Patch index of the b-th block, XCD-aware: blocks go to the 8 XCDs round-robin, and each XCD
 // gets a contiguous band of patch rows so that overlapping patches share its L2.
@@ -446,8 +459,9 @@ __global__ __launch_bounds__(64 * kTdW) void k_tridiag(const cf* __restrict__ G,
                   dadd(dadd(pw[4][r], pw[5][r]), dadd(pw[6][r], pw[7][r])));
       else ps = pw[0][r];
       const dcplx pv = dscale(ps, tau);
-      const double kr = wave_sum(below ? v.x * pv.x + v.y * pv.y : 0.0);
-      const double ki = wave_sum(below ? v.x * pv.y - v.y * pv.x : 0.0);
+      double kr = below ? v.x * pv.x + v.y * pv.y : 0.0;
+      double ki = below ? v.x * pv.y - v.y * pv.x : 0.0;
+      wave_sum2(kr, ki);
       const dcplx K = dscale(dcplx{kr, ki}, 0.5 * tau);
       const dcplx wr = below ? dsub(pv, dmul(K, v)) : dcplx{0.0, 0.0};
       wsw[w][r] = wr;
