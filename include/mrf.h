@@ -220,7 +220,8 @@ mrf_status mrf_frames_to_voxels(const mrf_c64* X, int L, int Nv, mrf_c64* Y, hip
  * mean squared error; Adam with bias correction; optional cosine decay of lr over total_steps.
  * GEMMs on MFMA in FP32 or BF16 (operands rounded to nearest even), FP32 accumulation and
  * FP32 master weights. Parameters are one flat FP32 array [W1 b1 W2 b2 ...], W_l [out][in].
- * The gate: k* = the grid atom nearest to the prediction in (log T1, log T2); residual =
+ * The gate: k* = the grid atom nearest to the prediction in Euclidean distance on (log T1,
+ * log T2), among the grid's atoms (ties to the lower index); residual =
  * 1 - |<d_k* V / ||d_k*||, alpha / ||alpha||>|; voxels with residual > theta take the exhaustive
  * subspace match (mrf_dict_match_subspace) instead.
  * ==================================================================================== */
@@ -249,7 +250,10 @@ mrf_status mrf_mlp_param_count(mrf_mlp_t mlp, size_t* n);
 mrf_status mrf_mlp_params(mrf_mlp_t mlp, float** params, float** grads);
 mrf_status mrf_mlp_reset_optimizer(mrf_mlp_t mlp, hipStream_t stream);
 /* The (T1, T2) grid of the gate: n1 T1 values log_t1_0 + i dlog_t1, n2 T2 values likewise;
- * grid_index [n1][n2] (device int32) the atom of each point or -1. Synchronises. */
+ * grid_index [n1][n2] (device int32) the atom of each point or -1. Every T1 row must hold an
+ * atom, and a row's atoms must occupy T2 indices 0 .. (its largest) without gaps (the T2 <= T1
+ * rule of the dictionary gives this); otherwise MRF_INVALID_ARG. mrf_mlp_match returns MRF_SHAPE
+ * if the grid names an atom index >= the dictionary's M. Synchronises. */
 mrf_status mrf_mlp_set_grid(mrf_mlp_t mlp, int n1, double log_t1_0, double dlog_t1, int n2, double log_t2_0,
                             double dlog_t2, const int32_t* grid_index, hipStream_t stream);
 /* Mean and standard deviation of log T1, log T2 over the dictionary (the target scaling);

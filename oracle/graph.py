@@ -75,10 +75,11 @@ def laplacian_from_weights(W):
     return np.diag(W.sum(axis=1)) - W
 
 
-def knn_laplacian(maps, p, s, K, sigma2=0.0):
-    """Return dict(L dense [Np, Np], sigma2, lmax, nbr, d2)."""
-    F = patch_features(maps, p, s)
-    d2 = pairwise_sqdist(F)
+def knn_weights(d2, K, sigma2=0.0):
+    """Symmetric K-NN weight matrix from squared distances d2 [Np, Np]: directed weights
+    exp(-d2 / sigma^2) (eq. (8)) on each row's K nearest, then W = max(W, W^T).
+    Returns (W, sigma2, nbr)."""
+    d2 = np.asarray(d2, np.float64)
     n = d2.shape[0]
     K = min(int(K), n - 1)
     nbr = knn_lists(d2, K)
@@ -87,6 +88,13 @@ def knn_laplacian(maps, p, s, K, sigma2=0.0):
     for i in range(n):
         for j in nbr[i]:
             Wd[i, j] = np.exp(-d2[i, j] / sig2)
-    W = np.maximum(Wd, Wd.T)
+    return np.maximum(Wd, Wd.T), sig2, nbr
+
+
+def knn_laplacian(maps, p, s, K, sigma2=0.0):
+    """Return dict(L dense [Np, Np], sigma2, lmax, nbr, d2)."""
+    F = patch_features(maps, p, s)
+    d2 = pairwise_sqdist(F)
+    W, sig2, nbr = knn_weights(d2, K, sigma2)
     Lap = laplacian_from_weights(W)
     return dict(L=Lap, sigma2=sig2, lmax=float(Lap.max()), nbr=nbr, d2=d2)

@@ -14,11 +14,14 @@ own and is defined here:
             atom m = mulhi32(u, M), phase phi = 2 pi (u + 1/2) 2^-32, SNR ~ U[snr_lo, snr_hi] dB,
             noise n ~ CN(0, sigma^2 I_r) by Box-Muller with sigma^2 = 10^(-SNR/10) / L,
             alpha = exp(i phi) d_m V / ||d_m|| + n
-  gate      k* = the grid atom nearest to the prediction in (log T1, log T2) (T2 index
-            clamped into the kept T2 <= T1 region); residual = 1 - |<d_k* V/||d_k*||, alpha/||alpha||>|;
+  gate      k* = the kept grid atom (T2 <= T1) nearest to the prediction in Euclidean distance on
+            (log T1, log T2), ties to the lower atom index;
+            residual = 1 - |<d_k* V/||d_k*||, alpha/||alpha||>|;
             voxels whose residual exceeds theta fall back to the exhaustive match.
 Pins: Philox against the published known-answer vectors; central finite differences
-against the analytic backward; one Adam step against its closed form.
+against the analytic backward; one Adam step against its closed form; the gate's grid atom
+against hand-worked cases on a small grid (boundary of the kept region, unequal axis
+spacings) and against per-axis rounding where the rounded grid point is kept.
 """
 import numpy as np
 
@@ -170,15 +173,23 @@ def target_stats(lut):
     return lg.mean(axis=0), lg.std(axis=0)
 
 
-def nearest_grid_atom(logt, t1_axis, t2_axis, grid_index):
-    """k* for predicted (log T1, log T2) [B, 2] on a log-spaced grid (B1 index 0)."""
-    l1 = np.log(t1_axis); l2 = np.log(t2_axis)
-    i1 = np.clip(np.rint((logt[:, 0] - l1[0]) / (l1[1] - l1[0])), 0, len(l1) - 1).astype(np.int64)
-    i2 = np.clip(np.rint((logt[:, 1] - l2[0]) / (l2[1] - l2[0])), 0, len(l2) - 1).astype(np.int64)
-    gi = grid_index[:, :, 0]
-    i2max = np.array([np.max(np.flatnonzero(gi[a] >= 0)) for a in range(gi.shape[0])])
-    i2 = np.minimum(i2, i2max[i1])
-    return gi[i1, i2]
+def nearest_grid_atom(logt, t1_axis, t2_axis, grid_index, chunk=2048):
+    """k* for predicted (log T1, log T2) [B, 2]: the kept grid atom (B1 index 0) at the least
+    Euclidean distance in (log T1, log T2); ties go to the lower atom index."""
+    logt = np.asarray(logt, np.float64)
+    l1 = np.log(np.asarray(t1_axis, np.float64))
+    l2 = np.log(np.asarray(t2_axis, np.float64))
+    gi = np.asarray(grid_index)[:, :, 0]
+    a, b = np.nonzero(gi >= 0)
+    atom = gi[a, b]
+    order = np.argsort(atom, kind="stable")
+    a, b, atom = a[order], b[order], atom[order]
+    out = np.empty(logt.shape[0], np.int64)
+    for c0 in range(0, logt.shape[0], chunk):
+        t = logt[c0:c0 + chunk]
+        d2 = (t[:, :1] - l1[a][None, :]) ** 2 + (t[:, 1:2] - l2[b][None, :]) ** 2
+        out[c0:c0 + chunk] = atom[np.argmin(d2, axis=1)]     # argmin keeps the first (lowest) index
+    return out
 
 
 def learned_match(alpha, params, stats, Dr_unit, atom_norms, t1_axis, t2_axis, grid_index, theta,

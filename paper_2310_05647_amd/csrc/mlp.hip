@@ -42,6 +42,7 @@ struct mrf_mlp_s {
   int n1, n2;
   double l1_0, dl1, l2_0, dl2;
   int *gidx, *i2max;            // [n1][n2] atom index (or -1), [n1] largest kept T2 index
+  int gmax;                     // largest atom index in the grid
 };
 
 namespace mrf {
@@ -347,7 +348,12 @@ __global__ __launch_bounds__(256) void k_init(float* __restrict__ W, long n, flo
   W[i] = sd * sqrtf(-2.f * logf(u01(u.x))) * cosf(6.283185307179586f * u01(u.y));
 }
 
-// Gate: k* nearest grid atom to exp(y * std + mean), residual, rho; flags voxels above theta.
+// Gate: k* = the kept grid atom nearest to the prediction exp(y * std + mean) in Euclidean distance
+// on (log T1, log T2), ties to the lower atom index; then the residual and rho, and voxels above
+// theta are flagged. Row a of the grid keeps T2 indices 0 .. i2max[a] (checked by set_grid), so a
+// row's nearest kept point is floor(x2) or floor(x2) + 1 clamped into that range; rows are taken
+// in ascending order with a strict comparison, which keeps the lower index on ties, and a row is
+// skipped when its T1 distance alone reaches the best found.
 __global__ __launch_bounds__(256) void k_gate(const float* __restrict__ y, const double* __restrict__ stats, int n1,
                                               int n2, double l1_0, double dl1, double l2_0, double dl2,
                                               const int* __restrict__ gidx, const int* __restrict__ i2max,
@@ -360,11 +366,29 @@ __global__ __launch_bounds__(256) void k_gate(const float* __restrict__ y, const
   if (v >= Nv) return;
   const double lt1 = (double)y[(size_t)v * 2] * stats[2] + stats[0];
   const double lt2 = (double)y[(size_t)v * 2 + 1] * stats[3] + stats[1];
-  int i1 = (int)rint((lt1 - l1_0) / dl1), i2 = (int)rint((lt2 - l2_0) / dl2);
-  i1 = min(max(i1, 0), n1 - 1);
-  i2 = min(max(i2, 0), n2 - 1);
-  i2 = min(i2, i2max[i1]);
-  const int k = gidx[(size_t)i1 * n2 + i2];
+  const double x2 = (lt2 - l2_0) / dl2;
+  const double fl = floor(x2);
+  const int blo = fl < 0.0 ? -1 : (fl >= (double)n2 ? n2 : (int)fl);
+  double best = 1.0e300;
+  int ba = 0, bb = 0;
+  for (int a = 0; a < n1; ++a) {
+    const double d1 = lt1 - (l1_0 + a * dl1);
+    const double d11 = d1 * d1;
+    if (d11 >= best) continue;
+    const int hi = i2max[a];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int b = min(max(blo + c, 0), hi);
+      const double d2 = lt2 - (l2_0 + b * dl2);
+      const double dd = d11 + d2 * d2;
+      if (dd < best) {
+        best = dd;
+        ba = a;
+        bb = b;
+      }
+    }
+  }
+  const int k = gidx[(size_t)ba * n2 + bb];
   const cf* a = alpha + (size_t)v * r;
   const cf* d = dhr + (size_t)k * r;
   float nr = 0.f, ipr = 0.f, ipi = 0.f;
@@ -616,10 +640,20 @@ extern "C" mrf_status mrf_mlp_set_grid(mrf_mlp_t P, int n1, double log_t1_0, dou
   std::vector<int> gi((size_t)n1 * n2), mx(n1, -1);
   MRF_CHECK_HIP(hipMemcpyAsync(gi.data(), grid_index, gi.size() * 4, hipMemcpyDeviceToHost, s));
   MRF_CHECK_HIP(hipStreamSynchronize(s));
+  int kmax = -1;
   for (int a = 0; a < n1; ++a)
     for (int b = 0; b < n2; ++b)
-      if (gi[(size_t)a * n2 + b] >= 0) mx[a] = b;
-  for (int a = 0; a < n1; ++a) MRF_REQUIRE(mx[a] >= 0, MRF_INVALID_ARG, "mlp_set_grid: a T1 row without atoms");
+      if (gi[(size_t)a * n2 + b] >= 0) {
+        mx[a] = b;
+        kmax = std::max(kmax, (int)gi[(size_t)a * n2 + b]);
+      }
+  for (int a = 0; a < n1; ++a) {
+    MRF_REQUIRE(mx[a] >= 0, MRF_INVALID_ARG, "mlp_set_grid: a T1 row without atoms");
+    // the gate searches T2 indices 0 .. mx[a] of each row: they must all hold an atom
+    for (int b = 0; b <= mx[a]; ++b)
+      MRF_REQUIRE(gi[(size_t)a * n2 + b] >= 0, MRF_INVALID_ARG,
+                  "mlp_set_grid: a row's kept T2 indices must run from 0 without gaps");
+  }
   hipFree(P->gidx);
   hipFree(P->i2max);
   P->gidx = nullptr;
@@ -630,6 +664,7 @@ extern "C" mrf_status mrf_mlp_set_grid(mrf_mlp_t P, int n1, double log_t1_0, dou
   MRF_CHECK_HIP(hipMemcpyAsync(P->i2max, mx.data(), (size_t)n1 * 4, hipMemcpyHostToDevice, s));
   MRF_CHECK_HIP(hipStreamSynchronize(s));
   P->n1 = n1; P->n2 = n2; P->l1_0 = log_t1_0; P->dl1 = dlog_t1; P->l2_0 = log_t2_0; P->dl2 = dlog_t2;
+  P->gmax = kmax;
   return MRF_OK;
 }
 
@@ -745,6 +780,7 @@ extern "C" mrf_status mrf_mlp_match(mrf_mlp_t P, mrf_dict_t D, const mrf_c64* al
   clear_error();
   MRF_REQUIRE(P && D && alpha && idx && t12 && Nv >= 1, MRF_INVALID_ARG, "mlp_match: null argument");
   MRF_REQUIRE(P->gidx, MRF_INVALID_ARG, "mlp_match: call mrf_mlp_set_grid first");
+  MRF_REQUIRE(P->gmax < D->M, MRF_SHAPE, "mlp_match: the gate's grid names atoms beyond the dictionary");
   MRF_REQUIRE(D->r >= 1 && 2 * D->r == P->nin, MRF_SHAPE, "mlp_match: the dictionary needs a basis with 2 r = n_in");
   size_t need = 0;
   mrf_mlp_match_workspace_size(P, Nv, &need);

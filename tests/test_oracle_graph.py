@@ -81,3 +81,32 @@ def test_trace_form_equals_half_the_pairwise_form():
             pair += W[i, j] * np.sum(np.abs(P[i] - P[j]) ** 2)
     tr = np.vdot(X, ops.laplacian_apply(X, g["L"], p, s)).real
     assert abs(tr - 0.5 * pair) <= 1e-10 * abs(pair)
+
+
+def test_one_sided_knn_edges_are_kept_with_their_weight():
+    """Reading Q7: W = max(W, W^T). Four nodes with hand-chosen squared distances so that
+    K-NN membership is one-sided: with K = 1, node 2's nearest is 0 and node 3's nearest is 1,
+    but neither 0 nor 1 picks them back. Worked by hand (sigma^2 = 1): the symmetric weights
+    are w01 = e^-1 (mutual), w02 = e^-2 (from 2 only), w13 = e^-4 (from 3 only); a mean
+    (e^-2 / 2) or a min (0) would change L."""
+    d2 = np.array([[0, 1, 2, 5],
+                   [1, 0, 3, 4],
+                   [2, 3, 0, 6],
+                   [5, 4, 6, 0]], float)
+    e1, e2, e4 = np.exp(-1.0), np.exp(-2.0), np.exp(-4.0)
+    expect_L = np.array([[e1 + e2, -e1, -e2, 0.0],
+                         [-e1, e1 + e4, 0.0, -e4],
+                         [-e2, 0.0, e2, 0.0],
+                         [0.0, -e4, 0.0, e4]])
+    for sig2 in (1.0, 0.0):     # 0: median rule; the directed K-NN values 1, 1, 2, 4 give 1
+        W, s2, nbr = graph.knn_weights(d2, 1, sig2)
+        assert s2 == 1.0
+        np.testing.assert_array_equal(nbr[:, 0], [1, 0, 0, 1])
+        np.testing.assert_allclose(graph.laplacian_from_weights(W), expect_L, rtol=1e-15, atol=0)
+    # K = 2: 0 and 1 pick {1, 2} and {0, 2}; 2 picks {0, 1}; 3 picks {1, 0}. Edges 3-0 and 3-1
+    # come from node 3 alone and keep its weights e^-5 and e^-4.
+    W, _, _ = graph.knn_weights(d2, 2, 1.0)
+    expect_W = np.zeros((4, 4))
+    for (i, j), d in {(0, 1): 1, (0, 2): 2, (1, 2): 3, (0, 3): 5, (1, 3): 4}.items():
+        expect_W[i, j] = expect_W[j, i] = np.exp(-d)
+    np.testing.assert_allclose(W, expect_W, rtol=1e-15, atol=0)

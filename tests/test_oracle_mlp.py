@@ -84,3 +84,54 @@ def test_synth_batch_statistics():
     assert abs(var - expect) < 0.1 * expect
     a2, m2 = mlp.synth_batch(Dr, seed=123, step=0, batch=20000, snr_lo=30.0, snr_hi=30.0, L=L)
     np.testing.assert_array_equal(alpha, a2)
+
+
+def test_gate_grid_atom_hand_worked_cases():
+    """Gate atom = the kept grid atom nearest in (log T1, log T2). A 3 x 3 grid with T1 axis
+    100, 300, 900 ms (log step ln 3 = 1.0986) and T2 axis 50, 100, 200 ms (log step ln 2 = 0.6931);
+    T2 <= T1 keeps (0,0) (0,1) | (1,0) (1,1) (1,2) | (2,0) (2,1) (2,2), atoms 0..7 in that order.
+    Worked by hand, distances in log units:
+      (110, 200): (0,2) is not kept; (0,1) at sqrt(ln(1.1)^2 + ln(2)^2) = 0.700 beats
+                  (1,2) at ln(300/110) = 1.003                                       -> atom 1
+      (164, 200): 0.45 of a T1 step above row 0: (1,2) at ln(300/164) = 0.604 beats (0,1) at
+                  sqrt(ln(1.64)^2 + ln(2)^2) = 0.852 (rounding each axis and clamping T2 into
+                  row 0 would give atom 1)                                           -> atom 4
+      (300, 110): (1,1) at ln(1.1) = 0.095                                           -> atom 3
+      (300, 30):  below the T2 axis: (1,0) at ln(50/30) = 0.511                      -> atom 2
+      (100, 50), (900, 200): grid points                                             -> atoms 0, 7"""
+    t1 = np.array([100.0, 300.0, 900.0])
+    t2 = np.array([50.0, 100.0, 200.0])
+    gi = -np.ones((3, 3, 1), np.int32)
+    m = 0
+    for a in range(3):
+        for b in range(3):
+            if t2[b] <= t1[a]:
+                gi[a, b, 0] = m
+                m += 1
+    assert m == 8
+    pts = np.log(np.array([[110, 200], [164, 200], [300, 110], [300, 30], [100, 50], [900, 200]], float))
+    np.testing.assert_array_equal(mlp.nearest_grid_atom(pts, t1, t2, gi), [1, 4, 3, 2, 0, 7])
+
+
+def test_gate_grid_atom_is_per_axis_rounding_inside_the_kept_region():
+    """On a rectangular log grid the nearest point is the per-axis rounding; where that point is
+    kept it is also the nearest kept atom (C1's 60 x 40 grid, random predictions)."""
+    import mrfgen
+    grid = mrfgen.param_grid(mrfgen.get_config("C1"))
+    l1, l2 = np.log(grid["t1_axis"]), np.log(grid["t2_axis"])
+    rng = np.random.default_rng(6)
+    p = np.stack([rng.uniform(l1[0] - 0.1, l1[-1] + 0.1, 4000), rng.uniform(l2[0] - 0.1, l2[-1] + 0.1, 4000)], 1)
+    i1 = np.clip(np.rint((p[:, 0] - l1[0]) / (l1[1] - l1[0])), 0, len(l1) - 1).astype(int)
+    i2 = np.clip(np.rint((p[:, 1] - l2[0]) / (l2[1] - l2[0])), 0, len(l2) - 1).astype(int)
+    kept = grid["grid_index"][i1, i2, 0]
+    inside = kept >= 0
+    assert inside.sum() > 1000 and (~inside).sum() > 100
+    k = mlp.nearest_grid_atom(p, grid["t1_axis"], grid["t2_axis"], grid["grid_index"])
+    np.testing.assert_array_equal(k[inside], kept[inside])
+    # outside the kept region the chosen atom is kept and no kept atom is nearer
+    assert np.all(k >= 0)
+    T1, T2 = np.log(grid["lut"][:, 0].astype(np.float64)), np.log(grid["lut"][:, 1].astype(np.float64))
+    out = np.flatnonzero(~inside)[:50]
+    for v in out:
+        d2 = (p[v, 0] - T1) ** 2 + (p[v, 1] - T2) ** 2
+        assert d2[k[v]] <= d2.min() + 1e-9

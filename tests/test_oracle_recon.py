@@ -73,3 +73,109 @@ def test_c1_small_recon_improves_on_the_initial_match():
     e1 = metrics.nmse(ph["T1"], out["maps"][0], m)
     assert e1 < e0
     assert metrics.snr_db(X, out["X"]) > metrics.snr_db(X, nufft.nufft_adj(b, traj, cfg["N"]))
+
+
+def _landweber_problem(seed=1, N=4, L=2, Ns=48):
+    rng = np.random.default_rng(seed)
+    traj = rng.uniform(-math.pi, math.pi, (L, Ns, 2))
+    b = rng.standard_normal((L, Ns)) + 1j * rng.standard_normal((L, Ns))
+    A = [np.stack([nufft.nufft_fwd(e.reshape(1, N, N), traj[l:l + 1])[0] for e in np.eye(N * N)], 1)
+         for l in range(L)]
+    lam = max(np.linalg.eigvalsh(a.conj().T @ a).max() for a in A)
+    return rng, traj, b, A, lam
+
+
+def test_stopping_rule_of_algorithm_1():
+    """Algorithm 1 stops after the first iteration n with cost(n-1)/cost(n) - 1 < tol. With
+    lambda1 = lambda2 = 0 and V = I the iterates are Landweber's, whose costs are computed here
+    from the dense frame operators; tol is placed so that the printed ratio and the variant
+    1 - cost(n)/cost(n-1) stop at different iterations, and the recon must follow the former."""
+    rng, traj, b, A, lam = _landweber_problem()
+    N, L = 4, 2
+    mu = 1.0 / lam
+    x = [a.conj().T @ b[l] for l, a in enumerate(A)]
+    cost = []
+    for n in range(60):
+        r = [A[l] @ x[l] - b[l] for l in range(L)]
+        cost.append(0.5 * sum(np.vdot(v, v).real for v in r))
+        x = [x[l] - mu * (A[l].conj().T @ r[l]) for l in range(L)]
+    cost = np.array(cost)
+    ratio = cost[:-1] / cost[1:] - 1.0          # index n-1 holds the test after iteration n
+    alt = 1.0 - cost[1:] / cost[:-1]
+    assert np.all(np.diff(cost) < 0)
+    # tol between the two forms at some iteration k, so they stop at different n
+    tol = None
+    for k in range(3, 40):
+        t = 0.5 * (ratio[k] + alt[k])
+        n_paper = 1 + int(np.argmax(ratio < t))
+        n_alt = 1 + int(np.argmax(alt < t))
+        if n_paper != n_alt and np.any(ratio < t):
+            tol = t
+            break
+    assert tol is not None
+    D, lut = _tiny_dict(rng, L)
+    out = recon.recon(b, traj, D, lut, np.eye(L), N, 2, 1, 2, 4, lam1_0=0.0, lam2=0.0, mu0=mu, lamA=lam,
+                      n_max=200, tol=tol)
+    st = out["stats"]
+    assert st["stop"] == "tolerance"
+    assert st["iters"] == n_paper != n_alt
+    np.testing.assert_allclose(st["cost"], cost[:n_paper + 1], rtol=1e-10)
+    # without a tolerance all n_max iterations run
+    out = recon.recon(b, traj, D, lut, np.eye(L), N, 2, 1, 2, 4, lam1_0=0.0, lam2=0.0, mu0=mu, lamA=lam,
+                      n_max=n_paper + 3, tol=None)
+    assert out["stats"]["iters"] == n_paper + 3 and out["stats"]["stop"] == "max_iter"
+
+
+def _dense_SL(N, p, s, Lap):
+    """The pixel operator S_L X = Q*(Q(X) L) of one frame as a dense N^2 x N^2 matrix."""
+    from oracle import ops
+    cols = [ops.laplacian_apply(e.reshape(1, N, N), Lap, p, s)[0].ravel() for e in np.eye(N * N)]
+    return np.stack(cols, 1).real
+
+
+def test_step_size_bounds_the_gradient_lipschitz_constant():
+    """The step of reading Q9: mu = min(mu0, 1/(lamA + 2 c_max lambda1 max(L))) must not exceed
+    1/lambda_max(A^H A + lambda1 S_L), the gradient's Lipschitz constant for eq. (15).
+    (1) Random K-NN graphs with overlapping 4x4 patches and the dense NUFFT of a frame: the bound
+        holds.
+    (2) p = s (Q unitary) and one edge of weight w between two patches: lambda_max(S_L) = 2w =
+        2 max(L) exactly, so with A^H A = eps I the bound is attained: mu lambda_max = 1.
+    (3) 2x2 patches at stride 1 on a 3x3 image (coverage 4 at the centre), all four patches joined
+        with weight w: a unit image at the centre has Rayleigh quotient sum_i L_ii = 12 w =
+        c_max max(L), so the factor c_max is needed for the bound to hold."""
+    from oracle import graph, patches
+    # (1)
+    rng = np.random.default_rng(3)
+    N, p, s = 8, 4, 2
+    traj = rng.uniform(-math.pi, math.pi, (1, 40, 2))
+    A = np.stack([nufft.nufft_fwd(e.reshape(1, N, N), traj)[0] for e in np.eye(N * N)], 1)
+    AhA = A.conj().T @ A
+    lamA = np.linalg.eigvalsh(AhA).max()
+    cmax = float(patches.coverage(N, p, s).max())
+    assert cmax == 4.0
+    for K in (1, 3, 8):
+        maps = np.stack([rng.uniform(300, 2500, (N, N)), rng.uniform(40, 300, (N, N)), rng.uniform(0, 100, (N, N))])
+        g = graph.knn_laplacian(maps, p, s, K)
+        for lam1_0 in (0.01, 1.0, 100.0):
+            lam1 = lam1_0 * g["lmax"]
+            H = AhA + lam1 * _dense_SL(N, p, s, g["L"])
+            mu = recon.step_size(10.0, lamA, lam1, g["lmax"], cmax)
+            assert mu * np.linalg.eigvalsh(H).max() <= 1.0 + 1e-12
+    # (2)
+    w, eps = 0.7, 1e-3
+    Lap = np.zeros((4, 4))
+    Lap[0, 0] = Lap[1, 1] = w
+    Lap[0, 1] = Lap[1, 0] = -w
+    H = eps * np.eye(16) + 5.0 * _dense_SL(4, 2, 2, Lap)
+    mu = recon.step_size(10.0, eps, 5.0, w, 1.0)
+    assert abs(mu * np.linalg.eigvalsh(H).max() - 1.0) <= 1e-12
+    # (3)
+    assert patches.coverage(3, 2, 1).max() == 4.0
+    Lap = w * (4.0 * np.eye(4) - np.ones((4, 4)))
+    SL = _dense_SL(3, 2, 1, Lap)
+    e = np.zeros(9)
+    e[4] = 1.0
+    assert abs(e @ SL @ e - 4 * 3 * w) <= 1e-12
+    H = eps * np.eye(9) + 5.0 * SL
+    mu = recon.step_size(10.0, eps, 5.0, 3 * w, 4.0)
+    assert mu * np.linalg.eigvalsh(H).max() <= 1.0 + 1e-12
