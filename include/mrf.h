@@ -147,6 +147,20 @@ mrf_status mrf_llr_workspace_size(int n, int L, int p, int s, int rank_cap, size
 mrf_status mrf_llr_prox(const mrf_c64* X, mrf_c64* QtP, int n, int L, int p, int s, float tau, int rank_cap,
                         double* nuc_norm, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* The X update of eq. (23) following the SVT of eq. (22):
+ *   Xout = (Z + kappa Q*(P')) / (1 + kappa c(v)),  P' = SVT_tau(Q_{q_i}(X)) per patch as in
+ *   mrf_llr_prox, kappa = mu lambda2 beta, c(v) the number of patches covering pixel v
+ * (eq. (23) divides by the scalar 1 + kappa, exact when patches do not overlap; the per-pixel
+ * c(v) makes it the exact minimiser of eq. (21) for overlapping patches). Z [L][n][n] is given
+ * either in full (beta_coef = NULL) or, for 8 x 8 patches at stride 4, as the subspace
+ * expansion Z = beta_coef V^H of eq. (17) (Z = NULL; beta_coef [n*n][r] voxel-major, V [L][r],
+ * 1 <= r <= 16), formed inside the update's tiles and never stored. Xout must not alias X or Z.
+ * ws: at least mrf_llr_xupdate_workspace_size bytes. Asynchronous. */
+mrf_status mrf_llr_xupdate_workspace_size(int n, int L, int p, int s, int rank_cap, size_t* bytes);
+mrf_status mrf_llr_xupdate(const mrf_c64* X, const mrf_c64* Z, const mrf_c64* beta_coef, const mrf_c64* V, int r,
+                           int n, int L, int p, int s, float tau, int rank_cap, double kappa, mrf_c64* Xout, void* ws,
+                           size_t ws_bytes, hipStream_t stream);
+
 /* ====================================================================================
  * Temporal subspace (Sec. III-B, eq. (17)): P_S(X) = X V V^H for every voxel's time course,
  * with V [L][r] an orthonormal basis approximated from the dictionary (an input, as P_S is
@@ -351,6 +365,17 @@ mrf_status mrf_recon_batched(int nslices, const mrf_recon_t* recons, const hipSt
 /* Final match Phi_D(X): any of X_out [L][n][n], maps [3][n][n] (T1, T2, PD), idx [n*n],
  * rho [n*n] may be NULL. Asynchronous. */
 mrf_status mrf_recon_finish(mrf_recon_t r, mrf_c64* X_out, float* maps, int32_t* idx, float* rho, hipStream_t stream);
+/* Parity diagnostic: graph number k (k = 0: the graph built at mrf_recon_init from M^0;
+ * k = n: the graph built from M^n before iteration n + 1) is not built from the match but taken
+ * as given: the Laplacian L in CSR (host arrays: rowptr [Np + 1] from 0 to nnz, col [nnz]
+ * ascending within each row with the diagonal present, val [nnz] = entries of L), with its sigma^2
+ * and max(L) (which set lambda1 and mu). The match M^k is still computed. Lets a run follow an
+ * external reference's graphs so that floating-point drift is told apart from discrete changes of
+ * the graph (arg-max and K-NN near-ties). Copies the arrays to device memory owned by the recon
+ * (synchronous); a later call for the same k replaces the earlier one. MRF_SHAPE if nnz exceeds
+ * the graph's capacity (Np (2 K + 1)). */
+mrf_status mrf_recon_inject_graph(mrf_recon_t r, int k, int nnz, const int* rowptr, const int* col, const float* val,
+                                  double sigma2, double lmax);
 /* Copies the statistics of the run so far (host struct). */
 mrf_status mrf_recon_get_stats(mrf_recon_t r, mrf_recon_stats* out);
 /* The whole of Algorithm 1: init + iterate(n_max) + finish; stats may be NULL. */

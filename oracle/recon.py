@@ -23,6 +23,7 @@ Pins: with lambda1 = lambda2 = 0 and V = I the loop is a Landweber iteration tha
 converges to the least-squares solution (numpy.linalg.lstsq on a tiny dense operator).
 """
 import numpy as np
+import scipy.sparse as sp
 
 from . import graph, match, nufft, ops
 from .patches import coverage
@@ -35,8 +36,10 @@ def step_size(mu0, lamA, lam1, lmax, cmax):
 
 
 def recon(b, traj, atoms, lut, V, N, p, s, K, r_llr, lam1_0=0.1, lam2=0.1, beta=0.2,
-          mu0=1.0, lamA=0.0, sigma2=0.0, n_max=10, tol=None, osf=2, W=6, X0=None):
-    """Return dict(X, maps, idx, rho, stats)."""
+          mu0=1.0, lamA=0.0, sigma2=0.0, n_max=10, tol=None, osf=2, W=6, X0=None, keep_graphs=False):
+    """Return dict(X, maps, idx, rho, stats). keep_graphs: stats["graphs"] lists every Laplacian
+    used (scipy CSR [Np, Np]; graph k serves iteration k + 1). The Laplacian is applied from
+    sparse storage (the same entries; only the non-zeros enter the sums)."""
     b = np.asarray(b, np.complex128)
     V = np.asarray(V, np.complex128)
     tau = 1.0 / beta
@@ -56,13 +59,15 @@ def recon(b, traj, atoms, lut, V, N, p, s, K, r_llr, lam1_0=0.1, lam2=0.1, beta=
 
     X = adj(b) if X0 is None else np.asarray(X0, np.complex128)
     g = rebuild(X)
-    Lap, lam1 = g["L"], lam1_0 * g["lmax"]
+    Lap, lam1 = sp.csr_matrix(g["L"]), lam1_0 * g["lmax"]
     mu = step_size(mu0, lamA, lam1, g["lmax"], cmax)
     r = fwd(X) - b
     nuc = ops.nuclear_norm(X, p, s)
     c_prev, terms = ops.cost(r, X, Lap, lam1, lam2, nuc, p, s)
     stats = dict(cost=[c_prev], terms=[terms], mu=[mu], lam1=[lam1], sigma2=[g["sigma2"]],
                  lmax=[g["lmax"]], iters=0, stop="max_iter")
+    if keep_graphs:
+        stats["graphs"] = [Lap]
     for n in range(n_max):
         grad = adj(r) + lam1 * ops.laplacian_apply(X, Lap, p, s)
         Z = ops.project(X - mu * grad, V)
@@ -79,10 +84,12 @@ def recon(b, traj, atoms, lut, V, N, p, s, K, r_llr, lam1_0=0.1, lam2=0.1, beta=
         c_prev = c
         if n + 1 < n_max:
             g = rebuild(X)
-            Lap, lam1 = g["L"], lam1_0 * g["lmax"]
+            Lap, lam1 = sp.csr_matrix(g["L"]), lam1_0 * g["lmax"]
             mu = step_size(mu0, lamA, lam1, g["lmax"], cmax)
             stats["mu"].append(mu); stats["lam1"].append(lam1)
             stats["sigma2"].append(g["sigma2"]); stats["lmax"].append(g["lmax"])
+            if keep_graphs:
+                stats["graphs"].append(Lap)
     idx, rho, score, params = match.match_subspace(X, atoms, lut, V)
     maps = match.maps_from_match(idx, rho, lut, N)
     return dict(X=X, maps=maps, idx=idx, rho=rho, score=score, stats=stats)

@@ -8,7 +8,8 @@ package fails loudly when libmrf.so has not been built.
 from ._lib import MrfError, lib, library_path, check, timing_enable, timing_report  # noqa: F401
 from .nufft import NufftPlan, autotune  # noqa: F401
 from .graph import PatchGraph  # noqa: F401
-from .llr import llr_prox  # noqa: F401
-from .subspace import Dictionary, frames_to_voxels, subspace_coeffs, subspace_project  # noqa: F401
+from .llr import llr_prox, llr_xupdate  # noqa: F401
+from .subspace import (Dictionary, frames_to_voxels, subspace_coeffs,  # noqa: F401
+                       subspace_project)
 from .recon import Recon, recon_batched  # noqa: F401
 from .mlp import MLP  # noqa: F401

@@ -72,6 +72,9 @@ _decl("mrf_laplacian_quad", [c_void_p, c_void_p, c_int, c_void_p, c_void_p])
 _decl("mrf_llr_workspace_size", [c_int, c_int, c_int, c_int, c_int, P(c_size_t)])
 _decl("mrf_llr_prox", [c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_float, c_int, c_void_p, c_void_p,
                        c_size_t, c_void_p])
+_decl("mrf_llr_xupdate_workspace_size", [c_int, c_int, c_int, c_int, c_int, P(c_size_t)])
+_decl("mrf_llr_xupdate", [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_int, c_float, c_int,
+                          ctypes.c_double, c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_subspace_coeffs_workspace_size", [c_int, c_int, c_int, P(c_size_t)])
 _decl("mrf_subspace_coeffs", [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_subspace_project", [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_size_t, c_void_p])
@@ -108,6 +111,8 @@ _decl("mrf_recon_iterate", [c_void_p, c_int, P(c_int), c_void_p])
 _decl("mrf_recon_set_serial", [c_void_p, c_int])
 _decl("mrf_recon_finish", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p])
 _decl("mrf_recon_get_stats", [c_void_p, P(ReconStats)])
+_decl("mrf_recon_inject_graph", [c_void_p, c_int, c_int, P(c_int), P(c_int), P(c_float), ctypes.c_double,
+                                 ctypes.c_double])
 _decl("mrf_recon", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, P(ReconStats), c_void_p])
 
 

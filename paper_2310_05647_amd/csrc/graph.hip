@@ -832,6 +832,19 @@ mrf_status sum_partials2(const double* part, long n, double* tmp, double* out, h
   return MRF_OK;
 }
 const PatchGeom& graph_geom(const mrf_graph_s* G) { return G->g; }
+size_t graph_capacity(const mrf_graph_s* G) { return G->cap; }
+
+// Replaces the graph's Laplacian by a given CSR (device arrays, already checked by the caller) and
+// its scalars (device doubles: sigma^2, max(L), nnz, 0). Asynchronous device-to-device copies.
+mrf_status graph_set_csr(mrf_graph_s* G, const int* rowptr, const int* col, const float* val, int nnz,
+                         const double* scal, hipStream_t s) {
+  if ((size_t)nnz > G->cap) return fail(MRF_SHAPE, "graph: CSR larger than the graph's capacity");
+  MRF_CHECK_HIP(hipMemcpyAsync(G->rowptr, rowptr, (size_t)(G->g.Np + 1) * 4, hipMemcpyDeviceToDevice, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(G->col, col, (size_t)nnz * 4, hipMemcpyDeviceToDevice, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(G->val, val, (size_t)nnz * 4, hipMemcpyDeviceToDevice, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(G->scal, scal, 4 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return MRF_OK;
+}
 
 }  // namespace mrf
 

@@ -1537,6 +1537,8 @@ mrf_status llr_xupdate(const cf* Z, const cf* U, const cf* C, const PatchGeom& g
 
 size_t llr_ws_bytes(const PatchGeom& g, int rcap) { return llr_ws_layout(g, rcap, nullptr).bytes; }
 
+__global__ void k_set_d(double* __restrict__ p, double v) { p[0] = v; }
+
 }  // namespace mrf
 
 using namespace mrf;
@@ -1576,4 +1578,47 @@ extern "C" mrf_status mrf_llr_prox(const mrf_c64* X, mrf_c64* QtP, int n, int L,
   r = llr_coef((const cf*)X, g, L, rank_cap, U, f, C, st);
   if (r != MRF_OK) return r;
   return llr_xupdate(nullptr, U, C, g, L, rank_cap, nullptr, 1.0, (cf*)QtP, st);
+}
+
+extern "C" mrf_status mrf_llr_xupdate_workspace_size(int n, int L, int p, int s, int rank_cap, size_t* bytes) {
+  mrf_status e = mrf_llr_workspace_size(n, L, p, s, rank_cap, bytes);
+  if (e == MRF_OK) *bytes += 256;   // the device copy of kappa
+  return e;
+}
+
+extern "C" mrf_status mrf_llr_xupdate(const mrf_c64* X, const mrf_c64* Z, const mrf_c64* beta_coef, const mrf_c64* V,
+                                      int r, int n, int L, int p, int s, float tau, int rank_cap, double kappa,
+                                      mrf_c64* Xout, void* ws, size_t ws_bytes, hipStream_t st) {
+  clear_error();
+  PatchGeom g;
+  MRF_REQUIRE(X && Xout, MRF_INVALID_ARG, "llr_xupdate: null argument");
+  MRF_REQUIRE((Z != nullptr) != (beta_coef != nullptr), MRF_INVALID_ARG, "llr_xupdate: give exactly one of Z and beta_coef");
+  MRF_REQUIRE(!beta_coef || (V && r >= 1 && r <= 16), MRF_INVALID_ARG, "llr_xupdate: beta_coef needs V and 1 <= r <= 16");
+  MRF_REQUIRE(X != (const mrf_c64*)Xout && Z != (const mrf_c64*)Xout, MRF_INVALID_ARG,
+              "llr_xupdate: Xout must not alias X or Z");
+  MRF_REQUIRE(make_geom(n, p, s, &g), MRF_SHAPE, "llr_xupdate: need p % s == 0 and (n - p) % s == 0");
+  MRF_REQUIRE(p * p <= kMaxPP && (p * p == 64 || p * p == 16 || p * p < 16), MRF_SHAPE, "llr_xupdate: p must be 2, 3, 4 or 8");
+  MRF_REQUIRE(n % 16 == 0, MRF_SHAPE, "llr_xupdate: n must be a multiple of 16");
+  MRF_REQUIRE(rank_cap >= 1 && rank_cap <= kMaxRllr && L >= 1 && tau >= 0.f && kappa >= 0.0 && std::isfinite(kappa),
+              MRF_INVALID_ARG, "llr_xupdate: bad rank cap, L, tau or kappa");
+  MRF_REQUIRE(!beta_coef || llr_xupdate_beta_ok(g, rank_cap, r), MRF_NOT_SUPPORTED,
+              "llr_xupdate: Z from beta_coef needs 8 x 8 patches at stride 4");
+  size_t need = 0;
+  mrf_llr_xupdate_workspace_size(n, L, p, s, rank_cap, &need);
+  MRF_REQUIRE(ws && ws_bytes >= need, MRF_WORKSPACE, "llr_xupdate: workspace too small");
+  const size_t PP = (size_t)p * p;
+  char* base = (char*)ws;
+  size_t off = llr_ws_bytes(g, rank_cap);
+  cf* U = (cf*)(base + off); off += al((size_t)g.Np * rank_cap * PP * sizeof(cf));
+  float* f = (float*)(base + off); off += al((size_t)g.Np * rank_cap * 4);
+  cf* C = (cf*)(base + off); off += al((size_t)g.Np * rank_cap * L * sizeof(cf));
+  double* kap = (double*)(base + off);
+  double* nuc = kap + 1;
+  MRF_LAUNCH("llr_set_kappa", st, k_set_d<<<1, 1, 0, st>>>(kap, kappa));
+  mrf_status e = llr_analyse((const cf*)X, g, L, tau, rank_cap, ws, U, f, nuc, nullptr, st);
+  if (e != MRF_OK) return e;
+  if ((e = llr_coef((const cf*)X, g, L, rank_cap, U, f, C, st))) return e;
+  if (beta_coef)
+    return llr_xupdate_beta((const cf*)beta_coef, (const cf*)V, r, U, C, g, L, rank_cap, kap, 1.0, (cf*)Xout, st);
+  return llr_xupdate((const cf*)Z, U, C, g, L, rank_cap, kap, 1.0, (cf*)Xout, st);
 }

@@ -38,6 +38,9 @@ mrf_status graph_build(mrf_graph_s* G, const float* maps, int K, float sigma2, h
 mrf_status lap_quad(mrf_graph_s* G, const cf* X, int L, double* out, hipStream_t s);
 mrf_status lap_apply_sub(const mrf_graph_s* G, const cf* A, cf* Y, int r, hipStream_t s);
 const double* graph_scalars(const mrf_graph_s* G);
+size_t graph_capacity(const mrf_graph_s* G);
+mrf_status graph_set_csr(mrf_graph_s* G, const int* rowptr, const int* col, const float* val, int nnz,
+                         const double* scal, hipStream_t s);
 // subspace.hip
 size_t reduce_ws_bytes(int L, int Nv, int r);
 mrf_status subspace_reduce(const cf* X, const cf* Gd, const double* mu_dev, const cf* V, int L, int Nv, int r,
@@ -116,6 +119,14 @@ struct mrf_recon_s {
   double c_prev;
   mrf_recon_stats st;
   std::vector<void*> allocs;
+  // graphs supplied by mrf_recon_inject_graph, by graph number (device copies owned here)
+  struct Injected {
+    int k, nnz;
+    int *rowptr, *col;
+    float* val;
+    double* scal;
+  };
+  std::vector<Injected> inj;
 };
 
 namespace {
@@ -139,13 +150,25 @@ mrf_status join(mrf_recon_s* R, int k, int bit, hipStream_t s) {
   return MRF_OK;
 }
 
+const mrf_recon_s::Injected* injected(const mrf_recon_s* R, int k) {
+  for (const auto& g : R->inj)
+    if (g.k == k) return &g;
+  return nullptr;
+}
+
+// M = Phi_D(X) and the graph built from it (graph number R->st.n_graph: 0 at the initialisation,
+// n before iteration n + 1), or the graph supplied for that number; then lambda1 and mu.
 mrf_status rebuild(mrf_recon_s* R, hipStream_t s) {
   mrf_status e;
   if ((e = subspace_reduce(R->X, nullptr, nullptr, dict_basis(R->dict), R->L, R->Nv, R->r, R->aX, (cf*)R->rws2, s)))
     return e;
   if ((e = match_subspace(R->dict, R->aX, R->Nv, R->idx, R->rho, nullptr, nullptr, s))) return e;
   if ((e = maps_from_match(R->dict, R->idx, R->rho, R->Nv, R->maps, s))) return e;
-  if ((e = graph_build(R->graph, R->maps, R->prm.K, R->prm.sigma2, s))) return e;
+  if (const auto* ig = injected(R, R->st.n_graph))
+    e = graph_set_csr(R->graph, ig->rowptr, ig->col, ig->val, ig->nnz, ig->scal, s);
+  else
+    e = graph_build(R->graph, R->maps, R->prm.K, R->prm.sigma2, s);
+  if (e) return e;
   MRF_LAUNCH("recon_scalars", s,
              k_scalars<<<1, 1, 0, s>>>(graph_scalars(R->graph), R->sc, R->prm.lam1_0, R->prm.lamA, R->cmax, R->prm.mu0,
                                        R->prm.lam2, R->prm.beta));
@@ -282,6 +305,9 @@ extern "C" mrf_status mrf_recon_destroy(mrf_recon_t R) {
   }
   if (R->ev_fork) hipEventDestroy(R->ev_fork);
   for (void* p : R->allocs) hipFree(p);
+  for (auto& g : R->inj) {
+    hipFree(g.rowptr); hipFree(g.col); hipFree(g.val); hipFree(g.scal);
+  }
   if (R->hsc) hipHostFree(R->hsc);
   mrf_graph_destroy(R->graph);
   delete R;
@@ -428,6 +454,48 @@ extern "C" mrf_status mrf_recon_finish(mrf_recon_t R, mrf_c64* X_out, float* map
   if (maps) MRF_CHECK_HIP(hipMemcpyAsync(maps, R->maps, (size_t)3 * R->Nv * 4, hipMemcpyDeviceToDevice, s));
   if (idx) MRF_CHECK_HIP(hipMemcpyAsync(idx, R->idx, (size_t)R->Nv * 4, hipMemcpyDeviceToDevice, s));
   if (rho) MRF_CHECK_HIP(hipMemcpyAsync(rho, R->rho, (size_t)R->Nv * 4, hipMemcpyDeviceToDevice, s));
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_recon_inject_graph(mrf_recon_t R, int k, int nnz, const int* rowptr, const int* col,
+                                             const float* val, double sigma2, double lmax) {
+  clear_error();
+  MRF_REQUIRE(R && rowptr && col && val, MRF_INVALID_ARG, "recon_inject_graph: null argument");
+  MRF_REQUIRE(k >= 0 && k <= MRF_MAX_ITERS, MRF_INVALID_ARG, "recon_inject_graph: graph number out of range");
+  const int Np = R->g.Np;
+  MRF_REQUIRE(nnz >= Np && (size_t)nnz <= graph_capacity(R->graph), MRF_SHAPE,
+              "recon_inject_graph: nnz must lie between the patch count and the graph's capacity");
+  MRF_REQUIRE(rowptr[0] == 0 && rowptr[Np] == nnz, MRF_INVALID_ARG, "recon_inject_graph: rowptr must run from 0 to nnz");
+  for (int i = 0; i < Np; ++i) {
+    MRF_REQUIRE(rowptr[i + 1] > rowptr[i], MRF_INVALID_ARG, "recon_inject_graph: every row needs its diagonal");
+    bool diag = false;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+      MRF_REQUIRE(col[e] >= 0 && col[e] < Np && (e == rowptr[i] || col[e] > col[e - 1]), MRF_INVALID_ARG,
+                  "recon_inject_graph: columns must be in range and ascending within a row");
+      diag |= col[e] == i;
+    }
+    MRF_REQUIRE(diag, MRF_INVALID_ARG, "recon_inject_graph: every row needs its diagonal");
+  }
+  MRF_REQUIRE(sigma2 > 0.0 && lmax >= 0.0, MRF_INVALID_ARG, "recon_inject_graph: need sigma2 > 0 and lmax >= 0");
+  mrf_recon_s::Injected g{k, nnz, nullptr, nullptr, nullptr, nullptr};
+  const double scal[4] = {sigma2, lmax, (double)nnz, 0.0};
+  bool ok = hipMalloc(&g.rowptr, (size_t)(Np + 1) * 4) == hipSuccess && hipMalloc(&g.col, (size_t)nnz * 4) == hipSuccess &&
+            hipMalloc(&g.val, (size_t)nnz * 4) == hipSuccess && hipMalloc(&g.scal, sizeof scal) == hipSuccess;
+  ok = ok && hipMemcpy(g.rowptr, rowptr, (size_t)(Np + 1) * 4, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(g.col, col, (size_t)nnz * 4, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(g.val, val, (size_t)nnz * 4, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(g.scal, scal, sizeof scal, hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    hipFree(g.rowptr); hipFree(g.col); hipFree(g.val); hipFree(g.scal);
+    return fail(MRF_OOM, "recon_inject_graph: device allocation or copy failed");
+  }
+  for (auto& old : R->inj)
+    if (old.k == k) {
+      hipFree(old.rowptr); hipFree(old.col); hipFree(old.val); hipFree(old.scal);
+      old = g;
+      return MRF_OK;
+    }
+  R->inj.push_back(g);
   return MRF_OK;
 }
 

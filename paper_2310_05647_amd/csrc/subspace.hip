@@ -274,7 +274,9 @@ __device__ inline bool better(float s, int m, float bs, int bm) { return s > bs 
 // results meet in LDS (ties to the lowest atom throughout). Four waves per SIMD let one wave's
 // score updates run under another's MFMAs. Atoms past M in the last tile are zero in the packed
 // operands: they score 0 and lose every tie to a real atom of lower index, so they need no mask.
-// Re<dhr_m, alpha> of the winner alone is formed at the end from alpha and dhr_m.
+// Re<dhr_m, alpha> of the winner alone is formed at the end from alpha and dhr_m. A voxel whose
+// alpha holds a NaN scores NaN everywhere and gets atom 0 (rho 0, score 0), never an index
+// outside the dictionary.
 __global__ __launch_bounds__(256, 4) void k_match_sub(const cf* __restrict__ alpha, int Nv, int r,
                                                    const float* __restrict__ bpk, const cf* __restrict__ dhr,
                                                    int ntile, int M,
@@ -368,7 +370,9 @@ __global__ __launch_bounds__(256, 4) void k_match_sub(const cf* __restrict__ alp
       if (better(ws_s[q][lane], ws_m[q][lane], bb.s, bb.m)) bb = Best{ws_s[q][lane], ws_m[q][lane]};
     const int v = vbase + lane;
     if (v < Nv) {
-      const int m = bb.m;
+      // every score of a voxel is NaN only when its alpha holds a NaN: then no comparison
+      // succeeded and the sentinel stands; such a voxel is given atom 0
+      const int m = bb.m < M ? bb.m : 0;
       idx_out[v] = m;
       const float nrm = norms[m];
       if (rho_out) {
@@ -409,13 +413,18 @@ int reduce_chunks(int L, int Nv) {
 
 size_t reduce_ws_bytes(int L, int Nv, int r) { return (size_t)reduce_chunks(L, Nv) * r * Nv * sizeof(cf); }
 
+// frame chunks of a reduction: MFMA blocks take 64 voxels, so fewer chunks fill the chip (never
+// more than reduce_chunks, which sizes the workspace)
+int reduce_nch(int L, int Nv, bool mfma) {
+  return mfma ? std::max(1, std::min(reduce_chunks(L, Nv), (int)ceil_div(2048, ceil_div(Nv, 64))))
+              : reduce_chunks(L, Nv);
+}
+
 // alpha [Nv][r] = (X - mu G) V, with mu from a device scalar (G may be null)
 mrf_status subspace_reduce(const cf* X, const cf* Gd, const double* mu_dev, const cf* V, int L, int Nv, int r,
                            cf* alpha, cf* part, hipStream_t s) {
   const bool mf = !Gd && r <= 16;
-  // MFMA blocks take 64 voxels, so fewer chunks fill the chip (never more than the workspace holds)
-  const int nch = mf ? std::max(1, std::min(reduce_chunks(L, Nv), (int)ceil_div(2048, ceil_div(Nv, 64))))
-                     : reduce_chunks(L, Nv);
+  const int nch = reduce_nch(L, Nv, mf);
   const int fch = (L + nch - 1) / nch;
   if (mf)
     MRF_LAUNCH("subspace_reduce", s,

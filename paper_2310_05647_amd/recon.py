@@ -1,6 +1,7 @@
 """Algorithm 1 binding: mrf_recon_create / init / iterate / finish."""
 import ctypes
 
+import numpy as np
 import torch
 
 from ._lib import ReconParams, ReconStats, check, lib
@@ -33,6 +34,22 @@ class Recon:
         check(lib.mrf_recon_iterate(self.handle, int(n), ctypes.byref(stopped), stream_ptr(stream)),
               "mrf_recon_iterate")
         return bool(stopped.value)
+
+    def inject_graph(self, k, L, sigma2, lmax):
+        """Graph number k of the run is taken as given (mrf_recon_inject_graph): L is the dense
+        Laplacian [Np, Np] (numpy, or a sparse matrix with .toarray()); its CSR keeps the non-zeros
+        and the diagonal, as float32."""
+        L = np.asarray(L.toarray() if hasattr(L, "toarray") else L)
+        nz = (L != 0) | np.eye(L.shape[0], dtype=bool)
+        rows, cols = np.nonzero(nz)                      # row-major: rows ascending, columns ascending
+        rowptr = np.zeros(L.shape[0] + 1, np.int32)
+        np.cumsum(np.bincount(rows, minlength=L.shape[0]), out=rowptr[1:])
+        col = np.ascontiguousarray(cols, np.int32)
+        val = np.ascontiguousarray(L[rows, cols], np.float32)
+        ip = ctypes.POINTER(ctypes.c_int)
+        check(lib.mrf_recon_inject_graph(self.handle, int(k), int(col.size), rowptr.ctypes.data_as(ip),
+                                         col.ctypes.data_as(ip), val.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                         float(sigma2), float(lmax)), "mrf_recon_inject_graph")
 
     def set_serial(self, serial):
         """Schedule mask for later iterations (see the constructor's serial)."""

@@ -79,3 +79,24 @@ def test_subspace_match_c2_scale_sampled():
     sel = rng.choice(Nv, 2000, replace=False)
     nd = _check_match(alpha[sel], atoms, grid["lut"], V, idx[sel], rho[sel], score[sel])
     say(f"C2 match: {nd} near-tie disagreements in the 2000-voxel sample")
+
+
+def test_subspace_match_nan_voxel_gets_atom_zero():
+    """A NaN coefficient makes every score of its voxel NaN: the voxel gets atom 0 with rho 0 and
+    score 0 (an index inside the dictionary), and the other voxels are unaffected."""
+    from paper_2310_05647_amd import Dictionary
+    w = c1_workload()
+    atoms, lut, V = w["atoms"], w["grid"]["lut"], w["V"]
+    rng = np.random.default_rng(4)
+    m = rng.integers(0, atoms.shape[0], 200)
+    alpha = ((atoms[m] * rng.uniform(1, 100, (200, 1))) @ V).astype(np.complex64)
+    bad = [3, 64, 199]
+    alpha[bad, 2] = np.nan
+    d = Dictionary(to_dev(atoms), to_dev(lut), to_dev(V))
+    idx, rho, score, params = [t.cpu().numpy() for t in d.match_subspace(to_dev(alpha))]
+    say(f"NaN voxels: idx {idx[bad]}, rho {rho[bad]}, score {score[bad]}")
+    assert np.all(idx[bad] == 0) and np.all(rho[bad] == 0) and np.all(score[bad] == 0)
+    np.testing.assert_array_equal(params[bad], lut[[0, 0, 0]])
+    good = np.setdiff1d(np.arange(200), bad)
+    ref = d.match_subspace(to_dev(alpha[good]))[0].cpu().numpy()
+    np.testing.assert_array_equal(idx[good], ref)

@@ -30,3 +30,18 @@ def random_maps(rng, N, zero_frac=0.0):
     if zero_frac > 0:
         maps[:, rng.uniform(size=(N, N)) < zero_frac] = 0.0
     return maps.astype(np.float32)
+
+
+def c2_workload(seed=0):
+    """The 256 x 256, L = 1000 workload: C2 dictionary and basis, smooth phantom, truth series,
+    VDS spiral (1 of 48 interleaves, 2048 samples), b = the oracle's A X + 40 dB noise."""
+    cfg = mrfgen.get_config("C2")
+    atoms, grid = mrfgen.make_dictionary(cfg)
+    V, _ = mrfgen.subspace_basis(atoms, cfg["r"])
+    ph = mrfgen.make_phantom(cfg, seed)
+    X = mrfgen.truth_fingerprints(cfg, ph)
+    traj = mrfgen.vds_spiral(cfg["N"], cfg["L"], cfg["Ns"], cfg["n_interleaves"])
+    b_clean = onufft.nufft_fwd(X, traj)
+    sig2 = mrfgen.noise_sigma(np.mean(np.abs(b_clean) ** 2), cfg["snr_db"])
+    b = (b_clean + mrfgen.complex_noise(b_clean.shape, sig2, seed + 17)).astype(np.complex64)
+    return dict(cfg=cfg, atoms=atoms, grid=grid, V=V, phantom=ph, X=X, traj=traj, b=b)
