@@ -170,6 +170,17 @@ mrf_status mrf_subspace_coeffs_workspace_size(int L, int Nv, int r, size_t* byte
 /* alpha [Nv][r] (voxel-major) = X V. */
 mrf_status mrf_subspace_coeffs(const mrf_c64* X, const mrf_c64* V, int L, int Nv, int r, mrf_c64* alpha,
                                void* ws, size_t ws_bytes, hipStream_t stream);
+/* For callers that cannot allocate device memory or take a workspace (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): mrf_subspace_coeffs with its
+ * partial sums (frame chunks x r x Nv complex values) in a library-owned static device array of
+ * 16 MiB per GPU, held until the process ends (enough for Nv = 65 536, r = 10 at any L). Same
+ * kernels and result as mrf_subspace_coeffs. MRF_WORKSPACE if the partial sums would exceed
+ * 16 MiB. Allocates nothing: no hipMalloc, hipFree or allocating library routine (the first call
+ * on a device looks up the array's device address). Every call on one GPU shares the array:
+ * calls that overlap on one GPU (several streams or host threads) race, so the caller must order
+ * them. Asynchronous. */
+mrf_status mrf_subspace_coeffs_noalloc(const mrf_c64* X, const mrf_c64* V, int L, int Nv, int r, mrf_c64* alpha,
+                                       hipStream_t stream);
 /* Z [L][Nv] = U V V^H; ws needs the coeffs workspace plus Nv * r * 8 bytes. */
 mrf_status mrf_subspace_project(const mrf_c64* U, const mrf_c64* V, int L, int Nv, int r, mrf_c64* Z,
                                 void* ws, size_t ws_bytes, hipStream_t stream);

@@ -9,7 +9,7 @@ from ._lib import MrfError, lib, library_path, check, timing_enable, timing_repo
 from .nufft import NufftPlan, autotune  # noqa: F401
 from .graph import PatchGraph  # noqa: F401
 from .llr import llr_prox, llr_xupdate  # noqa: F401
-from .subspace import (Dictionary, frames_to_voxels, subspace_coeffs,  # noqa: F401
+from .subspace import (Dictionary, frames_to_voxels, subspace_coeffs, subspace_coeffs_noalloc,  # noqa: F401
                        subspace_project)
 from .recon import Recon, recon_batched  # noqa: F401
 from .mlp import MLP  # noqa: F401

@@ -77,6 +77,7 @@ _decl("mrf_llr_xupdate", [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, 
                           ctypes.c_double, c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_subspace_coeffs_workspace_size", [c_int, c_int, c_int, P(c_size_t)])
 _decl("mrf_subspace_coeffs", [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_size_t, c_void_p])
+_decl("mrf_subspace_coeffs_noalloc", [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_void_p])
 _decl("mrf_subspace_project", [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_dict_create", [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_int, c_void_p, P(c_void_p)])
 _decl("mrf_dict_destroy", [c_void_p])

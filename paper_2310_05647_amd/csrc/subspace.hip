@@ -8,6 +8,7 @@
 // run on MFMA (v_mfma_f32_16x16x4f32) with the arg-max fused into its epilogue.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -551,6 +552,49 @@ extern "C" mrf_status mrf_subspace_coeffs(const mrf_c64* X, const mrf_c64* V, in
   MRF_REQUIRE(L >= 1 && Nv >= 1 && r >= 1 && r <= kMaxR, MRF_INVALID_ARG, "subspace_coeffs: bad sizes");
   MRF_REQUIRE(ws && ws_bytes >= reduce_ws_bytes(L, Nv, r), MRF_WORKSPACE, "subspace_coeffs: workspace too small");
   return subspace_reduce((const cf*)X, nullptr, nullptr, (const cf*)V, L, Nv, r, (cf*)alpha, (cf*)ws, s);
+}
+
+// ---------------------------------------------------------------- no-allocation variant
+// The partial sums of mrf_subspace_coeffs_noalloc live in this file-scope device array (one copy
+// per GPU, held until the process ends). Host code never passes the array's name to a kernel or a
+// copy: on the host that name is only a stand-in, so its device address is looked up once per
+// device (hipGetSymbolAddress with the device current) and kept in g_scratch_dev.
+constexpr size_t kCoeffScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) char scratch[kCoeffScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_dev;   // by device ordinal; null until looked up
+
+mrf_status scratch_address(void** out) {
+  int dev = -1;
+  MRF_CHECK_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    MRF_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    MRF_REQUIRE(p, MRF_DEVICE, "subspace_coeffs_noalloc: no device address for the scratch array");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return MRF_OK;
+}
+}  // namespace
+
+extern "C" mrf_status mrf_subspace_coeffs_noalloc(const mrf_c64* X, const mrf_c64* V, int L, int Nv, int r,
+                                                  mrf_c64* alpha, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(X && V && alpha, MRF_INVALID_ARG, "subspace_coeffs_noalloc: null argument");
+  MRF_REQUIRE(L >= 1 && Nv >= 1 && r >= 1 && r <= kMaxR, MRF_INVALID_ARG, "subspace_coeffs_noalloc: bad sizes");
+  // the partial sums the reduction writes: chunks x r x Nv (what mrf_subspace_coeffs uses of its workspace)
+  const size_t need = (size_t)reduce_nch(L, Nv, true) * r * Nv * sizeof(cf);
+  MRF_REQUIRE(need <= kCoeffScratchBytes, MRF_WORKSPACE,
+              "subspace_coeffs_noalloc: the partial sums exceed the 16 MiB scratch array (chunks x r x Nv x 8 bytes)");
+  void* part = nullptr;
+  mrf_status e = scratch_address(&part);
+  if (e) return e;
+  return subspace_reduce((const cf*)X, nullptr, nullptr, (const cf*)V, L, Nv, r, (cf*)alpha, (cf*)part, s);
 }
 
 extern "C" mrf_status mrf_subspace_project(const mrf_c64* U, const mrf_c64* V, int L, int Nv, int r, mrf_c64* Z,

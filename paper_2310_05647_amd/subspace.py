@@ -22,6 +22,19 @@ def subspace_coeffs(X, V, stream=None):
     return out
 
 
+def subspace_coeffs_noalloc(X, V, out, stream=None):
+    """out [Nv, r] = X V through mrf_subspace_coeffs_noalloc (no workspace; the library's static
+    scratch array). The caller provides out."""
+    L = X.shape[0]
+    Nv = X[0].numel()
+    r = V.shape[1]
+    need(V, torch.complex64, (L, r), "V")
+    need(out, torch.complex64, (Nv, r), "out")
+    check(lib.mrf_subspace_coeffs_noalloc(ptr(X), ptr(V), L, Nv, r, ptr(out), stream_ptr(stream)),
+          "mrf_subspace_coeffs_noalloc")
+    return out
+
+
 def subspace_project(U, V, stream=None):
     """P_S(U) = U V V^H for U [L, ...] frame-major."""
     L = U.shape[0]
