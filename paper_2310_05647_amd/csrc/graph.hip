@@ -37,6 +37,17 @@ struct mrf_graph_s {
   double* scal;    // [4]: sigma2, lmax, nnz, positive distances
   double* part;    // [max quad-form blocks]
   size_t cap, npart;
+  // the Laplacian trace on cells (p = 2 s; see k_qc_lists): per cell the merged (Delta, weight)
+  // entries whose partner cell lies in the cell's LDS window, those outside it, and the diagonal
+  // weight; built with the CSR
+  bool qc;                // the geometry has the cell form
+  int* qc_cnt;            // [2][nslot] entry counts (in window, outside)
+  int* qc_ptr;            // [3][nslot + 1] exclusive scans of qc_cnt (the third is scratch)
+  int2* qc_in;            // [2 cap] (packed Delta, weight bits)
+  int2* qc_out;           // [2 cap]
+  float* qc_wd;           // [nslot]
+  int* qc_fslot;          // [nslot + 1]: slots with out-of-window entries, then their count
+  int nslot, ntx;         // slots (tile-major cells, border tiles padded) and tiles per side
 };
 
 namespace mrf {
@@ -626,6 +637,445 @@ __global__ __launch_bounds__(64 * kQuadWpb) void k_lap_quad_edges(const cf* __re
   if (lane == 0) part[(size_t)c * g.Np + i] = acc;
 }
 
+// ---------------------------------------------------------------- Laplacian trace on cells
+// For p = 2 s every patch is 2 x 2 cells of s x s pixels, and cell (cy, cx) of patch i (origin
+// cell (a, b)) is image cell (a + cy, b + cx). With Delta = origin(j) - origin(i) in cells,
+//   Tr(Q L Q^H) = sum_cells c [ Wd(c) ||x_c||^2 + 2 sum_{Delta > 0} Wc(c, Delta) Re<x_c, x_{c+Delta}> ],
+// Wd(c) = sum of L_ii over the patches i covering c, Wc(c, Delta) = sum of L_ij over the upper
+// entries (j > i) of those rows with origin(j) - origin(i) = Delta; <x_c, x_d> runs over the s^2
+// aligned pixels and all frames. Patches with similar neighbourhoods share (cell, Delta) pairs, so
+// this touches each distinct pixel pair once instead of once per edge (2.7 times fewer at 256 x 256,
+// K = 16). Cells are numbered tile-major ("slots": tile t of kQcTB x kQcTB cells, then the cell in
+// the tile), so a tile's entries are one contiguous segment. The trace kernel stages a tile's
+// window (the tile and a halo of kQcH cells) for kQcF frames at a time in LDS, with the tile's
+// entries; pairs whose partner lies outside the window are summed by a second kernel that reads
+// both cells from global memory.
+// Launch shapes (measured choices; each may be set with -D when tuning)
+#ifndef MRF_QC_TB
+#define MRF_QC_TB 8
+#endif
+#ifndef MRF_QC_H
+#define MRF_QC_H 4
+#endif
+#ifndef MRF_QC_F
+#define MRF_QC_F 2
+#endif
+#ifndef MRF_QC_STAGES
+#define MRF_QC_STAGES 8
+#endif
+#ifndef MRF_QC_WAVES
+#define MRF_QC_WAVES 8
+#endif
+#ifndef MRF_QC_MINB
+#define MRF_QC_MINB 2
+#endif
+#ifndef MRF_QC_FARBLOCKS
+#define MRF_QC_FARBLOCKS 16384
+#endif
+constexpr int kQcTB = MRF_QC_TB, kQcH = MRF_QC_H, kQcF = MRF_QC_F;   // tile and halo (cells), frames per stage
+constexpr int kQcStages = MRF_QC_STAGES;    // frame stages per trace block
+constexpr int kQcWaves = MRF_QC_WAVES;      // waves per trace block
+constexpr int kQcEcap = 1024;               // tile entries held in LDS (more are read from global memory)
+constexpr int kQcRcap = 128;                // row entries staged in LDS by the list builder (a multiple of 64)
+constexpr int kQcFarBlocks = MRF_QC_FARBLOCKS;
+
+__device__ inline int qc_pack(int dy, int dx) { return (dy << 16) | (dx & 0xffff); }
+__device__ inline int qc_dy(int k) { return k >> 16; }
+__device__ inline int qc_dx(int k) { return (int)(short)(k & 0xffff); }
+
+// slot -> cell coordinates (false for slots of border tiles that lie outside the image)
+__device__ inline bool qc_slot_cell(int slot, int nc, int ntx, int& cy, int& cx) {
+  const int tile = slot / (kQcTB * kQcTB), k = slot % (kQcTB * kQcTB);
+  cy = (tile / ntx) * kQcTB + k / kQcTB;
+  cx = (tile % ntx) * kQcTB + k % kQcTB;
+  return cy < nc && cx < nc;
+}
+
+// Whether cell (qy, qx) lies in the trace window of the tile that holds cell (cy, cx).
+__device__ inline bool qc_in_window(int cy, int cx, int qy, int qx) {
+  const int ty0 = (cy / kQcTB) * kQcTB, tx0 = (cx / kQcTB) * kQcTB;
+  return qy >= ty0 - kQcH && qy < ty0 + kQcTB + kQcH && qx >= tx0 - kQcH && qx < tx0 + kQcTB + kQcH;
+}
+
+// One wave per slot: the rows of the covering patches are staged in LDS with their merge keys
+// (up to kQcRcap entries each, all loads in flight together; a longer row's tail is read from
+// global memory), then lane 0 merges the off-diagonal entries of the four rows (columns ascending,
+// so the key Delta = origin(j) - origin(i) ascends lexicographically within a row); equal Delta
+// from several patches are summed in ascending patch order. A pair of cells {c, d = c + Delta}
+// (Delta > 0 from c's upper entries, Delta < 0 from its lower ones) is summed once, by the side
+// whose window holds the other cell: by c if d lies in c's window; otherwise by d if c lies in
+// d's window (d then holds it as its entry -Delta); otherwise by the out-of-window kernel, listed
+// under c. Each side decides from the same two window tests, and both sum the same L_ij in the
+// same order, so every pair is taken exactly once. COUNT: entry counts (in window, outside) and the
+// diagonal weight; otherwise the entries are written at the scanned offsets.
+template <bool COUNT>
+__global__ __launch_bounds__(256) void k_qc_lists(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                  const float* __restrict__ val, PatchGeom g, int ntx, int nslot,
+                                                  int* __restrict__ cnt, const int* __restrict__ ptr,
+                                                  int2* __restrict__ ent_in, int2* __restrict__ ent_out,
+                                                  float* __restrict__ wd, size_t cap2) {
+  constexpr int RPL = kQcRcap / 64;   // staged entries per lane and row
+  __shared__ int skey[4][4][kQcRcap];
+  __shared__ float sval[4][4][kQcRcap];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int slot = blockIdx.x * 4 + w;
+  if (slot >= nslot) return;                  // whole waves; no block barrier below
+  int cy, cx;
+  const bool live = qc_slot_cell(slot, g.nc, ntx, cy, cx);
+  const int M = 2 * g.n1;   // key = dy M + dx orders Delta lexicographically (|dx| < n1); 0 = diagonal
+  int pi[4], r0[4], r1[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int ay = cy - 1 + (k >> 1), bx = cx - 1 + (k & 1);
+    const bool on = live && ay >= 0 && bx >= 0 && ay < g.n1 && bx < g.n1;
+    pi[k] = on ? ay * g.n1 + bx : -1;
+    r0[k] = on ? rowptr[pi[k]] : 0;
+    r1[k] = on ? rowptr[pi[k] + 1] : 0;
+  }
+  int cv[4][RPL];
+  float vv[4][RPL];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int e = r0[k] + lane + 64 * r;
+      const bool in = e < r1[k];
+      cv[k][r] = in ? col[e] : -1;
+      vv[k][r] = in ? val[e] : 0.f;
+    }
+  float dg[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    float d = 0.f;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int j = cv[k][r];
+      const int key = j >= 0 ? (j / g.n1 - pi[k] / g.n1) * M + (j % g.n1 - pi[k] % g.n1) : 0x7fffffff;
+      skey[w][k][lane + 64 * r] = key;
+      sval[w][k][lane + 64 * r] = vv[k][r];
+      d += key == 0 ? vv[k][r] : 0.f;   // the diagonal (one lane of the row at most)
+    }
+    // the row's diagonal, whichever lane holds it (zero when it lies beyond the staged part)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o);
+    dg[k] = d;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (lane != 0) return;
+  if (COUNT)
+    for (int k = 0; k < 4; ++k)   // a diagonal beyond the staged part of a long row
+      if (pi[k] >= 0 && r1[k] - r0[k] > kQcRcap && dg[k] == 0.f) {
+        int lo = r0[k] + kQcRcap, hi = r1[k];
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (col[mid] < pi[k]) lo = mid + 1;
+          else hi = mid;
+        }
+        if (lo < r1[k] && col[lo] == pi[k]) dg[k] = val[lo];
+      }
+  int pos[4], end[4];
+  for (int k = 0; k < 4; ++k) {
+    pos[k] = 0;
+    end[k] = r1[k] - r0[k];
+  }
+  auto keyat = [&](int k) {
+    if (pos[k] < kQcRcap) return skey[w][k][pos[k]];
+    const int j = col[r0[k] + pos[k]];
+    return (j / g.n1 - pi[k] / g.n1) * M + (j % g.n1 - pi[k] % g.n1);
+  };
+  auto valat = [&](int k) { return pos[k] < kQcRcap ? sval[w][k][pos[k]] : val[r0[k] + pos[k]]; };
+  int nin = 0, nout = 0;
+  const int base_in = COUNT ? 0 : ptr[slot], base_out = COUNT ? 0 : ptr[nslot + 1 + slot];
+  while (true) {
+    int best = 0x7fffffff;
+    int keys[4];
+    for (int k = 0; k < 4; ++k) {
+      keys[k] = pi[k] >= 0 && pos[k] < end[k] ? keyat(k) : 0x7fffffff;
+      best = min(best, keys[k]);
+    }
+    if (best == 0x7fffffff) break;
+    float wsum = 0.f;
+    for (int k = 0; k < 4; ++k)
+      if (keys[k] == best) {
+        wsum += valat(k);
+        ++pos[k];
+      }
+    if (best == 0) continue;                  // the diagonal: Wd
+    const int dy = (best + g.n1 + M * g.n1) / M - g.n1, dx = best - dy * M;
+    const int ny = cy + dy, nx = cx + dx;
+    const bool mine = qc_in_window(cy, cx, ny, nx);        // the partner lies in this cell's window
+    const bool theirs = qc_in_window(ny, nx, cy, cx);      // this cell lies in the partner's window
+    int where;                                 // 0: in-window list, 1: out-of-window list, -1: not here
+    if (best > 0) where = mine ? 0 : (theirs ? -1 : 1);
+    else where = (!theirs && mine) ? 0 : -1;  // the partner owns the pair (upper side)
+    if (where < 0) continue;
+    if (!COUNT) {
+      // in-window entries carry the partner's offset in the trace kernel's LDS window (rows of
+      // (kQcTB + 2 kQcH) s + 2 pixels), out-of-window ones its offset in the image
+      const int wstr = (kQcTB + 2 * kQcH) * g.s + 2;
+      const int off = where == 0 ? (dy * wstr + dx) * g.s : (dy * g.N + dx) * g.s;
+      const int2 e = make_int2(off, __float_as_int(wsum));
+      if (where == 0) {
+        if ((size_t)(base_in + nin) < cap2) ent_in[base_in + nin] = e;
+      } else if ((size_t)(base_out + nout) < cap2) {
+        ent_out[base_out + nout] = e;
+      }
+    }
+    if (where == 0) ++nin;
+    else ++nout;
+  }
+  if (COUNT) {
+    cnt[slot] = nin;
+    cnt[nslot + slot] = nout;
+    wd[slot] = (dg[0] + dg[1]) + (dg[2] + dg[3]);
+  }
+}
+
+// One block: exclusive scans of the two count arrays [2][n] into ptr [2][n + 1], and the list of
+// slots with out-of-window entries (fslot, its length in *nfs).
+__global__ __launch_bounds__(1024) void k_qc_scan(const int* __restrict__ cnt, int n, int* __restrict__ ptr,
+                                                  int* __restrict__ fslot, int* __restrict__ nfs) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x, per = (n + 1023) / 1024;
+  for (int h = 0; h < 3; ++h) {
+    const int* cc = cnt + (size_t)(h == 0 ? 0 : n);
+    int* pp = ptr + (size_t)h * (n + 1);
+    int sum = 0;
+    for (int k = 0; k < per; ++k) {
+      const int i = t * per + k;
+      if (i < n) sum += h < 2 ? cc[i] : (cc[i] > 0);
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int v = t >= o ? part[t - o] : 0;
+      __syncthreads();
+      part[t] += v;
+      __syncthreads();
+    }
+    int run = t == 0 ? 0 : part[t - 1];
+    for (int k = 0; k < per; ++k) {
+      const int i = t * per + k;
+      if (i < n) {
+        if (h < 2) {
+          pp[i] = run;
+          run += cc[i];
+        } else if (cc[i] > 0) {
+          fslot[run++] = i;
+        }
+      }
+    }
+    if (t == 1023) {
+      if (h < 2) pp[n] = part[1023];
+      else nfs[0] = part[1023];
+    }
+    __syncthreads();
+  }
+}
+
+// Trace over in-window pairs. Block: one tile of kQcTB^2 cells and kQcStages x kQcF frames; the
+// tile's entries (up to kQcEcap) and, stage by stage, the window (tile + halo) of kQcF frames are
+// held in LDS (rows padded by S pixels so that the S rows of a cell fall in different banks).
+// Lanes: S^2 pixels x (64 / S^2) cells; each lane keeps its pixel of its cell for the kQcF frames
+// and runs over the cell's entries. Blocks are dealt to XCDs by frame chunk (chunk c on XCD c mod 8),
+// so the tiles of a chunk share an L2.
+template <int S>
+__global__ __launch_bounds__(64 * kQcWaves, MRF_QC_MINB) void k_qc_trace(const cf* __restrict__ X,
+                                                     const int* __restrict__ ptr,
+                                                     const int2* __restrict__ ent, const float* __restrict__ wd,
+                                                     PatchGeom g, int L, int ntx, int nfc, double* __restrict__ part) {
+  constexpr int NTHR = 64 * kQcWaves;
+  constexpr int WPX = (kQcTB + 2 * kQcH) * S;
+  // window row stride (pixels): a row is 2 (mod 8) 16-byte units longer than a multiple of 128
+  // bytes, so the 8 lanes of an LDS pass (4 cells x 2 rows, below) read 8 different bank groups
+  constexpr int STR = WPX + 2;
+  constexpr int NT = kQcTB * kQcTB;
+  constexpr int CPW = 64 / S;                             // cells per wave: one lane per cell row
+  constexpr int WPF = kQcWaves / kQcF;                    // waves per frame of a stage
+  static_assert(kQcWaves % kQcF == 0, "the waves split evenly over a stage's frames");
+  constexpr int STEPS = (NT + WPF * CPW - 1) / (WPF * CPW);
+  typedef typename PixVec<2>::T VT;                       // two pixels (16 bytes)
+  __shared__ __align__(16) cf win[kQcF][WPX][STR];
+  __shared__ int2 sent[kQcEcap];
+  __shared__ int lp[NT + 1];
+  __shared__ float swd[NT];
+  __shared__ double red[kQcWaves];
+  const int b = blockIdx.x;
+  const int ntile = ntx * ntx;
+  const int q = b >> 3;
+  const int tile = q % ntile;
+  const int fc = (q / ntile) * 8 + (b & 7);
+  if (fc >= nfc) {                                        // whole block, before any barrier
+    if (threadIdx.x == 0) part[b] = 0.0;                  // the sum covers every block's partial
+    return;
+  }
+  const int ty = tile / ntx, tx = tile % ntx;
+  const int wy0 = (ty * kQcTB - kQcH) * S, wx0 = (tx * kQcTB - kQcH) * S;
+  const int tp0 = ptr[tile * NT];
+  const int nent = ptr[tile * NT + NT] - tp0;
+  for (int t = threadIdx.x; t <= NT; t += NTHR) lp[t] = ptr[tile * NT + t] - tp0;
+  for (int t = threadIdx.x; t < NT; t += NTHR) swd[t] = wd[tile * NT + t];
+  for (int t = threadIdx.x; t < min(nent, kQcEcap); t += NTHR) sent[t] = ent[tp0 + t];
+  const size_t NN = (size_t)g.N * g.N;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int fsel = w / WPF, wf = w % WPF;                 // this wave's frame of the stage, and its rank there
+  // lane -> (cell of the wave, row of the cell): lanes 4m .. 4m + 3 hold four neighbouring cells
+  const int uy = (lane >> 2) % S, lc = (lane & 3) + 4 * (lane / (4 * S));
+  // window staging: float4 = two pixels (window columns start at even pixels: S even, N even).
+  // The loads of stage k + 1 are issued before the compute of stage k, so they are in flight
+  // while it runs.
+  constexpr int Q4 = WPX / 2;
+  constexpr int NTOT = kQcF * WPX * Q4;
+  constexpr int NLD = (NTOT + NTHR - 1) / NTHR;
+  const int nstage = min(kQcStages, (L - fc * kQcStages * kQcF + kQcF - 1) / kQcF);
+  // this thread's part of the window: frame, pixel offset in the frame (-1 outside the image) and
+  // LDS position of each of its NLD pixel pairs, the same for every stage
+  int gofs[NLD], lofs[NLD], fof[NLD];
+#pragma unroll
+  for (int r = 0; r < NLD; ++r) {
+    const int t = threadIdx.x + r * NTHR;
+    const int f = t / (WPX * Q4), rem = t % (WPX * Q4);
+    const int y = rem / Q4, x2 = (rem % Q4) * 2;
+    const int gy = wy0 + y, gx = wx0 + x2;
+    fof[r] = f;
+    gofs[r] = t < NTOT && gy >= 0 && gy < g.N && gx >= 0 && gx < g.N ? gy * g.N + gx : -1;
+    lofs[r] = (f * WPX + y) * STR + x2;
+  }
+  float4 v[NLD];
+  auto issue = [&](int stg) {
+    const int f0 = (fc * kQcStages + stg) * kQcF;
+    const cf* xf = X + (size_t)f0 * NN;
+#pragma unroll
+    for (int r = 0; r < NLD; ++r)
+      v[r] = gofs[r] >= 0 && f0 + fof[r] < L ? *reinterpret_cast<const float4*>(xf + (size_t)fof[r] * NN + gofs[r])
+                                            : make_float4(0.f, 0.f, 0.f, 0.f);
+  };
+  issue(0);
+  double acc = 0.0;
+  for (int stg = 0; stg < nstage; ++stg) {
+    const int f0 = (fc * kQcStages + stg) * kQcF;
+    __syncthreads();                                      // the previous stage's window is read
+#pragma unroll
+    for (int r = 0; r < NLD; ++r)
+      if (gofs[r] >= 0 && f0 + fof[r] < L) *reinterpret_cast<float4*>(&win[0][0][0] + lofs[r]) = v[r];
+    __syncthreads();
+    if (stg + 1 < nstage) issue(stg + 1);
+    // frames past L were not staged: their waves skip them, never multiplying by zero
+    if (f0 + fsel >= L) continue;
+    const cf* wbase = &win[fsel][0][0];
+    for (int st = 0; st < STEPS; ++st) {
+      const int k = (wf * STEPS + st) * CPW + lc;         // cell in the tile
+      const int tcy = k / kQcTB, tcx = k % kQcTB;
+      if (k >= NT || ty * kQcTB + tcy >= g.nc || tx * kQcTB + tcx >= g.nc) continue;
+      const int base = ((tcy + kQcH) * S + uy) * STR + (tcx + kQcH) * S;   // this lane's cell row
+      VT xa[S / 2];
+      float d = 0.f;
+#pragma unroll
+      for (int h = 0; h < S / 2; ++h) {
+        xa[h] = *reinterpret_cast<const VT*>(wbase + base + 2 * h);
+        d += PixVec<2>::dot(xa[h], xa[h]);
+      }
+      float off = 0.f;
+      const int e1 = lp[k + 1];
+      int e = lp[k];
+      // two entries per step: their window reads are in flight together
+      for (; e + 1 < e1; e += 2) {
+        const int2 ea = e < kQcEcap ? sent[e] : ent[tp0 + e];
+        const int2 eb = e + 1 < kQcEcap ? sent[e + 1] : ent[tp0 + e + 1];
+        float da = 0.f, db = 0.f;
+#pragma unroll
+        for (int h = 0; h < S / 2; ++h) {
+          const VT va = *reinterpret_cast<const VT*>(wbase + base + ea.x + 2 * h);
+          const VT vb = *reinterpret_cast<const VT*>(wbase + base + eb.x + 2 * h);
+          da += PixVec<2>::dot(xa[h], va);
+          db += PixVec<2>::dot(xa[h], vb);
+        }
+        off += __int_as_float(ea.y) * da;
+        off += __int_as_float(eb.y) * db;
+      }
+      if (e < e1) {
+        const int2 en = e < kQcEcap ? sent[e] : ent[tp0 + e];
+        float dot = 0.f;
+#pragma unroll
+        for (int h = 0; h < S / 2; ++h)
+          dot += PixVec<2>::dot(xa[h], *reinterpret_cast<const VT*>(wbase + base + en.x + 2 * h));
+        off += __int_as_float(en.y) * dot;
+      }
+      acc += (double)swd[k] * (double)d + 2.0 * (double)off;
+    }
+  }
+  acc = wave_sum_d(acc);
+  if (lane == 0) red[w] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < kQcWaves; ++k) t += red[k];
+    part[b] = t;
+  }
+}
+
+// Trace over the out-of-window pairs. Work items are (slot with such entries, chunk of
+// 128 / S^2 frames); XCD x (blocks b = x mod 8) takes the chunks c = x (mod 8), and its waves run
+// through all slots of one chunk before the next, so the frames in use fit the XCD's L2. Each
+// wave sums its items into one partial. Lanes: the S rows x S/2 pixel pairs of the cell x the
+// chunk's frames; a wave reads a batch of 64 entries with one load per lane and hands them round
+// by lane exchange.
+template <int S>
+__global__ __launch_bounds__(256) void k_qc_far(const cf* __restrict__ X, const int* __restrict__ ptr,
+                                                const int2* __restrict__ ent, const int* __restrict__ fslot,
+                                                const int* __restrict__ nfs, PatchGeom g, int L, int ntx,
+                                                double* __restrict__ part) {
+  typedef typename PixVec<2>::T VT;
+  constexpr int PPL = S * (S / 2);                        // pixel pairs of a cell
+  constexpr int FCH = 64 / PPL;                           // frames per chunk
+  const int lane = threadIdx.x & 63;
+  const int xcd = blockIdx.x & 7;
+  const int wl = (blockIdx.x >> 3) * 4 + (threadIdx.x >> 6);   // wave rank within its XCD
+  const int nwl = (gridDim.x >> 3) * 4;
+  const int nf = nfs[0];
+  const int nchunk = (L + FCH - 1) / FCH;
+  const int nchx = (nchunk - xcd + 7) / 8;                // chunks of this XCD
+  const int nitem = nf * nchx;
+  const int pp = lane % PPL, fl = lane / PPL;
+  const int uy = pp / (S / 2), h = pp % (S / 2);
+  const size_t NN = (size_t)g.N * g.N;
+  double acc = 0.0;
+  for (int it = wl; it < nitem; it += nwl) {
+    const int cq = it / nf, slot = fslot[it - cq * nf];
+    const int f = (xcd + 8 * cq) * FCH + fl;
+    int cy, cx;
+    qc_slot_cell(slot, g.nc, ntx, cy, cx);
+    const int pa = (cy * S + uy) * g.N + cx * S + 2 * h;   // this lane's pixel pair
+    const bool fv = f < L;
+    const VT xa = fv ? *reinterpret_cast<const VT*>(X + (size_t)f * NN + pa) : VT{};
+    float off = 0.f;
+    const int e0 = ptr[slot], e1 = ptr[slot + 1];
+    for (int eb = e0; eb < e1; eb += 64) {
+      const int2 mine = eb + lane < e1 ? ent[eb + lane] : make_int2(0, 0);
+      const int n = min(64, e1 - eb);
+      int m = 0;
+      for (; m + 1 < n; m += 2) {                         // two entries' loads in flight
+        const int pa_ = __shfl(mine.x, m), wa = __shfl(mine.y, m);
+        const int pb_ = __shfl(mine.x, m + 1), wb = __shfl(mine.y, m + 1);
+        if (fv) {
+          const VT va = *reinterpret_cast<const VT*>(X + (size_t)f * NN + pa + pa_);
+          const VT vb = *reinterpret_cast<const VT*>(X + (size_t)f * NN + pa + pb_);
+          off += __int_as_float(wa) * PixVec<2>::dot(xa, va);
+          off += __int_as_float(wb) * PixVec<2>::dot(xa, vb);
+        }
+      }
+      if (m < n) {
+        const int po = __shfl(mine.x, m), wv = __shfl(mine.y, m);
+        if (fv) off += __int_as_float(wv) * PixVec<2>::dot(xa, *reinterpret_cast<const VT*>(X + (size_t)f * NN + pa + po));
+      }
+    }
+    acc += 2.0 * (double)off;
+  }
+  acc = wave_sum_d(acc);
+  if (lane == 0) part[(size_t)xcd * nwl + wl] = acc;
+}
+
 // S_L applied to per-voxel subspace coefficients A[v][k] (k < r), voxel-major. Four threads per
 // voxel: thread q of a quad takes the covering patches q, q + 4, ... of the voxel's cell (in
 // raster order of (a, b)) and sums their rows of L; the quad's partial sums then meet by two
@@ -727,6 +1177,24 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 // -------------------------------------------------------------- internal entry points
 mrf_status sum_partials2(const double* part, long n, double* tmp, double* out, hipStream_t s);
 
+// Cell entry lists of the Laplacian trace from the current CSR (p = 2 s only).
+mrf_status qc_build(mrf_graph_s* G, hipStream_t s) {
+  if (!G->qc) return MRF_OK;
+  const PatchGeom& g = G->g;
+  const int n = G->nslot;
+  const size_t cap2 = 2 * G->cap;
+  int* nfs = G->qc_fslot + n;
+  MRF_LAUNCH("graph_qc_lists", s,
+             k_qc_lists<true><<<ceil_div(n, 4), 256, 0, s>>>(G->rowptr, G->col, G->val, g, G->ntx, n, G->qc_cnt, nullptr,
+                                                            nullptr, nullptr, G->qc_wd, cap2));
+  MRF_LAUNCH("graph_qc_lists", s, k_qc_scan<<<1, 1024, 0, s>>>(G->qc_cnt, n, G->qc_ptr, G->qc_fslot, nfs));
+  MRF_LAUNCH("graph_qc_lists", s,
+             k_qc_lists<false><<<ceil_div(n, 4), 256, 0, s>>>(G->rowptr, G->col, G->val, g, G->ntx, n, nullptr,
+                                                             G->qc_ptr, G->qc_in, G->qc_out, nullptr, cap2));
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+
 mrf_status graph_build(mrf_graph_s* G, const float* maps, int K, float sigma2, hipStream_t s) {
   const PatchGeom& g = G->g;
   const int nf = 3 * g.p * g.p;
@@ -760,7 +1228,7 @@ mrf_status graph_build(mrf_graph_s* G, const float* maps, int K, float sigma2, h
   MRF_LAUNCH("graph_csr_fill", s, k_csr_fill<<<g.Np, 256, 0, s>>>(G->W, G->deg, g.Np, G->rowptr, G->col, G->val));
   MRF_CHECK_LAUNCH();
   G->K = K;
-  return MRF_OK;
+  return qc_build(G, s);
 }
 
 int lap_frame_chunks(const PatchGeom& g, int L) {
@@ -779,6 +1247,30 @@ mrf_status lap_apply_full(const mrf_graph_s* G, const cf* X, cf* Y, int L, hipSt
 mrf_status lap_quad(mrf_graph_s* G, const cf* X, int L, double* out, hipStream_t s) {
   const PatchGeom& g = G->g;
   const int PP = g.p * g.p;
+  if (G->qc) {
+    const int ntx = G->ntx, n = G->nslot;
+    const int nfc = ceil_div(L, kQcStages * kQcF);
+    const int grid = 8 * ntx * ntx * ceil_div(nfc, 8);
+    const long nfar = 4L * kQcFarBlocks;
+    if ((size_t)(grid + nfar) <= G->npart && (reinterpret_cast<uintptr_t>(X) & 15) == 0) {   // float4 window loads
+      const int* pin = G->qc_ptr;
+      const int* pout = G->qc_ptr + n + 1;
+      const int* nfs = G->qc_fslot + n;
+#define MRF_QC(Sv)                                                                                              \
+  MRF_LAUNCH("lap_quad", s, k_qc_trace<Sv><<<grid, 64 * kQcWaves, 0, s>>>(X, pin, G->qc_in, G->qc_wd, g, L, ntx, nfc,  \
+                                                                         G->part));                             \
+  MRF_LAUNCH("lap_quad_far", s,                                                                                 \
+             k_qc_far<Sv><<<kQcFarBlocks, 256, 0, s>>>(X, pout, G->qc_out, G->qc_fslot, nfs, g, L, ntx, G->part + grid))
+      if (g.s == 4) {
+        MRF_QC(4);
+      } else {
+        MRF_QC(2);
+      }
+#undef MRF_QC
+      MRF_CHECK_LAUNCH();
+      return sum_partials2(G->part, grid + nfar, G->part + G->npart, out, s);
+    }
+  }
   if (PP == 64 || PP == 16) {
     const int fch = PP == 64 ? kQuadFch64 : kQuadFch16;
     const int nchunk = ceil_div(L, fch);
@@ -843,7 +1335,7 @@ mrf_status graph_set_csr(mrf_graph_s* G, const int* rowptr, const int* col, cons
   MRF_CHECK_HIP(hipMemcpyAsync(G->col, col, (size_t)nnz * 4, hipMemcpyDeviceToDevice, s));
   MRF_CHECK_HIP(hipMemcpyAsync(G->val, val, (size_t)nnz * 4, hipMemcpyDeviceToDevice, s));
   MRF_CHECK_HIP(hipMemcpyAsync(G->scal, scal, 4 * sizeof(double), hipMemcpyDeviceToDevice, s));
-  return MRF_OK;
+  return qc_build(G, s);
 }
 
 }  // namespace mrf
@@ -867,6 +1359,12 @@ extern "C" mrf_status mrf_graph_create(int n, int p, int s, int k_max, int max_f
   G->cap = (size_t)g.Np * (2 * k_max + 1);
   G->npart = std::max((size_t)g.nc * g.nc * lap_frame_chunks(g, max_frames),
                       (size_t)g.Np * ceil_div(max_frames, 4));
+  {  // partials of the cell form of the trace: one per trace block and per out-of-window wave
+    const int ntx = ceil_div(g.nc, kQcTB);
+    const size_t qc_part = (size_t)8 * ntx * ntx * ceil_div(ceil_div(max_frames, kQcStages * kQcF), 8) +
+                           4 * (size_t)kQcFarBlocks;
+    G->npart = std::max(G->npart, qc_part);
+  }
   bool ok = hipMalloc(&G->F, (size_t)g.Np * G->nf * 4) == hipSuccess &&
             hipMalloc(&G->knn, (size_t)g.Np * k_max * 4) == hipSuccess &&
             hipMalloc(&G->knd2, (size_t)g.Np * k_max * 4) == hipSuccess &&
@@ -876,6 +1374,19 @@ extern "C" mrf_status mrf_graph_create(int n, int p, int s, int k_max, int max_f
             hipMalloc(&G->cnt, (size_t)g.Np * 4) == hipSuccess && hipMalloc(&G->deg, (size_t)g.Np * 4) == hipSuccess &&
             hipMalloc(&G->mx, 16) == hipSuccess && hipMalloc(&G->scal, 4 * sizeof(double)) == hipSuccess &&
             hipMalloc(&G->part, (G->npart + 256) * sizeof(double)) == hipSuccess;
+  // the cell form of the trace: cells of s x s pixels with p = 2 s, s in {2, 4}, N even
+  G->qc = p == 2 * s && (s == 2 || s == 4) && n % 2 == 0;
+  if (ok && G->qc) {
+    G->ntx = ceil_div(g.nc, kQcTB);
+    G->nslot = G->ntx * G->ntx * kQcTB * kQcTB;
+    const size_t ns = (size_t)G->nslot;
+    ok = hipMalloc(&G->qc_cnt, 2 * ns * sizeof(int)) == hipSuccess &&
+         hipMalloc(&G->qc_ptr, 3 * (ns + 1) * sizeof(int)) == hipSuccess &&
+         hipMalloc(&G->qc_in, 2 * G->cap * sizeof(int2)) == hipSuccess &&
+         hipMalloc(&G->qc_out, 2 * G->cap * sizeof(int2)) == hipSuccess &&
+         hipMalloc(&G->qc_wd, ns * sizeof(float)) == hipSuccess &&
+         hipMalloc(&G->qc_fslot, (ns + 1) * sizeof(int)) == hipSuccess;
+  }
   if (!ok) {
     mrf_graph_destroy(G);
     return fail(MRF_OOM, "graph_create: device allocation failed");
@@ -889,6 +1400,8 @@ extern "C" mrf_status mrf_graph_destroy(mrf_graph_t G) {
   if (!G) return MRF_OK;
   hipFree(G->F); hipFree(G->knn); hipFree(G->knd2); hipFree(G->W); hipFree(G->rowptr); hipFree(G->col);
   hipFree(G->val); hipFree(G->cnt); hipFree(G->deg); hipFree(G->mx); hipFree(G->scal); hipFree(G->part);
+  hipFree(G->qc_cnt); hipFree(G->qc_ptr); hipFree(G->qc_in); hipFree(G->qc_out); hipFree(G->qc_wd);
+  hipFree(G->qc_fslot);
   delete G;
   return MRF_OK;
 }

@@ -139,3 +139,22 @@ def test_quad_with_hub_rows_matches_oracle(zero_rows):
     say(f"  hub rows: longest upper row {upper}; quad rel {abs(q - qref) / abs(qref):.2e}")
     assert upper > 64
     assert abs(q - qref) <= 1e-5 * abs(qref)
+
+
+def test_quad_on_smooth_256_maps_matches_oracle():
+    """The graph of the 256 x 256 workload's maps (8 x 8 patches at stride 4, K = 16; mostly local
+    edges, so most cell pairs meet inside the trace kernel's LDS window and the rest take the
+    out-of-window kernel), 13 frames (a ragged last frame group): the trace against
+    Re<X, Q*(Q(X) L)> formed by the oracle with the GPU's own L."""
+    import os
+    f = np.load(os.path.join(os.path.dirname(__file__), "golden", "c2_two_iterations.npz"))
+    maps = f["maps"].astype(np.float32)
+    g, Lg, inf = _gpu_graph(maps, 8, 4, 16)
+    rng = np.random.default_rng(256)
+    N, L = 256, 13
+    X = (rng.standard_normal((L, N, N)) + 1j * rng.standard_normal((L, N, N))).astype(np.complex64)
+    q = float(g.quad(to_dev(X)).cpu().numpy()[0])
+    import scipy.sparse as sp
+    qref = float(np.vdot(X.astype(np.complex128), oops.laplacian_apply(X, sp.csr_matrix(Lg), 8, 4)).real)
+    say(f"  256 x 256 maps: quad rel {abs(q - qref) / abs(qref):.2e}")
+    assert abs(q - qref) <= 1e-5 * abs(qref)
