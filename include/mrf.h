@@ -219,7 +219,8 @@ typedef enum mrf_match_mode {
   MRF_MATCH_FP32 = 0,
   MRF_MATCH_BF16_RERANK4 = 1,
   MRF_MATCH_FP8_RERANK4 = 2,
-  MRF_MATCH_LEARNED = 3
+  MRF_MATCH_LEARNED = 3,
+  MRF_MATCH_SUBSPACE = 4   /* the subspace match of mrf_dict_match_subspace (only as a final match of mrf_recon) */
 } mrf_match_mode;
 
 /* Workspace bytes of mrf_dict_match for Nv fingerprints (FP32 / BF16 / FP8 modes). */
@@ -285,6 +286,13 @@ mrf_status mrf_mlp_set_grid(mrf_mlp_t mlp, int n1, double log_t1_0, double dlog_
  * stats_host [4] = (mean1, mean2, std1, std2) if not NULL (synchronises then). */
 mrf_status mrf_mlp_target_stats(mrf_mlp_t mlp, mrf_dict_t d, double* stats_host, hipStream_t stream);
 mrf_status mrf_mlp_train_workspace_size(mrf_mlp_t mlp, int batch, size_t* bytes);
+/* The network's state: parameters, Adam moments and step count, target scaling and the gate's
+ * grid. mrf_mlp_state_bytes gives the size; save writes it to buf (host or device memory) and
+ * synchronises; load restores it into a network of the same architecture (MRF_SHAPE otherwise),
+ * so that inference, and training continued from it, give what the saved network gives. */
+mrf_status mrf_mlp_state_bytes(mrf_mlp_t mlp, size_t* bytes);
+mrf_status mrf_mlp_save(mrf_mlp_t mlp, void* buf, size_t bytes, hipStream_t stream);
+mrf_status mrf_mlp_load(mrf_mlp_t mlp, const void* buf, size_t bytes, hipStream_t stream);
 /* One synthetic batch: z [batch][n_in], t [batch][2] (standardised targets), m [batch] or NULL. */
 mrf_status mrf_mlp_synth(mrf_mlp_t mlp, mrf_dict_t d, uint64_t seed, int step, int batch, float snr_lo, float snr_hi,
                          float* z, float* t, int32_t* m, hipStream_t stream);
@@ -349,6 +357,8 @@ typedef struct mrf_recon_stats {
   double lam1[MRF_MAX_ITERS + 1];
   double sigma2[MRF_MAX_ITERS + 1];
   double lmax[MRF_MAX_ITERS + 1];
+  double iter_ms[MRF_MAX_ITERS + 1]; /* host wall time of iteration n (1 .. iters): from its first
+                                        enqueued kernel to its cost on the host; [0]: initialisation */
 } mrf_recon_stats;
 
 typedef struct mrf_recon_s* mrf_recon_t;
@@ -387,6 +397,25 @@ mrf_status mrf_recon_finish(mrf_recon_t r, mrf_c64* X_out, float* maps, int32_t*
  * the graph's capacity (Np (2 K + 1)). */
 mrf_status mrf_recon_inject_graph(mrf_recon_t r, int k, int nnz, const int* rowptr, const int* col, const float* val,
                                   double sigma2, double lmax);
+/* The final match Phi_D(X^) of Algorithm 1 (mrf_recon_finish and mrf_recon): MRF_MATCH_SUBSPACE
+ * (default; the subspace match used inside the loop), MRF_MATCH_FP32 / _BF16_RERANK4 /
+ * _FP8_RERANK4 (the full-length match of mrf_dict_match on X^'s voxel time courses), or
+ * MRF_MATCH_LEARNED (mrf_mlp_match on X^ V with gate threshold theta; mlp must have its grid set
+ * and be trained for the dictionary's basis). maps [3][n][n] then hold (T1, T2) of the chosen
+ * match and PD = rho. Allocates the work buffers the mode needs (recon-owned; replaced by a later
+ * call, freed by mrf_recon_destroy) and synchronises. With MRF_MATCH_LEARNED, mrf_recon_finish
+ * synchronises once (the fallback count). */
+mrf_status mrf_recon_set_final_match(mrf_recon_t r, mrf_match_mode mode, mrf_mlp_t mlp, float theta);
+/* Checkpoint of a run between iterations (after mrf_recon_init or mrf_recon_iterate): X^n, the
+ * residual A X^n - b, the eigen-analysis of Q(X^n) that the next SVT uses, the device scalars,
+ * the statistics and the stopping state. mrf_recon_checkpoint_bytes gives the size; save writes it
+ * to buf (host or device memory, at least that many bytes) and synchronises `stream`. load
+ * restores it into a recon created with the same parameters, plan and dictionary (checked against
+ * the sizes recorded in buf; MRF_SHAPE otherwise), with the measurements b of the run; the
+ * iterations that follow give bit-for-bit the same results as the uninterrupted run. */
+mrf_status mrf_recon_checkpoint_bytes(mrf_recon_t r, size_t* bytes);
+mrf_status mrf_recon_checkpoint_save(mrf_recon_t r, void* buf, size_t bytes, hipStream_t stream);
+mrf_status mrf_recon_checkpoint_load(mrf_recon_t r, const mrf_c64* b, const void* buf, size_t bytes, hipStream_t stream);
 /* Copies the statistics of the run so far (host struct). */
 mrf_status mrf_recon_get_stats(mrf_recon_t r, mrf_recon_stats* out);
 /* The whole of Algorithm 1: init + iterate(n_max) + finish; stats may be NULL. */

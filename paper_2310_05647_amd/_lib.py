@@ -40,7 +40,8 @@ _D = ctypes.c_double * (MAX_ITERS + 1)
 
 class ReconStats(ctypes.Structure):
     _fields_ = [("iters", c_int), ("stop_reason", c_int), ("n_graph", c_int), ("cost", _D), ("data", _D),
-                ("tr", _D), ("nuc", _D), ("mu", _D), ("lam1", _D), ("sigma2", _D), ("lmax", _D)]
+                ("tr", _D), ("nuc", _D), ("mu", _D), ("lam1", _D), ("sigma2", _D), ("lmax", _D),
+                ("iter_ms", _D)]
 
 
 def _decl(name, args, res=c_int):
@@ -96,6 +97,9 @@ _decl("mrf_mlp_set_grid", [c_void_p, c_int, ctypes.c_double, ctypes.c_double, c_
                            c_void_p, c_void_p])
 _decl("mrf_mlp_target_stats", [c_void_p, c_void_p, c_void_p, c_void_p])
 _decl("mrf_mlp_train_workspace_size", [c_void_p, c_int, P(c_size_t)])
+_decl("mrf_mlp_state_bytes", [c_void_p, P(c_size_t)])
+_decl("mrf_mlp_save", [c_void_p, c_void_p, c_size_t, c_void_p])
+_decl("mrf_mlp_load", [c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_mlp_synth", [c_void_p, c_void_p, _u64, c_int, c_int, c_float, c_float, c_void_p, c_void_p, c_void_p, c_void_p])
 _decl("mrf_mlp_forward", [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_mlp_grads", [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_size_t, c_void_p])
@@ -112,6 +116,10 @@ _decl("mrf_recon_iterate", [c_void_p, c_int, P(c_int), c_void_p])
 _decl("mrf_recon_set_serial", [c_void_p, c_int])
 _decl("mrf_recon_finish", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p])
 _decl("mrf_recon_get_stats", [c_void_p, P(ReconStats)])
+_decl("mrf_recon_set_final_match", [c_void_p, c_int, c_void_p, c_float])
+_decl("mrf_recon_checkpoint_bytes", [c_void_p, P(c_size_t)])
+_decl("mrf_recon_checkpoint_save", [c_void_p, c_void_p, c_size_t, c_void_p])
+_decl("mrf_recon_checkpoint_load", [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_recon_inject_graph", [c_void_p, c_int, c_int, P(c_int), P(c_int), P(c_float), ctypes.c_double,
                                  ctypes.c_double])
 _decl("mrf_recon", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, P(ReconStats), c_void_p])

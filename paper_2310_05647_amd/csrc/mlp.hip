@@ -819,3 +819,104 @@ extern "C" mrf_status mrf_mlp_match(mrf_mlp_t P, mrf_dict_t D, const mrf_c64* al
   }
   return MRF_OK;
 }
+
+// ------------------------------------------------------------------ save / load
+namespace {
+struct MlpHeader {
+  uint64_t magic;
+  int version, nin, hid, nhl, nout, t, have_stats, n1, n2, gmax, pad;
+  uint64_t np;
+  double l1_0, dl1, l2_0, dl2;
+};
+constexpr uint64_t kMlpMagic = 0x4d52464d4c507631ull;   // "MRFMLPv1"
+size_t mal(size_t b) { return (b + 255) & ~(size_t)255; }
+struct MlpLayout {
+  size_t p, m, v, stats, gidx, i2max, total;
+};
+MlpLayout mlp_layout(const mrf_mlp_s* P) {
+  MlpLayout c;
+  c.p = mal(sizeof(MlpHeader));
+  c.m = c.p + mal(P->np * 4);
+  c.v = c.m + mal(P->np * 4);
+  c.stats = c.v + mal(P->np * 4);
+  c.gidx = c.stats + mal(32);
+  c.i2max = c.gidx + mal((size_t)P->n1 * P->n2 * 4);
+  c.total = c.i2max + mal((size_t)P->n1 * 4);
+  return c;
+}
+}  // namespace
+
+extern "C" mrf_status mrf_mlp_state_bytes(mrf_mlp_t P, size_t* bytes) {
+  clear_error();
+  MRF_REQUIRE(P && bytes, MRF_INVALID_ARG, "mlp_state_bytes: null argument");
+  *bytes = mlp_layout(P).total;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_mlp_save(mrf_mlp_t P, void* buf, size_t bytes, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(P && buf, MRF_INVALID_ARG, "mlp_save: null argument");
+  const MlpLayout c = mlp_layout(P);
+  MRF_REQUIRE(bytes >= c.total, MRF_WORKSPACE, "mlp_save: buffer smaller than mrf_mlp_state_bytes");
+  MlpHeader h{};
+  h.magic = kMlpMagic;
+  h.version = 1;
+  h.nin = P->nin; h.hid = P->hid; h.nhl = P->nhl; h.nout = P->nout; h.t = P->t; h.have_stats = P->have_stats;
+  h.n1 = P->gidx ? P->n1 : 0; h.n2 = P->gidx ? P->n2 : 0; h.gmax = P->gmax; h.np = P->np;
+  h.l1_0 = P->l1_0; h.dl1 = P->dl1; h.l2_0 = P->l2_0; h.dl2 = P->dl2;
+  char* o = (char*)buf;
+  MRF_CHECK_HIP(hipMemcpyAsync(o + c.p, P->p, P->np * 4, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(o + c.m, P->m, P->np * 4, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(o + c.v, P->v, P->np * 4, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(o + c.stats, P->stats, 32, hipMemcpyDefault, s));
+  if (h.n1) {
+    MRF_CHECK_HIP(hipMemcpyAsync(o + c.gidx, P->gidx, (size_t)h.n1 * h.n2 * 4, hipMemcpyDefault, s));
+    MRF_CHECK_HIP(hipMemcpyAsync(o + c.i2max, P->i2max, (size_t)h.n1 * 4, hipMemcpyDefault, s));
+  }
+  MRF_CHECK_HIP(hipStreamSynchronize(s));
+  MRF_CHECK_HIP(hipMemcpy(o, &h, sizeof h, hipMemcpyDefault));
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_mlp_load(mrf_mlp_t P, const void* buf, size_t bytes, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(P && buf, MRF_INVALID_ARG, "mlp_load: null argument");
+  MlpHeader h{};
+  const char* o = (const char*)buf;
+  MRF_REQUIRE(bytes >= sizeof h, MRF_WORKSPACE, "mlp_load: buffer too small");
+  MRF_CHECK_HIP(hipMemcpy(&h, o, sizeof h, hipMemcpyDefault));
+  MRF_REQUIRE(h.magic == kMlpMagic && h.version == 1, MRF_INVALID_ARG, "mlp_load: not a saved MLP");
+  MRF_REQUIRE(h.nin == P->nin && h.hid == P->hid && h.nhl == P->nhl && h.nout == P->nout && h.np == P->np, MRF_SHAPE,
+              "mlp_load: the saved network's architecture differs from this one");
+  // the layout with the saved grid's size
+  const int n1 = P->n1, n2 = P->n2;
+  P->n1 = h.n1;
+  P->n2 = h.n2;
+  const MlpLayout c = mlp_layout(P);
+  P->n1 = n1;
+  P->n2 = n2;
+  MRF_REQUIRE(bytes >= c.total, MRF_WORKSPACE, "mlp_load: buffer smaller than the saved state");
+  MRF_CHECK_HIP(hipMemcpyAsync(P->p, o + c.p, P->np * 4, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(P->m, o + c.m, P->np * 4, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(P->v, o + c.v, P->np * 4, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(P->stats, o + c.stats, 32, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipStreamSynchronize(s));
+  if (h.n1) {
+    int *gi = nullptr, *mx = nullptr;
+    if (hipMalloc(&gi, (size_t)h.n1 * h.n2 * 4) != hipSuccess || hipMalloc(&mx, (size_t)h.n1 * 4) != hipSuccess) {
+      hipFree(gi);
+      return fail(MRF_OOM, "mlp_load: device allocation failed");
+    }
+    MRF_CHECK_HIP(hipMemcpy(gi, o + c.gidx, (size_t)h.n1 * h.n2 * 4, hipMemcpyDefault));
+    MRF_CHECK_HIP(hipMemcpy(mx, o + c.i2max, (size_t)h.n1 * 4, hipMemcpyDefault));
+    hipFree(P->gidx);
+    hipFree(P->i2max);
+    P->gidx = gi;
+    P->i2max = mx;
+    P->n1 = h.n1; P->n2 = h.n2; P->gmax = h.gmax;
+    P->l1_0 = h.l1_0; P->dl1 = h.dl1; P->l2_0 = h.l2_0; P->dl2 = h.dl2;
+  }
+  P->t = h.t;
+  P->have_stats = h.have_stats != 0;
+  return MRF_OK;
+}

@@ -17,10 +17,13 @@
 // (the exact minimiser of eq. (21) for overlapping patches); mu = min(mu0, 1/(lamA + 2 c_max
 // lambda1 max(L))) with lamA a bound on lambda_max(A^H A) (mu = mu0 when lamA <= 0).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "common.hpp"
+#include "dict.hpp"
 #include "patch.hpp"
 
 namespace mrf {
@@ -87,6 +90,16 @@ __global__ void k_cost(double* __restrict__ sc, double lam2) {
   sc[SC_COST] = 0.5 * sc[SC_RN2] + sc[SC_LAM1] * sc[SC_QUAD] + lam2 * sc[SC_NUC];
 }
 
+// maps [3][Nv] = (T1, T2) from per-voxel parameter rows (stride np) and PD = rho
+__global__ void k_maps_params(const float* __restrict__ prm, int np, const float* __restrict__ rho, int Nv,
+                              float* __restrict__ maps) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= Nv) return;
+  maps[v] = prm[(size_t)v * np];
+  maps[Nv + v] = prm[(size_t)v * np + 1];
+  maps[2 * Nv + v] = rho[v];
+}
+
 __global__ void k_copy_c(const cf* __restrict__ a, cf* __restrict__ b, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) b[i] = a[i];
 }
@@ -127,6 +140,14 @@ struct mrf_recon_s {
     double* scal;
   };
   std::vector<Injected> inj;
+  // the final match (mrf_recon_set_final_match)
+  int fin_mode = MRF_MATCH_SUBSPACE;
+  mrf_mlp_t fin_mlp = nullptr;
+  float fin_theta = 0.f;
+  void* fin_ws = nullptr;
+  size_t fin_ws_bytes = 0;
+  float* fin_prm = nullptr;     // [Nv][nparam] (full-length modes) or [Nv][2] (learned)
+  std::chrono::steady_clock::time_point t_step;   // enqueue time of the iteration in flight
 };
 
 namespace {
@@ -308,6 +329,8 @@ extern "C" mrf_status mrf_recon_destroy(mrf_recon_t R) {
   for (auto& g : R->inj) {
     hipFree(g.rowptr); hipFree(g.col); hipFree(g.val); hipFree(g.scal);
   }
+  hipFree(R->fin_ws);
+  hipFree(R->fin_prm);
   if (R->hsc) hipHostFree(R->hsc);
   mrf_graph_destroy(R->graph);
   delete R;
@@ -317,6 +340,7 @@ extern "C" mrf_status mrf_recon_destroy(mrf_recon_t R) {
 extern "C" mrf_status mrf_recon_init(mrf_recon_t R, const mrf_c64* b, const mrf_c64* X0, hipStream_t s) {
   clear_error();
   MRF_REQUIRE(R && b, MRF_INVALID_ARG, "recon_init: null argument");
+  const auto t0 = std::chrono::steady_clock::now();
   R->b = (const cf*)b;
   R->st = mrf_recon_stats{};
   R->pending_graph = false;
@@ -334,6 +358,7 @@ extern "C" mrf_status mrf_recon_init(mrf_recon_t R, const mrf_c64* b, const mrf_
   record_graph(R, h);
   R->c_prev = h[SC_COST];
   R->initialised = true;
+  R->st.iter_ms[0] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return MRF_OK;
 }
 
@@ -345,6 +370,7 @@ bool active(const mrf_recon_s* R) { return R->st.stop_reason == 0 && R->st.iters
 // with the projection (eqs. (15), (17)), the SVT of Q(X^n) from the previous eigen-analysis and
 // the X update (eq. (23)), and the cost of X^{n+1}, whose terms are copied to the host.
 mrf_status enqueue_step(mrf_recon_s* R, hipStream_t s) {
+  R->t_step = std::chrono::steady_clock::now();
   const int L = R->L, Nv = R->Nv, r = R->r, rc = R->prm.rank_cap;
   const cf* V = dict_basis(R->dict);
   mrf_status e;
@@ -382,6 +408,9 @@ mrf_status complete_step(mrf_recon_s* R, hipStream_t s) {
   R->pending_graph = false;
   R->st.iters += 1;
   record(R, h, false);
+  if (R->st.iters <= MRF_MAX_ITERS)
+    R->st.iter_ms[R->st.iters] =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - R->t_step).count();
   const double c = h[SC_COST];
   if (R->prm.tol >= 0.0 && R->c_prev / c - 1.0 < R->prm.tol) {
     R->st.stop_reason = 1;
@@ -447,9 +476,28 @@ extern "C" mrf_status mrf_recon_finish(mrf_recon_t R, mrf_c64* X_out, float* map
   MRF_REQUIRE(R && R->initialised, MRF_INVALID_ARG, "recon_finish: call mrf_recon_init first");
   mrf_status e;
   const cf* V = dict_basis(R->dict);
-  if ((e = subspace_reduce(R->X, nullptr, nullptr, V, R->L, R->Nv, R->r, R->aX, (cf*)R->rws, s))) return e;
-  if ((e = match_subspace(R->dict, R->aX, R->Nv, R->idx, R->rho, nullptr, nullptr, s))) return e;
-  if ((e = maps_from_match(R->dict, R->idx, R->rho, R->Nv, R->maps, s))) return e;
+  const int Nv = R->Nv;
+  if (R->fin_mode == MRF_MATCH_SUBSPACE || R->fin_mode == MRF_MATCH_LEARNED)
+    if ((e = subspace_reduce(R->X, nullptr, nullptr, V, R->L, Nv, R->r, R->aX, (cf*)R->rws, s))) return e;
+  if (R->fin_mode == MRF_MATCH_SUBSPACE) {
+    if ((e = match_subspace(R->dict, R->aX, Nv, R->idx, R->rho, nullptr, nullptr, s))) return e;
+    if ((e = maps_from_match(R->dict, R->idx, R->rho, Nv, R->maps, s))) return e;
+  } else if (R->fin_mode == MRF_MATCH_LEARNED) {
+    int nfb = 0;
+    if ((e = mrf_mlp_match(R->fin_mlp, R->dict, (const mrf_c64*)R->aX, Nv, 0, R->fin_theta, R->idx, R->fin_prm, R->rho,
+                           nullptr, nullptr, &nfb, R->fin_ws, R->fin_ws_bytes, s)))
+      return e;
+    MRF_LAUNCH("recon_maps", s, k_maps_params<<<ceil_div(Nv, 256), 256, 0, s>>>(R->fin_prm, 2, R->rho, Nv, R->maps));
+  } else {
+    // X^ to voxel-major time courses in the gradient buffer (free once the iterations are done)
+    if ((e = mrf_frames_to_voxels((const mrf_c64*)R->X, R->L, Nv, (mrf_c64*)R->ZG, s))) return e;
+    if ((e = mrf_dict_match(R->dict, (const mrf_c64*)R->ZG, Nv, (mrf_match_mode)R->fin_mode, R->idx, R->rho, nullptr,
+                            R->fin_prm, nullptr, R->fin_ws, R->fin_ws_bytes, s)))
+      return e;
+    MRF_LAUNCH("recon_maps", s,
+               k_maps_params<<<ceil_div(Nv, 256), 256, 0, s>>>(R->fin_prm, R->dict->nparam, R->rho, Nv, R->maps));
+  }
+  MRF_CHECK_LAUNCH();
   if (X_out) MRF_CHECK_HIP(hipMemcpyAsync(X_out, R->X, (size_t)R->L * R->Nv * 8, hipMemcpyDeviceToDevice, s));
   if (maps) MRF_CHECK_HIP(hipMemcpyAsync(maps, R->maps, (size_t)3 * R->Nv * 4, hipMemcpyDeviceToDevice, s));
   if (idx) MRF_CHECK_HIP(hipMemcpyAsync(idx, R->idx, (size_t)R->Nv * 4, hipMemcpyDeviceToDevice, s));
@@ -496,6 +544,134 @@ extern "C" mrf_status mrf_recon_inject_graph(mrf_recon_t R, int k, int nnz, cons
       return MRF_OK;
     }
   R->inj.push_back(g);
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_recon_set_final_match(mrf_recon_t R, mrf_match_mode mode, mrf_mlp_t mlp, float theta) {
+  clear_error();
+  MRF_REQUIRE(R, MRF_INVALID_ARG, "recon_set_final_match: null handle");
+  MRF_REQUIRE(mode == MRF_MATCH_SUBSPACE || mode == MRF_MATCH_FP32 || mode == MRF_MATCH_BF16_RERANK4 ||
+                  mode == MRF_MATCH_FP8_RERANK4 || mode == MRF_MATCH_LEARNED,
+              MRF_INVALID_ARG, "recon_set_final_match: unknown mode");
+  MRF_REQUIRE(mode != MRF_MATCH_LEARNED || mlp, MRF_INVALID_ARG, "recon_set_final_match: the learned mode needs an MLP");
+  MRF_REQUIRE(theta == theta, MRF_INVALID_ARG, "recon_set_final_match: theta is NaN");
+  size_t ws = 0, prm = 0;
+  if (mode == MRF_MATCH_LEARNED) {
+    mrf_status e = mrf_mlp_match_workspace_size(mlp, R->Nv, &ws);
+    if (e) return e;
+    prm = (size_t)R->Nv * 2 * sizeof(float);
+  } else if (mode != MRF_MATCH_SUBSPACE) {
+    mrf_status e = mrf_dict_match_workspace_size(R->dict, R->Nv, mode, &ws);
+    if (e) return e;
+    prm = (size_t)R->Nv * R->dict->nparam * sizeof(float);
+  }
+  MRF_CHECK_HIP(hipDeviceSynchronize());   // the previous buffers may still be in use
+  hipFree(R->fin_ws);
+  hipFree(R->fin_prm);
+  R->fin_ws = nullptr;
+  R->fin_prm = nullptr;
+  R->fin_ws_bytes = 0;
+  R->fin_mode = MRF_MATCH_SUBSPACE;
+  if ((ws && hipMalloc(&R->fin_ws, ws) != hipSuccess) || (prm && hipMalloc((void**)&R->fin_prm, prm) != hipSuccess)) {
+    hipFree(R->fin_ws);
+    R->fin_ws = nullptr;
+    return fail(MRF_OOM, "recon_set_final_match: device allocation failed");
+  }
+  R->fin_ws_bytes = ws;
+  R->fin_mode = mode;
+  R->fin_mlp = mlp;
+  R->fin_theta = theta;
+  return MRF_OK;
+}
+
+namespace {
+// checkpoint: a header (sizes for the check on load, stopping state, statistics), then the arrays
+struct CkptHeader {
+  uint64_t magic;
+  int version, N, L, Ns, Np, rcap, pp, r, pending, pad;
+  double c_prev;
+  mrf_recon_stats st;
+};
+constexpr uint64_t kCkptMagic = 0x4d52464c4c52636bull;   // "MRFLLRck"
+size_t ck_al(size_t b) { return (b + 255) & ~(size_t)255; }
+struct CkptLayout {
+  size_t x, res, u, f, sc, total;
+};
+CkptLayout ckpt_layout(const mrf_recon_s* R) {
+  CkptLayout c;
+  const size_t pp = (size_t)R->prm.p * R->prm.p, np = R->g.Np, rc = R->prm.rank_cap;
+  c.x = ck_al(sizeof(CkptHeader));
+  c.res = c.x + ck_al((size_t)R->L * R->Nv * 8);
+  c.u = c.res + ck_al((size_t)R->L * R->Ns * 8);
+  c.f = c.u + ck_al(np * rc * pp * 8);
+  c.sc = c.f + ck_al(np * rc * 4);
+  c.total = c.sc + ck_al(SC_N * 8);
+  return c;
+}
+}  // namespace
+
+extern "C" mrf_status mrf_recon_checkpoint_bytes(mrf_recon_t R, size_t* bytes) {
+  clear_error();
+  MRF_REQUIRE(R && bytes, MRF_INVALID_ARG, "recon_checkpoint_bytes: null argument");
+  *bytes = ckpt_layout(R).total;
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_recon_checkpoint_save(mrf_recon_t R, void* buf, size_t bytes, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(R && buf, MRF_INVALID_ARG, "recon_checkpoint_save: null argument");
+  MRF_REQUIRE(R->initialised, MRF_INVALID_ARG, "recon_checkpoint_save: call mrf_recon_init first");
+  const CkptLayout c = ckpt_layout(R);
+  MRF_REQUIRE(bytes >= c.total, MRF_WORKSPACE, "recon_checkpoint_save: buffer smaller than mrf_recon_checkpoint_bytes");
+  CkptHeader h{};
+  h.magic = kCkptMagic;
+  h.version = 1;
+  h.N = R->N; h.L = R->L; h.Ns = R->Ns; h.Np = R->g.Np; h.rcap = R->prm.rank_cap; h.pp = R->prm.p * R->prm.p;
+  h.r = R->r;
+  h.pending = R->pending_graph ? 1 : 0;
+  h.c_prev = R->c_prev;
+  h.st = R->st;
+  char* o = (char*)buf;
+  MRF_CHECK_HIP(hipMemcpyAsync(o + c.x, R->X, (size_t)R->L * R->Nv * 8, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(o + c.res, R->res, (size_t)R->L * R->Ns * 8, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(o + c.u, R->U, (size_t)h.Np * h.rcap * h.pp * 8, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(o + c.f, R->f, (size_t)h.Np * h.rcap * 4, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(o + c.sc, R->sc, SC_N * 8, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipStreamSynchronize(s));
+  MRF_CHECK_HIP(hipMemcpy(o, &h, sizeof h, hipMemcpyDefault));
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_recon_checkpoint_load(mrf_recon_t R, const mrf_c64* b, const void* buf, size_t bytes,
+                                                hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(R && b && buf, MRF_INVALID_ARG, "recon_checkpoint_load: null argument");
+  const CkptLayout c = ckpt_layout(R);
+  MRF_REQUIRE(bytes >= c.total, MRF_WORKSPACE, "recon_checkpoint_load: buffer smaller than mrf_recon_checkpoint_bytes");
+  CkptHeader h{};
+  const char* o = (const char*)buf;
+  MRF_CHECK_HIP(hipMemcpy(&h, o, sizeof h, hipMemcpyDefault));
+  MRF_REQUIRE(h.magic == kCkptMagic && h.version == 1, MRF_INVALID_ARG, "recon_checkpoint_load: not a checkpoint");
+  MRF_REQUIRE(h.N == R->N && h.L == R->L && h.Ns == R->Ns && h.Np == R->g.Np && h.rcap == R->prm.rank_cap &&
+                  h.pp == R->prm.p * R->prm.p && h.r == R->r,
+              MRF_SHAPE, "recon_checkpoint_load: the checkpoint's sizes differ from this recon's");
+  MRF_CHECK_HIP(hipMemcpyAsync(R->X, o + c.x, (size_t)R->L * R->Nv * 8, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(R->res, o + c.res, (size_t)R->L * R->Ns * 8, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(R->U, o + c.u, (size_t)h.Np * h.rcap * h.pp * 8, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(R->f, o + c.f, (size_t)h.Np * h.rcap * 4, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(R->sc, o + c.sc, SC_N * 8, hipMemcpyDefault, s));
+  R->b = (const cf*)b;
+  R->st = h.st;
+  R->c_prev = h.c_prev;
+  R->pending_graph = h.pending != 0;
+  R->initialised = true;
+  if (!R->pending_graph && active(R)) {
+    // saved right after the initialisation: its graph is rebuilt from X^0 (the same deterministic
+    // kernels on the same data give the same graph, lambda1 and mu); the statistics already hold it
+    mrf_status e = rebuild(R, s);
+    if (e) return e;
+  }
+  MRF_CHECK_HIP(hipStreamSynchronize(s));
   return MRF_OK;
 }
 

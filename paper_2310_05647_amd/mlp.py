@@ -125,6 +125,19 @@ class MLP:
         out["n_fallback"] = nfb.value
         return out
 
+    def save(self, stream=None):
+        """The network's state (mrf_mlp_save) as a host uint8 tensor."""
+        n = ctypes.c_size_t()
+        check(lib.mrf_mlp_state_bytes(self.handle, ctypes.byref(n)), "mrf_mlp_state_bytes")
+        buf = torch.empty(n.value, dtype=torch.uint8)
+        check(lib.mrf_mlp_save(self.handle, ctypes.c_void_p(buf.data_ptr()), n.value, stream_ptr(stream)), "mrf_mlp_save")
+        return buf
+
+    def load(self, buf, stream=None):
+        """Restores a state written by save (host or device uint8 tensor)."""
+        check(lib.mrf_mlp_load(self.handle, ctypes.c_void_p(buf.data_ptr()), buf.numel(), stream_ptr(stream)),
+              "mrf_mlp_load")
+
     def close(self):
         if getattr(self, "handle", None):
             lib.mrf_mlp_destroy(self.handle)

@@ -51,6 +51,30 @@ class Recon:
                                          col.ctypes.data_as(ip), val.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                                          float(sigma2), float(lmax)), "mrf_recon_inject_graph")
 
+    MATCH_MODES = {"subspace": 4, "fp32": 0, "bf16": 1, "fp8": 2, "learned": 3}
+
+    def set_final_match(self, mode="subspace", mlp=None, theta=0.0):
+        """The final match of the run (mrf_recon_set_final_match): "subspace" (default), "fp32",
+        "bf16", "fp8" (full-length) or "learned" (with mlp and the gate threshold theta)."""
+        check(lib.mrf_recon_set_final_match(self.handle, self.MATCH_MODES[mode], mlp.handle if mlp is not None else None,
+                                            float(theta)), "mrf_recon_set_final_match")
+
+    def checkpoint(self, stream=None):
+        """The run's state between iterations (mrf_recon_checkpoint_save) as a host uint8 tensor."""
+        n = ctypes.c_size_t()
+        check(lib.mrf_recon_checkpoint_bytes(self.handle, ctypes.byref(n)), "mrf_recon_checkpoint_bytes")
+        buf = torch.empty(n.value, dtype=torch.uint8)
+        check(lib.mrf_recon_checkpoint_save(self.handle, ctypes.c_void_p(buf.data_ptr()), n.value, stream_ptr(stream)),
+              "mrf_recon_checkpoint_save")
+        return buf
+
+    def restore(self, b, buf, stream=None):
+        """Continues a run from checkpoint(); b are the run's measurements."""
+        need(b, torch.complex64, (self.L, self.plan.Ns), "b")
+        self._b = b
+        check(lib.mrf_recon_checkpoint_load(self.handle, ptr(b), ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                            stream_ptr(stream)), "mrf_recon_checkpoint_load")
+
     def set_serial(self, serial):
         """Schedule mask for later iterations (see the constructor's serial)."""
         check(lib.mrf_recon_set_serial(self.handle, int(serial)), "mrf_recon_set_serial")
@@ -73,7 +97,7 @@ class Recon:
         g = st.n_graph
         return dict(iters=st.iters, stop=st.stop_reason, cost=list(st.cost[:k]), data=list(st.data[:k]),
                     tr=list(st.tr[:k]), nuc=list(st.nuc[:k]), mu=list(st.mu[:g]), lam1=list(st.lam1[:g]),
-                    sigma2=list(st.sigma2[:g]), lmax=list(st.lmax[:g]))
+                    sigma2=list(st.sigma2[:g]), lmax=list(st.lmax[:g]), iter_ms=list(st.iter_ms[:k]))
 
     def run(self, b, X0=None, stream=None):
         self.init(b, X0, stream)
