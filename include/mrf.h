@@ -214,13 +214,17 @@ mrf_status mrf_dict_match_subspace(mrf_dict_t d, const mrf_c64* alpha, int Nv, i
  *   MRF_MATCH_FP32          scores from FP32 atoms and fingerprints (v_mfma_f32_16x16x4f32)
  *   MRF_MATCH_BF16_RERANK4  atoms and fingerprints rounded to BF16 (v_mfma_f32_16x16x32_bf16)
  *   MRF_MATCH_FP8_RERANK4   OCP E4M3 with one scale per row (max |component| -> 448), FP8 MFMA
+ *   MRF_MATCH_BF16X3_RERANK split BF16 (hi + lo parts of atoms and fingerprints), three BF16 MFMA
+ *                           products per score: 3x the BF16 work at close to FP32 scores
  *   MRF_MATCH_LEARNED       (C4) the MLP estimate with the residual gate; see mrf_mlp_*      */
 typedef enum mrf_match_mode {
   MRF_MATCH_FP32 = 0,
   MRF_MATCH_BF16_RERANK4 = 1,
   MRF_MATCH_FP8_RERANK4 = 2,
   MRF_MATCH_LEARNED = 3,
-  MRF_MATCH_SUBSPACE = 4   /* the subspace match of mrf_dict_match_subspace (only as a final match of mrf_recon) */
+  MRF_MATCH_SUBSPACE = 4,  /* the subspace match of mrf_dict_match_subspace (only as a final match of mrf_recon) */
+  MRF_MATCH_BF16X3_RERANK = 5  /* split BF16: each value as hi + lo BF16 parts, scores from the
+                                  three products hi hi + hi lo + lo hi (about 16 mantissa bits) */
 } mrf_match_mode;
 
 /* Workspace bytes of mrf_dict_match for Nv fingerprints (FP32 / BF16 / FP8 modes). */
@@ -232,6 +236,14 @@ mrf_status mrf_dict_match_workspace_size(mrf_dict_t d, int Nv, mrf_match_mode mo
  * Asynchronous; MRF_NOT_SUPPORTED for MRF_MATCH_LEARNED (use mrf_mlp_match). */
 mrf_status mrf_dict_match(mrf_dict_t d, const mrf_c64* fp, int Nv, mrf_match_mode mode, int32_t* idx, float* rho,
                           float* score, float* params, int32_t* cand, void* ws, size_t ws_bytes, hipStream_t stream);
+/* mrf_dict_match with the re-rank depth chosen: the `depth` (1..32) best candidates by the
+ * mode's scores (each of the 8 atom groups keeps its best 8; the depth best of those 64 are taken,
+ * ties to the lower index) are re-ranked exactly in FP32; cand [Nv][depth] (optional). A deeper
+ * re-rank recovers the FP32 result where low-precision scores reorder near neighbours of a dense
+ * dictionary. mrf_dict_match is depth 4. Same workspace. */
+mrf_status mrf_dict_match_depth(mrf_dict_t d, const mrf_c64* fp, int Nv, mrf_match_mode mode, int depth, int32_t* idx,
+                                float* rho, float* score, float* params, int32_t* cand, void* ws, size_t ws_bytes,
+                                hipStream_t stream);
 /* Y [Nv][L] = X [L][Nv] (frame-major image series to voxel-major fingerprints). Asynchronous. */
 mrf_status mrf_frames_to_voxels(const mrf_c64* X, int L, int Nv, mrf_c64* Y, hipStream_t stream);
 

@@ -86,6 +86,8 @@ _decl("mrf_dict_match_subspace", [c_void_p, c_void_p, c_int, c_void_p, c_void_p,
 _decl("mrf_dict_match_workspace_size", [c_void_p, c_int, c_int, P(c_size_t)])
 _decl("mrf_dict_match", [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                          c_size_t, c_void_p])
+_decl("mrf_dict_match_depth", [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                               c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_frames_to_voxels", [c_void_p, c_int, c_int, c_void_p, c_void_p])
 _u64 = ctypes.c_uint64
 _decl("mrf_mlp_create", [c_int, c_int, c_int, c_int, _u64, c_void_p, P(c_void_p)])

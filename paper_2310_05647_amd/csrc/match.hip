@@ -1,5 +1,5 @@
 // Full-length dictionary matching Phi_D (eq. (5), Sec. II-B) in FP32, BF16 or FP8 on MFMA, with
-// an FP32 re-rank of the four best candidates.
+// an FP32 re-rank of the best candidates (4 by default, up to 32).
 //
 // Scores: z_{v,m} = <dn_m, x_v> = sum_l conj(dn_ml) x_vl with the unit-norm atoms dn, so the
 // arg-max of |z| is that of |<d_m, x>| / ||d_m||. As a real GEMM with K over real and imaginary
@@ -16,9 +16,9 @@
 // next chunk is loaded into registers. A block walks the atom tiles t = g (mod 8) of its group
 // g = blockIdx mod 8, so the blocks of one XCD stream the same atom tiles through its L2, and
 // keeps per lane a running top-4 (score desc, atom index asc) for each of its 4 fingerprint
-// columns. The 8 candidate lists of a fingerprint column are merged into the block's top-4,
-// written as the group's partial result; k_rerank merges the 8 groups and recomputes the four
-// best exactly in FP32 from the FP32 atoms.
+// columns. The 8 candidate lists of a fingerprint column (32 candidates) are merged into the
+// block's top-kGroupK, written as the group's partial result; k_rerank takes the best `depth` of
+// the 8 groups' candidates and recomputes them exactly in FP32 from the FP32 atoms.
 #include <cfloat>
 #include <cmath>
 #include <type_traits>
@@ -32,12 +32,14 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
-enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2 };
+enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2, P_BF16X3 = 3 };
 constexpr int kGroups = 8;        // atom groups (one per XCD)
 constexpr int kTileM = 128;       // atoms per block tile
 constexpr int kTileN = 128;       // fingerprints per block tile
 constexpr int kRowB = 144;        // LDS bytes per staged row (128 + pad)
 constexpr int kE4m3Max = 448;
+constexpr int kGroupK = 8;        // candidates per group and fingerprint in the partial results
+constexpr int kMaxDepth = 32;     // deepest re-rank
 
 template <int P>
 struct MT;
@@ -50,6 +52,11 @@ template <>
 struct MT<P_BF16> {
   static constexpr int KC = 32;
   static constexpr int STEPS = 2;   // 16 frames each
+};
+template <>
+struct MT<P_BF16X3> {   // rows as BF16 (hi, lo) pairs: A hi, B hi, A lo, B lo staged
+  static constexpr int KC = 32;
+  static constexpr int STEPS = 2;
 };
 template <>
 struct MT<P_FP8> {
@@ -80,9 +87,12 @@ __device__ inline void top4_insert(float (&sc)[4], int (&id)[4], float s, int m)
 template <int P>
 __global__ __launch_bounds__(256) void k_match_top4(const void* __restrict__ A, const float* __restrict__ sa, int M,
                                                     const void* __restrict__ B, int Nv, int L, int Lp,
-                                                    float* __restrict__ pscore, int* __restrict__ pidx) {
+                                                    float* __restrict__ pscore, int* __restrict__ pidx,
+                                                    const void* __restrict__ A2 = nullptr,
+                                                    const void* __restrict__ B2 = nullptr) {
   typedef MT<P> T;
-  __shared__ __attribute__((aligned(16))) unsigned char stage[2 * kTileM * kRowB];   // A rows then B rows
+  constexpr int NGRP = P == P_BF16X3 ? 4 : 2;   // staged row groups: A, B (hi), then A, B (lo)
+  __shared__ __attribute__((aligned(16))) unsigned char stage[NGRP * kTileM * kRowB];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int wa = w >> 1, wf = w & 1;
   const int q = lane >> 4, n16 = lane & 15, h = q >> 1, o = q & 1;
@@ -101,8 +111,8 @@ __global__ __launch_bounds__(256) void k_match_top4(const void* __restrict__ A, 
       li[tf][k] = -1;
     }
 
-  // register staging of one chunk: 2048 units of 16 B (P_F32: 4096 units of 8 B)
-  constexpr int NU = P == P_F32 ? 16 : 8;
+  // register staging of one chunk: 2048 units of 16 B (P_F32: 4096 units of 8 B; P_BF16X3: 4096 of 16 B)
+  constexpr int NU = P == P_F32 ? 16 : (P == P_BF16X3 ? 16 : 8);
   typedef typename std::conditional<P == P_F32, uint2, uint4>::type U;
   U nxt[NU];
   auto load = [&](int a0, int c) {
@@ -120,12 +130,16 @@ __global__ __launch_bounds__(256) void k_match_top4(const void* __restrict__ A, 
         if (gr < lim && f < L) v = base[(size_t)gr * L + f];
         nxt[k] = v;
       } else {
-        const int row = u >> 3, seg = u & 7;
-        const bool isA = row < kTileM;
-        const int gr = isA ? a0 + row : f0 + row - kTileM;
+        // u = tid + 256 k with tid >> 3 < 32: the staged row is 32 k + (tid >> 3), so its group
+        // (0 A, 1 B, 2 A lo, 3 B lo) is k / 4, fixed for each unrolled k
+        const int seg = tid & 7;
+        const int grp = k / (kTileM / 32);
+        const int rr = (tid >> 3) + 32 * (k % (kTileM / 32));
+        const bool isA = (grp & 1) == 0;
+        const int gr = isA ? a0 + rr : f0 + rr;
         const int lim = isA ? M : Nv;
-        constexpr int EB = P == P_BF16 ? 2 : 1;   // bytes per element
-        const unsigned char* base = (const unsigned char*)(isA ? A : B);
+        constexpr int EB = P == P_FP8 ? 1 : 2;   // bytes per element
+        const unsigned char* base = (const unsigned char*)(grp == 0 ? A : grp == 1 ? B : grp == 2 ? A2 : B2);
         if (gr < lim) {
           const size_t off = (size_t)gr * 2 * Lp * EB + (size_t)(seg >> 2) * Lp * EB + (size_t)c * T::KC * EB + (seg & 3) * 16;
           v = *(const U*)(base + off);
@@ -202,6 +216,39 @@ __global__ __launch_bounds__(256) void k_match_top4(const void* __restrict__ A, 
                                                                    __builtin_bit_cast(bf16x8, bi), im[ta][tf], 0, 0, 0);
             }
           }
+        } else if constexpr (P == P_BF16X3) {
+          const int ob = s * 32 + o * 16;
+          const unsigned char* As2 = As + 2 * kTileM * kRowB;
+          const unsigned char* Bs2 = Bs + 2 * kTileM * kRowB;
+          const unsigned sg = h ? 0x80008000u : 0u;
+          uint4 a[4], al[4];
+#pragma unroll
+          for (int ta = 0; ta < 4; ++ta) {
+            a[ta] = *(const uint4*)(As + ta * 16 * kRowB + h * 64 + ob);
+            al[ta] = *(const uint4*)(As2 + ta * 16 * kRowB + h * 64 + ob);
+          }
+#pragma unroll
+          for (int tf = 0; tf < 4; ++tf) {
+            const uint4 br = *(const uint4*)(Bs + tf * 16 * kRowB + h * 64 + ob);
+            const uint4 bi = *(const uint4*)(Bs + tf * 16 * kRowB + (1 - h) * 64 + ob);
+            const uint4 brl = *(const uint4*)(Bs2 + tf * 16 * kRowB + h * 64 + ob);
+            const uint4 bil = *(const uint4*)(Bs2 + tf * 16 * kRowB + (1 - h) * 64 + ob);
+#pragma unroll
+            for (int ta = 0; ta < 4; ++ta) {
+              const uint4 an = make_uint4(a[ta].x ^ sg, a[ta].y ^ sg, a[ta].z ^ sg, a[ta].w ^ sg);
+              const uint4 anl = make_uint4(al[ta].x ^ sg, al[ta].y ^ sg, al[ta].z ^ sg, al[ta].w ^ sg);
+              // hi hi + hi lo + lo hi; the lo lo product is below the accumulation's rounding
+              f32x4 r = re[ta][tf], i = im[ta][tf];
+              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[ta]), __builtin_bit_cast(bf16x8, brl), r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al[ta]), __builtin_bit_cast(bf16x8, br), r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[ta]), __builtin_bit_cast(bf16x8, br), r, 0, 0, 0);
+              i = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, an), __builtin_bit_cast(bf16x8, bil), i, 0, 0, 0);
+              i = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, anl), __builtin_bit_cast(bf16x8, bi), i, 0, 0, 0);
+              i = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, an), __builtin_bit_cast(bf16x8, bi), i, 0, 0, 0);
+              re[ta][tf] = r;
+              im[ta][tf] = i;
+            }
+          }
         } else {
           const int ob = o * 32;
           i32x8 a[4], an[4];
@@ -263,17 +310,23 @@ __global__ __launch_bounds__(256) void k_match_top4(const void* __restrict__ A, 
   }
   __syncthreads();
   if (tid < kTileN && f0 + tid < Nv) {
-    float sc[4] = {-1.f, -1.f, -1.f, -1.f};
-    int id[4] = {-1, -1, -1, -1};
+    constexpr int K = kGroupK;
+    float sc[K];
+    int id[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      sc[k] = -1.f;
+      id[k] = -1;
+    }
     for (int j = 0; j < 32; ++j) {
       const float s = cs[tid * 32 + j];
       const int m = ci[tid * 32 + j];
       if (m < 0) continue;
       // insertion with ties broken by the lower index (the lists arrive in no index order)
-      if (s > sc[3] || (s == sc[3] && (id[3] < 0 || m < id[3]))) {
-        sc[3] = s;
-        id[3] = m;
-        for (int k = 3; k > 0; --k) {
+      if (s > sc[K - 1] || (s == sc[K - 1] && (id[K - 1] < 0 || m < id[K - 1]))) {
+        sc[K - 1] = s;
+        id[K - 1] = m;
+        for (int k = K - 1; k > 0; --k) {
           const bool up = sc[k] > sc[k - 1] || (sc[k] == sc[k - 1] && (id[k - 1] < 0 || id[k] < id[k - 1]));
           if (!up) break;
           const float ts = sc[k];
@@ -285,11 +338,11 @@ __global__ __launch_bounds__(256) void k_match_top4(const void* __restrict__ A, 
         }
       }
     }
-    const size_t o4 = ((size_t)(f0 + tid) * kGroups + g) * 4;
+    const size_t oK = ((size_t)(f0 + tid) * kGroups + g) * K;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      pscore[o4 + k] = sc[k];
-      pidx[o4 + k] = id[k];
+    for (int k = 0; k < K; ++k) {
+      pscore[oK + k] = sc[k];
+      pidx[oK + k] = id[k];
     }
   }
 }
@@ -313,59 +366,70 @@ __device__ inline unsigned long long wmax64(unsigned long long v) {
   return v;
 }
 
-// One wave per fingerprint: the 4 best of the 8 groups' candidates (score desc, index asc), then
-// z = <dn_m, x> in FP32 for each and the exact arg-max of |z| (ties to the lower index).
+// One wave per fingerprint: the `depth` best of the 8 groups' kGroupK candidates (score desc,
+// index asc; one candidate per lane), then z = <dn_m, x> in FP32 for each, two candidates at a
+// time, and the exact arg-max of |z| (ties to the lower index).
 __global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ pscore, const int* __restrict__ pidx,
                                                 const cf* __restrict__ X, int Nv, int L, const cf* __restrict__ dn,
                                                 const float* __restrict__ norms, const float* __restrict__ lut,
-                                                int nparam, int* __restrict__ idx, float* __restrict__ rho,
+                                                int nparam, int depth, int* __restrict__ idx, float* __restrict__ rho,
                                                 float* __restrict__ score, float* __restrict__ params,
                                                 int* __restrict__ cand) {
+  static_assert(kGroups * kGroupK == 64, "one candidate per lane");
   const int v = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (v >= Nv) return;
   unsigned long long key = 0ull;
-  if (lane < kGroups * 4) {
-    const float s = pscore[(size_t)v * kGroups * 4 + lane];
-    const int m = pidx[(size_t)v * kGroups * 4 + lane];
+  {
+    const float s = pscore[(size_t)v * 64 + lane];
+    const int m = pidx[(size_t)v * 64 + lane];
     if (m >= 0 && s >= 0.f)
       key = ((unsigned long long)__float_as_uint(s) << 32) | (unsigned long long)(0xffffffffu - (unsigned)m);
   }
-  int cm[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  // the depth best, in order: lane k keeps the k-th
+  int mine = -1;
+  for (int k = 0; k < depth; ++k) {
     const unsigned long long best = wmax64(key);
-    cm[k] = best ? (int)(0xffffffffu - (unsigned)(best & 0xffffffffull)) : -1;
+    const int m = best ? (int)(0xffffffffu - (unsigned)(best & 0xffffffffull)) : -1;
+    if (lane == k) mine = m;
     if (best && key == best) key = 0ull;
   }
   const cf* x = X + (size_t)v * L;
   int bm = -1;
   float bz = -1.f, bre = 0.f;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (cm[k] < 0) continue;   // uniform over the wave
-    const cf* d = dn + (size_t)cm[k] * L;
-    float zr = 0.f, zi = 0.f;
-    for (int f = lane; f < L; f += 64) {
-      const cf a = d[f], b = x[f];
-      zr += a.x * b.x + a.y * b.y;
-      zi += a.x * b.y - a.y * b.x;
-    }
-    zr = wsumf(zr);
-    zi = wsumf(zi);
+  auto take = [&](int m, float zr, float zi) {
     const float az = sqrtf(zr * zr + zi * zi);
-    if (az > bz || (az == bz && cm[k] < bm)) {
+    if (az > bz || (az == bz && m < bm)) {
       bz = az;
-      bm = cm[k];
+      bm = m;
       bre = zr;
     }
+  };
+  for (int k = 0; k < depth; k += 2) {
+    const int ma = __shfl(mine, k), mb = k + 1 < depth ? __shfl(mine, k + 1) : -1;
+    if (ma < 0) break;   // uniform over the wave; the list is in descending order
+    const cf* da = dn + (size_t)ma * L;
+    const cf* db = dn + (size_t)(mb >= 0 ? mb : ma) * L;
+    float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
+    for (int f = lane; f < L; f += 64) {
+      const cf a = da[f], b = db[f], xx = x[f];
+      ar += a.x * xx.x + a.y * xx.y;
+      ai += a.x * xx.y - a.y * xx.x;
+      br += b.x * xx.x + b.y * xx.y;
+      bi += b.x * xx.y - b.y * xx.x;
+    }
+    ar = wsumf(ar);
+    ai = wsumf(ai);
+    br = wsumf(br);
+    bi = wsumf(bi);
+    take(ma, ar, ai);
+    if (mb >= 0) take(mb, br, bi);
   }
   if (lane == 0) {
     idx[v] = bm;
     if (score) score[v] = bm >= 0 ? bz : 0.f;
     if (rho) rho[v] = bm >= 0 ? fmaxf(bre / norms[bm], 0.f) : 0.f;
-    if (cand)
-      for (int k = 0; k < 4; ++k) cand[(size_t)v * 4 + k] = cm[k];
   }
+  if (cand && lane < depth) cand[(size_t)v * depth + lane] = mine;
   if (params && lane < nparam) params[(size_t)v * nparam + lane] = bm >= 0 ? lut[(size_t)bm * nparam + lane] : 0.f;
 }
 
@@ -376,9 +440,11 @@ __device__ inline uint16_t to_bf16(float f) {   // round to nearest even
 }
 
 // One block per row: BF16 copy, and FP8 copy with scale max|component| / 448, of a complex row.
+__device__ inline float from_bf16(uint16_t b) { return __uint_as_float((unsigned)b << 16); }
+
 __global__ __launch_bounds__(256) void k_quant_rows(const cf* __restrict__ src, int rows, int L, int Lp,
-                                                    uint16_t* __restrict__ d16, uint8_t* __restrict__ d8,
-                                                    float* __restrict__ s8) {
+                                                    uint16_t* __restrict__ d16, uint16_t* __restrict__ d16lo,
+                                                    uint8_t* __restrict__ d8, float* __restrict__ s8) {
   __shared__ float red[256];
   const int row = blockIdx.x, t = threadIdx.x;
   const cf* x = src + (size_t)row * L;
@@ -399,10 +465,18 @@ __global__ __launch_bounds__(256) void k_quant_rows(const cf* __restrict__ src, 
     const cf b = f + 1 < L ? x[f + 1] : cf{0.f, 0.f};
     if (d16) {
       uint16_t* r16 = d16 + (size_t)row * 2 * Lp;
-      r16[f] = to_bf16(a.x);
-      r16[f + 1] = to_bf16(b.x);
-      r16[Lp + f] = to_bf16(a.y);
-      r16[Lp + f + 1] = to_bf16(b.y);
+      const uint16_t h0 = to_bf16(a.x), h1 = to_bf16(b.x), h2 = to_bf16(a.y), h3 = to_bf16(b.y);
+      r16[f] = h0;
+      r16[f + 1] = h1;
+      r16[Lp + f] = h2;
+      r16[Lp + f + 1] = h3;
+      if (d16lo) {   // the remainders, exact in FP32, rounded to BF16
+        uint16_t* l16 = d16lo + (size_t)row * 2 * Lp;
+        l16[f] = to_bf16(a.x - from_bf16(h0));
+        l16[f + 1] = to_bf16(b.x - from_bf16(h1));
+        l16[Lp + f] = to_bf16(a.y - from_bf16(h2));
+        l16[Lp + f + 1] = to_bf16(b.y - from_bf16(h3));
+      }
     }
     if (d8) {
       uint8_t* r8 = d8 + (size_t)row * 2 * Lp;
@@ -414,10 +488,10 @@ __global__ __launch_bounds__(256) void k_quant_rows(const cf* __restrict__ src, 
   }
 }
 
-mrf_status quantise_rows(const cf* src, int rows, int L, int Lp, uint16_t* d16, uint8_t* d8, float* s8,
-                         hipStream_t s) {
+mrf_status quantise_rows(const cf* src, int rows, int L, int Lp, uint16_t* d16, uint16_t* d16lo, uint8_t* d8,
+                         float* s8, hipStream_t s) {
   if (rows <= 0) return MRF_OK;
-  MRF_LAUNCH("match_quantise", s, k_quant_rows<<<rows, 256, 0, s>>>(src, rows, L, Lp, d16, d8, s8));
+  MRF_LAUNCH("match_quantise", s, k_quant_rows<<<rows, 256, 0, s>>>(src, rows, L, Lp, d16, d16lo, d8, s8));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
 }
@@ -440,7 +514,7 @@ __global__ __launch_bounds__(256) void k_transpose(const cf* __restrict__ X, int
 
 struct MatchWs {
   void* rows;      // fingerprint rows in the mode's format
-  float* pscore;   // [Nv][kGroups][4]
+  float* pscore;   // [Nv][kGroups][kGroupK]
   int* pidx;
   size_t bytes;
 };
@@ -455,11 +529,12 @@ MatchWs match_ws(const mrf_dict_s* D, int Nv, int mode, void* base) {
     return (void*)q;
   };
   const size_t rb = mode == MRF_MATCH_BF16_RERANK4 ? (size_t)Nv * 2 * D->Lp * 2
+                    : mode == MRF_MATCH_BF16X3_RERANK ? (size_t)Nv * 2 * D->Lp * 2 * 2
                     : mode == MRF_MATCH_FP8_RERANK4 ? (size_t)Nv * 2 * D->Lp
                                                     : 0;
   w.rows = take(rb);
-  w.pscore = (float*)take((size_t)Nv * kGroups * 4 * 4);
-  w.pidx = (int*)take((size_t)Nv * kGroups * 4 * 4);
+  w.pscore = (float*)take((size_t)Nv * kGroups * kGroupK * 4);
+  w.pidx = (int*)take((size_t)Nv * kGroups * kGroupK * 4);
   w.bytes = off;
   return w;
 }
@@ -481,8 +556,9 @@ extern "C" mrf_status mrf_frames_to_voxels(const mrf_c64* X, int L, int Nv, mrf_
 extern "C" mrf_status mrf_dict_match_workspace_size(mrf_dict_t D, int Nv, mrf_match_mode mode, size_t* bytes) {
   clear_error();
   MRF_REQUIRE(D && bytes && Nv >= 1, MRF_INVALID_ARG, "dict_match_workspace_size: bad argument");
-  MRF_REQUIRE(mode == MRF_MATCH_FP32 || mode == MRF_MATCH_BF16_RERANK4 || mode == MRF_MATCH_FP8_RERANK4, MRF_NOT_SUPPORTED,
-              "dict_match_workspace_size: mode not supported by this call");
+  MRF_REQUIRE(mode == MRF_MATCH_FP32 || mode == MRF_MATCH_BF16_RERANK4 || mode == MRF_MATCH_FP8_RERANK4 ||
+                  mode == MRF_MATCH_BF16X3_RERANK,
+              MRF_NOT_SUPPORTED, "dict_match_workspace_size: mode not supported by this call");
   *bytes = match_ws(D, Nv, mode, nullptr).bytes;
   return MRF_OK;
 }
@@ -490,11 +566,19 @@ extern "C" mrf_status mrf_dict_match_workspace_size(mrf_dict_t D, int Nv, mrf_ma
 extern "C" mrf_status mrf_dict_match(mrf_dict_t D, const mrf_c64* fp, int Nv, mrf_match_mode mode, int32_t* idx,
                                      float* rho, float* score, float* params, int32_t* cand, void* ws, size_t ws_bytes,
                                      hipStream_t s) {
+  return mrf_dict_match_depth(D, fp, Nv, mode, 4, idx, rho, score, params, cand, ws, ws_bytes, s);
+}
+
+extern "C" mrf_status mrf_dict_match_depth(mrf_dict_t D, const mrf_c64* fp, int Nv, mrf_match_mode mode, int depth,
+                                           int32_t* idx, float* rho, float* score, float* params, int32_t* cand,
+                                           void* ws, size_t ws_bytes, hipStream_t s) {
   clear_error();
   MRF_REQUIRE(D && fp && idx, MRF_INVALID_ARG, "dict_match: null argument");
   MRF_REQUIRE(Nv >= 1, MRF_INVALID_ARG, "dict_match: Nv must be >= 1");
-  MRF_REQUIRE(mode == MRF_MATCH_FP32 || mode == MRF_MATCH_BF16_RERANK4 || mode == MRF_MATCH_FP8_RERANK4, MRF_NOT_SUPPORTED,
-              "dict_match: mode not supported by this call");
+  MRF_REQUIRE(depth >= 1 && depth <= kMaxDepth, MRF_INVALID_ARG, "dict_match: the re-rank depth must be in [1, 32]");
+  MRF_REQUIRE(mode == MRF_MATCH_FP32 || mode == MRF_MATCH_BF16_RERANK4 || mode == MRF_MATCH_FP8_RERANK4 ||
+                  mode == MRF_MATCH_BF16X3_RERANK,
+              MRF_NOT_SUPPORTED, "dict_match: mode not supported by this call");
   const MatchWs w = match_ws(D, Nv, mode, ws);
   MRF_REQUIRE(ws && ws_bytes >= w.bytes, MRF_WORKSPACE, "dict_match: workspace too small");
   const int grid = kGroups * ceil_div(Nv, kTileN);
@@ -502,20 +586,27 @@ extern "C" mrf_status mrf_dict_match(mrf_dict_t D, const mrf_c64* fp, int Nv, mr
   if (mode == MRF_MATCH_FP32) {
     MRF_LAUNCH("match_full_fp32", s,
                k_match_top4<P_F32><<<grid, 256, 0, s>>>(D->dn, nullptr, D->M, X, Nv, D->L, D->Lp, w.pscore, w.pidx));
+  } else if (mode == MRF_MATCH_BF16X3_RERANK) {
+    uint16_t* hi = (uint16_t*)w.rows;
+    uint16_t* lo = hi + (size_t)Nv * 2 * D->Lp;
+    MRF_LAUNCH("match_quantise", s, k_quant_rows<<<Nv, 256, 0, s>>>(X, Nv, D->L, D->Lp, hi, lo, nullptr, nullptr));
+    MRF_LAUNCH("match_full_bf16x3", s,
+               k_match_top4<P_BF16X3><<<grid, 256, 0, s>>>(D->d16, nullptr, D->M, hi, Nv, D->L, D->Lp, w.pscore, w.pidx,
+                                                           D->d16lo, lo));
   } else if (mode == MRF_MATCH_BF16_RERANK4) {
     MRF_LAUNCH("match_quantise", s,
-               k_quant_rows<<<Nv, 256, 0, s>>>(X, Nv, D->L, D->Lp, (uint16_t*)w.rows, nullptr, nullptr));
+               k_quant_rows<<<Nv, 256, 0, s>>>(X, Nv, D->L, D->Lp, (uint16_t*)w.rows, nullptr, nullptr, nullptr));
     MRF_LAUNCH("match_full_bf16", s,
                k_match_top4<P_BF16><<<grid, 256, 0, s>>>(D->d16, nullptr, D->M, w.rows, Nv, D->L, D->Lp, w.pscore, w.pidx));
   } else {
     MRF_LAUNCH("match_quantise", s,
-               k_quant_rows<<<Nv, 256, 0, s>>>(X, Nv, D->L, D->Lp, nullptr, (uint8_t*)w.rows, nullptr));
+               k_quant_rows<<<Nv, 256, 0, s>>>(X, Nv, D->L, D->Lp, nullptr, nullptr, (uint8_t*)w.rows, nullptr));
     MRF_LAUNCH("match_full_fp8", s,
                k_match_top4<P_FP8><<<grid, 256, 0, s>>>(D->d8, D->s8, D->M, w.rows, Nv, D->L, D->Lp, w.pscore, w.pidx));
   }
   MRF_LAUNCH("match_rerank", s,
              k_rerank<<<ceil_div(Nv, 4), 256, 0, s>>>(w.pscore, w.pidx, X, Nv, D->L, D->dn, D->norms, D->lut, D->nparam,
-                                                     idx, rho, score, params, cand));
+                                                     depth, idx, rho, score, params, cand));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
 }

@@ -551,7 +551,7 @@ extern "C" mrf_status mrf_recon_set_final_match(mrf_recon_t R, mrf_match_mode mo
   clear_error();
   MRF_REQUIRE(R, MRF_INVALID_ARG, "recon_set_final_match: null handle");
   MRF_REQUIRE(mode == MRF_MATCH_SUBSPACE || mode == MRF_MATCH_FP32 || mode == MRF_MATCH_BF16_RERANK4 ||
-                  mode == MRF_MATCH_FP8_RERANK4 || mode == MRF_MATCH_LEARNED,
+                  mode == MRF_MATCH_FP8_RERANK4 || mode == MRF_MATCH_BF16X3_RERANK || mode == MRF_MATCH_LEARNED,
               MRF_INVALID_ARG, "recon_set_final_match: unknown mode");
   MRF_REQUIRE(mode != MRF_MATCH_LEARNED || mlp, MRF_INVALID_ARG, "recon_set_final_match: the learned mode needs an MLP");
   MRF_REQUIRE(theta == theta, MRF_INVALID_ARG, "recon_set_final_match: theta is NaN");

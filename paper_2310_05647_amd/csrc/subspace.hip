@@ -501,6 +501,7 @@ extern "C" mrf_status mrf_dict_create(const mrf_c64* atoms, const float* lut, in
   bool ok = hipMalloc(&D->lut, (size_t)M * nparam * 4) == hipSuccess && hipMalloc(&D->norms, (size_t)M * 4) == hipSuccess &&
             hipMalloc(&D->dn, (size_t)M * L * sizeof(cf)) == hipSuccess &&
             hipMalloc(&D->d16, (size_t)M * 2 * D->Lp * 2) == hipSuccess &&
+            hipMalloc(&D->d16lo, (size_t)M * 2 * D->Lp * 2) == hipSuccess &&
             hipMalloc(&D->d8, (size_t)M * 2 * D->Lp) == hipSuccess && hipMalloc(&D->s8, (size_t)M * 4) == hipSuccess;
   if (ok && V)
     ok = hipMalloc(&D->dhr, (size_t)M * r * sizeof(cf)) == hipSuccess &&
@@ -519,7 +520,7 @@ extern "C" mrf_status mrf_dict_create(const mrf_c64* atoms, const float* lut, in
   k_dict_prep<<<M, 256, 0, s>>>((const cf*)atoms, (const cf*)V, M, L, V ? r : 0, D->norms, D->dhr, D->dn);
   if (V) k_dict_pack<<<ceil_div((long)D->ntile * 640, 256), 256, 0, s>>>(D->dhr, M, r, D->ntile, D->bpk);
   e = hipGetLastError();
-  if (e == hipSuccess && quantise_rows(D->dn, M, L, D->Lp, D->d16, D->d8, D->s8, s) != MRF_OK) e = hipErrorLaunchFailure;
+  if (e == hipSuccess && quantise_rows(D->dn, M, L, D->Lp, D->d16, D->d16lo, D->d8, D->s8, s) != MRF_OK) e = hipErrorLaunchFailure;
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     mrf_dict_destroy(D);
@@ -533,7 +534,7 @@ extern "C" mrf_status mrf_dict_destroy(mrf_dict_t D) {
   clear_error();
   if (!D) return MRF_OK;
   hipFree(D->lut); hipFree(D->norms); hipFree(D->dhr); hipFree(D->bpk); hipFree(D->V); hipFree(D->dn);
-  hipFree(D->d16); hipFree(D->d8); hipFree(D->s8);
+  hipFree(D->d16); hipFree(D->d16lo); hipFree(D->d8); hipFree(D->s8);
   delete D;
   return MRF_OK;
 }

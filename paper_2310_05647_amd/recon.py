@@ -51,7 +51,7 @@ class Recon:
                                          col.ctypes.data_as(ip), val.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                                          float(sigma2), float(lmax)), "mrf_recon_inject_graph")
 
-    MATCH_MODES = {"subspace": 4, "fp32": 0, "bf16": 1, "fp8": 2, "learned": 3}
+    MATCH_MODES = {"subspace": 4, "fp32": 0, "bf16": 1, "fp8": 2, "learned": 3, "bf16x3": 5}
 
     def set_final_match(self, mode="subspace", mlp=None, theta=0.0):
         """The final match of the run (mrf_recon_set_final_match): "subspace" (default), "fp32",

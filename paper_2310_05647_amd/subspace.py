@@ -50,7 +50,7 @@ def subspace_project(U, V, stream=None):
     return out
 
 
-MATCH_MODES = {"fp32": 0, "bf16": 1, "fp8": 2}
+MATCH_MODES = {"fp32": 0, "bf16": 1, "fp8": 2, "bf16x3": 5}
 
 
 def frames_to_voxels(X, stream=None):
@@ -93,10 +93,10 @@ class Dictionary:
                                           stream_ptr(stream)), "mrf_dict_match_subspace")
         return idx, rho, score, params
 
-    def match(self, fp, mode="fp32", want_cand=False, stream=None):
+    def match(self, fp, mode="fp32", want_cand=False, depth=4, stream=None):
         """Full-length match of fp [Nv, L] complex64 (device). mode: "fp32", "bf16" or "fp8"
-        (top-4 on MFMA in that precision, then an FP32 re-rank). Returns (idx, rho, score, params)
-        and, with want_cand, the [Nv, 4] candidates of the re-rank."""
+        (the `depth` best on MFMA in that precision, then an FP32 re-rank; mrf_dict_match_depth).
+        Returns (idx, rho, score, params) and, with want_cand, the [Nv, depth] re-rank candidates."""
         Nv = fp.shape[0]
         need(fp, torch.complex64, (Nv, self.L), "fp")
         m = MATCH_MODES[mode]
@@ -108,9 +108,10 @@ class Dictionary:
         rho = torch.empty(Nv, dtype=torch.float32, device=dev)
         score = torch.empty(Nv, dtype=torch.float32, device=dev)
         params = torch.empty((Nv, self.nparam), dtype=torch.float32, device=dev)
-        cand = torch.empty((Nv, 4), dtype=torch.int32, device=dev) if want_cand else None
-        check(lib.mrf_dict_match(self.handle, ptr(fp), Nv, m, ptr(idx), ptr(rho), ptr(score), ptr(params), ptr(cand),
-                                 ptr(ws), ws.numel(), stream_ptr(stream)), "mrf_dict_match")
+        cand = torch.empty((Nv, depth), dtype=torch.int32, device=dev) if want_cand else None
+        check(lib.mrf_dict_match_depth(self.handle, ptr(fp), Nv, m, int(depth), ptr(idx), ptr(rho), ptr(score),
+                                       ptr(params), ptr(cand), ptr(ws), ws.numel(), stream_ptr(stream)),
+              "mrf_dict_match_depth")
         out = (idx, rho, score, params)
         return out + (cand,) if want_cand else out
 

@@ -103,7 +103,7 @@ def _check(mode, fp, atoms, lut, out, ref):
     np.testing.assert_array_equal(params[same], rparams[same].astype(np.float32))
     # the candidates are distinct atoms, best first by the low-precision score
     c = cand[rscore > 0]
-    assert np.all((c[:, :, None] != c[:, None, :]) | np.eye(4, dtype=bool)[None])
+    assert np.all((c[:, :, None] != c[:, None, :]) | np.eye(c.shape[1], dtype=bool)[None])
     return diff.size, outside, float(same.mean())
 
 
@@ -171,3 +171,49 @@ def test_full_match_degenerate_sizes():
         assert idx[0] == 1 and cand[0, 3] == -1 and sorted(cand[0, :3]) == [0, 1, 2]
         np.testing.assert_allclose(rho[0], 2.0, rtol=1e-5)
         np.testing.assert_array_equal(params[0], lut[1])
+
+
+def test_rerank_depth_c3_dictionary():
+    """The re-rank depth (mrf_dict_match_depth) on the 50 000-atom dictionary: at every depth the
+    result is exact wherever the FP64 best is among the candidates (the checks of _check), the
+    candidates of depth d are the first d of depth 32 (one ordering by the low-precision score),
+    and the agreement with FP64 does not fall as the depth grows."""
+    from paper_2310_05647_amd import Dictionary
+    cfg = mrfgen.get_config("C3")
+    atoms, grid = mrfgen.make_dictionary(cfg)
+    lut = grid["lut"]
+    fp = _fingerprints(cfg, 1024, cfg["L"], 12, b1=True)
+    ref = omatch.precision_match_ref(fp, atoms, lut)
+    d = Dictionary(to_dev(atoms), to_dev(lut))
+    for mode in ("bf16", "fp8"):
+        deep = d.match(to_dev(fp), mode=mode, want_cand=True, depth=32)[4].cpu().numpy()
+        prev = -1.0
+        for depth in (4, 8, 16, 32):
+            out = d.match(to_dev(fp), mode=mode, want_cand=True, depth=depth)
+            nd, outside, agree = _check(mode, fp, atoms, lut, out, ref)
+            cand = out[4].cpu().numpy()
+            live = np.abs(fp).sum(1) > 0
+            np.testing.assert_array_equal(cand[live], deep[live, :depth])
+            say(f"C3 {mode} depth {depth}: agreement {agree:.4f} ({outside} with the FP64 best outside the candidates)")
+            # a deeper re-rank can only add FP32 near-tie flips (two voxels of slack for them)
+            assert agree >= prev - 2.0 / fp.shape[0]
+            prev = agree
+
+
+def test_split_bf16_match_reaches_fp32_agreement():
+    """Split BF16 (hi + lo parts, three BF16 products per score) on the 50 000-atom dictionary:
+    scores within about 1e-5 of FP32's, so with the FP32 re-rank of 4 the index agreement with the
+    FP64 oracle matches the FP32 mode's (>= 0.99), and the result is exact wherever the FP64 best
+    reached the re-rank."""
+    from paper_2310_05647_amd import Dictionary
+    cfg = mrfgen.get_config("C3")
+    atoms, grid = mrfgen.make_dictionary(cfg)
+    lut = grid["lut"]
+    fp = _fingerprints(cfg, 1024, cfg["L"], 13, b1=True)
+    ref = omatch.precision_match_ref(fp, atoms, lut)
+    d = Dictionary(to_dev(atoms), to_dev(lut))
+    for depth in (4, 8):
+        out = d.match(to_dev(fp), mode="bf16x3", want_cand=True, depth=depth)
+        nd, outside, agree = _check("bf16x3", fp, atoms, lut, out, ref)
+        say(f"C3 split bf16 depth {depth}: agreement {agree:.4f} ({outside} with the FP64 best outside the candidates)")
+        assert agree >= 0.99
