@@ -13,7 +13,8 @@
 //             [snr_lo, snr_hi] dB from u2, and (c = 1, 2, ...) Box-Muller normals for complex noise
 //             of variance 10^(-SNR/10) / L per coefficient (exact in distribution in the subspace:
 //             the columns of V are orthonormal); alpha = exp(i phase) d_m V / ||d_m|| + noise
-//   gate      k* = the grid atom nearest to the prediction in (log T1, log T2); residual =
+//   gate      k* = the kept grid atom nearest to the prediction in Euclidean distance on
+//             (log T1, log T2), ties to the lower index; residual =
 //             1 - |<d_k* V / ||d_k*||, alpha / ||alpha||>|; residual > theta -> exhaustive match.
 //
 // GEMMs: one MFMA kernel with 64 x 64 output tiles (4 waves of 32 x 32), K staged through LDS in
@@ -283,15 +284,28 @@ __global__ __launch_bounds__(256) void k_reduce_slices(const float* __restrict__
 }
 
 // db[n] = sum_b G[b][n]: block per 64 columns, 4 row phases, fixed-order tree
-__global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ G, int Bn, int N, float* __restrict__ db) {
+// Column sums db[c] = sum_b G[b][c] in two fixed-order stages: block (x, y) sums rows
+// y * kColRows .. of 64 columns into part[y][c] (4 row phases per column, then a fixed tree), and
+// one thread per column adds the partials in order.
+constexpr int kColRows = 128;
+__global__ __launch_bounds__(256) void k_colsum_part(const float* __restrict__ G, int Bn, int N, float* __restrict__ part) {
   __shared__ float red[4][64];
   const int c = blockIdx.x * 64 + (threadIdx.x & 63), ph = threadIdx.x >> 6;
+  const int b0 = blockIdx.y * kColRows, b1 = min(Bn, b0 + kColRows);
   float s = 0.f;
   if (c < N)
-    for (int b = ph; b < Bn; b += 4) s += G[(size_t)b * N + c];
+    for (int b = b0 + ph; b < b1; b += 4) s += G[(size_t)b * N + c];
   red[ph][threadIdx.x & 63] = s;
   __syncthreads();
-  if (ph == 0 && c < N) db[c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+  if (ph == 0 && c < N)
+    part[(size_t)blockIdx.y * N + c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+__global__ __launch_bounds__(256) void k_colsum_final(const float* __restrict__ part, int nch, int N, float* __restrict__ db) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= N) return;
+  float s = 0.f;
+  for (int k = 0; k < nch; ++k) s += part[(size_t)k * N + c];
+  db[c] = s;
 }
 
 // g = 2 (y - t) / (B nout); per-block partial sums of (y - t)^2 into lpart
@@ -518,7 +532,11 @@ mrf_status mlp_backward(mrf_mlp_s* P, bool bf16, int B, TrainWs& w, hipStream_t 
     else e = gemm<false, LAY_MN, LAY_MN, EPI_STORE>(out, in, B, gout, out, w.acts[l], in, w.part, in, nullptr, nullptr, 0, kSplitK, s, "mlp_dw");
     if (e) return e;
     MRF_LAUNCH("mlp_dw_reduce", s, k_reduce_slices<<<ceil_div((long)out * in, 256), 256, 0, s>>>(w.part, kSplitK, (long)out * in, dW));
-    MRF_LAUNCH("mlp_db", s, k_colsum<<<ceil_div(out, 64), 256, 0, s>>>(gout, B, out, db));
+    {  // the split-K partials were consumed by the reduction above: their buffer holds these
+      const int nch = ceil_div(B, kColRows);
+      MRF_LAUNCH("mlp_db", s, k_colsum_part<<<dim3(ceil_div(out, 64), nch), 256, 0, s>>>(gout, B, out, w.part));
+      MRF_LAUNCH("mlp_db", s, k_colsum_final<<<ceil_div(out, 256), 256, 0, s>>>(w.part, nch, out, db));
+    }
     if (l > 0) {
       // gin[b][in] = (sum_o gout[b][o] W[o][in]) * (h[b][in] > 0)
       const float* W = P->p + P->offW[l];
