@@ -3,7 +3,7 @@
 This package is shared by the CPU oracle's tests and by the GPU library's tests and
 benchmark. It draws random numbers and simulates the inputs the method takes
 (sequence, dictionary + look-up table, projection basis, phantom maps, ground-truth
-fingerprints, trajectories, measurement noise). It contains none of the
+fingerprints, trajectories, coil sensitivities, measurement noise). It contains none of the
 reconstruction's own arithmetic: no NUFFT, no patch operator, no graph, no
 thresholding and no matching.
 """
@@ -15,9 +15,10 @@ from .phantom import make_phantom
 from .fingerprints import truth_fingerprints
 from .traj import vds_spiral
 from .noise import complex_noise, noise_sigma
+from .coils import coil_maps
 
 __all__ = [
     "CONFIGS", "get_config", "fisp_sequence", "make_dictionary", "param_grid",
     "subspace_basis", "make_phantom", "truth_fingerprints", "vds_spiral",
-    "complex_noise", "noise_sigma",
+    "complex_noise", "noise_sigma", "coil_maps",
 ]

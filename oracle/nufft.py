@@ -1,4 +1,5 @@
-"""Oracle: the single-coil acquisition operator A = F_u of eq. (1) and its adjoint.
+"""Oracle: the acquisition operator of eq. (1), single-coil A = F_u and multi-coil A = F_u C, and
+their adjoints.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -20,7 +21,10 @@ inverse DFT times G^2, crop, deapodise, scale 1/N).
 
 Pins: brute-force NUDFT on tiny grids, the adjoint identity, the full Cartesian
 special case against numpy's orthonormal FFT, the I0 series against scipy, and the
-closed-form phi_hat against numerical quadrature (tests/test_oracle_nufft.py).
+closed-form phi_hat against numerical quadrature (tests/test_oracle_nufft.py); for the
+multi-coil pair, a dense brute-force stack of NUDFT diag(S_c) blocks, its adjoint identity,
+the single-coil reduction (one coil of sensitivity 1), and A^H A = I for full Cartesian
+sampling with sum_c |S_c|^2 = 1.
 """
 import math
 
@@ -161,6 +165,39 @@ def operator_norm(traj, N, x0, iters=30, osf=2, W=6):
     lam = 0.0
     for _ in range(iters):
         y = nufft_adj(nufft_fwd(x, traj, osf, W), traj, N, osf, W)
+        lam = float(np.vdot(x, y).real)
+        x = y / np.linalg.norm(y)
+    return lam
+
+
+# ---------------------------------------------------------------- multi-coil acquisition
+# Eq. (1) with coil sensitivities: the acquisition is A = F_u C, where C stacks the coils'
+# pixel-wise sensitivity maps S_c and F_u is the single-coil operator above applied to every
+# coil image: b_c = F_u (S_c X). Its adjoint combines the coils: A^H b = sum_c conj(S_c) F_u^H b_c.
+
+def nufft_fwd_mc(X, traj, smaps, osf=2, W=6):
+    """b [Nc, L, Ns] with b_c = A (S_c X); smaps [Nc, N, N] complex."""
+    X = np.asarray(X, np.complex128)
+    return np.stack([nufft_fwd(X * np.asarray(S, np.complex128)[None], traj, osf, W) for S in smaps])
+
+
+def nufft_adj_mc(b, traj, N, smaps, osf=2, W=6):
+    """X = sum_c conj(S_c) A^H b_c, the exact adjoint of nufft_fwd_mc; b [Nc, L, Ns]."""
+    b = np.asarray(b, np.complex128)
+    out = None
+    for c, S in enumerate(smaps):
+        term = np.conj(np.asarray(S, np.complex128))[None] * nufft_adj(b[c], traj, N, osf, W)
+        out = term if out is None else out + term
+    return out
+
+
+def operator_norm_mc(traj, N, smaps, x0, iters=30, osf=2, W=6):
+    """lambda_max(A^H A) of the multi-coil operator by power iteration from x0 [L, N, N]."""
+    x = np.asarray(x0, np.complex128)
+    x = x / np.linalg.norm(x)
+    lam = 0.0
+    for _ in range(iters):
+        y = nufft_adj_mc(nufft_fwd_mc(x, traj, smaps, osf, W), traj, N, smaps, osf, W)
         lam = float(np.vdot(x, y).real)
         x = y / np.linalg.norm(y)
     return lam
