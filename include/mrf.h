@@ -103,6 +103,25 @@ mrf_status mrf_nufft_autotune(const mrf_nufft_desc* desc, const float* traj, int
  * synchronises. Algorithm 1's step-size rule takes this bound (see mrf_recon_params.lamA). */
 mrf_status mrf_nufft_opnorm(mrf_nufft_plan_t plan, int iters, unsigned seed, double* lam, hipStream_t stream);
 
+/* Multi-coil acquisition (Sec. II, eq. (1)): the forward operator is F_u C, where C multiplies
+ * every frame by each coil's sensitivity map and F_u is the single-coil operator above.
+ *   smaps  device complex64 [ncoils][N][N], one map per coil, shared by all frames; caller-owned,
+ *          read during the call only.
+ *   ksp    [ncoils][L][Ns]: coil c's series at ksp + c L Ns.
+ * mrf_nufft_fwd_mc : ksp_c = A (S_c img) for every coil.
+ * mrf_nufft_adj_mc : img = sum_c conj(S_c) A^H ksp_c, coils summed in index order (overwrites
+ *                    img; deterministic run to run).
+ * Same workspace as the single-coil calls (coils run one after another on `stream`; the cost is
+ * ncoils single-coil transforms). Errors: MRF_INVALID_ARG for null pointers or ncoils < 1,
+ * MRF_WORKSPACE for a missing or short workspace. */
+mrf_status mrf_nufft_fwd_mc(mrf_nufft_plan_t plan, const mrf_c64* smaps, int ncoils, const mrf_c64* img,
+                            mrf_c64* ksp, void* ws, size_t ws_bytes, hipStream_t stream);
+mrf_status mrf_nufft_adj_mc(mrf_nufft_plan_t plan, const mrf_c64* smaps, int ncoils, const mrf_c64* ksp,
+                            mrf_c64* img, void* ws, size_t ws_bytes, hipStream_t stream);
+/* lambda_max((F_u C)^H F_u C) by power iteration, as mrf_nufft_opnorm (smaps null: single coil). */
+mrf_status mrf_nufft_opnorm_mc(mrf_nufft_plan_t plan, const mrf_c64* smaps, int ncoils, int iters, unsigned seed,
+                               double* lam, hipStream_t stream);
+
 
 /* ====================================================================================
  * Patch graph on the parameter manifold (Sec. III-A): eq. (8) weights, eq. (10) Laplacian,
@@ -382,6 +401,15 @@ mrf_status mrf_recon_destroy(mrf_recon_t r);
 /* Initialisation of Algorithm 1 with measurements b [L][Ns] (kept by pointer until the last
  * call that uses it) and an optional X0 [L][n][n] (NULL: X0 = A^H b). Synchronises. */
 mrf_status mrf_recon_init(mrf_recon_t r, const mrf_c64* b, const mrf_c64* X0, hipStream_t stream);
+/* Multi-coil data (eq. (1)): from the next mrf_recon_init on, the data term is
+ * 0.5 ||F_u C X - b||^2 with C the coil sensitivities smaps [ncoils][n][n] (device complex64,
+ * copied here; the caller's buffer may be freed afterwards), b then holds ncoils series
+ * [ncoils][L][Ns], X0 = A^H b is the coil-combined adjoint and lamA must bound
+ * lambda_max((F_u C)^H F_u C) (mrf_nufft_opnorm_mc). smaps NULL returns to a single coil. Clears
+ * the initialised state (call mrf_recon_init again); allocates the residual for all coils and
+ * synchronises. A checkpoint records the coil count and loads only into a recon with the same
+ * count. MRF_INVALID_ARG for a null handle or ncoils < 1 with maps, MRF_OOM. */
+mrf_status mrf_recon_set_coils(mrf_recon_t r, const mrf_c64* smaps, int ncoils, hipStream_t stream);
 /* Runs up to n more iterations (stops early on the tolerance or at n_max). Synchronises once
  * per iteration to read the cost. *stopped (may be NULL) is set when no iteration is left. */
 mrf_status mrf_recon_iterate(mrf_recon_t r, int n, int* stopped, hipStream_t stream);

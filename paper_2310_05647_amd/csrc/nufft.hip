@@ -77,10 +77,13 @@ __device__ inline bool strip_and_chunk(int nstrips, int nchunks, int& sx, int& c
 
 // Row pass, forward: rows of X (deapodised, zero-padded to G) -> T rows. Grid-stride over groups
 // of RPB rows; the next group's inputs are loaded into registers while this group transforms.
+// A sensitivity map smap (N x N, shared by all frames; null for a single coil) multiplies each
+// pixel first: the multi-coil operator of eq. (1) runs this pass once per coil.
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_row_fwd(const cf* __restrict__ X, cf* __restrict__ T,
                                                     const float* __restrict__ dinv,
-                                                    const cf* __restrict__ twg, int nrows) {
+                                                    const cf* __restrict__ twg, int nrows,
+                                                    const cf* __restrict__ smap) {
   constexpr int N = G / 2;
   constexpr int RPB = row_rpb(G);          // rows per group
   constexpr int PS = 3;                    // one pad element per 8 (LDS banks)
@@ -114,7 +117,8 @@ __global__ __launch_bounds__(kBlock) void k_row_fwd(const cf* __restrict__ X, cf
         const int y = (int)(row % N);
         int n = x - N / 2;
         if (n < 0) n += G;
-        buf[rr * TS + padx<PS>(n)] = cscale(pre[i], dinv[x] * dinv[y]);
+        const cf v = smap ? cmul(smap[y * N + x], pre[i]) : pre[i];   // coil c sees S_c x
+        buf[rr * TS + padx<PS>(n)] = cscale(v, dinv[x] * dinv[y]);
       }
     }
     lds_sync();
@@ -129,11 +133,14 @@ __global__ __launch_bounds__(kBlock) void k_row_fwd(const cf* __restrict__ X, cf
   }
 }
 
-// Row pass, adjoint: T rows -> inverse transform -> crop to N columns, deapodise, scale.
+// Row pass, adjoint: T rows -> inverse transform -> crop to N columns, deapodise, scale. With a
+// sensitivity map the result is multiplied by its conjugate and, for every coil after the first,
+// added to X: the adjoint of the multi-coil operator, one coil per launch.
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_row_adj(const cf* __restrict__ T, cf* __restrict__ X,
                                                     const float* __restrict__ dinv,
-                                                    const cf* __restrict__ twg, int nrows, float scale) {
+                                                    const cf* __restrict__ twg, int nrows, float scale,
+                                                    const cf* __restrict__ smap, int accumulate) {
   constexpr int N = G / 2;
   constexpr int RPB = row_rpb(G);
   constexpr int PS = 3;
@@ -171,7 +178,10 @@ __global__ __launch_bounds__(kBlock) void k_row_adj(const cf* __restrict__ T, cf
         int n = x - N / 2;
         if (n < 0) n += G;
         const int y = (int)(row % N);
-        X[row * N + x] = cscale(buf[rr * TS + padx<PS>(n)], dinv[x] * dinv[y] * scale);
+        cf v = cscale(buf[rr * TS + padx<PS>(n)], dinv[x] * dinv[y] * scale);
+        if (smap) v = cconjmul(smap[y * N + x], v);          // coil combine: conj(S_c) A_c^H b_c
+        if (accumulate) v = cadd(X[row * N + x], v);         // coils summed in index order
+        X[row * N + x] = v;
       }
     }
     lds_sync();
@@ -804,19 +814,21 @@ static int row_blocks(long ngroups) {
 }
 
 template <int G, int TX>
-static void launch_fwd_g(const mrf_nufft_plan_s* p, const cf* img, cf* T, cf* part, hipStream_t s) {
+static void launch_fwd_g(const mrf_nufft_plan_s* p, const cf* img, cf* T, cf* part, const cf* smap,
+                         hipStream_t s) {
   const int nrows = p->L * p->N;
   constexpr int RPB = row_rpb(G);
   const int FC = frames_per_chunk(p);
   MRF_LAUNCH("nufft_row_fwd", s,
              k_row_fwd<G><<<row_blocks<k_row_fwd<G>>((nrows + RPB - 1) / RPB), kBlock, 0, s>>>(img, T, p->dinv,
-                                                                                          p->tw, nrows));
+                                                                                          p->tw, nrows, smap));
   MRF_LAUNCH("nufft_col_fwd", s,
              k_col_fwd<G, TX><<<col_blocks(p, FC), kBlock, 0, s>>>(T, p->ent, p->tile_ptr, p->tw, part, p->L, FC));
 }
 
 template <int G, int TX>
-static void launch_adj_g(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, cf* T, cf* rg, hipStream_t s) {
+static void launch_adj_g(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, cf* T, cf* rg, const cf* smap,
+                         int accumulate, hipStream_t s) {
   const int nrows = p->L * p->N;
   constexpr int RPB = row_rpb(G);
   const int FC = frames_per_chunk(p);
@@ -828,7 +840,8 @@ static void launch_adj_g(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, cf* 
   MRF_LAUNCH("nufft_row_adj", s,
              k_row_adj<G><<<row_blocks<k_row_adj<G>>((nrows + RPB - 1) / RPB), kBlock, 0, s>>>(T, img, p->dinv,
                                                                                           p->tw, nrows,
-                                                                                          1.0f / p->N));
+                                                                                          1.0f / p->N, smap,
+                                                                                          accumulate));
 }
 
 #define MRF_DISPATCH_G_TX(FN, ...)                                                   \
@@ -852,10 +865,11 @@ static void launch_adj_g(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, cf* 
     default: return fail(MRF_SHAPE, "nufft: unsupported grid / tile combination");  \
   }
 
-mrf_status nufft_fwd_partials(const mrf_nufft_plan_s* p, const cf* img, void* ws, hipStream_t s) {
+mrf_status nufft_fwd_partials(const mrf_nufft_plan_s* p, const cf* img, void* ws, hipStream_t s,
+                              const cf* smap = nullptr) {
   cf* T = (cf*)ws;
   cf* part = (cf*)((char*)ws + p->ws_T);
-  MRF_DISPATCH_G_TX(launch_fwd_g, p, img, T, part, s);
+  MRF_DISPATCH_G_TX(launch_fwd_g, p, img, T, part, smap, s);
   MRF_CHECK_LAUNCH();
   return MRF_OK;
 }
@@ -866,17 +880,24 @@ mrf_status sum_partials(const double* part, long n, double* out, hipStream_t s);
 
 long nufft_resid_blocks(const mrf_nufft_plan_s* p) { return ceil_div((long)p->L * p->Ns, kBlock); }
 
-// r = A img - b and rn2 (device double) = ||r||^2; part needs nufft_resid_blocks doubles.
+// r = A img - b and rn2 (device double) = ||r||^2; part needs nufft_resid_blocks doubles per coil.
+// With ncoils >= 1 sensitivity maps (smaps [ncoils][N][N]) A is the multi-coil operator of eq. (1):
+// b and r hold ncoils k-space series one after another, and ||r||^2 sums over all of them in one
+// fixed-order reduction of the coils' block partials.
 mrf_status nufft_residual(const mrf_nufft_plan_s* p, const cf* img, const cf* b, cf* r, void* ws, double* part,
-                          double* rn2, hipStream_t s) {
-  mrf_status st = nufft_fwd_partials(p, img, ws, s);
-  if (st != MRF_OK) return st;
-  const long total = (long)p->L * p->Ns;
-  MRF_LAUNCH("nufft_combine_resid", s,
-             k_combine_resid<<<ceil_div(total, kBlock), kBlock, 0, s>>>(nufft_partials(p, ws), p->samp_ent, b, r,
-                                                                        total, 1.0f / p->N, part));
-  MRF_CHECK_LAUNCH();
-  return sum_partials(part, nufft_resid_blocks(p), rn2, s);
+                          double* rn2, hipStream_t s, const cf* smaps, int ncoils) {
+  const long total = (long)p->L * p->Ns, nb = nufft_resid_blocks(p);
+  const long nc = smaps ? ncoils : 1;
+  for (long c = 0; c < nc; ++c) {
+    mrf_status st = nufft_fwd_partials(p, img, ws, s, smaps ? smaps + c * p->N * p->N : nullptr);
+    if (st != MRF_OK) return st;
+    MRF_LAUNCH("nufft_combine_resid", s,
+               k_combine_resid<<<ceil_div(total, kBlock), kBlock, 0, s>>>(nufft_partials(p, ws), p->samp_ent,
+                                                                          b + c * total, r + c * total, total,
+                                                                          1.0f / p->N, part + c * nb));
+    MRF_CHECK_LAUNCH();
+  }
+  return sum_partials(part, nc * nb, rn2, s);
 }
 
 int nufft_n(const mrf_nufft_plan_s* p) { return p->N; }
@@ -885,11 +906,25 @@ int nufft_nsamp(const mrf_nufft_plan_s* p) { return p->Ns; }
 size_t nufft_ws_bytes(const mrf_nufft_plan_s* p) { return p->ws_bytes; }
 const int4* nufft_samp_ent(const mrf_nufft_plan_s* p) { return p->samp_ent; }
 
-mrf_status nufft_adj_impl(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, void* ws, hipStream_t s) {
+mrf_status nufft_adj_impl(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, void* ws, hipStream_t s,
+                          const cf* smap = nullptr, int accumulate = 0) {
   cf* T = (cf*)ws;
   cf* rg = (cf*)((char*)ws + p->ws_T);
-  MRF_DISPATCH_G_TX(launch_adj_g, p, ksp, img, T, rg, s);
+  MRF_DISPATCH_G_TX(launch_adj_g, p, ksp, img, T, rg, smap, accumulate, s);
   MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+
+// img = sum_c conj(S_c) A^H ksp_c over the coils in index order (the adjoint of eq. (1)'s F_u C);
+// smaps null: the single-coil adjoint.
+mrf_status nufft_adj_coils(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, void* ws, hipStream_t s,
+                           const cf* smaps, int ncoils) {
+  if (!smaps) return nufft_adj_impl(p, ksp, img, ws, s);
+  const long total = (long)p->L * p->Ns;
+  for (long c = 0; c < ncoils; ++c) {
+    mrf_status st = nufft_adj_impl(p, ksp + c * total, img, ws, s, smaps + c * p->N * p->N, c > 0);
+    if (st != MRF_OK) return st;
+  }
   return MRF_OK;
 }
 
@@ -918,10 +953,43 @@ extern "C" mrf_status mrf_nufft_adj(mrf_nufft_plan_t p, const mrf_c64* ksp, mrf_
   return nufft_adj_impl(p, (const cf*)ksp, (cf*)img, ws, s);
 }
 
+extern "C" mrf_status mrf_nufft_fwd_mc(mrf_nufft_plan_t p, const mrf_c64* smaps, int ncoils, const mrf_c64* img,
+                                       mrf_c64* ksp, void* ws, size_t ws_bytes, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(p && smaps && img && ksp, MRF_INVALID_ARG, "nufft_fwd_mc: null argument");
+  MRF_REQUIRE(ncoils >= 1, MRF_INVALID_ARG, "nufft_fwd_mc: ncoils must be >= 1");
+  MRF_REQUIRE(ws && ws_bytes >= p->ws_bytes, MRF_WORKSPACE, "nufft_fwd_mc: workspace missing or too small");
+  const long total = (long)p->L * p->Ns;
+  for (long c = 0; c < ncoils; ++c) {
+    mrf_status st = nufft_fwd_partials(p, (const cf*)img, ws, s, (const cf*)smaps + c * p->N * p->N);
+    if (st != MRF_OK) return st;
+    MRF_LAUNCH("nufft_combine", s,
+               k_combine<<<ceil_div(total, kBlock), kBlock, 0, s>>>(nufft_partials(p, ws), p->samp_ent,
+                                                                    (cf*)ksp + c * total, total, 1.0f / p->N));
+    MRF_CHECK_LAUNCH();
+  }
+  return MRF_OK;
+}
+
+extern "C" mrf_status mrf_nufft_adj_mc(mrf_nufft_plan_t p, const mrf_c64* smaps, int ncoils, const mrf_c64* ksp,
+                                       mrf_c64* img, void* ws, size_t ws_bytes, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(p && smaps && img && ksp, MRF_INVALID_ARG, "nufft_adj_mc: null argument");
+  MRF_REQUIRE(ncoils >= 1, MRF_INVALID_ARG, "nufft_adj_mc: ncoils must be >= 1");
+  MRF_REQUIRE(ws && ws_bytes >= p->ws_bytes, MRF_WORKSPACE, "nufft_adj_mc: workspace missing or too small");
+  return nufft_adj_coils(p, (const cf*)ksp, (cf*)img, ws, s, (const cf*)smaps, ncoils);
+}
+
 extern "C" mrf_status mrf_nufft_opnorm(mrf_nufft_plan_t p, int iters, unsigned seed, double* lam, hipStream_t s) {
+  return mrf_nufft_opnorm_mc(p, nullptr, 0, iters, seed, lam, s);
+}
+
+extern "C" mrf_status mrf_nufft_opnorm_mc(mrf_nufft_plan_t p, const mrf_c64* smaps, int ncoils, int iters,
+                                          unsigned seed, double* lam, hipStream_t s) {
   clear_error();
   MRF_REQUIRE(p && lam && iters >= 1, MRF_INVALID_ARG, "nufft_opnorm: null argument or iters < 1");
-  const long nimg = (long)p->L * p->N * p->N, nksp = (long)p->L * p->Ns;
+  MRF_REQUIRE(!smaps || ncoils >= 1, MRF_INVALID_ARG, "nufft_opnorm: ncoils must be >= 1 with sensitivity maps");
+  const long nimg = (long)p->L * p->N * p->N, nksp = (long)p->L * p->Ns * (smaps ? ncoils : 1);
   cf *x = nullptr, *y = nullptr, *k = nullptr;
   void* ws = nullptr;
   double* d = nullptr;
@@ -940,8 +1008,13 @@ extern "C" mrf_status mrf_nufft_opnorm(mrf_nufft_plan_t p, int iters, unsigned s
   k_sum_pairs<<<1, 1, 0, s>>>(d, nb, d + 2 * nb);
   k_scale_c<<<1024, 256, 0, s>>>(x, nimg, d + 2 * nb + 1);
   for (int it = 0; it < iters && st == MRF_OK; ++it) {
-    st = mrf_nufft_fwd(p, (const mrf_c64*)x, (mrf_c64*)k, ws, p->ws_bytes, s);
-    if (st == MRF_OK) st = mrf_nufft_adj(p, (const mrf_c64*)k, (mrf_c64*)y, ws, p->ws_bytes, s);
+    if (smaps) {
+      st = mrf_nufft_fwd_mc(p, smaps, ncoils, (const mrf_c64*)x, (mrf_c64*)k, ws, p->ws_bytes, s);
+      if (st == MRF_OK) st = mrf_nufft_adj_mc(p, smaps, ncoils, (const mrf_c64*)k, (mrf_c64*)y, ws, p->ws_bytes, s);
+    } else {
+      st = mrf_nufft_fwd(p, (const mrf_c64*)x, (mrf_c64*)k, ws, p->ws_bytes, s);
+      if (st == MRF_OK) st = mrf_nufft_adj(p, (const mrf_c64*)k, (mrf_c64*)y, ws, p->ws_bytes, s);
+    }
     if (st != MRF_OK) break;
     k_dots<<<nb, kBlock, 0, s>>>(x, y, nimg, d);               // <x, y> (x unit norm), ||y||^2
     k_sum_pairs<<<1, 1, 0, s>>>(d, nb, d + 2 * nb);

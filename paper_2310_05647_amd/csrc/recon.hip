@@ -29,8 +29,9 @@
 namespace mrf {
 // nufft.hip
 mrf_status nufft_residual(const mrf_nufft_plan_s* p, const cf* img, const cf* b, cf* r, void* ws, double* part,
-                          double* rn2, hipStream_t s);
-mrf_status nufft_adj_impl(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, void* ws, hipStream_t s);
+                          double* rn2, hipStream_t s, const cf* smaps, int ncoils);
+mrf_status nufft_adj_coils(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, void* ws, hipStream_t s,
+                           const cf* smaps, int ncoils);
 long nufft_resid_blocks(const mrf_nufft_plan_s* p);
 int nufft_n(const mrf_nufft_plan_s* p);
 int nufft_frames(const mrf_nufft_plan_s* p);
@@ -148,6 +149,13 @@ struct mrf_recon_s {
   size_t fin_ws_bytes = 0;
   float* fin_prm = nullptr;     // [Nv][nparam] (full-length modes) or [Nv][2] (learned)
   std::chrono::steady_clock::time_point t_step;   // enqueue time of the iteration in flight
+  // coil sensitivities (mrf_recon_set_coils): a device copy, and the residual and its block
+  // partials sized for all coils; res1 / rpart1 are the single-coil buffers of mrf_recon_create
+  cf* smaps = nullptr;
+  int ncoils = 0;
+  cf* res1 = nullptr;
+  double* rpart1 = nullptr;
+  std::vector<void*> coil_bufs;
 };
 
 namespace {
@@ -207,7 +215,8 @@ mrf_status evaluate_enqueue(mrf_recon_s* R, hipStream_t s) {
                        nullptr, aux_stream(R, 0, 1, s))))
     return e;
   if ((e = lap_quad(R->graph, R->X, R->L, R->sc + SC_QUAD, aux_stream(R, 1, 1, s)))) return e;
-  if ((e = nufft_residual(R->plan, R->X, R->b, R->res, R->nws, R->rpart, R->sc + SC_RN2, s))) return e;
+  if ((e = nufft_residual(R->plan, R->X, R->b, R->res, R->nws, R->rpart, R->sc + SC_RN2, s, R->smaps, R->ncoils)))
+    return e;
   if ((e = join(R, 0, 1, s)) || (e = join(R, 1, 1, s))) return e;
   MRF_LAUNCH("recon_cost", s, k_cost<<<1, 1, 0, s>>>(R->sc, R->prm.lam2));
   MRF_CHECK_LAUNCH();
@@ -299,6 +308,8 @@ extern "C" mrf_status mrf_recon_create(const mrf_recon_params* prm, mrf_nufft_pl
             (R->rws2 = alloc(reduce_ws_bytes(L, (int)Nv, (int)rr))) && (R->lws = alloc(llr_ws_bytes(R->g, (int)rc))) &&
             (R->sc = (double*)alloc(SC_N * 8)) && (R->rpart = (double*)alloc(nufft_resid_blocks(plan) * 8));
   if (ok) ok = hipHostMalloc((void**)&R->hsc, SC_N * sizeof(double), hipHostMallocDefault) == hipSuccess;
+  R->res1 = R->res;
+  R->rpart1 = R->rpart;
   if (!ok) {
     mrf_recon_destroy(R);
     return fail(MRF_OOM, "recon_create: device allocation failed");
@@ -326,6 +337,7 @@ extern "C" mrf_status mrf_recon_destroy(mrf_recon_t R) {
   }
   if (R->ev_fork) hipEventDestroy(R->ev_fork);
   for (void* p : R->allocs) hipFree(p);
+  for (void* p : R->coil_bufs) hipFree(p);
   for (auto& g : R->inj) {
     hipFree(g.rowptr); hipFree(g.col); hipFree(g.val); hipFree(g.scal);
   }
@@ -334,6 +346,40 @@ extern "C" mrf_status mrf_recon_destroy(mrf_recon_t R) {
   if (R->hsc) hipHostFree(R->hsc);
   mrf_graph_destroy(R->graph);
   delete R;
+  return MRF_OK;
+}
+
+// Multi-coil data (eq. (1)): the data term's operator becomes F_u C. Copies the maps; the residual
+// buffer grows to ncoils series. The recon must be initialised again afterwards.
+extern "C" mrf_status mrf_recon_set_coils(mrf_recon_t R, const mrf_c64* smaps, int ncoils, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(R, MRF_INVALID_ARG, "recon_set_coils: null handle");
+  MRF_REQUIRE(!smaps || ncoils >= 1, MRF_INVALID_ARG, "recon_set_coils: ncoils must be >= 1 with sensitivity maps");
+  MRF_CHECK_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < 2; ++k) MRF_CHECK_HIP(hipStreamSynchronize(R->aux[k]));
+  for (void* p : R->coil_bufs) hipFree(p);
+  R->coil_bufs.clear();
+  R->smaps = nullptr;
+  R->ncoils = 0;
+  R->res = R->res1;
+  R->rpart = R->rpart1;
+  R->initialised = false;
+  if (!smaps) return MRF_OK;
+  const size_t nmap = (size_t)ncoils * R->Nv, nres = (size_t)ncoils * R->L * R->Ns;
+  const size_t npart = (size_t)ncoils * nufft_resid_blocks(R->plan);
+  void *m = nullptr, *r = nullptr, *q = nullptr;
+  if (hipMalloc(&m, nmap * 8) != hipSuccess || hipMalloc(&r, nres * 8) != hipSuccess ||
+      hipMalloc(&q, npart * 8) != hipSuccess) {
+    hipFree(m); hipFree(r); hipFree(q);
+    return fail(MRF_OOM, "recon_set_coils: device allocation failed");
+  }
+  R->coil_bufs = {m, r, q};
+  MRF_CHECK_HIP(hipMemcpyAsync(m, smaps, nmap * 8, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipStreamSynchronize(s));
+  R->smaps = (cf*)m;
+  R->ncoils = ncoils;
+  R->res = (cf*)r;
+  R->rpart = (double*)q;
   return MRF_OK;
 }
 
@@ -348,7 +394,7 @@ extern "C" mrf_status mrf_recon_init(mrf_recon_t R, const mrf_c64* b, const mrf_
   if (X0) {
     MRF_LAUNCH("recon_copy", s, k_copy_c<<<1024, 256, 0, s>>>((const cf*)X0, R->X, (size_t)R->L * R->Nv));
     MRF_CHECK_LAUNCH();
-  } else if ((e = nufft_adj_impl(R->plan, R->b, R->X, R->nws, s))) {
+  } else if ((e = nufft_adj_coils(R->plan, R->b, R->X, R->nws, s, R->smaps, R->ncoils))) {   // X0 = A^H b
     return e;
   }
   if ((e = rebuild(R, s))) return e;
@@ -380,7 +426,7 @@ mrf_status enqueue_step(mrf_recon_s* R, hipStream_t s) {
   if ((e = fork(R, 2, s))) return e;
   if (R->pending_graph && (e = rebuild(R, aux_stream(R, 0, 2, s)))) return e;
   if ((e = llr_coef(R->X, R->g, L, rc, R->U, R->f, R->C, aux_stream(R, 1, 2, s)))) return e;
-  if ((e = nufft_adj_impl(R->plan, R->res, R->ZG, R->nws, s))) return e;                      // G = A^H r
+  if ((e = nufft_adj_coils(R->plan, R->res, R->ZG, R->nws, s, R->smaps, R->ncoils))) return e;  // G = A^H r
   if ((e = subspace_reduce(R->ZG, nullptr, nullptr, V, L, Nv, r, R->aU, (cf*)R->rws, s))) return e;  // G V
   // aX = X V is current: the graph rebuild (or the initialisation) computed it from this X
   if ((e = join(R, 0, 2, s))) return e;
@@ -588,7 +634,7 @@ namespace {
 // checkpoint: a header (sizes for the check on load, stopping state, statistics), then the arrays
 struct CkptHeader {
   uint64_t magic;
-  int version, N, L, Ns, Np, rcap, pp, r, pending, pad;
+  int version, N, L, Ns, Np, rcap, pp, r, pending, ncoils;   // ncoils 0: single coil, no maps
   double c_prev;
   mrf_recon_stats st;
 };
@@ -602,7 +648,7 @@ CkptLayout ckpt_layout(const mrf_recon_s* R) {
   const size_t pp = (size_t)R->prm.p * R->prm.p, np = R->g.Np, rc = R->prm.rank_cap;
   c.x = ck_al(sizeof(CkptHeader));
   c.res = c.x + ck_al((size_t)R->L * R->Nv * 8);
-  c.u = c.res + ck_al((size_t)R->L * R->Ns * 8);
+  c.u = c.res + ck_al((size_t)std::max(1, R->ncoils) * R->L * R->Ns * 8);
   c.f = c.u + ck_al(np * rc * pp * 8);
   c.sc = c.f + ck_al(np * rc * 4);
   c.total = c.sc + ck_al(SC_N * 8);
@@ -629,11 +675,13 @@ extern "C" mrf_status mrf_recon_checkpoint_save(mrf_recon_t R, void* buf, size_t
   h.N = R->N; h.L = R->L; h.Ns = R->Ns; h.Np = R->g.Np; h.rcap = R->prm.rank_cap; h.pp = R->prm.p * R->prm.p;
   h.r = R->r;
   h.pending = R->pending_graph ? 1 : 0;
+  h.ncoils = R->ncoils;
   h.c_prev = R->c_prev;
   h.st = R->st;
   char* o = (char*)buf;
   MRF_CHECK_HIP(hipMemcpyAsync(o + c.x, R->X, (size_t)R->L * R->Nv * 8, hipMemcpyDefault, s));
-  MRF_CHECK_HIP(hipMemcpyAsync(o + c.res, R->res, (size_t)R->L * R->Ns * 8, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(o + c.res, R->res, (size_t)std::max(1, R->ncoils) * R->L * R->Ns * 8,
+                               hipMemcpyDefault, s));
   MRF_CHECK_HIP(hipMemcpyAsync(o + c.u, R->U, (size_t)h.Np * h.rcap * h.pp * 8, hipMemcpyDefault, s));
   MRF_CHECK_HIP(hipMemcpyAsync(o + c.f, R->f, (size_t)h.Np * h.rcap * 4, hipMemcpyDefault, s));
   MRF_CHECK_HIP(hipMemcpyAsync(o + c.sc, R->sc, SC_N * 8, hipMemcpyDefault, s));
@@ -653,10 +701,11 @@ extern "C" mrf_status mrf_recon_checkpoint_load(mrf_recon_t R, const mrf_c64* b,
   MRF_CHECK_HIP(hipMemcpy(&h, o, sizeof h, hipMemcpyDefault));
   MRF_REQUIRE(h.magic == kCkptMagic && h.version == 1, MRF_INVALID_ARG, "recon_checkpoint_load: not a checkpoint");
   MRF_REQUIRE(h.N == R->N && h.L == R->L && h.Ns == R->Ns && h.Np == R->g.Np && h.rcap == R->prm.rank_cap &&
-                  h.pp == R->prm.p * R->prm.p && h.r == R->r,
+                  h.pp == R->prm.p * R->prm.p && h.r == R->r && h.ncoils == R->ncoils,
               MRF_SHAPE, "recon_checkpoint_load: the checkpoint's sizes differ from this recon's");
   MRF_CHECK_HIP(hipMemcpyAsync(R->X, o + c.x, (size_t)R->L * R->Nv * 8, hipMemcpyDefault, s));
-  MRF_CHECK_HIP(hipMemcpyAsync(R->res, o + c.res, (size_t)R->L * R->Ns * 8, hipMemcpyDefault, s));
+  MRF_CHECK_HIP(hipMemcpyAsync(R->res, o + c.res, (size_t)std::max(1, R->ncoils) * R->L * R->Ns * 8,
+                               hipMemcpyDefault, s));
   MRF_CHECK_HIP(hipMemcpyAsync(R->U, o + c.u, (size_t)h.Np * h.rcap * h.pp * 8, hipMemcpyDefault, s));
   MRF_CHECK_HIP(hipMemcpyAsync(R->f, o + c.f, (size_t)h.Np * h.rcap * 4, hipMemcpyDefault, s));
   MRF_CHECK_HIP(hipMemcpyAsync(R->sc, o + c.sc, SC_N * 8, hipMemcpyDefault, s));

@@ -1,4 +1,5 @@
-"""NUFFT pair binding: mrf_nufft_plan_create / mrf_nufft_fwd / mrf_nufft_adj."""
+"""NUFFT pair binding: mrf_nufft_plan_create / mrf_nufft_fwd / mrf_nufft_adj, and the multi-coil
+operator F_u C of eq. (1) (mrf_nufft_fwd_mc / mrf_nufft_adj_mc / mrf_nufft_opnorm_mc)."""
 import ctypes
 
 import torch
@@ -71,6 +72,42 @@ class NufftPlan:
         lam = ctypes.c_double()
         check(lib.mrf_nufft_opnorm(self.handle, int(iters), int(seed), ctypes.byref(lam), _stream(stream)),
               "mrf_nufft_opnorm")
+        return lam.value
+
+    def _maps(self, smaps):
+        if smaps.dim() != 3:
+            raise ValueError("smaps must be [ncoils, n, n]")
+        _need(smaps, torch.complex64, (smaps.shape[0], self.n, self.n), "smaps")
+        return smaps.shape[0]
+
+    def fwd_mc(self, smaps, img, out=None, stream=None):
+        """ksp [ncoils, L, Ns]: every coil's samples of S_c img."""
+        nc = self._maps(smaps)
+        _need(img, torch.complex64, (self.L, self.n, self.n), "img")
+        if out is None:
+            out = torch.empty((nc, self.L, self.Ns), dtype=torch.complex64, device=img.device)
+        _need(out, torch.complex64, (nc, self.L, self.Ns), "ksp")
+        check(lib.mrf_nufft_fwd_mc(self.handle, _ptr(smaps), nc, _ptr(img), _ptr(out), _ptr(self.ws),
+                                   self.ws.numel(), _stream(stream)), "mrf_nufft_fwd_mc")
+        return out
+
+    def adj_mc(self, smaps, ksp, out=None, stream=None):
+        """img [L, n, n] = sum_c conj(S_c) A^H ksp_c."""
+        nc = self._maps(smaps)
+        _need(ksp, torch.complex64, (nc, self.L, self.Ns), "ksp")
+        if out is None:
+            out = torch.empty((self.L, self.n, self.n), dtype=torch.complex64, device=ksp.device)
+        _need(out, torch.complex64, (self.L, self.n, self.n), "img")
+        check(lib.mrf_nufft_adj_mc(self.handle, _ptr(smaps), nc, _ptr(ksp), _ptr(out), _ptr(self.ws),
+                                   self.ws.numel(), _stream(stream)), "mrf_nufft_adj_mc")
+        return out
+
+    def opnorm_mc(self, smaps, iters=30, seed=1, stream=None):
+        """lambda_max((F_u C)^H F_u C) by power iteration on the device."""
+        nc = self._maps(smaps)
+        lam = ctypes.c_double()
+        check(lib.mrf_nufft_opnorm_mc(self.handle, _ptr(smaps), nc, int(iters), int(seed), ctypes.byref(lam),
+                                      _stream(stream)), "mrf_nufft_opnorm_mc")
         return lam.value
 
     def close(self):

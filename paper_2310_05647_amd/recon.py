@@ -1,4 +1,4 @@
-"""Algorithm 1 binding: mrf_recon_create / init / iterate / finish."""
+"""Algorithm 1 binding: mrf_recon_create / set_coils / init / iterate / finish."""
 import ctypes
 
 import numpy as np
@@ -23,9 +23,27 @@ class Recon:
               "mrf_recon_create")
         self.handle = h
         self.n, self.L = plan.n, plan.L
+        self.ncoils = 0
+
+    def set_coils(self, smaps, stream=None):
+        """Multi-coil data (eq. (1)): smaps [ncoils, n, n] complex64 (device; copied), or None for a
+        single coil. b then is [ncoils, L, Ns] and lamA should come from plan.opnorm_mc(smaps)."""
+        if smaps is None:
+            check(lib.mrf_recon_set_coils(self.handle, None, 0, stream_ptr(stream)), "mrf_recon_set_coils")
+            self.ncoils = 0
+            return
+        if smaps.dim() != 3:
+            raise ValueError("smaps must be [ncoils, n, n]")
+        need(smaps, torch.complex64, (smaps.shape[0], self.n, self.n), "smaps")
+        check(lib.mrf_recon_set_coils(self.handle, ptr(smaps), smaps.shape[0], stream_ptr(stream)),
+              "mrf_recon_set_coils")
+        self.ncoils = smaps.shape[0]
+
+    def _b_shape(self):
+        return ((self.ncoils,) if self.ncoils else ()) + (self.L, self.plan.Ns)
 
     def init(self, b, X0=None, stream=None):
-        need(b, torch.complex64, (self.L, self.plan.Ns), "b")
+        need(b, torch.complex64, self._b_shape(), "b")
         self._b = b
         check(lib.mrf_recon_init(self.handle, ptr(b), ptr(X0), stream_ptr(stream)), "mrf_recon_init")
 
@@ -70,7 +88,7 @@ class Recon:
 
     def restore(self, b, buf, stream=None):
         """Continues a run from checkpoint(); b are the run's measurements."""
-        need(b, torch.complex64, (self.L, self.plan.Ns), "b")
+        need(b, torch.complex64, self._b_shape(), "b")
         self._b = b
         check(lib.mrf_recon_checkpoint_load(self.handle, ptr(b), ctypes.c_void_p(buf.data_ptr()), buf.numel(),
                                             stream_ptr(stream)), "mrf_recon_checkpoint_load")

@@ -179,3 +179,47 @@ def test_step_size_bounds_the_gradient_lipschitz_constant():
     H = eps * np.eye(9) + 5.0 * SL
     mu = recon.step_size(10.0, eps, 5.0, 3 * w, 4.0)
     assert mu * np.linalg.eigvalsh(H).max() <= 1.0 + 1e-12
+
+
+def test_multicoil_landweber_converges_to_the_stacked_lstsq():
+    """Eq. (1) with coils and lambda1 = lambda2 = 0, V = I: the loop is Landweber iteration on the
+    stacked system [A diag(S_1); ...; A diag(S_Nc)] x_l = [b_1l; ...; b_Nc,l], whose least-squares
+    solution is formed here from the single-coil operator's columns and the maps by hand."""
+    rng = np.random.default_rng(3)
+    N, L, Ns, Nc = 4, 2, 9, 3                        # 27 rows per frame for 16 unknowns
+    traj = rng.uniform(-math.pi, math.pi, (L, Ns, 2))
+    S = rng.standard_normal((Nc, N, N)) + 1j * rng.standard_normal((Nc, N, N))
+    b = rng.standard_normal((Nc, L, Ns)) + 1j * rng.standard_normal((Nc, L, Ns))
+    D, lut = _tiny_dict(rng, L)
+    x_ls, lam = [], 0.0
+    for l in range(L):
+        A = np.stack([nufft.nufft_fwd(e.reshape(1, N, N), traj[l:l + 1])[0] for e in np.eye(N * N)], 1)
+        M = np.concatenate([A * S[c].ravel()[None, :] for c in range(Nc)])
+        lam = max(lam, np.linalg.eigvalsh(M.conj().T @ M).max())
+        x_ls.append(np.linalg.lstsq(M, b[:, l].ravel(), rcond=None)[0].reshape(N, N))
+    x_ls = np.stack(x_ls)
+    out = recon.recon(b, traj, D, lut, np.eye(L), N, 2, 1, 2, 4, lam1_0=0.0, lam2=0.0,
+                      mu0=1.0 / lam, lamA=lam, n_max=3000, smaps=S)
+    assert np.linalg.norm(out["X"] - x_ls) <= 1e-6 * np.linalg.norm(x_ls)
+    c = np.array(out["stats"]["cost"])
+    assert np.all(np.diff(c) <= 1e-12 * c[0])
+
+
+def test_two_equal_coils_reduce_to_one():
+    """S_1 = S_2 = 1/sqrt(2) with b_1 = b_2 = b/sqrt(2): the data term and its gradient are the
+    single-coil ones, so the whole run (graph, costs, X) is the single-coil run."""
+    cfg = mrfgen.get_config("C1", N=32, L=40, Ns=256)
+    atoms, grid = mrfgen.make_dictionary(cfg)
+    V, _ = mrfgen.subspace_basis(atoms, cfg["r"])
+    X = mrfgen.truth_fingerprints(cfg, mrfgen.make_phantom(cfg, 0))
+    traj = mrfgen.vds_spiral(cfg["N"], cfg["L"], cfg["Ns"], cfg["n_interleaves"])
+    b = nufft.nufft_fwd(X, traj)
+    b = b + 0.01 * np.abs(b).mean() * np.random.default_rng(4).standard_normal(b.shape)
+    S = np.full((2, cfg["N"], cfg["N"]), 1 / math.sqrt(2))
+    kw = dict(lam1_0=0.1, lam2=0.05, beta=0.2, mu0=0.5, n_max=2)
+    one = recon.recon(b, traj, atoms, grid["lut"], V, cfg["N"], 4, 2, 6, 6, **kw)
+    two = recon.recon(np.stack([b, b]) / math.sqrt(2), traj, atoms, grid["lut"], V, cfg["N"], 4, 2, 6, 6,
+                      smaps=S, **kw)
+    np.testing.assert_allclose(two["stats"]["cost"], one["stats"]["cost"], rtol=1e-10)
+    assert np.linalg.norm(two["X"] - one["X"]) <= 1e-10 * np.linalg.norm(one["X"])
+    assert np.array_equal(two["idx"], one["idx"])

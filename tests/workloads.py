@@ -45,3 +45,22 @@ def c2_workload(seed=0):
     sig2 = mrfgen.noise_sigma(np.mean(np.abs(b_clean) ** 2), cfg["snr_db"])
     b = (b_clean + mrfgen.complex_noise(b_clean.shape, sig2, seed + 17)).astype(np.complex64)
     return dict(cfg=cfg, atoms=atoms, grid=grid, V=V, phantom=ph, X=X, traj=traj, b=b)
+
+
+@functools.lru_cache(maxsize=2)
+def mc_workload(seed=0, N=32, L=60, Ns=512, ncoils=4):
+    """A cropped C1 acquired by ncoils coils (eq. (1)): b_c = the oracle's A (S_c X) + 40 dB noise;
+    lamA = lambda_max of the multi-coil normal operator (oracle power iteration)."""
+    cfg = mrfgen.get_config("C1", N=N, L=L, Ns=Ns)
+    atoms, grid = mrfgen.make_dictionary(cfg)
+    V, _ = mrfgen.subspace_basis(atoms, cfg["r"])
+    ph = mrfgen.make_phantom(cfg, seed)
+    X = mrfgen.truth_fingerprints(cfg, ph)
+    traj = mrfgen.vds_spiral(N, L, Ns, cfg["n_interleaves"])
+    S = mrfgen.coil_maps(N, ncoils, seed)
+    b_clean = onufft.nufft_fwd_mc(X, traj, S)
+    sig2 = mrfgen.noise_sigma(np.mean(np.abs(b_clean) ** 2), cfg["snr_db"])
+    b = (b_clean + mrfgen.complex_noise(b_clean.shape, sig2, seed + 31)).astype(np.complex64)
+    x0 = mrfgen.complex_noise((L, N, N), 1.0, seed + 37)
+    lamA = onufft.operator_norm_mc(traj, N, S, x0, iters=20)
+    return dict(cfg=cfg, atoms=atoms, grid=grid, V=V, phantom=ph, X=X, traj=traj, smaps=S, b=b, lamA=lamA)
