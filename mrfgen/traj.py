@@ -26,3 +26,20 @@ def vds_spiral(N, L, Ns, n_interleaves, alpha=1.5, interleaves_per_frame=1, fram
         out[l, :, 0] = k.real
         out[l, :, 1] = k.imag
     return out
+
+
+def radial_cartesian_mask(N, L, n_spokes, frame0=0):
+    """Pseudo-radial Cartesian sampling (Sec. IV, the third sampling pattern): per frame, n_spokes
+    lines through the k-space centre at angles j pi / n_spokes plus the frame's golden-angle
+    rotation, each traced at unit steps over [-N/2, N/2) and rounded to the nearest point of the
+    N x N Cartesian grid. Returns uint8 [L, N, N]; entry [l, ky + N/2, kx + N/2] is 1 where
+    frequency (kx, ky) (cycles per field of view) is sampled in frame l."""
+    mask = np.zeros((L, N, N), np.uint8)
+    t = np.arange(-N // 2, N // 2, dtype=np.float64)
+    for l in range(L):
+        for j in range(n_spokes):
+            ang = j * np.pi / n_spokes + (frame0 + l) * GOLDEN
+            kx = np.clip(np.rint(t * np.cos(ang)), -N // 2, N // 2 - 1).astype(np.int64)
+            ky = np.clip(np.rint(t * np.sin(ang)), -N // 2, N // 2 - 1).astype(np.int64)
+            mask[l, ky + N // 2, kx + N // 2] = 1
+    return mask

@@ -25,7 +25,7 @@ converges to the least-squares solution (numpy.linalg.lstsq on a tiny dense oper
 import numpy as np
 import scipy.sparse as sp
 
-from . import graph, match, nufft, ops
+from . import cartesian, graph, match, nufft, ops
 from .patches import coverage
 
 
@@ -37,22 +37,27 @@ def step_size(mu0, lamA, lam1, lmax, cmax):
 
 def recon(b, traj, atoms, lut, V, N, p, s, K, r_llr, lam1_0=0.1, lam2=0.1, beta=0.2,
           mu0=1.0, lamA=0.0, sigma2=0.0, n_max=10, tol=None, osf=2, W=6, X0=None, keep_graphs=False,
-          smaps=None):
+          smaps=None, mask=None):
     """Return dict(X, maps, idx, rho, stats). keep_graphs: stats["graphs"] lists every Laplacian
     used (scipy CSR [Np, Np]; graph k serves iteration k + 1). The Laplacian is applied from
     sparse storage (the same entries; only the non-zeros enter the sums). smaps [Nc, N, N]: the
-    acquisition is eq. (1)'s multi-coil F_u C (b [Nc, L, Ns]); None: a single coil."""
+    acquisition is eq. (1)'s multi-coil F_u C (b [Nc, L, Ns]); None: a single coil. mask [L, N, N]:
+    Cartesian sampling (oracle.cartesian; traj unused, b [L, N, N] or [Nc, L, N, N])."""
     b = np.asarray(b, np.complex128)
     V = np.asarray(V, np.complex128)
     tau = 1.0 / beta
     cmax = float(coverage(N, p, s).max())
 
     def fwd(X):
+        if mask is not None:
+            return cartesian.cart_fwd_mc(X, mask, smaps) if smaps is not None else cartesian.cart_fwd(X, mask)
         if smaps is not None:
             return nufft.nufft_fwd_mc(X, traj, smaps, osf, W)
         return nufft.nufft_fwd(X, traj, osf, W)
 
     def adj(r):
+        if mask is not None:
+            return cartesian.cart_adj_mc(r, mask, smaps) if smaps is not None else cartesian.cart_adj(r, mask)
         if smaps is not None:
             return nufft.nufft_adj_mc(r, traj, N, smaps, osf, W)
         return nufft.nufft_adj(r, traj, N, osf, W)
