@@ -147,7 +147,8 @@ def bench_precision_match(torch, mrf, dev, fp, truth, mask, oracle_sample=256, d
     return out
 
 
-def bench_learned_match(torch, mrf, dev, d, V, Xn, truth, mask, grid, epochs=20, batch=4096, samples=2_000_000):
+def bench_learned_match(torch, mrf, dev, d, V, Xn, truth, mask, grid, epochs=20, batch=4096, samples=2_000_000,
+                        max_steps=None):
     """MLP trained on the device (2 M noisy atoms per epoch, SNR 20-60 dB, BF16 GEMMs), then the
     gated learned match on the 65 536 reconstructed fingerprints against the plain FP32 exhaustive
     subspace match: for a sweep of gate thresholds the T1/T2 NMSE over the tissue and how many
@@ -157,7 +158,7 @@ def bench_learned_match(torch, mrf, dev, d, V, Xn, truth, mask, grid, epochs=20,
     net = mrf.MLP(n_in=2 * V.shape[1], hidden=256, layers=3, seed=1)
     net.set_grid(grid)
     steps_per_epoch = (samples + batch - 1) // batch
-    steps = epochs * steps_per_epoch
+    steps = epochs * steps_per_epoch if max_steps is None else max_steps
     torch.cuda.synchronize()
     t0 = time.time()
     losses = net.train(d, steps=steps, batch=batch, lr=1e-3, total_steps=steps, seed=2, bf16=True)
@@ -188,7 +189,8 @@ def bench_learned_match(torch, mrf, dev, d, V, Xn, truth, mask, grid, epochs=20,
     ms_plain = _time(torch, lambda: d.match_subspace(mrf.subspace_coeffs(Xn, Vd)), 5)
     ms_proj = _time(torch, lambda: mrf.subspace_coeffs(Xn, Vd), 5)
     ms_learn = _time(torch, lambda: net.match(d, mrf.subspace_coeffs(Xn, Vd), theta=theta, bf16=True), 5)
-    out = dict(train_steps=steps, train_s=round(train_s, 3), train_ms_per_epoch=round(1e3 * train_s / epochs, 2),
+    out = dict(train_steps=steps, train_s=round(train_s, 3),
+               train_ms_per_epoch=round(1e3 * train_s * steps_per_epoch / steps, 2),
                final_loss=float(lo[-100:].mean()), plain_nmse_t1=plain_err[0], plain_nmse_t2=plain_err[1],
                theta=theta, sweep=sweep, projection_ms=round(ms_proj, 4),
                plain_ms=round(ms_plain, 4), learned_ms=round(ms_learn, 4),
@@ -197,6 +199,36 @@ def bench_learned_match(torch, mrf, dev, d, V, Xn, truth, mask, grid, epochs=20,
     log("learned at theta %s: %.3f ms vs plain %.3f ms; NMSE sweep %s" % (theta, ms_learn, ms_plain, sweep))
     net.close()
     return out
+
+
+def bench_multicoil(torch, mrf, dev, plan, d, cfg, Xtrue, ncoils=8, iters=3):
+    """Multi-coil acquisition (eq. (1), A = F_u C) on the 256 x 256, L = 1000 series with ncoils
+    smooth synthetic sensitivities: the F_u C / (F_u C)^H pair, and Algorithm 1's iteration with
+    the residual over every coil (iters iterations after one warm-up)."""
+    import mrfgen
+    S = torch.from_numpy(mrfgen.coil_maps(cfg["N"], ncoils, seed=0)).to(dev)
+    X = torch.from_numpy(Xtrue).to(dev)
+    kb = plan.fwd_mc(S, X)
+    img = torch.empty_like(X)
+    pair_ms = _time(torch, lambda: (plan.fwd_mc(S, X, kb), plan.adj_mc(S, kb, img)), 5)
+    bh = kb.cpu().numpy()
+    b = torch.from_numpy(bh + mrfgen.complex_noise(bh.shape, mrfgen.noise_sigma(np.mean(np.abs(bh) ** 2),
+                                                                                   cfg["snr_db"]), 23)).to(dev)
+    del kb, img, X
+    lam = plan.opnorm_mc(S, 20)
+    rc = mrf.Recon(plan, d, cfg["p"], cfg["s"], cfg["K"], cfg["r_llr"], lam1_0=cfg["lam1_0"], lam2=cfg["lam2"],
+                   beta=cfg["beta"], mu0=cfg["mu0"], lamA=lam, n_max=100000, tol=-1.0)
+    rc.set_coils(S)
+    rc.init(b)
+    rc.iterate(1)
+    it_ms = _time(torch, lambda: rc.iterate(1), iters)
+    st = rc.stats()
+    rc.close()
+    log("multi-coil (%d coils): pair %.3f ms, iteration %.3f ms" % (ncoils, pair_ms, it_ms))
+    return dict(coils=ncoils, pair_ms=round(pair_ms, 4), pair_ms_per_coil=round(pair_ms / ncoils, 4),
+                coil_frame_pairs_per_s=round(1e3 * ncoils * cfg["L"] / pair_ms, 1), lamA=round(lam, 4),
+                iteration_ms=round(it_ms, 4), iterations_per_s=round(1e3 / it_ms, 3),
+                cost_decreasing=bool(np.all(np.diff(st["cost"]) < 0)))
 
 
 def bench_batched(torch, mrf, dev, rounds=3):
@@ -286,7 +318,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-match-forms", action="store_true", help="skip the precision and learned match components")
     ap.add_argument("--mlp-epochs", type=int, default=20)
+    ap.add_argument("--mlp-steps", type=int, default=None,
+                    help="train the MLP for this many steps instead (short profiled runs); its quality then drops")
     ap.add_argument("--no-batched", action="store_true", help="skip the 8-slice batched component")
+    ap.add_argument("--no-multicoil", action="store_true", help="skip the 8-coil component")
     ap.add_argument("--serial", type=int, default=0,
                     help="recon schedule mask: bit 0 runs the cost terms, bit 1 the rest of an iteration on one "
                          "stream (default 0: independent parts overlap on the recon's two extra streams)")
@@ -393,6 +428,12 @@ def main():
     # roofline of the kernels that take the most time per step
     inf = _plan_entries(plan)
     Np = ((N - cfg["p"]) // cfg["s"] + 1) ** 2
+    # the Laplacian trace runs as two launches (in-window cell pairs, then the far pairs) that
+    # share one algorithmic read of X: priced together under lap_quad
+    if "lap_quad_far" in per_kernel and "lap_quad" in per_kernel:
+        a, f = per_kernel["lap_quad"], per_kernel.pop("lap_quad_far")
+        a["ms_per_step"] += f["ms_per_step"]
+        a["avg_ms"] += f["avg_ms"]
     rows = []
     for name in sorted(per_kernel, key=lambda k: -per_kernel[k]["ms_per_step"]):
         w = algorithmic_work(name, cfg, inf, Np)
@@ -414,10 +455,12 @@ def main():
         del fpv
         grid_c2 = mrfgen.param_grid(cfg)
         comps_extra["learned_match"] = bench_learned_match(torch, mrf, dev, d, V, Xhat, truth, tmask, grid_c2,
-                                                          epochs=args.mlp_epochs)
+                                                          epochs=args.mlp_epochs, max_steps=args.mlp_steps)
     if not args.no_batched:
         rc.close()
         comps_extra["batched_c5"] = bench_batched(torch, mrf, dev)
+    if not args.no_multicoil:
+        comps_extra["multicoil"] = bench_multicoil(torch, mrf, dev, plan, d, cfg, Xtrue)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -103,6 +103,18 @@ mrf_status mrf_nufft_autotune(const mrf_nufft_desc* desc, const float* traj, int
  * synchronises. Algorithm 1's step-size rule takes this bound (see mrf_recon_params.lamA). */
 mrf_status mrf_nufft_opnorm(mrf_nufft_plan_t plan, int iters, unsigned seed, double* lam, hipStream_t stream);
 
+/* Pseudo-radial Cartesian sampling (Sec. IV, the third sampling pattern): a plan whose operator is
+ * A_l X_l = M_l (F X_l), F the unitary centred 2D DFT (the definition above with every frequency
+ * on the integer grid, w = 2 pi k / N: k-space point [ky + n/2][kx + n/2] holds frequency
+ * (kx, ky)) and M_l the 0/1 mask of frame l. mask: uint8 [nframes][n][n] (host or device;
+ * copied into the plan). The plan serves every call that takes an mrf_nufft_plan_t (fwd, adj,
+ * the multi-coil calls, opnorm, mrf_recon_create) with Ns = n * n: ksp is the dense masked
+ * k-space [L][n][n], zero where the mask is; the adjoint applies the mask to its input first.
+ * n: 32, 64, 128, 192, 256, 320, 384 or 512. Workspace: L n^2 complex64. Synchronises `stream`.
+ * mrf_nufft_autotune does not apply. MRF_SHAPE for an unsupported n, MRF_OOM. */
+mrf_status mrf_cart_plan_create(int n, int nframes, const uint8_t* mask, hipStream_t stream,
+                                mrf_nufft_plan_t* out);
+
 /* Multi-coil acquisition (Sec. II, eq. (1)): the forward operator is F_u C, where C multiplies
  * every frame by each coil's sensitivity map and F_u is the single-coil operator above.
  *   smaps  device complex64 [ncoils][N][N], one map per coil, shared by all frames; caller-owned,

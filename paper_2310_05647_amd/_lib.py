@@ -62,6 +62,7 @@ _decl("mrf_nufft_workspace_size", [c_void_p, P(c_size_t)])
 _decl("mrf_nufft_fwd", [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_nufft_adj", [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_nufft_opnorm", [c_void_p, c_int, ctypes.c_uint, P(ctypes.c_double), c_void_p])
+_decl("mrf_cart_plan_create", [c_int, c_int, c_void_p, c_void_p, P(c_void_p)])
 _decl("mrf_nufft_fwd_mc", [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_nufft_adj_mc", [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_nufft_opnorm_mc", [c_void_p, c_void_p, c_int, c_int, ctypes.c_uint, P(ctypes.c_double), c_void_p])

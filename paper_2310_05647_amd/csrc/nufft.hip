@@ -24,6 +24,7 @@
 #include <thread>
 #include <vector>
 
+#include "cart.hpp"
 #include "common.hpp"
 #include "fft.hpp"
 
@@ -51,9 +52,16 @@ struct mrf_nufft_plan_s {
   float* dinv;        // [N] 1 / phi_hat((x - N/2) / G)
   mrf::cf* tw;        // [G] exp(-2 pi i k / G)
   size_t ws_T, ws_part, ws_bytes;
+  // kind 1: Cartesian sampling (mrf_cart_plan_create): G = N, Ns = N * N, mask [L][N][N]; the
+  // trajectory tables above are unused
+  int kind;
+  uint8_t* mask;
 };
 
 namespace mrf {
+
+inline bool is_cart(const mrf_nufft_plan_s* p) { return p->kind == 1; }
+inline CartOp cart_op(const mrf_nufft_plan_s* p) { return CartOp{p->N, p->L, p->tw, p->mask}; }
 
 // ------------------------------------------------------------------ kernels
 // Work distribution of the column kernels: block b handles strip sx of frame chunk c. Blocks are
@@ -770,10 +778,47 @@ extern "C" mrf_status mrf_nufft_plan_create(const mrf_nufft_desc* d, const float
   return MRF_OK;
 }
 
+extern "C" mrf_status mrf_cart_plan_create(int n, int nframes, const uint8_t* mask, hipStream_t stream,
+                                           mrf_nufft_plan_t* out) {
+  clear_error();
+  MRF_REQUIRE(mask && out, MRF_INVALID_ARG, "cart_plan_create: null argument");
+  *out = nullptr;
+  MRF_REQUIRE(nframes >= 1, MRF_INVALID_ARG, "cart_plan_create: nframes must be >= 1");
+  MRF_REQUIRE(cart_supported(n), MRF_SHAPE, "cart_plan_create: n must be 32, 64, 128, 192, 256, 320, 384 or 512");
+  MRF_REQUIRE((long)nframes * n * n < (1L << 31), MRF_SHAPE, "cart_plan_create: too many k-space points");
+  auto* p = new mrf_nufft_plan_s{};
+  p->kind = 1;
+  p->N = n; p->G = n; p->L = nframes; p->Ns = n * n;
+  std::vector<cf> tw(n);
+  for (int k = 0; k < n; ++k) tw[k] = cf{(float)std::cos(-2.0 * M_PI * k / n), (float)std::sin(-2.0 * M_PI * k / n)};
+  const size_t nm = (size_t)nframes * n * n;
+  hipError_t e = hipMalloc(&p->tw, n * sizeof(cf));
+  if (e == hipSuccess) e = hipMalloc(&p->mask, nm);
+  if (e != hipSuccess) {
+    hipFree(p->tw); hipFree(p->mask);
+    delete p;
+    return fail(MRF_OOM, "cart_plan_create: device allocation failed");
+  }
+  e = hipMemcpy(p->tw, tw.data(), n * sizeof(cf), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->mask, mask, nm, hipMemcpyDefault, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    hipFree(p->tw); hipFree(p->mask);
+    delete p;
+    return fail(MRF_DEVICE, std::string("cart_plan_create: upload: ") + hipGetErrorString(e));
+  }
+  p->ws_T = (nm * sizeof(cf) + 255) & ~(size_t)255;
+  p->ws_part = 0;
+  p->ws_bytes = p->ws_T;
+  *out = p;
+  return MRF_OK;
+}
+
 extern "C" mrf_status mrf_nufft_plan_destroy(mrf_nufft_plan_t p) {
   clear_error();
   if (!p) return MRF_OK;
   hipFree(p->ent); hipFree(p->tile_ptr); hipFree(p->samp_ent); hipFree(p->dinv); hipFree(p->tw);
+  hipFree(p->mask);
   delete p;
   return MRF_OK;
 }
@@ -878,7 +923,9 @@ const cf* nufft_partials(const mrf_nufft_plan_s* p, void* ws) { return (const cf
 
 mrf_status sum_partials(const double* part, long n, double* out, hipStream_t s);
 
-long nufft_resid_blocks(const mrf_nufft_plan_s* p) { return ceil_div((long)p->L * p->Ns, kBlock); }
+long nufft_resid_blocks(const mrf_nufft_plan_s* p) {
+  return is_cart(p) ? cart_part_blocks(p->N, p->L) : ceil_div((long)p->L * p->Ns, kBlock);
+}
 
 // r = A img - b and rn2 (device double) = ||r||^2; part needs nufft_resid_blocks doubles per coil.
 // With ncoils >= 1 sensitivity maps (smaps [ncoils][N][N]) A is the multi-coil operator of eq. (1):
@@ -888,6 +935,14 @@ mrf_status nufft_residual(const mrf_nufft_plan_s* p, const cf* img, const cf* b,
                           double* rn2, hipStream_t s, const cf* smaps, int ncoils) {
   const long total = (long)p->L * p->Ns, nb = nufft_resid_blocks(p);
   const long nc = smaps ? ncoils : 1;
+  if (is_cart(p)) {
+    for (long c = 0; c < nc; ++c) {
+      mrf_status st = cart_resid(cart_op(p), img, b + c * total, r + c * total, (cf*)ws, part + c * nb,
+                                 smaps ? smaps + c * p->N * p->N : nullptr, s);
+      if (st != MRF_OK) return st;
+    }
+    return sum_partials(part, nc * nb, rn2, s);
+  }
   for (long c = 0; c < nc; ++c) {
     mrf_status st = nufft_fwd_partials(p, img, ws, s, smaps ? smaps + c * p->N * p->N : nullptr);
     if (st != MRF_OK) return st;
@@ -908,6 +963,7 @@ const int4* nufft_samp_ent(const mrf_nufft_plan_s* p) { return p->samp_ent; }
 
 mrf_status nufft_adj_impl(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, void* ws, hipStream_t s,
                           const cf* smap = nullptr, int accumulate = 0) {
+  if (is_cart(p)) return cart_adj(cart_op(p), ksp, img, (cf*)ws, smap, accumulate, s);
   cf* T = (cf*)ws;
   cf* rg = (cf*)((char*)ws + p->ws_T);
   MRF_DISPATCH_G_TX(launch_adj_g, p, ksp, img, T, rg, smap, accumulate, s);
@@ -935,6 +991,7 @@ extern "C" mrf_status mrf_nufft_fwd(mrf_nufft_plan_t p, const mrf_c64* img, mrf_
   clear_error();
   MRF_REQUIRE(p && img && ksp, MRF_INVALID_ARG, "nufft_fwd: null argument");
   MRF_REQUIRE(ws && ws_bytes >= p->ws_bytes, MRF_WORKSPACE, "nufft_fwd: workspace missing or too small");
+  if (is_cart(p)) return cart_fwd(cart_op(p), (const cf*)img, (cf*)ksp, (cf*)ws, nullptr, s);
   mrf_status st = nufft_fwd_partials(p, (const cf*)img, ws, s);
   if (st != MRF_OK) return st;
   const long total = (long)p->L * p->Ns;
@@ -961,6 +1018,12 @@ extern "C" mrf_status mrf_nufft_fwd_mc(mrf_nufft_plan_t p, const mrf_c64* smaps,
   MRF_REQUIRE(ws && ws_bytes >= p->ws_bytes, MRF_WORKSPACE, "nufft_fwd_mc: workspace missing or too small");
   const long total = (long)p->L * p->Ns;
   for (long c = 0; c < ncoils; ++c) {
+    if (is_cart(p)) {
+      mrf_status st = cart_fwd(cart_op(p), (const cf*)img, (cf*)ksp + c * total, (cf*)ws,
+                               (const cf*)smaps + c * p->N * p->N, s);
+      if (st != MRF_OK) return st;
+      continue;
+    }
     mrf_status st = nufft_fwd_partials(p, (const cf*)img, ws, s, (const cf*)smaps + c * p->N * p->N);
     if (st != MRF_OK) return st;
     MRF_LAUNCH("nufft_combine", s,

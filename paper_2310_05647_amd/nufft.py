@@ -120,3 +120,23 @@ class NufftPlan:
             self.close()
         except Exception:
             pass
+
+
+class CartPlan(NufftPlan):
+    """Pseudo-radial Cartesian sampling (mrf_cart_plan_create): A_l X_l = M_l F X_l, F the unitary
+    centred DFT. mask: uint8 [L, n, n] (device). k-space arrays are [L, n * n] (dense, zero where
+    the mask is); every NufftPlan method applies."""
+
+    def __init__(self, mask, stream=None):
+        L, n, n2 = mask.shape
+        if n != n2:
+            raise ValueError("mask must be [L, n, n]")
+        _need(mask, torch.uint8, (L, n, n), "mask")
+        self.n, self.L, self.Ns = int(n), int(L), int(n) * int(n)
+        h = ctypes.c_void_p()
+        check(lib.mrf_cart_plan_create(self.n, self.L, _ptr(mask), _stream(stream), ctypes.byref(h)),
+              "mrf_cart_plan_create")
+        self.handle = h
+        sz = ctypes.c_size_t()
+        check(lib.mrf_nufft_workspace_size(h, ctypes.byref(sz)), "mrf_nufft_workspace_size")
+        self.ws = torch.empty(max(1, sz.value), dtype=torch.uint8, device=mask.device)

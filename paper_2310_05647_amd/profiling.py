@@ -7,6 +7,8 @@ duration in ns) and ``counters_collection`` (one row per dispatch and counter).
     python -m paper_2310_05647_amd.profiling stats --db DIR --out FILE --command "..."
     python -m paper_2310_05647_amd.profiling traffic --fetch DIR --write DIR --kernel LABEL \\
         --out FILE --command-fetch "..." --command-write "..."
+    python -m paper_2310_05647_amd.profiling counters --db DIR [--db DIR ...] --kernels SUBSTR,... \\
+        --out FILE --command "..." [--command "..."]
 
 The traffic summary scales each counter by what it reads for a plain streaming kernel of known
 size in the same run (bench.py launches one: 256 MiB read, 256 MiB written), and records the
@@ -27,7 +29,15 @@ KERNELS = {
     "llr_coef": ("k_coef_strip", "llr.hip"),
     "llr_xupdate": ("k_xupdate_mfma<10, true, true>", "llr.hip"),
     "llr_backxf": ("k_backxf", "llr.hip"),
-    "lap_quad": ("k_lap_quad_edges<64, 2, 8>", "graph.hip"),
+    "lap_quad": ("k_qc_trace", "graph.hip"),
+    "lap_quad_far": ("k_qc_far", "graph.hip"),
+    "graph_qc_lists": ("k_qc_lists", "graph.hip"),
+    "llr_eig": ("k_eig_val", "llr.hip"),
+    "llr_eigvec": ("k_eig_vec", "llr.hip"),
+    "match_full": ("k_match_top4", "match.hip"),
+    "match_rerank": ("k_rerank", "match.hip"),
+    "mlp_gemm": ("k_gemm", "mlp.hip"),
+    "mlp_synth": ("k_synth", "mlp.hip"),
     "nufft_col_adj": ("k_col_adj", "nufft.hip"),
     "nufft_col_fwd": ("k_col_fwd", "nufft.hip"),
     "nufft_row_fwd": ("k_row_fwd", "nufft.hip"),
@@ -147,6 +157,38 @@ def traffic_bytes(profiles_dir, label):
     return float(d["hbm_bytes_per_launch"])
 
 
+def counter_table(dbs):
+    """{kernel name: {counter: (mean per dispatch, dispatches)}} over one or more counter runs."""
+    out = {}
+    for db in dbs:
+        c = _db(db)
+        rows = c.execute("select kernel_name, counter_name, avg(value), count(*) from counters_collection "
+                         "group by kernel_name, counter_name").fetchall()
+        for n, cn, v, k in rows:
+            out.setdefault(n, {})[cn] = (v, k)
+    return out
+
+
+def write_counters(dbs, kernels, out, commands):
+    """Mean value per dispatch of every collected counter, for each kernel whose symbol contains one
+    of the given substrings (all instantiations listed), with the source hashes of their files."""
+    table = counter_table(dbs)
+    lines = ["# rocprofv3 hardware counters, mean per dispatch"] + ["command: " + c for c in commands]
+    for src in sorted({v[1] for v in KERNELS.values()}):
+        lines.append("source_sha256 csrc/%s: %s" % (src, source_sha(src)))
+    for sub in kernels:
+        hits = sorted(n for n in table if sub in n)
+        for n in hits:
+            lines.append("")
+            lines.append("kernel: " + _short(n, 160))
+            for cn in sorted(table[n]):
+                v, k = table[n][cn]
+                lines.append("  %-40s %18.1f   (%d dispatches)" % (cn, v, k))
+    lines.append("")
+    with open(out, "w") as f:
+        f.write("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -161,9 +203,16 @@ def main():
     b.add_argument("--out", required=True)
     b.add_argument("--command-fetch", required=True)
     b.add_argument("--command-write", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("--db", required=True, action="append")
+    c.add_argument("--kernels", required=True)
+    c.add_argument("--out", required=True)
+    c.add_argument("--command", required=True, action="append")
     args = ap.parse_args()
     if args.cmd == "stats":
         write_stats(args.db, args.out, args.command)
+    elif args.cmd == "counters":
+        write_counters(args.db, args.kernels.split(","), args.out, args.command)
     else:
         write_traffic(args.fetch, args.write, args.kernel, args.out, args.command_fetch, args.command_write)
 

@@ -64,3 +64,21 @@ def mc_workload(seed=0, N=32, L=60, Ns=512, ncoils=4):
     x0 = mrfgen.complex_noise((L, N, N), 1.0, seed + 37)
     lamA = onufft.operator_norm_mc(traj, N, S, x0, iters=20)
     return dict(cfg=cfg, atoms=atoms, grid=grid, V=V, phantom=ph, X=X, traj=traj, smaps=S, b=b, lamA=lamA)
+
+
+@functools.lru_cache(maxsize=2)
+def cart_workload(seed=0, N=64, L=100, n_spokes=4):
+    """A cropped C1 under pseudo-radial Cartesian sampling (about 6% of k-space per frame at
+    N = 64 with 4 spokes): b = the oracle's M F X + 40 dB noise on the sampled points (dense
+    [L, N, N], zero elsewhere); lamA = 1 (F is unitary and M a projection)."""
+    from oracle import cartesian as ocart
+    cfg = mrfgen.get_config("C1", N=N, L=L)
+    atoms, grid = mrfgen.make_dictionary(cfg)
+    V, _ = mrfgen.subspace_basis(atoms, cfg["r"])
+    ph = mrfgen.make_phantom(cfg, seed)
+    X = mrfgen.truth_fingerprints(cfg, ph)
+    mask = mrfgen.radial_cartesian_mask(N, L, n_spokes)
+    b_clean = ocart.cart_fwd(X, mask)
+    sig2 = mrfgen.noise_sigma(np.sum(np.abs(b_clean) ** 2) / mask.sum(), cfg["snr_db"])
+    b = (b_clean + mask * mrfgen.complex_noise(b_clean.shape, sig2, seed + 41)).astype(np.complex64)
+    return dict(cfg=cfg, atoms=atoms, grid=grid, V=V, phantom=ph, X=X, mask=mask, b=b, lamA=1.0)
