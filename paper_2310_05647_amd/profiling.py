@@ -169,6 +169,31 @@ def counter_table(dbs):
     return out
 
 
+N_XCD, N_SIMD, CLOCK_HZ = 8, 1024, 2.4e9   # MI355X: GRBM_GUI_ACTIVE reads as the sum over its 8 XCDs
+
+
+def derived(c):
+    """Derived per-dispatch figures from whichever counters are present: busy time, MFMA
+    utilisation (busy MFMA cycles over SIMD cycles), MFMA flops (512 per MOP), LDS bank-conflict
+    share of LDS-active cycles, L2 hit rate."""
+    g = lambda k: c[k][0] if k in c else None
+    out = []
+    gui = g("GRBM_GUI_ACTIVE")
+    if gui:
+        out.append(("busy_ms", gui / N_XCD / CLOCK_HZ * 1e3))
+        if g("SQ_VALU_MFMA_BUSY_CYCLES") is not None:
+            out.append(("mfma_util_pct", 100.0 * g("SQ_VALU_MFMA_BUSY_CYCLES") / (gui / N_XCD * N_SIMD)))
+    mops = sum(g(k) or 0.0 for k in ("SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_MFMA_MOPS_BF16",
+                                     "SQ_INSTS_VALU_MFMA_MOPS_F8"))
+    if mops:
+        out.append(("mfma_gflop", mops * 512 / 1e9))
+    if g("SQ_LDS_IDX_ACTIVE"):
+        out.append(("lds_bank_conflict_pct", 100.0 * g("SQ_LDS_BANK_CONFLICT") / g("SQ_LDS_IDX_ACTIVE")))
+    if g("TCC_REQ_sum"):
+        out.append(("l2_hit_pct", 100.0 * g("TCC_HIT_sum") / g("TCC_REQ_sum")))
+    return out
+
+
 def write_counters(dbs, kernels, out, commands):
     """Mean value per dispatch of every collected counter, for each kernel whose symbol contains one
     of the given substrings (all instantiations listed), with the source hashes of their files."""
@@ -184,6 +209,8 @@ def write_counters(dbs, kernels, out, commands):
             for cn in sorted(table[n]):
                 v, k = table[n][cn]
                 lines.append("  %-40s %18.1f   (%d dispatches)" % (cn, v, k))
+            for dn, dv in derived(table[n]):
+                lines.append("  = %-38s %18.3f" % (dn, dv))
     lines.append("")
     with open(out, "w") as f:
         f.write("\n".join(lines))
