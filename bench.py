@@ -231,6 +231,54 @@ def bench_multicoil(torch, mrf, dev, plan, d, cfg, Xtrue, ncoils=8, iters=3):
                 cost_decreasing=bool(np.all(np.diff(st["cost"]) < 0)))
 
 
+def bench_radial(torch, mrf, dev, iters=50, n_spokes=13, lam1_0s=(0.1, 0.01, 0.001, 0.0)):
+    """Pseudo-radial Cartesian sampling (the paper's third pattern; about 5% of k-space per frame
+    with 13 golden-angle-rotated spokes at 256 x 256) at L = 500, the length of its sampling-pattern
+    comparison and parameter sweep: MS-LLR for a sweep of lambda1^0 (0.1 is the paper's choice; 0
+    is the LLR-only ablation), each run for `iters` iterations (the paper's N_max) from
+    X^0 = A^H b; tissue NMSE of T1, T2 and PD against the phantom, the step size, and the time
+    per iteration."""
+    import mrfgen
+    cfg = mrfgen.get_config("C2", L=500)
+    atoms, grid = mrfgen.make_dictionary(cfg)
+    V, _ = mrfgen.subspace_basis(atoms, cfg["r"])
+    ph = mrfgen.make_phantom(cfg, 0)
+    X = torch.from_numpy(mrfgen.truth_fingerprints(cfg, ph)).to(dev)
+    N, L = cfg["N"], cfg["L"]
+    mask = torch.from_numpy(mrfgen.radial_cartesian_mask(N, L, n_spokes)).to(dev)
+    plan = mrf.CartPlan(mask)
+    bh = plan.fwd(X).cpu().numpy()
+    mh = mask.cpu().numpy().reshape(L, N * N).astype(bool)
+    sig2 = mrfgen.noise_sigma(np.mean(np.abs(bh[mh]) ** 2), cfg["snr_db"])
+    b = torch.from_numpy((bh + mh * mrfgen.complex_noise(bh.shape, sig2, 29)).astype(np.complex64)).to(dev)
+    del X
+    d = mrf.Dictionary(torch.from_numpy(atoms).to(dev), torch.from_numpy(grid["lut"]).to(dev),
+                       torch.from_numpy(V).to(dev))
+    tm = ph["mask"] & (ph["PD"] > 0)
+    out = dict(N=N, L=L, spokes=n_spokes, sampled_fraction=round(float(mh.mean()), 4), iterations=iters)
+    for lam1_0 in lam1_0s:
+        name = "llr_only" if lam1_0 == 0.0 else "ms_llr_lam1_0_%g" % lam1_0
+        rc = mrf.Recon(plan, d, cfg["p"], cfg["s"], cfg["K"], cfg["r_llr"], lam1_0=lam1_0, lam2=cfg["lam2"],
+                       beta=cfg["beta"], mu0=cfg["mu0"], lamA=1.0, n_max=iters, tol=-1.0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = rc.run(b)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / iters
+        maps = r["maps"].cpu().numpy()
+        st = r["stats"]
+        out[name] = dict(ms_per_iteration=round(ms, 3), mu_last=st["mu"][-1], cost_last=st["cost"][-1],
+                         nmse_t1=_nmse(maps[0].ravel(), ph["T1"].ravel(), tm.ravel()),
+                         nmse_t2=_nmse(maps[1].ravel(), ph["T2"].ravel(), tm.ravel()),
+                         nmse_pd=_nmse(maps[2].ravel(), ph["PD"].ravel(), tm.ravel()))
+        rc.close()
+        log("radial Cartesian %s: %.3f ms/iteration, tissue NMSE T1 %.3e T2 %.3e PD %.3e" % (
+            name, ms, out[name]["nmse_t1"], out[name]["nmse_t2"], out[name]["nmse_pd"]))
+    d.close()
+    plan.close()
+    return out
+
+
 def bench_batched(torch, mrf, dev, rounds=3):
     """Eight uneven slices (N = 128, 192, 256, 320, each with L = 500 at 2 spiral interleaves per
     frame and L = 1000 at 1), every slice's NUFFT strip width chosen by the autotuner; one round =
@@ -294,20 +342,61 @@ def bench_batched(torch, mrf, dev, rounds=3):
     return out
 
 
-def cpu_baseline(cfg, traj, frames=320):
-    """The oracle's NUFFT pair (FP64 KB gridding) on a frame sample, scaled to the volume."""
+def cpu_baseline(cfg, frames=32):
+    """The oracle's Algorithm 1 iteration (FP64, the host's numpy) at 256 x 256, on a bounded
+    sample: the steps whose work grows with L (gradient with one NUFFT pair, projection, per-patch
+    SVT and X update, residual, nuclear norm, cost) are timed on the first `frames` frames and
+    scaled by L / frames; the graph rebuild (subspace match of the 65 536 voxels and the K-NN
+    patch graph), whose work does not depend on L, is timed once at full size. Each step is the
+    oracle's own function, called in Algorithm 1's order."""
+    import mrfgen
+    import scipy.sparse as sp
+    from oracle import graph as ograph
+    from oracle import match as omatch
     from oracle import nufft as onufft
-    rng = np.random.default_rng(0)
-    N = cfg["N"]
-    X = rng.standard_normal((frames, N, N)) + 1j * rng.standard_normal((frames, N, N))
-    t = time.perf_counter()
-    b = onufft.nufft_fwd(X, traj[:frames])
-    onufft.nufft_adj(b, traj[:frames], N)
-    dt = time.perf_counter() - t
-    per_volume = dt * cfg["L"] / frames
-    return dict(value=1.0 / per_volume, unit="NUFFT pairs/s", cores=1, kind="oracle",
-                sample="oracle FP64 NUFFT pair (KB gridding, numpy.fft, single-threaded) on %d of the %d "
-                       "frames of the 256x256 workload, %.1f s, scaled to the full volume" % (frames, cfg["L"], dt))
+    from oracle import ops as oops
+    from oracle.recon import step_size
+    from oracle.patches import coverage
+    c = mrfgen.get_config("C2", L=frames)
+    atoms, grid = mrfgen.make_dictionary(c)
+    V, _ = mrfgen.subspace_basis(atoms, c["r"])
+    V = V.astype(np.complex128)
+    X = mrfgen.truth_fingerprints(c, mrfgen.make_phantom(c, 0))
+    traj = mrfgen.vds_spiral(c["N"], frames, c["Ns"], c["n_interleaves"])
+    N, p, s = c["N"], c["p"], c["s"]
+    b = onufft.nufft_fwd(X, traj)
+    X = onufft.nufft_adj(b, traj, N)
+    t = {}
+    t0 = time.perf_counter()
+    idx, rho, _, _ = omatch.match_subspace(X, atoms, grid["lut"], V)
+    g = ograph.knn_laplacian(omatch.maps_from_match(idx, rho, grid["lut"], N), p, s, c["K"], 0.0)
+    t["rebuild"] = time.perf_counter() - t0
+    Lap = sp.csr_matrix(g["L"])
+    lam1 = c["lam1_0"] * g["lmax"]
+    mu = step_size(c["mu0"], 65.0, lam1, g["lmax"], float(coverage(N, p, s).max()))
+    r = onufft.nufft_fwd(X, traj) - b
+    t0 = time.perf_counter()
+    grad = onufft.nufft_adj(r, traj, N) + lam1 * oops.laplacian_apply(X, Lap, p, s)
+    Z = oops.project(X - mu * grad, V)
+    QtP, _ = oops.llr_prox(X, p, s, 1.0 / c["beta"], c["r_llr"])
+    X = oops.x_update(Z, QtP, mu, c["lam2"], c["beta"], p, s)
+    r = onufft.nufft_fwd(X, traj) - b
+    nuc = oops.nuclear_norm(X, p, s)
+    oops.cost(r, X, Lap, lam1, c["lam2"], nuc, p, s)
+    t["body"] = time.perf_counter() - t0
+    per_iter = t["body"] * cfg["L"] / frames + t["rebuild"]
+    try:   # the BLAS pool numpy's products and decompositions ran on; the rest is single-threaded
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
+    except ImportError:
+        threads = 1
+    return dict(value=round(1.0 / per_iter, 6), unit="NUFFT pairs/s", cores=threads, kind="oracle",
+                seconds_per_iteration=round(per_iter, 2),
+                sample="oracle (FP64 numpy) Algorithm 1 iteration at 256x256: the L-proportional steps "
+                       "(NUFFT pair, Laplacian, projection, per-patch SVT, X update, residual, nuclear norm, cost) "
+                       "on %d of the %d frames, %.1f s, scaled to %d frames; the L-independent graph rebuild "
+                       "(subspace match of 65536 voxels, K-NN patch graph) at full size, %.1f s; numpy's BLAS "
+                       "on %d host threads" % (frames, cfg["L"], t["body"], cfg["L"], t["rebuild"], threads))
 
 
 def main():
@@ -322,6 +411,7 @@ def main():
                     help="train the MLP for this many steps instead (short profiled runs); its quality then drops")
     ap.add_argument("--no-batched", action="store_true", help="skip the 8-slice batched component")
     ap.add_argument("--no-multicoil", action="store_true", help="skip the 8-coil component")
+    ap.add_argument("--no-radial", action="store_true", help="skip the pseudo-radial Cartesian component")
     ap.add_argument("--serial", type=int, default=0,
                     help="recon schedule mask: bit 0 runs the cost terms, bit 1 the rest of an iteration on one "
                          "stream (default 0: independent parts overlap on the recon's two extra streams)")
@@ -461,11 +551,13 @@ def main():
         comps_extra["batched_c5"] = bench_batched(torch, mrf, dev)
     if not args.no_multicoil:
         comps_extra["multicoil"] = bench_multicoil(torch, mrf, dev, plan, d, cfg, Xtrue)
+    if not args.no_radial:
+        comps_extra["radial_cartesian"] = bench_radial(torch, mrf, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(cfg, traj)
+        cpu = cpu_baseline(cfg)
 
     out = {
         "metric": METRIC,
