@@ -26,6 +26,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from . import cartesian, graph, match, nufft, ops
+from . import toeplitz as toep
 from .patches import coverage
 
 
@@ -37,12 +38,14 @@ def step_size(mu0, lamA, lam1, lmax, cmax):
 
 def recon(b, traj, atoms, lut, V, N, p, s, K, r_llr, lam1_0=0.1, lam2=0.1, beta=0.2,
           mu0=1.0, lamA=0.0, sigma2=0.0, n_max=10, tol=None, osf=2, W=6, X0=None, keep_graphs=False,
-          smaps=None, mask=None):
+          smaps=None, mask=None, toeplitz=False):
     """Return dict(X, maps, idx, rho, stats). keep_graphs: stats["graphs"] lists every Laplacian
     used (scipy CSR [Np, Np]; graph k serves iteration k + 1). The Laplacian is applied from
     sparse storage (the same entries; only the non-zeros enter the sums). smaps [Nc, N, N]: the
     acquisition is eq. (1)'s multi-coil F_u C (b [Nc, L, Ns]); None: a single coil. mask [L, N, N]:
-    Cartesian sampling (oracle.cartesian; traj unused, b [L, N, N] or [Nc, L, N, N])."""
+    Cartesian sampling (oracle.cartesian; traj unused, b [L, N, N] or [Nc, L, N, N]). toeplitz:
+    the data term's gradient A^H A X - A^H b and its cost value through the Toeplitz normal
+    operator (oracle.toeplitz; single coil, non-Cartesian), with no forward transform in the loop."""
     b = np.asarray(b, np.complex128)
     V = np.asarray(V, np.complex128)
     tau = 1.0 / beta
@@ -68,25 +71,43 @@ def recon(b, traj, atoms, lut, V, N, p, s, K, r_llr, lam1_0=0.1, lam2=0.1, beta=
         g = graph.knn_laplacian(maps, p, s, K, sigma2)
         return g
 
+    if toeplitz:
+        Khat = toep.kernel_spectrum(toep.psf_circulant(traj, N, osf, W))
+        AHb = adj(b)
+        bn2 = float(np.vdot(b, b).real)
+
+    def data_state(X):   # what the data term's gradient and value need: r = A X - b, or A^H A X
+        return toep.toeplitz_normal(X, Khat) if toeplitz else fwd(X) - b
+
+    def data_grad(st):
+        return st - AHb if toeplitz else adj(st)
+
+    def cost_of(st, X, Lap, lam1, nuc):
+        if not toeplitz:
+            return ops.cost(st, X, Lap, lam1, lam2, nuc, p, s)
+        c, (_, tr, _) = ops.cost(np.zeros(1), X, Lap, lam1, lam2, nuc, p, s)
+        data = toep.data_term(X, st, AHb, bn2)
+        return c + data, (data, tr, nuc)
+
     X = adj(b) if X0 is None else np.asarray(X0, np.complex128)
     g = rebuild(X)
     Lap, lam1 = sp.csr_matrix(g["L"]), lam1_0 * g["lmax"]
     mu = step_size(mu0, lamA, lam1, g["lmax"], cmax)
-    r = fwd(X) - b
+    r = data_state(X)
     nuc = ops.nuclear_norm(X, p, s)
-    c_prev, terms = ops.cost(r, X, Lap, lam1, lam2, nuc, p, s)
+    c_prev, terms = cost_of(r, X, Lap, lam1, nuc)
     stats = dict(cost=[c_prev], terms=[terms], mu=[mu], lam1=[lam1], sigma2=[g["sigma2"]],
                  lmax=[g["lmax"]], iters=0, stop="max_iter")
     if keep_graphs:
         stats["graphs"] = [Lap]
     for n in range(n_max):
-        grad = adj(r) + lam1 * ops.laplacian_apply(X, Lap, p, s)
+        grad = data_grad(r) + lam1 * ops.laplacian_apply(X, Lap, p, s)
         Z = ops.project(X - mu * grad, V)
         QtP, _ = ops.llr_prox(X, p, s, tau, r_llr)
         X = ops.x_update(Z, QtP, mu, lam2, beta, p, s)
-        r = fwd(X) - b
+        r = data_state(X)
         nuc = ops.nuclear_norm(X, p, s)
-        c, terms = ops.cost(r, X, Lap, lam1, lam2, nuc, p, s)
+        c, terms = cost_of(r, X, Lap, lam1, nuc)
         stats["cost"].append(c); stats["terms"].append(terms)
         stats["iters"] = n + 1
         if tol is not None and c_prev / c - 1.0 < tol:

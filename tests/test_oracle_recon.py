@@ -243,3 +243,20 @@ def test_cartesian_fully_sampled_recon_is_the_truth():
                       n_max=1, mask=mask)
     np.testing.assert_allclose(out["X"], X, rtol=0, atol=1e-10)
     assert np.array_equal(out["idx"].reshape(N, N), k)
+
+
+def test_toeplitz_recon_follows_the_gridded_recon():
+    """The Toeplitz normal operator gives the same iterates as A^H (A X - b) to the KB error, and
+    the same costs: LLR-only (lambda1^0 = 0, so no graph decision enters the iterate), 4 iterations."""
+    cfg = mrfgen.get_config("C1", N=32, L=40, Ns=256)
+    atoms, grid = mrfgen.make_dictionary(cfg)
+    V, _ = mrfgen.subspace_basis(atoms, cfg["r"])
+    X = mrfgen.truth_fingerprints(cfg, mrfgen.make_phantom(cfg, 0))
+    traj = mrfgen.vds_spiral(cfg["N"], cfg["L"], cfg["Ns"], cfg["n_interleaves"])
+    b = nufft.nufft_fwd(X, traj)
+    b = b + 0.01 * np.abs(b).mean() * np.random.default_rng(6).standard_normal(b.shape)
+    kw = dict(lam1_0=0.0, lam2=0.05, beta=0.2, mu0=1.0, lamA=40.0, n_max=4)
+    g = recon.recon(b, traj, atoms, grid["lut"], V, cfg["N"], 4, 2, 6, 6, **kw)
+    t = recon.recon(b, traj, atoms, grid["lut"], V, cfg["N"], 4, 2, 6, 6, toeplitz=True, **kw)
+    assert np.linalg.norm(t["X"] - g["X"]) <= 1e-4 * np.linalg.norm(g["X"])
+    np.testing.assert_allclose(t["stats"]["cost"], g["stats"]["cost"], rtol=1e-4)
