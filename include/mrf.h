@@ -115,6 +115,27 @@ mrf_status mrf_nufft_opnorm(mrf_nufft_plan_t plan, int iters, unsigned seed, dou
 mrf_status mrf_cart_plan_create(int n, int nframes, const uint8_t* mask, hipStream_t stream,
                                 mrf_nufft_plan_t* out);
 
+/* Toeplitz normal operator for the gradient of eq. (15): A^H A X as a convolution of each frame
+ * with its point-spread kernel K_l[d] = (1/N^2) sum_j exp(i omega_j . d) (the centre offsets of A
+ * and A^H cancel), done as a circular convolution on the 2N x 2N grid: the padded row FFTs, a
+ * column pass multiplying the 2D spectrum by the real kernel spectrum, the cropped inverse row
+ * FFTs. No spreading or interpolation runs per application.
+ * mrf_toeplitz_create: desc and traj as for mrf_nufft_plan_create (n: 16, 32, 64, 128 or 256); the
+ *   kernel is the gridded adjoint of unit data on a 2n image of the same samples (a temporary plan
+ *   of side 2n), its spectrum stored as float32 [L][2n][2n] (4 L (2n)^2 bytes, owned by the
+ *   handle). Setup call: allocates temporaries of about L (2n)^2 24 bytes, synchronises.
+ * mrf_toeplitz_normal: Y [L][n][n] = A^H A X, X [L][n][n]; ws of mrf_toeplitz_workspace_size
+ *   (8 L n 2n bytes). Asynchronous. X and Y may not alias.
+ * Within the KB error of the gridded pair (mrf_nufft_adj of mrf_nufft_fwd). MRF_SHAPE for an
+ * unsupported n, MRF_WORKSPACE for a short workspace, MRF_OOM. */
+typedef struct mrf_toeplitz_s* mrf_toeplitz_t;
+mrf_status mrf_toeplitz_create(const mrf_nufft_desc* desc, const float* traj, hipStream_t stream,
+                               mrf_toeplitz_t* out);
+mrf_status mrf_toeplitz_destroy(mrf_toeplitz_t t);
+mrf_status mrf_toeplitz_workspace_size(mrf_toeplitz_t t, size_t* bytes);
+mrf_status mrf_toeplitz_normal(mrf_toeplitz_t t, const mrf_c64* X, mrf_c64* Y, void* ws, size_t ws_bytes,
+                               hipStream_t stream);
+
 /* Multi-coil acquisition (Sec. II, eq. (1)): the forward operator is F_u C, where C multiplies
  * every frame by each coil's sensitivity map and F_u is the single-coil operator above.
  *   smaps  device complex64 [ncoils][N][N], one map per coil, shared by all frames; caller-owned,
@@ -422,6 +443,19 @@ mrf_status mrf_recon_init(mrf_recon_t r, const mrf_c64* b, const mrf_c64* X0, hi
  * synchronises. A checkpoint records the coil count and loads only into a recon with the same
  * count. MRF_INVALID_ARG for a null handle or ncoils < 1 with maps, MRF_OOM. */
 mrf_status mrf_recon_set_coils(mrf_recon_t r, const mrf_c64* smaps, int ncoils, hipStream_t stream);
+/* Toeplitz normal operator in Algorithm 1 (the gradient of eq. (15)): from the next
+ * mrf_recon_init on, the data term's gradient is A^H A X - A^H b with A^H A X from
+ * mrf_toeplitz_normal (t, made from the plan's own desc and trajectory; handle kept by pointer),
+ * and its value is 0.5 (<X, A^H A X> - 2 Re <X, A^H b> + ||b||^2): no forward transform runs in
+ * the loop and A^H only once, at initialisation. Each iteration applies A^H A once, to X^{n+1}
+ * for its cost, and the next gradient reuses it. The iterates equal the gridded pair's to the
+ * KB error; the data term's value loses about 1e-7 of ||A X||^2 to the cancellation of its three
+ * parts (accumulated in FP64 from FP32 inputs). t NULL returns to the gridded pair. Single coil
+ * only: MRF_NOT_SUPPORTED with coil maps set (and set_coils refuses while t is set);
+ * MRF_SHAPE if t's n or frame count differ or its workspace exceeds the plan's. Clears the
+ * initialised state; allocates two image series; synchronises. A checkpoint restores into a
+ * recon in the same mode (A^H b and A^H A X are recomputed from b and X). */
+mrf_status mrf_recon_set_toeplitz(mrf_recon_t r, mrf_toeplitz_t t, hipStream_t stream);
 /* Runs up to n more iterations (stops early on the tolerance or at n_max). Synchronises once
  * per iteration to read the cost. *stopped (may be NULL) is set when no iteration is left. */
 mrf_status mrf_recon_iterate(mrf_recon_t r, int n, int* stopped, hipStream_t stream);

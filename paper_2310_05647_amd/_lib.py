@@ -63,6 +63,10 @@ _decl("mrf_nufft_fwd", [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void
 _decl("mrf_nufft_adj", [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_nufft_opnorm", [c_void_p, c_int, ctypes.c_uint, P(ctypes.c_double), c_void_p])
 _decl("mrf_cart_plan_create", [c_int, c_int, c_void_p, c_void_p, P(c_void_p)])
+_decl("mrf_toeplitz_create", [P(NufftDesc), c_void_p, c_void_p, P(c_void_p)])
+_decl("mrf_toeplitz_destroy", [c_void_p])
+_decl("mrf_toeplitz_workspace_size", [c_void_p, P(c_size_t)])
+_decl("mrf_toeplitz_normal", [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_nufft_fwd_mc", [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_nufft_adj_mc", [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_nufft_opnorm_mc", [c_void_p, c_void_p, c_int, c_int, ctypes.c_uint, P(ctypes.c_double), c_void_p])
@@ -119,6 +123,7 @@ _decl("mrf_recon_destroy", [c_void_p])
 _decl("mrf_recon_batched", [c_int, c_void_p, c_void_p, c_int, P(c_int)])
 _decl("mrf_recon_init", [c_void_p, c_void_p, c_void_p, c_void_p])
 _decl("mrf_recon_set_coils", [c_void_p, c_void_p, c_int, c_void_p])
+_decl("mrf_recon_set_toeplitz", [c_void_p, c_void_p, c_void_p])
 _decl("mrf_recon_iterate", [c_void_p, c_int, P(c_int), c_void_p])
 _decl("mrf_recon_set_serial", [c_void_p, c_int])
 _decl("mrf_recon_finish", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p])

@@ -910,6 +910,51 @@ static void launch_adj_g(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, cf* 
     default: return fail(MRF_SHAPE, "nufft: unsupported grid / tile combination");  \
   }
 
+// The row passes alone, for any grid of the dispatch list (used by the Toeplitz normal operator):
+// T [nrows][G] = FFT_x of the rows of X [nrows][G/2] (times dinv, zero-padded, centred), and its
+// transpose X [nrows][G/2] (+)= crop of the inverse FFT times dinv times scale.
+template <int G>
+static void rows_fwd_g(const cf* X, cf* T, const float* dinv, const cf* tw, int nrows, hipStream_t s) {
+  constexpr int RPB = row_rpb(G);
+  MRF_LAUNCH("toeplitz_row_fwd", s,
+             k_row_fwd<G><<<row_blocks<k_row_fwd<G>>((nrows + RPB - 1) / RPB), kBlock, 0, s>>>(X, T, dinv, tw, nrows,
+                                                                                          nullptr));
+}
+
+template <int G>
+static void rows_adj_g(const cf* T, cf* X, const float* dinv, const cf* tw, int nrows, float scale, hipStream_t s) {
+  constexpr int RPB = row_rpb(G);
+  MRF_LAUNCH("toeplitz_row_adj", s,
+             k_row_adj<G><<<row_blocks<k_row_adj<G>>((nrows + RPB - 1) / RPB), kBlock, 0, s>>>(T, X, dinv, tw, nrows,
+                                                                                          scale, nullptr, 0));
+}
+
+#define MRF_DISPATCH_G(FN, ...)                                                  \
+  switch (G) {                                                                   \
+    case 32: FN<32>(__VA_ARGS__); break;                                         \
+    case 64: FN<64>(__VA_ARGS__); break;                                         \
+    case 128: FN<128>(__VA_ARGS__); break;                                       \
+    case 256: FN<256>(__VA_ARGS__); break;                                       \
+    case 384: FN<384>(__VA_ARGS__); break;                                       \
+    case 512: FN<512>(__VA_ARGS__); break;                                       \
+    case 640: FN<640>(__VA_ARGS__); break;                                       \
+    case 1024: FN<1024>(__VA_ARGS__); break;                                     \
+    default: return fail(MRF_SHAPE, "row pass: unsupported grid");              \
+  }
+
+mrf_status rows_fwd_padded(int G, const cf* X, cf* T, const float* dinv, const cf* tw, int nrows, hipStream_t s) {
+  MRF_DISPATCH_G(rows_fwd_g, X, T, dinv, tw, nrows, s);
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+
+mrf_status rows_adj_cropped(int G, const cf* T, cf* X, const float* dinv, const cf* tw, int nrows, float scale,
+                            hipStream_t s) {
+  MRF_DISPATCH_G(rows_adj_g, T, X, dinv, tw, nrows, scale, s);
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+
 mrf_status nufft_fwd_partials(const mrf_nufft_plan_s* p, const cf* img, void* ws, hipStream_t s,
                               const cf* smap = nullptr) {
   cf* T = (cf*)ws;

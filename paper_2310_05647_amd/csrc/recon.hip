@@ -32,6 +32,12 @@ mrf_status nufft_residual(const mrf_nufft_plan_s* p, const cf* img, const cf* b,
                           double* rn2, hipStream_t s, const cf* smaps, int ncoils);
 mrf_status nufft_adj_coils(const mrf_nufft_plan_s* p, const cf* ksp, cf* img, void* ws, hipStream_t s,
                            const cf* smaps, int ncoils);
+mrf_status sum_partials(const double* part, long n, double* out, hipStream_t s);
+// toeplitz.hip
+mrf_status toeplitz_apply(const mrf_toeplitz_s* T, const cf* X, cf* Y, void* ws, hipStream_t s);
+size_t toeplitz_ws_bytes(const mrf_toeplitz_s* T);
+int toeplitz_n(const mrf_toeplitz_s* T);
+int toeplitz_frames(const mrf_toeplitz_s* T);
 long nufft_resid_blocks(const mrf_nufft_plan_s* p);
 int nufft_n(const mrf_nufft_plan_s* p);
 int nufft_frames(const mrf_nufft_plan_s* p);
@@ -101,6 +107,42 @@ __global__ void k_maps_params(const float* __restrict__ prm, int np, const float
   maps[2 * Nv + v] = rho[v];
 }
 
+// Toeplitz data term: block partials of Re<x, A^H A x> - 2 Re<x, A^H b> (each block a fixed
+// grid-stride share, summed in a fixed order), so that adding ||b||^2 gives ||A x - b||^2.
+constexpr int kToepDataBlocks = 1024;
+__global__ __launch_bounds__(256) void k_toep_data(const cf* __restrict__ X, const cf* __restrict__ TX,
+                                                   const cf* __restrict__ AHb, long n, double* __restrict__ part) {
+  __shared__ double red[4];
+  double q = 0.0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const cf x = X[i], t = TX[i], a = AHb[i];
+    q += (double)x.x * t.x + (double)x.y * t.y - 2.0 * ((double)x.x * a.x + (double)x.y * a.y);
+  }
+  for (int o = 32; o > 0; o >>= 1) q += __shfl_down(q, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// sum of |b|^2 in the same blocked order
+__global__ __launch_bounds__(256) void k_norm2(const cf* __restrict__ b, long n, double* __restrict__ part) {
+  __shared__ double red[4];
+  double q = 0.0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256)
+    q += (double)b[i].x * b[i].x + (double)b[i].y * b[i].y;
+  for (int o = 32; o > 0; o >>= 1) q += __shfl_down(q, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_add_scalar(double* __restrict__ a, const double* __restrict__ b) { a[0] += b[0]; }
+
+__global__ void k_sub_c(cf* __restrict__ a, const cf* __restrict__ b, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    a[i] = cf{a[i].x - b[i].x, a[i].y - b[i].y};
+}
+
 __global__ void k_copy_c(const cf* __restrict__ a, cf* __restrict__ b, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) b[i] = a[i];
 }
@@ -156,6 +198,12 @@ struct mrf_recon_s {
   cf* res1 = nullptr;
   double* rpart1 = nullptr;
   std::vector<void*> coil_bufs;
+  // Toeplitz normal operator (mrf_recon_set_toeplitz): T(X), A^H b, (A^H b) V, ||b||^2 and the
+  // data term's block partials; its workspace is the NUFFT workspace, idle in this mode
+  mrf_toeplitz_s* toep = nullptr;
+  cf *TX = nullptr, *AHb = nullptr, *AHbV = nullptr;
+  double *tpart = nullptr, *bn2 = nullptr;
+  std::vector<void*> toep_bufs;
 };
 
 namespace {
@@ -215,8 +263,17 @@ mrf_status evaluate_enqueue(mrf_recon_s* R, hipStream_t s) {
                        nullptr, aux_stream(R, 0, 1, s))))
     return e;
   if ((e = lap_quad(R->graph, R->X, R->L, R->sc + SC_QUAD, aux_stream(R, 1, 1, s)))) return e;
-  if ((e = nufft_residual(R->plan, R->X, R->b, R->res, R->nws, R->rpart, R->sc + SC_RN2, s, R->smaps, R->ncoils)))
+  if (R->toep) {
+    // ||A X - b||^2 = <X, A^H A X> - 2 Re <X, A^H b> + ||b||^2; A^H A X is kept for the next gradient
+    if ((e = toeplitz_apply(R->toep, R->X, R->TX, R->nws, s))) return e;
+    MRF_LAUNCH("recon_toep_data", s, k_toep_data<<<kToepDataBlocks, 256, 0, s>>>(R->X, R->TX, R->AHb,
+                                                                                (long)R->L * R->Nv, R->tpart));
+    if ((e = sum_partials(R->tpart, kToepDataBlocks, R->sc + SC_RN2, s))) return e;
+    MRF_LAUNCH("recon_toep_data", s, k_add_scalar<<<1, 1, 0, s>>>(R->sc + SC_RN2, R->bn2));
+  } else if ((e = nufft_residual(R->plan, R->X, R->b, R->res, R->nws, R->rpart, R->sc + SC_RN2, s, R->smaps,
+                                 R->ncoils))) {
     return e;
+  }
   if ((e = join(R, 0, 1, s)) || (e = join(R, 1, 1, s))) return e;
   MRF_LAUNCH("recon_cost", s, k_cost<<<1, 1, 0, s>>>(R->sc, R->prm.lam2));
   MRF_CHECK_LAUNCH();
@@ -254,6 +311,23 @@ void record_graph(mrf_recon_s* R, const double* h) {
     R->st.lmax[n] = h[SC_LMAX];
     R->st.n_graph = n + 1;
   }
+}
+
+// Toeplitz mode: A^H b (reusing X^0 when it is A^H b), (A^H b) V and ||b||^2 for the data term
+mrf_status toep_prepare(mrf_recon_s* R, bool x_is_ahb, hipStream_t s) {
+  mrf_status e;
+  if (x_is_ahb) {
+    MRF_LAUNCH("recon_copy", s, k_copy_c<<<1024, 256, 0, s>>>(R->X, R->AHb, (size_t)R->L * R->Nv));
+  } else if ((e = nufft_adj_coils(R->plan, R->b, R->AHb, R->nws, s, nullptr, 0))) {
+    return e;
+  }
+  if ((e = subspace_reduce(R->AHb, nullptr, nullptr, dict_basis(R->dict), R->L, R->Nv, R->r, R->AHbV, (cf*)R->rws,
+                           s)))
+    return e;
+  MRF_LAUNCH("recon_toep_data", s, k_norm2<<<kToepDataBlocks, 256, 0, s>>>(R->b, (long)R->L * R->Ns, R->tpart));
+  if ((e = sum_partials(R->tpart, kToepDataBlocks, R->bn2, s))) return e;
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
 }
 
 }  // namespace
@@ -338,6 +412,7 @@ extern "C" mrf_status mrf_recon_destroy(mrf_recon_t R) {
   if (R->ev_fork) hipEventDestroy(R->ev_fork);
   for (void* p : R->allocs) hipFree(p);
   for (void* p : R->coil_bufs) hipFree(p);
+  for (void* p : R->toep_bufs) hipFree(p);
   for (auto& g : R->inj) {
     hipFree(g.rowptr); hipFree(g.col); hipFree(g.val); hipFree(g.scal);
   }
@@ -355,6 +430,7 @@ extern "C" mrf_status mrf_recon_set_coils(mrf_recon_t R, const mrf_c64* smaps, i
   clear_error();
   MRF_REQUIRE(R, MRF_INVALID_ARG, "recon_set_coils: null handle");
   MRF_REQUIRE(!smaps || ncoils >= 1, MRF_INVALID_ARG, "recon_set_coils: ncoils must be >= 1 with sensitivity maps");
+  MRF_REQUIRE(!smaps || !R->toep, MRF_NOT_SUPPORTED, "recon_set_coils: not with the Toeplitz normal operator");
   MRF_CHECK_HIP(hipStreamSynchronize(s));
   for (int k = 0; k < 2; ++k) MRF_CHECK_HIP(hipStreamSynchronize(R->aux[k]));
   for (void* p : R->coil_bufs) hipFree(p);
@@ -383,6 +459,42 @@ extern "C" mrf_status mrf_recon_set_coils(mrf_recon_t R, const mrf_c64* smaps, i
   return MRF_OK;
 }
 
+// The data term's gradient and value through the Toeplitz normal operator t (built from the
+// plan's own trajectory); t null returns to the gridded pair. The recon must be initialised again.
+extern "C" mrf_status mrf_recon_set_toeplitz(mrf_recon_t R, mrf_toeplitz_t t, hipStream_t s) {
+  clear_error();
+  MRF_REQUIRE(R, MRF_INVALID_ARG, "recon_set_toeplitz: null handle");
+  MRF_REQUIRE(!t || (toeplitz_n(t) == R->N && toeplitz_frames(t) == R->L), MRF_SHAPE,
+              "recon_set_toeplitz: the operator's n or frame count differs from the recon's");
+  MRF_REQUIRE(!t || !R->smaps, MRF_NOT_SUPPORTED, "recon_set_toeplitz: not with coil sensitivities");
+  MRF_REQUIRE(!t || toeplitz_ws_bytes(t) <= nufft_ws_bytes(R->plan), MRF_SHAPE,
+              "recon_set_toeplitz: the plan's workspace is smaller than the operator's");
+  MRF_CHECK_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < 2; ++k) MRF_CHECK_HIP(hipStreamSynchronize(R->aux[k]));
+  for (void* p : R->toep_bufs) hipFree(p);
+  R->toep_bufs.clear();
+  R->toep = nullptr;
+  R->TX = R->AHb = R->AHbV = nullptr;
+  R->tpart = R->bn2 = nullptr;
+  R->initialised = false;
+  if (!t) return MRF_OK;
+  const size_t img = (size_t)R->L * R->Nv * sizeof(cf), nv = (size_t)R->Nv * R->r * sizeof(cf);
+  void *a = nullptr, *b = nullptr, *c = nullptr, *d = nullptr;
+  if (hipMalloc(&a, img) != hipSuccess || hipMalloc(&b, img) != hipSuccess || hipMalloc(&c, nv) != hipSuccess ||
+      hipMalloc(&d, (kToepDataBlocks + 1) * sizeof(double)) != hipSuccess) {
+    hipFree(a); hipFree(b); hipFree(c); hipFree(d);
+    return fail(MRF_OOM, "recon_set_toeplitz: device allocation failed");
+  }
+  R->toep_bufs = {a, b, c, d};
+  R->toep = t;
+  R->TX = (cf*)a;
+  R->AHb = (cf*)b;
+  R->AHbV = (cf*)c;
+  R->tpart = (double*)d;
+  R->bn2 = R->tpart + kToepDataBlocks;
+  return MRF_OK;
+}
+
 extern "C" mrf_status mrf_recon_init(mrf_recon_t R, const mrf_c64* b, const mrf_c64* X0, hipStream_t s) {
   clear_error();
   MRF_REQUIRE(R && b, MRF_INVALID_ARG, "recon_init: null argument");
@@ -397,6 +509,7 @@ extern "C" mrf_status mrf_recon_init(mrf_recon_t R, const mrf_c64* b, const mrf_
   } else if ((e = nufft_adj_coils(R->plan, R->b, R->X, R->nws, s, R->smaps, R->ncoils))) {   // X0 = A^H b
     return e;
   }
+  if (R->toep && (e = toep_prepare(R, !X0, s))) return e;
   if ((e = rebuild(R, s))) return e;
   double h[SC_N];
   if ((e = evaluate(R, s, h))) return e;
@@ -426,8 +539,14 @@ mrf_status enqueue_step(mrf_recon_s* R, hipStream_t s) {
   if ((e = fork(R, 2, s))) return e;
   if (R->pending_graph && (e = rebuild(R, aux_stream(R, 0, 2, s)))) return e;
   if ((e = llr_coef(R->X, R->g, L, rc, R->U, R->f, R->C, aux_stream(R, 1, 2, s)))) return e;
-  if ((e = nufft_adj_coils(R->plan, R->res, R->ZG, R->nws, s, R->smaps, R->ncoils))) return e;  // G = A^H r
-  if ((e = subspace_reduce(R->ZG, nullptr, nullptr, V, L, Nv, r, R->aU, (cf*)R->rws, s))) return e;  // G V
+  if (R->toep) {
+    // G V = (A^H A X) V - (A^H b) V, with A^H A X from the last cost evaluation
+    if ((e = subspace_reduce(R->TX, nullptr, nullptr, V, L, Nv, r, R->aU, (cf*)R->rws, s))) return e;
+    MRF_LAUNCH("recon_toep_grad", s, k_sub_c<<<ceil_div((long)Nv * r, 256), 256, 0, s>>>(R->aU, R->AHbV, (long)Nv * r));
+  } else {
+    if ((e = nufft_adj_coils(R->plan, R->res, R->ZG, R->nws, s, R->smaps, R->ncoils))) return e;  // G = A^H r
+    if ((e = subspace_reduce(R->ZG, nullptr, nullptr, V, L, Nv, r, R->aU, (cf*)R->rws, s))) return e;  // G V
+  }
   // aX = X V is current: the graph rebuild (or the initialisation) computed it from this X
   if ((e = join(R, 0, 2, s))) return e;
   if ((e = lap_apply_sub(R->graph, R->aX, R->Ya, r, s))) return e;                            // S_L(X V)
@@ -635,6 +754,7 @@ namespace {
 struct CkptHeader {
   uint64_t magic;
   int version, N, L, Ns, Np, rcap, pp, r, pending, ncoils;   // ncoils 0: single coil, no maps
+  int toeplitz, pad;                                          // 1: saved in the Toeplitz mode
   double c_prev;
   mrf_recon_stats st;
 };
@@ -671,11 +791,12 @@ extern "C" mrf_status mrf_recon_checkpoint_save(mrf_recon_t R, void* buf, size_t
   MRF_REQUIRE(bytes >= c.total, MRF_WORKSPACE, "recon_checkpoint_save: buffer smaller than mrf_recon_checkpoint_bytes");
   CkptHeader h{};
   h.magic = kCkptMagic;
-  h.version = 1;
+  h.version = 2;
   h.N = R->N; h.L = R->L; h.Ns = R->Ns; h.Np = R->g.Np; h.rcap = R->prm.rank_cap; h.pp = R->prm.p * R->prm.p;
   h.r = R->r;
   h.pending = R->pending_graph ? 1 : 0;
   h.ncoils = R->ncoils;
+  h.toeplitz = R->toep ? 1 : 0;
   h.c_prev = R->c_prev;
   h.st = R->st;
   char* o = (char*)buf;
@@ -699,9 +820,10 @@ extern "C" mrf_status mrf_recon_checkpoint_load(mrf_recon_t R, const mrf_c64* b,
   CkptHeader h{};
   const char* o = (const char*)buf;
   MRF_CHECK_HIP(hipMemcpy(&h, o, sizeof h, hipMemcpyDefault));
-  MRF_REQUIRE(h.magic == kCkptMagic && h.version == 1, MRF_INVALID_ARG, "recon_checkpoint_load: not a checkpoint");
+  MRF_REQUIRE(h.magic == kCkptMagic && h.version == 2, MRF_INVALID_ARG, "recon_checkpoint_load: not a checkpoint");
   MRF_REQUIRE(h.N == R->N && h.L == R->L && h.Ns == R->Ns && h.Np == R->g.Np && h.rcap == R->prm.rank_cap &&
-                  h.pp == R->prm.p * R->prm.p && h.r == R->r && h.ncoils == R->ncoils,
+                  h.pp == R->prm.p * R->prm.p && h.r == R->r && h.ncoils == R->ncoils &&
+                  h.toeplitz == (R->toep ? 1 : 0),
               MRF_SHAPE, "recon_checkpoint_load: the checkpoint's sizes differ from this recon's");
   MRF_CHECK_HIP(hipMemcpyAsync(R->X, o + c.x, (size_t)R->L * R->Nv * 8, hipMemcpyDefault, s));
   MRF_CHECK_HIP(hipMemcpyAsync(R->res, o + c.res, (size_t)std::max(1, R->ncoils) * R->L * R->Ns * 8,
@@ -714,6 +836,12 @@ extern "C" mrf_status mrf_recon_checkpoint_load(mrf_recon_t R, const mrf_c64* b,
   R->c_prev = h.c_prev;
   R->pending_graph = h.pending != 0;
   R->initialised = true;
+  if (R->toep) {
+    // A^H b, (A^H b) V, ||b||^2 and A^H A X are functions of b and the restored X: recomputed
+    mrf_status e = toep_prepare(R, false, s);
+    if (!e) e = toeplitz_apply(R->toep, R->X, R->TX, R->nws, s);
+    if (e) return e;
+  }
   if (!R->pending_graph && active(R)) {
     // saved right after the initialisation: its graph is rebuilt from X^0 (the same deterministic
     // kernels on the same data give the same graph, lambda1 and mu); the statistics already hold it

@@ -140,3 +140,42 @@ class CartPlan(NufftPlan):
         sz = ctypes.c_size_t()
         check(lib.mrf_nufft_workspace_size(h, ctypes.byref(sz)), "mrf_nufft_workspace_size")
         self.ws = torch.empty(max(1, sz.value), dtype=torch.uint8, device=mask.device)
+
+
+class Toeplitz:
+    """Toeplitz normal operator A^H A (mrf_toeplitz_create) for the trajectory traj [L, Ns, 2]
+    (float32, device) of an n x n image series."""
+
+    def __init__(self, n, traj, stream=None):
+        L, Ns, _ = traj.shape
+        _need(traj, torch.float32, (L, Ns, 2), "traj")
+        self.n, self.L = int(n), int(L)
+        desc = NufftDesc(self.n, self.L, int(Ns), 6, 2, 0)
+        h = ctypes.c_void_p()
+        check(lib.mrf_toeplitz_create(ctypes.byref(desc), _ptr(traj), _stream(stream), ctypes.byref(h)),
+              "mrf_toeplitz_create")
+        self.handle = h
+        sz = ctypes.c_size_t()
+        check(lib.mrf_toeplitz_workspace_size(h, ctypes.byref(sz)), "mrf_toeplitz_workspace_size")
+        self.ws = torch.empty(max(1, sz.value), dtype=torch.uint8, device=traj.device)
+
+    def normal(self, X, out=None, stream=None):
+        """A^H A X for X [L, n, n] complex64."""
+        _need(X, torch.complex64, (self.L, self.n, self.n), "X")
+        if out is None:
+            out = torch.empty_like(X)
+        _need(out, torch.complex64, (self.L, self.n, self.n), "out")
+        check(lib.mrf_toeplitz_normal(self.handle, _ptr(X), _ptr(out), _ptr(self.ws), self.ws.numel(),
+                                      _stream(stream)), "mrf_toeplitz_normal")
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.mrf_toeplitz_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -39,6 +39,13 @@ class Recon:
               "mrf_recon_set_coils")
         self.ncoils = smaps.shape[0]
 
+    def set_toeplitz(self, toeplitz, stream=None):
+        """Data-term gradient and value through a Toeplitz normal operator (built from this plan's
+        trajectory), or None for the gridded pair; call before init."""
+        self._toeplitz = toeplitz   # kept alive: the recon holds its handle by pointer
+        check(lib.mrf_recon_set_toeplitz(self.handle, toeplitz.handle if toeplitz is not None else None,
+                                         stream_ptr(stream)), "mrf_recon_set_toeplitz")
+
     def _b_shape(self):
         return ((self.ncoils,) if self.ncoils else ()) + (self.L, self.plan.Ns)
 

@@ -21,3 +21,16 @@ def rel_l2(a, b):
 
 def say(msg):
     print(msg, flush=True)
+
+
+def nuc_fp32_gram(X, p, s):
+    """Sum over the p x p patches (stride s) of sqrt(max(eig, 0)) of each patch Gram formed in FP32,
+    as the GPU forms it: the nuclear norm with the FP32 Gram's floor on vanishing singular values."""
+    L, N, _ = X.shape
+    X32 = np.asarray(X).astype(np.complex64)
+    out = 0.0
+    for y0 in range(0, N - p + 1, s):
+        for x0 in range(0, N - p + 1, s):
+            Q = X32[:, y0:y0 + p, x0:x0 + p].reshape(L, -1).T
+            out += np.sqrt(np.maximum(np.linalg.eigvalsh((Q @ Q.conj().T).astype(np.complex128)), 0.0)).sum()
+    return out

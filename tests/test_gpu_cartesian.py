@@ -16,7 +16,7 @@ import torch
 import mrfgen
 from oracle import cartesian as ocart
 from oracle import recon as orecon
-from tests.gpu_util import rel_l2, say, to_dev
+from tests.gpu_util import nuc_fp32_gram, rel_l2, say, to_dev
 from tests.workloads import cart_workload
 
 pytestmark = pytest.mark.gpu
@@ -110,18 +110,6 @@ def test_cartesian_recon_follows_the_oracle_with_its_graphs():
     assert agree >= 0.995
 
 
-def _nuc_fp32_gram(X, p, s):
-    """sum over patches of sqrt(max(eig, 0)) of the patch Gram formed in FP32 (as the GPU forms it)."""
-    L, N, _ = X.shape
-    X32 = X.astype(np.complex64)
-    out = 0.0
-    for y0 in range(0, N - p + 1, s):
-        for x0 in range(0, N - p + 1, s):
-            Q = X32[:, y0:y0 + p, x0:x0 + p].reshape(L, -1).T
-            out += np.sqrt(np.maximum(np.linalg.eigvalsh((Q @ Q.conj().T).astype(np.complex128)), 0.0)).sum()
-    return out
-
-
 def test_llr_only_ablation_runs_freely_with_the_oracle():
     """lambda1^0 = 0: no graph enters the iterate (the step size is min(mu0, 1/lamA)), so both runs
     take their own graphs and still agree: X and the data term within 1e-5, no manifold term.
@@ -143,7 +131,7 @@ def test_llr_only_ablation_runs_freely_with_the_oracle():
     # relative to the cost: at n = 0 the data term vanishes (X^0 = F^H M b and b is zero off the mask)
     ed = np.max(np.abs(np.array(st["data"]) - data_o) / np.array(o["stats"]["cost"]))
     en = abs(st["nuc"][-1] - nuc_o[-1]) / nuc_o[-1]
-    floor = abs(_nuc_fp32_gram(o["X"], cfg["p"], cfg["s"]) - nuc_o[-1]) / nuc_o[-1]
+    floor = abs(nuc_fp32_gram(o["X"], cfg["p"], cfg["s"]) - nuc_o[-1]) / nuc_o[-1]
     say(f"LLR-only (lambda1^0 = 0), 10 iterations: X rel-L2 {ex:.2e}, data term rel {ed:.2e}, "
         f"nuclear norm rel {en:.2e} (FP32-Gram floor on the oracle's X {floor:.2e})")
     assert ex <= 1e-5 and ed <= 1e-5
