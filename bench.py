@@ -231,6 +231,45 @@ def bench_multicoil(torch, mrf, dev, plan, d, cfg, Xtrue, ncoils=8, iters=3):
                 cost_decreasing=bool(np.all(np.diff(st["cost"]) < 0)))
 
 
+def bench_toeplitz(torch, mrf, dev, plan, d, cfg, traj_dev, b, lamA, iters=5):
+    """Toeplitz normal operator (NEXT-2) at 256 x 256, L = 1000: set-up time, one A^H A against the
+    gridded pair A^H A, Algorithm 1's iteration with the gradient and data term through it, and X
+    after `iters` iterations against the gridded run's (the two differ by the KB error)."""
+    N = cfg["N"]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    T = mrf.Toeplitz(N, traj_dev)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+    X = plan.adj(b)
+    Y = torch.empty_like(X)
+    op_ms = _time(torch, lambda: T.normal(X, Y), 10)
+    kb = plan.fwd(X)
+    pair_ms = _time(torch, lambda: (plan.fwd(X, kb), plan.adj(kb, Y)), 10)
+    del kb, Y
+    out = {}
+    for name, use in (("toeplitz", True), ("gridded", False)):
+        rc = mrf.Recon(plan, d, cfg["p"], cfg["s"], cfg["K"], cfg["r_llr"], lam1_0=cfg["lam1_0"], lam2=cfg["lam2"],
+                       beta=cfg["beta"], mu0=cfg["mu0"], lamA=lamA, n_max=100000, tol=-1.0)
+        if use:
+            rc.set_toeplitz(T)
+        rc.init(b)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rc.iterate(iters)
+        torch.cuda.synchronize()
+        out[name] = ((time.perf_counter() - t) * 1e3 / iters, rc.finish()["X"])
+        rc.close()
+    dx = float(torch.linalg.vector_norm(out["toeplitz"][1] - out["gridded"][1]) /
+               torch.linalg.vector_norm(out["gridded"][1]))
+    T.close()
+    log("Toeplitz: set-up %.2f s, A^H A %.3f ms (gridded pair %.3f ms), iteration %.3f ms (gridded %.3f ms), "
+        "X after %d iterations rel %.2e" % (setup_s, op_ms, pair_ms, out["toeplitz"][0], out["gridded"][0], iters, dx))
+    return dict(setup_s=round(setup_s, 3), normal_op_ms=round(op_ms, 4), gridded_pair_ms=round(pair_ms, 4),
+                iteration_ms=round(out["toeplitz"][0], 4), gridded_iteration_ms=round(out["gridded"][0], 4),
+                x_rel_diff_vs_gridded=dx, iterations=iters)
+
+
 def bench_radial(torch, mrf, dev, iters=50, n_spokes=13, lam1_0s=(0.1, 0.01, 0.001, 0.0)):
     """Pseudo-radial Cartesian sampling (the paper's third pattern; about 5% of k-space per frame
     with 13 golden-angle-rotated spokes at 256 x 256) at L = 500, the length of its sampling-pattern
@@ -412,6 +451,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 8-slice batched component")
     ap.add_argument("--no-multicoil", action="store_true", help="skip the 8-coil component")
     ap.add_argument("--no-radial", action="store_true", help="skip the pseudo-radial Cartesian component")
+    ap.add_argument("--no-toeplitz", action="store_true", help="skip the Toeplitz normal-operator component")
     ap.add_argument("--serial", type=int, default=0,
                     help="recon schedule mask: bit 0 runs the cost terms, bit 1 the rest of an iteration on one "
                          "stream (default 0: independent parts overlap on the recon's two extra streams)")
@@ -427,7 +467,8 @@ def main():
     dev = torch.device("cuda:0")
     cfg, atoms, grid, V, ph, Xtrue, traj = build_workload()
     N, L, Ns = cfg["N"], cfg["L"], cfg["Ns"]
-    plan = mrf.NufftPlan(N, torch.from_numpy(traj).to(dev))
+    traj_dev = torch.from_numpy(traj).to(dev)
+    plan = mrf.NufftPlan(N, traj_dev)
     lamA = plan.opnorm(30)
     log("lambda_max(A^H A) = %.3f" % lamA)
     d = mrf.Dictionary(torch.from_numpy(atoms).to(dev), torch.from_numpy(grid["lut"]).to(dev),
@@ -551,6 +592,8 @@ def main():
         comps_extra["batched_c5"] = bench_batched(torch, mrf, dev)
     if not args.no_multicoil:
         comps_extra["multicoil"] = bench_multicoil(torch, mrf, dev, plan, d, cfg, Xtrue)
+    if not args.no_toeplitz:
+        comps_extra["toeplitz"] = bench_toeplitz(torch, mrf, dev, plan, d, cfg, traj_dev, b, lamA)
     if not args.no_radial:
         comps_extra["radial_cartesian"] = bench_radial(torch, mrf, dev)
 
