@@ -106,8 +106,22 @@ def bench_precision_match(torch, mrf, dev, fp, truth, mask, oracle_sample=256, d
     import mrfgen
     from oracle import match as omatch
     cfg3 = mrfgen.get_config("C3")
+    t0 = time.perf_counter()
     atoms, grid = mrfgen.make_dictionary(cfg3)
+    cpu_dict_s = time.perf_counter() - t0
     lut = grid["lut"]
+    # the same 50 000-atom T1 x T2 x B1 dictionary made on the device (EPG, FP32)
+    fa, tr, te = mrfgen.fisp_sequence(cfg3["L"], cfg3["fa_range"], cfg3["fa_period"], cfg3["tr_ms"], cfg3["te_ms"])
+    cols = [torch.from_numpy(grid[k].astype(np.float32)).to(dev) for k in ("T1", "T2", "B1")]
+    fa_d, tr_d = torch.from_numpy(fa.astype(np.float32)).to(dev), torch.from_numpy(tr.astype(np.float32)).to(dev)
+    gen = lambda: mrf.epg_fisp(cols[0], cols[1], fa_d, tr_d, te, b1=cols[2], n_states=cfg3["epg_states"])
+    gpu_atoms = gen()
+    gpu_dict_ms = _time(torch, gen, 3)
+    ga = gpu_atoms.cpu().numpy()
+    dict_err = float(np.max(np.linalg.norm(ga - atoms, axis=1) / np.linalg.norm(atoms, axis=1)))
+    del gpu_atoms, ga
+    log("C3 dictionary (%d atoms x %d frames): CPU generator %.2f s, GPU EPG %.2f ms, worst per-atom rel diff %.1e"
+        % (atoms.shape[0], atoms.shape[1], cpu_dict_s, gpu_dict_ms, dict_err))
     d = mrf.Dictionary(torch.from_numpy(atoms).to(dev), torch.from_numpy(lut).to(dev))
     Nv = fp.shape[0]
     rng = np.random.default_rng(0)
@@ -116,6 +130,9 @@ def bench_precision_match(torch, mrf, dev, fp, truth, mask, oracle_sample=256, d
     ref_idx = omatch.precision_match_ref(fp[sample].cpu().numpy(), atoms, lut)[0]
     log("C3 oracle sample (%d voxels) %.1f s" % (oracle_sample, time.time() - t0))
     out = {"atoms": int(atoms.shape[0]), "fingerprints": int(Nv), "L": int(atoms.shape[1]),
+           "epg_dictionary": dict(gpu_ms=round(gpu_dict_ms, 3), cpu_generator_s=round(cpu_dict_s, 3),
+                                  atoms_per_s_gpu=round(atoms.shape[0] / gpu_dict_ms * 1e3, 1),
+                                  worst_rel_diff_vs_cpu=dict_err),
            "fingerprints_from": "the GPU reconstruction of the 256 x 256 series after its 30 iterations"}
 
     def run(mode, depth):
@@ -147,8 +164,27 @@ def bench_precision_match(torch, mrf, dev, fp, truth, mask, oracle_sample=256, d
     return out
 
 
+def offgrid_pool(torch, mrf, dev, cfg, V, n=200_000, seed=5):
+    """A training dictionary of n off-grid atoms made on the device: (T1, T2) drawn log-uniformly
+    over the C2 grid's ranges with T2 <= T1 (Philox), signals by the EPG kernel on the C2 train."""
+    import mrfgen
+    fa, tr, te = mrfgen.fisp_sequence(cfg["L"], cfg["fa_range"], cfg["fa_period"], cfg["tr_ms"], cfg["te_ms"])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    params = mrf.random_params(n, seed, cfg["t1_grid"][:2], cfg["t2_grid"][:2])
+    cols = mrf.params_columns(params)
+    atoms = mrf.epg_fisp(cols[0].contiguous(), cols[1].contiguous(), torch.from_numpy(fa.astype(np.float32)).to(dev),
+                         torch.from_numpy(tr.astype(np.float32)).to(dev), te, n_states=cfg["epg_states"])
+    pool = mrf.Dictionary(atoms, params[:, :2].contiguous(), torch.from_numpy(V).to(dev))
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t
+    del atoms
+    log("off-grid training pool: %d EPG atoms made on the device in %.3f s" % (n, gen_s))
+    return pool, gen_s
+
+
 def bench_learned_match(torch, mrf, dev, d, V, Xn, truth, mask, grid, epochs=20, batch=4096, samples=2_000_000,
-                        max_steps=None):
+                        max_steps=None, train_d=None):
     """MLP trained on the device (2 M noisy atoms per epoch, SNR 20-60 dB, BF16 GEMMs), then the
     gated learned match on the 65 536 reconstructed fingerprints against the plain FP32 exhaustive
     subspace match: for a sweep of gate thresholds the T1/T2 NMSE over the tissue and how many
@@ -161,7 +197,8 @@ def bench_learned_match(torch, mrf, dev, d, V, Xn, truth, mask, grid, epochs=20,
     steps = epochs * steps_per_epoch if max_steps is None else max_steps
     torch.cuda.synchronize()
     t0 = time.time()
-    losses = net.train(d, steps=steps, batch=batch, lr=1e-3, total_steps=steps, seed=2, bf16=True)
+    losses = net.train(train_d if train_d is not None else d, steps=steps, batch=batch, lr=1e-3, total_steps=steps,
+                       seed=2, bf16=True)
     torch.cuda.synchronize()
     train_s = time.time() - t0
     lo = losses.cpu().numpy()
@@ -587,6 +624,14 @@ def main():
         grid_c2 = mrfgen.param_grid(cfg)
         comps_extra["learned_match"] = bench_learned_match(torch, mrf, dev, d, V, Xhat, truth, tmask, grid_c2,
                                                           epochs=args.mlp_epochs, max_steps=args.mlp_steps)
+        # the same network trained on off-grid atoms made on the device (EPG), matched against
+        # the same grid dictionary
+        pool, pool_s = offgrid_pool(torch, mrf, dev, cfg, V)
+        comps_extra["learned_match_offgrid"] = bench_learned_match(
+            torch, mrf, dev, d, V, Xhat, truth, tmask, grid_c2, epochs=args.mlp_epochs, max_steps=args.mlp_steps,
+            train_d=pool)
+        comps_extra["learned_match_offgrid"]["pool"] = dict(atoms=pool.M, generation_s=round(pool_s, 3))
+        pool.close()
     if not args.no_batched:
         rc.close()
         comps_extra["batched_c5"] = bench_batched(torch, mrf, dev)

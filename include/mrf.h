@@ -136,6 +136,27 @@ mrf_status mrf_toeplitz_workspace_size(mrf_toeplitz_t t, size_t* bytes);
 mrf_status mrf_toeplitz_normal(mrf_toeplitz_t t, const mrf_c64* X, mrf_c64* Y, void* ws, size_t ws_bytes,
                                hipStream_t stream);
 
+/* FISP signal model (eqs. (2)-(3)) by the extended phase graph, on the device: the dictionary
+ * atoms d_m = B(eta_m; theta) with PD = 1 and off-grid training signals. States F+_k, F-_k, Z_k,
+ * k < n_states; an ideal inversion and one TR of recovery, then per frame l an RF rotation about
+ * x by fa_deg[l] * b1[m] degrees, the signal F+_0 exp(-TE/T2), relaxation over tr_ms[l] and one
+ * dephasing shift (orders >= n_states dropped).
+ * mrf_epg_fisp: t1, t2 [n_atoms] (ms), b1 [n_atoms] or NULL (1), fa_deg, tr_ms [n_frames] (all
+ *   device float32); out [n_atoms][n_frames] complex64 (device, caller-owned; unnormalised: pass
+ *   it to mrf_dict_create as is). n_states: 8, 16, 24 or 32 (MRF_SHAPE otherwise). FP32,
+ *   asynchronous. MRF_INVALID_ARG for null pointers, sizes < 1 or te_ms < 0.
+ * mrf_epg_random_params: params [n][3] (device) = (T1, T2, B1) drawn by Philox4x32-10 (counter
+ *   (i, 0x45504731, 0, 0), key = seed): T1 log-uniform on [t1_lo, t1_hi], T2 log-uniform on
+ *   [t2_lo, min(t2_hi, T1)] (so T2 <= T1, the rule of the paper's dictionary), B1 uniform on
+ *   [b1_lo, b1_hi]. Needs 0 < t2_lo <= t1_lo <= t1_hi, t2_lo <= t2_hi, b1_lo <= b1_hi.
+ * mrf_epg_params_to_columns: cols [3][n] (T1 row, T2 row, B1 row) from params [n][3], the inputs
+ *   of mrf_epg_fisp. */
+mrf_status mrf_epg_fisp(int n_atoms, int n_frames, int n_states, const float* t1, const float* t2, const float* b1,
+                        const float* fa_deg, const float* tr_ms, float te_ms, mrf_c64* out, hipStream_t stream);
+mrf_status mrf_epg_random_params(int n, uint64_t seed, float t1_lo, float t1_hi, float t2_lo, float t2_hi,
+                                 float b1_lo, float b1_hi, float* params, hipStream_t stream);
+mrf_status mrf_epg_params_to_columns(int n, const float* params, float* cols, hipStream_t stream);
+
 /* Multi-coil acquisition (Sec. II, eq. (1)): the forward operator is F_u C, where C multiplies
  * every frame by each coil's sensitivity map and F_u is the single-coil operator above.
  *   smaps  device complex64 [ncoils][N][N], one map per coil, shared by all frames; caller-owned,

@@ -78,3 +78,21 @@ def isochromat_fisp(t1, t2, fa_deg, tr_ms, te_ms, n_iso, b1=1.0):
         c, s = np.cos(phi), np.sin(phi)                 # precession by the gradient's twist
         M[0], M[1] = c * M[0] - s * M[1], s * M[0] + c * M[1]
     return out
+
+
+def random_params(n, seed, t1_range, t2_range, b1_range=(1.0, 1.0)):
+    """Off-grid parameter sets [n, 3] = (T1, T2, B1): for set i, Philox4x32-10 (oracle.mlp) with
+    counter (i, 0x45504731, 0, 0) and key (seed low, seed high) gives u1, u2, u3 in (0, 1);
+    T1 = exp(log t1_lo + u1 (log t1_hi - log t1_lo)), T2 = exp(log t2_lo + u2 (log min(t2_hi, T1)
+    - log t2_lo)) so that T2 <= T1, B1 = b1_lo + u3 (b1_hi - b1_lo)."""
+    from .mlp import _u01, philox4x32_10
+    i = np.arange(n, dtype=np.uint64)
+    ctr = np.stack([i, np.full(n, 0x45504731, np.uint64), np.zeros(n, np.uint64), np.zeros(n, np.uint64)], -1)
+    key = np.stack([np.full(n, seed & 0xFFFFFFFF, np.uint64), np.full(n, (seed >> 32) & 0xFFFFFFFF, np.uint64)], -1)
+    u = philox4x32_10(ctr, key)
+    a1, b1_ = np.log(t1_range[0]), np.log(t1_range[1])
+    T1 = np.exp(a1 + _u01(u[:, 0]) * (b1_ - a1))
+    a2, b2 = np.log(t2_range[0]), np.log(np.minimum(t2_range[1], T1))
+    T2 = np.exp(a2 + _u01(u[:, 1]) * (b2 - a2))
+    B1 = b1_range[0] + _u01(u[:, 2]) * (b1_range[1] - b1_range[0])
+    return np.stack([T1, T2, B1], -1)

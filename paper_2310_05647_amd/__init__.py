@@ -7,6 +7,7 @@ package fails loudly when libmrf.so has not been built.
 """
 from ._lib import MrfError, lib, library_path, check, timing_enable, timing_report  # noqa: F401
 from .nufft import CartPlan, NufftPlan, Toeplitz, autotune  # noqa: F401
+from .epg import epg_fisp, params_columns, random_params  # noqa: F401
 from .graph import PatchGraph  # noqa: F401
 from .llr import llr_prox, llr_xupdate  # noqa: F401
 from .subspace import (Dictionary, frames_to_voxels, subspace_coeffs, subspace_coeffs_noalloc,  # noqa: F401

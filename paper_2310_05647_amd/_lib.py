@@ -63,6 +63,11 @@ _decl("mrf_nufft_fwd", [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void
 _decl("mrf_nufft_adj", [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p])
 _decl("mrf_nufft_opnorm", [c_void_p, c_int, ctypes.c_uint, P(ctypes.c_double), c_void_p])
 _decl("mrf_cart_plan_create", [c_int, c_int, c_void_p, c_void_p, P(c_void_p)])
+_decl("mrf_epg_fisp", [c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_void_p,
+                       c_void_p])
+_decl("mrf_epg_random_params", [c_int, ctypes.c_uint64, c_float, c_float, c_float, c_float, c_float, c_float,
+                                c_void_p, c_void_p])
+_decl("mrf_epg_params_to_columns", [c_int, c_void_p, c_void_p, c_void_p])
 _decl("mrf_toeplitz_create", [P(NufftDesc), c_void_p, c_void_p, P(c_void_p)])
 _decl("mrf_toeplitz_destroy", [c_void_p])
 _decl("mrf_toeplitz_workspace_size", [c_void_p, P(c_size_t)])

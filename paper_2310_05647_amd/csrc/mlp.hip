@@ -28,6 +28,7 @@
 
 #include "common.hpp"
 #include "dict.hpp"
+#include "philox.hpp"
 
 struct mrf_mlp_s {
   int nin, hid, nhl, nout;      // input width, hidden width, hidden layers, outputs
@@ -50,27 +51,6 @@ namespace mrf {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-// ------------------------------------------------------------------ Philox4x32-10
-// Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3" (SC'11): ten rounds
-// of two 32x32 -> 64-bit multiplies with the Weyl key schedule.
-struct u4 {
-  unsigned x, y, z, w;
-};
-__device__ inline u4 philox(u4 c, unsigned k0, unsigned k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const unsigned long long p0 = (unsigned long long)0xD2511F53u * c.x;
-    const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * c.z;
-    const unsigned hi0 = (unsigned)(p0 >> 32), lo0 = (unsigned)p0;
-    const unsigned hi1 = (unsigned)(p1 >> 32), lo1 = (unsigned)p1;
-    c = u4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-  return c;
-}
-__device__ inline float u01(unsigned u) { return ((float)u + 0.5f) * 2.3283064365386963e-10f; }
 
 constexpr int kMaxR = 16;
 

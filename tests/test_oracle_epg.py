@@ -56,3 +56,15 @@ def test_matches_the_input_generator():
     ref = c_epg(t1, t2, fa, tr, te, 24, b1=b1)
     got = epg.epg_fisp(t1, t2, fa, tr, te, 24, b1=b1)
     assert np.abs(got - ref).max() <= 2e-7 * np.abs(ref).max()
+
+
+def test_random_params_ranges_and_rule():
+    p = epg.random_params(20000, 7, (100.0, 4000.0), (20.0, 2000.0), (0.8, 1.2))
+    T1, T2, B1 = p.T
+    assert np.all((T1 >= 100) & (T1 <= 4000)) and np.all((T2 >= 20) & (T2 <= T1 * (1 + 1e-12)))
+    assert np.all((B1 >= 0.8) & (B1 <= 1.2))
+    # log T1 is uniform: its mean is the midpoint of the log range (to sampling error)
+    assert abs(np.log(T1).mean() - 0.5 * (np.log(100) + np.log(4000))) < 0.03
+    # a different seed gives different draws, the same seed the same
+    assert not np.allclose(p, epg.random_params(20000, 8, (100.0, 4000.0), (20.0, 2000.0), (0.8, 1.2)))
+    np.testing.assert_array_equal(p, epg.random_params(20000, 7, (100.0, 4000.0), (20.0, 2000.0), (0.8, 1.2)))
