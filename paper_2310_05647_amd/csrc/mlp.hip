@@ -253,6 +253,136 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* 
       }
 }
 
+// BF16 GEMM with the same contract as k_gemm<true, ...>, software-pipelined: 64 x 64 tiles with
+// K steps of 64; the next step's operands are loaded into registers while the MFMAs of this one
+// run, then converted to BF16 once and stored to the other half of a double-buffered LDS tile (one
+// barrier per step). A lane's 8 consecutive k values of a row are one 16-byte LDS read.
+constexpr int kGB = 64, kGBK = 64, kGBP = kGBK + 8;   // tile, K step, LDS row pitch (bf16)
+__device__ inline unsigned short bf16_rne(float a) {
+  const unsigned u = __float_as_uint(a);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// With asum (A laid out [k][m] only), the blocks of the first column tile also write the FP32
+// sums over their k slice of A's rows, asum[z M + m] = sum_k A(m, k): the bias gradient of the
+// weight-gradient product, in a fixed order (per thread in k order, then the four waves in order).
+template <int ALAY, int BLAY, int EPI>
+__global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const float* __restrict__ A, int lda,
+                                                   const float* __restrict__ B, int ldb, float* __restrict__ C,
+                                                   int ldc, const float* __restrict__ bias,
+                                                   const float* __restrict__ mask, int mld, int ks,
+                                                   float* __restrict__ asum) {
+  __shared__ __align__(16) unsigned short As[2][kGB][kGBP];
+  __shared__ __align__(16) unsigned short Bs[2][kGB][kGBP];
+  __shared__ float sred[4][kGB];
+  const bool do_sum = ALAY == LAY_MN && asum && blockIdx.x == 0;
+  float rsum = 0.f;   // this thread's row (m0 + lane) of A over its k values
+  constexpr int PER = kGB * kGBK / 256;   // operand elements per thread and step
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int wm = w >> 1, wn = w & 1, q = lane >> 4, n16 = lane & 15;
+  const int n0 = blockIdx.x * kGB, m0 = blockIdx.y * kGB;
+  const int kb = blockIdx.z * ks, ke = min(K, kb + ks);
+  C += (size_t)blockIdx.z * M * ldc;
+  float ra[PER], rb[PER];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int idx = tid + 256 * j;
+      int r, c;
+      if (ALAY == LAY_K) { r = idx / kGBK; c = idx % kGBK; }
+      else { c = idx / kGB; r = idx % kGB; }
+      const int m = m0 + r, k = k0 + c;
+      ra[j] = (m < M && k < ke) ? (ALAY == LAY_K ? A[(size_t)m * lda + k] : A[(size_t)k * lda + m]) : 0.f;
+      if (BLAY == LAY_K) { r = idx / kGBK; c = idx % kGBK; }
+      else { c = idx / kGB; r = idx % kGB; }
+      const int n = n0 + r, k2 = k0 + c;
+      rb[j] = (n < N && k2 < ke) ? (BLAY == LAY_K ? B[(size_t)n * ldb + k2] : B[(size_t)k2 * ldb + n]) : 0.f;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int idx = tid + 256 * j;
+      int r, c;
+      if (ALAY == LAY_K) { r = idx / kGBK; c = idx % kGBK; }
+      else { c = idx / kGB; r = idx % kGB; }
+      if (ALAY == LAY_MN && do_sum) rsum += ra[j];   // r = lane for every j
+      As[buf][r][c] = bf16_rne(ra[j]);
+      if (BLAY == LAY_K) { r = idx / kGBK; c = idx % kGBK; }
+      else { c = idx / kGB; r = idx % kGB; }
+      Bs[buf][r][c] = bf16_rne(rb[j]);
+    }
+  };
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  load(kb);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kb; k0 < ke; k0 += kGBK) {
+    const bool more = k0 + kGBK < ke;
+    if (more) load(k0 + kGBK);
+#pragma unroll
+    for (int kk = 0; kk < kGBK; kk += 32) {
+      bf16x8 av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        av[a] = *(const bf16x8*)&As[buf][wm * 32 + a * 16 + n16][kk + 8 * q];
+        bv[a] = *(const bf16x8*)&Bs[buf][wn * 32 + a * 16 + n16][kk + 8 * q];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  if (ALAY == LAY_MN && do_sum) {
+    sred[w][lane] = rsum;
+    __syncthreads();
+    if (w == 0 && m0 + lane < M)
+      asum[(size_t)blockIdx.z * M + m0 + lane] = (sred[0][lane] + sred[1][lane]) + (sred[2][lane] + sred[3][lane]);
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = m0 + wm * 32 + a * 16 + 4 * q + i, n = n0 + wn * 32 + b * 16 + n16;
+        if (m < M && n < N) {
+          float v = acc[a][b][i];
+          if (EPI == EPI_BIAS_RELU) v = fmaxf(v + bias[n], 0.f);
+          else if (EPI == EPI_BIAS) v += bias[n];
+          else if (EPI == EPI_MASK) v = mask[(size_t)m * mld + n] > 0.f ? v : 0.f;
+          C[(size_t)m * ldc + n] = v;
+        }
+      }
+}
+
+// out[i] = sum_s part[s n + i] and out2[i] = sum_s part2[s n2 + i] (fixed order): the weight and
+// bias gradients from the split-K slices
+__global__ __launch_bounds__(256) void k_reduce_slices2(const float* __restrict__ part, int S, long n,
+                                                        float* __restrict__ out, const float* __restrict__ part2,
+                                                        long n2, float* __restrict__ out2) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    float s = 0.f;
+    for (int k = 0; k < S; ++k) s += part[(size_t)k * n + i];
+    out[i] = s;
+  } else if (i < n + n2) {
+    const long j = i - n;
+    float s = 0.f;
+    for (int k = 0; k < S; ++k) s += part2[(size_t)k * n2 + j];
+    out2[j] = s;
+  }
+}
+
 // out[i] = sum_s part[s n + i] (fixed order)
 __global__ __launch_bounds__(256) void k_reduce_slices(const float* __restrict__ part, int S, long n,
                                                        float* __restrict__ out) {
@@ -429,10 +559,14 @@ __global__ void k_zero_int(int* p) { p[0] = 0; }
 // ------------------------------------------------------------------ host side
 template <bool BF16, int AL, int BL, int EPI>
 mrf_status gemm(int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C, int ldc, const float* bias,
-                const float* mask, int mld, int S, hipStream_t s, const char* name) {
+                const float* mask, int mld, int S, hipStream_t s, const char* name, float* asum = nullptr) {
   const int ks = (K + S - 1) / S;
   dim3 grid(ceil_div(N, kG), ceil_div(M, kG), S);
-  MRF_LAUNCH(name, s, k_gemm<BF16, AL, BL, EPI><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, mask, mld, ks));
+  if (BF16)
+    MRF_LAUNCH(name, s, k_gemm_bf16<AL, BL, EPI><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, mask, mld, ks,
+                                                                     asum));
+  else
+    MRF_LAUNCH(name, s, k_gemm<false, AL, BL, EPI><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, mask, mld, ks));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
 }
@@ -486,7 +620,7 @@ TrainWs train_ws(const mrf_mlp_s* P, int B, void* base) {
   for (int l = 0; l < P->nl; ++l) w.acts.push_back(take((size_t)B * P->lout[l] * 4));
   w.g0 = take((size_t)B * wmax * 4);
   w.g1 = take((size_t)B * wmax * 4);
-  w.part = take((size_t)kSplitK * wmax * wmax * 4);
+  w.part = take((size_t)kSplitK * (wmax * wmax + wmax) * 4);
   w.lpart = take((size_t)ceil_div((long)B * P->nout, 256) * 4);
   w.loss = take(4);
   w.bytes = off;
@@ -508,11 +642,20 @@ mrf_status mlp_backward(mrf_mlp_s* P, bool bf16, int B, TrainWs& w, hipStream_t 
     float* dW = P->g + P->offW[l];
     float* db = P->g + P->offb[l];
     // dW[out][in] = sum_b gout[b][out] h[b][in]: split over the batch, fixed-order reduction
-    if (bf16) e = gemm<true, LAY_MN, LAY_MN, EPI_STORE>(out, in, B, gout, out, w.acts[l], in, w.part, in, nullptr, nullptr, 0, kSplitK, s, "mlp_dw");
-    else e = gemm<false, LAY_MN, LAY_MN, EPI_STORE>(out, in, B, gout, out, w.acts[l], in, w.part, in, nullptr, nullptr, 0, kSplitK, s, "mlp_dw");
-    if (e) return e;
-    MRF_LAUNCH("mlp_dw_reduce", s, k_reduce_slices<<<ceil_div((long)out * in, 256), 256, 0, s>>>(w.part, kSplitK, (long)out * in, dW));
-    {  // the split-K partials were consumed by the reduction above: their buffer holds these
+    if (bf16) {
+      // the BF16 product also sums gout's columns (the bias gradient, in FP32) per batch slice,
+      // and one reduction finishes both
+      float* dbpart = w.part + (size_t)kSplitK * out * in;
+      e = gemm<true, LAY_MN, LAY_MN, EPI_STORE>(out, in, B, gout, out, w.acts[l], in, w.part, in, nullptr, nullptr, 0,
+                                                kSplitK, s, "mlp_dw", dbpart);
+      if (e) return e;
+      MRF_LAUNCH("mlp_dw_reduce", s, k_reduce_slices2<<<ceil_div((long)out * in + out, 256), 256, 0, s>>>(
+                                         w.part, kSplitK, (long)out * in, dW, dbpart, out, db));
+    } else {
+      e = gemm<false, LAY_MN, LAY_MN, EPI_STORE>(out, in, B, gout, out, w.acts[l], in, w.part, in, nullptr, nullptr, 0, kSplitK, s, "mlp_dw");
+      if (e) return e;
+      MRF_LAUNCH("mlp_dw_reduce", s, k_reduce_slices<<<ceil_div((long)out * in, 256), 256, 0, s>>>(w.part, kSplitK, (long)out * in, dW));
+      // the split-K partials were consumed by the reduction above: their buffer holds these
       const int nch = ceil_div(B, kColRows);
       MRF_LAUNCH("mlp_db", s, k_colsum_part<<<dim3(ceil_div(out, 64), nch), 256, 0, s>>>(gout, B, out, w.part));
       MRF_LAUNCH("mlp_db", s, k_colsum_final<<<ceil_div(out, 256), 256, 0, s>>>(w.part, nch, out, db));
