@@ -45,6 +45,9 @@ const char* mrf_status_string(mrf_status st);
 const char* mrf_last_error(void);
 /* Library version as major*10000 + minor*100 + patch. */
 int mrf_version(void);
+/* "sources-sha256=<hex> built=<UTC time> arch=gfx950": the SHA-256 over the library's sources
+ * (csrc/ and include/, in name order) as the build step saw them, and when it ran. Static string. */
+const char* mrf_build_info(void);
 
 /* Per-kernel timing for benchmarks. While enabled, every kernel launch of the library is
  * bracketed by two HIP events recorded on the stream the kernel is launched on. */

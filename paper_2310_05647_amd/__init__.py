@@ -5,7 +5,8 @@ torch device tensors (PyTorch provides device memory and the stream); their data
 and the current HIP stream are handed to the C-ABI calls of include/mrf.h. Importing this
 package fails loudly when libmrf.so has not been built.
 """
-from ._lib import MrfError, lib, library_path, check, timing_enable, timing_report  # noqa: F401
+from ._lib import (MrfError, build_info, built_from_current_sources, check, lib, library_path,  # noqa: F401
+                   timing_enable, timing_report)
 from .nufft import CartPlan, NufftPlan, Toeplitz, autotune  # noqa: F401
 from .epg import epg_fisp, params_columns, random_params  # noqa: F401
 from .graph import PatchGraph  # noqa: F401

@@ -54,6 +54,7 @@ def _decl(name, args, res=c_int):
 _decl("mrf_status_string", [c_int], c_char_p)
 _decl("mrf_last_error", [], c_char_p)
 _decl("mrf_version", [], c_int)
+_decl("mrf_build_info", [], c_char_p)
 _decl("mrf_timing_enable", [c_int])
 _decl("mrf_timing_report", [c_char_p, c_size_t])
 _decl("mrf_nufft_plan_create", [P(NufftDesc), c_void_p, c_void_p, P(c_void_p)])
@@ -168,3 +169,14 @@ def timing_report():
         name, n, tot, mn, mx = line.split()
         out[name] = (int(n), float(tot), float(mn), float(mx))
     return out
+
+
+def build_info():
+    """{'sources-sha256': ..., 'built': ..., 'arch': ...} of the loaded library (mrf_build_info)."""
+    return dict(kv.split("=", 1) for kv in lib.mrf_build_info().decode().split())
+
+
+def built_from_current_sources():
+    """True when the loaded library's source hash equals the hash of the sources in this tree."""
+    from . import build
+    return build_info().get("sources-sha256") == build.source_sha()

@@ -27,10 +27,26 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src):
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+
+
+def source_sha():
+    """SHA-256 over csrc/*.hip, *.cpp, *.hpp and include/*.h, in name order (names and contents)."""
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp", ".hpp")))
+    files += sorted(os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE) if f.endswith(".h"))
+    for path in files:
+        h.update(os.path.basename(path).encode() + b"\0")
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _compile(src, defines=()):
     obj = os.path.join(OUT, os.path.basename(src) + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC] + FLAGS + lang + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + FLAGS + list(defines) + lang + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s%s" % (" ".join(cmd), r.stdout, r.stderr))
@@ -41,8 +57,11 @@ def build(verbose=False):
     os.makedirs(OUT, exist_ok=True)
     srcs = sources()
     jobs = min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
+    import time
+    info = ['-DMRF_SOURCE_SHA="%s"' % source_sha(),
+            '-DMRF_BUILD_TIME="%s"' % time.strftime("%Y-%m-%dT%H:%M:%SZ", time.gmtime())]
     with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda src: _compile(src, info if src.endswith("runtime.cpp") else ()), srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)

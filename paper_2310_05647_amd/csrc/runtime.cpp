@@ -45,6 +45,18 @@ extern "C" const char* mrf_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" int mrf_version(void) { return 100; }
 
+// The build step passes the SHA-256 of the sources it compiled and the build time, so that a
+// caller can tell whether the loaded library was built from the sources beside it.
+#ifndef MRF_SOURCE_SHA
+#define MRF_SOURCE_SHA "unknown"
+#endif
+#ifndef MRF_BUILD_TIME
+#define MRF_BUILD_TIME "unknown"
+#endif
+extern "C" const char* mrf_build_info(void) {
+  return "sources-sha256=" MRF_SOURCE_SHA " built=" MRF_BUILD_TIME " arch=gfx950";
+}
+
 // ------------------------------------------------------------------ timing
 namespace {
 struct Rec {

@@ -26,6 +26,15 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
+def test_library_was_built_from_these_sources():
+    """The loaded libmrf.so carries the SHA-256 of the sources it was compiled from; it must be
+    this tree's (a stale binary after a source change fails here, and in smoke())."""
+    import paper_2310_05647_amd as m
+    info = m.build_info()
+    assert info["arch"] == "gfx950" and len(info["sources-sha256"]) == 64
+    assert m.built_from_current_sources(), info
+
+
 def test_status_strings_and_version():
     import paper_2310_05647_amd as m
     assert m.lib.mrf_status_string(0) == b"MRF_OK"
