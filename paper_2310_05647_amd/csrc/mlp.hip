@@ -266,7 +266,59 @@ __device__ inline unsigned short bf16_rne(float a) {
 // With asum (A laid out [k][m] only), the blocks of the first column tile also write the FP32
 // sums over their k slice of A's rows, asum[z M + m] = sum_k A(m, k): the bias gradient of the
 // weight-gradient product, in a fixed order (per thread in k order, then the four waves in order).
-template <int ALAY, int BLAY, int EPI>
+// One operand tile (64 rows x 64 k) of a step: loads into registers (float4 where the layout,
+// the leading dimension and the extents allow: V4), then BF16 into LDS.
+template <int LAY, bool V4>
+struct TileOp {
+  static constexpr int NL = V4 ? kGB * kGBK / 1024 : kGB * kGBK / 256;
+  float v[V4 ? 4 * NL : NL];
+  __device__ inline void load(const float* __restrict__ X, int ld, int row0, int rows, int k0, int ke, int tid) {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      if (V4) {
+        const int idx = tid + 256 * j;
+        int r, c;
+        if (LAY == LAY_K) { r = idx >> 4; c = (idx & 15) << 2; }
+        else { c = idx >> 4; r = (idx & 15) << 2; }
+        const int row = row0 + r, k = k0 + c;
+        float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (row < rows && k < ke)
+          x = *(const float4*)(LAY == LAY_K ? X + (size_t)row * ld + k : X + (size_t)k * ld + row);
+        v[4 * j] = x.x; v[4 * j + 1] = x.y; v[4 * j + 2] = x.z; v[4 * j + 3] = x.w;
+      } else {
+        const int idx = tid + 256 * j;
+        int r, c;
+        if (LAY == LAY_K) { r = idx / kGBK; c = idx % kGBK; }
+        else { c = idx / kGB; r = idx % kGB; }
+        const int row = row0 + r, k = k0 + c;
+        v[j] = (row < rows && k < ke) ? (LAY == LAY_K ? X[(size_t)row * ld + k] : X[(size_t)k * ld + row]) : 0.f;
+      }
+    }
+  }
+  __device__ inline void store(unsigned short (*Xs)[kGBP], int tid) const {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      const int idx = tid + 256 * j;
+      if (V4) {
+        if (LAY == LAY_K) {
+          const int r = idx >> 4, c = (idx & 15) << 2;
+          *(uint2*)&Xs[r][c] = make_uint2(bf16pair(v[4 * j], v[4 * j + 1]), bf16pair(v[4 * j + 2], v[4 * j + 3]));
+        } else {
+          const int c = idx >> 4, r = (idx & 15) << 2;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) Xs[r + i][c] = bf16_rne(v[4 * j + i]);
+        }
+      } else {
+        int r, c;
+        if (LAY == LAY_K) { r = idx / kGBK; c = idx % kGBK; }
+        else { c = idx / kGB; r = idx % kGB; }
+        Xs[r][c] = bf16_rne(v[j]);
+      }
+    }
+  }
+};
+
+template <int ALAY, int BLAY, int EPI, bool AV4, bool BV4>
 __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const float* __restrict__ A, int lda,
                                                    const float* __restrict__ B, int ldb, float* __restrict__ C,
                                                    int ldc, const float* __restrict__ bias,
@@ -275,43 +327,27 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const fl
   __shared__ __align__(16) unsigned short As[2][kGB][kGBP];
   __shared__ __align__(16) unsigned short Bs[2][kGB][kGBP];
   __shared__ float sred[4][kGB];
-  const bool do_sum = ALAY == LAY_MN && asum && blockIdx.x == 0;
+  // the column sums read A's scalar tile (r = lane for every element): only without AV4
+  const bool do_sum = ALAY == LAY_MN && !AV4 && asum && blockIdx.x == 0;
   float rsum = 0.f;   // this thread's row (m0 + lane) of A over its k values
-  constexpr int PER = kGB * kGBK / 256;   // operand elements per thread and step
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int wm = w >> 1, wn = w & 1, q = lane >> 4, n16 = lane & 15;
   const int n0 = blockIdx.x * kGB, m0 = blockIdx.y * kGB;
   const int kb = blockIdx.z * ks, ke = min(K, kb + ks);
   C += (size_t)blockIdx.z * M * ldc;
-  float ra[PER], rb[PER];
+  TileOp<ALAY, AV4> ta;
+  TileOp<BLAY, BV4> tb;
   auto load = [&](int k0) {
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int idx = tid + 256 * j;
-      int r, c;
-      if (ALAY == LAY_K) { r = idx / kGBK; c = idx % kGBK; }
-      else { c = idx / kGB; r = idx % kGB; }
-      const int m = m0 + r, k = k0 + c;
-      ra[j] = (m < M && k < ke) ? (ALAY == LAY_K ? A[(size_t)m * lda + k] : A[(size_t)k * lda + m]) : 0.f;
-      if (BLAY == LAY_K) { r = idx / kGBK; c = idx % kGBK; }
-      else { c = idx / kGB; r = idx % kGB; }
-      const int n = n0 + r, k2 = k0 + c;
-      rb[j] = (n < N && k2 < ke) ? (BLAY == LAY_K ? B[(size_t)n * ldb + k2] : B[(size_t)k2 * ldb + n]) : 0.f;
-    }
+    ta.load(A, lda, m0, M, k0, ke, tid);
+    tb.load(B, ldb, n0, N, k0, ke, tid);
   };
   auto store = [&](int buf) {
+    if (!AV4 && ALAY == LAY_MN && do_sum) {
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int idx = tid + 256 * j;
-      int r, c;
-      if (ALAY == LAY_K) { r = idx / kGBK; c = idx % kGBK; }
-      else { c = idx / kGB; r = idx % kGB; }
-      if (ALAY == LAY_MN && do_sum) rsum += ra[j];   // r = lane for every j
-      As[buf][r][c] = bf16_rne(ra[j]);
-      if (BLAY == LAY_K) { r = idx / kGBK; c = idx % kGBK; }
-      else { c = idx / kGB; r = idx % kGB; }
-      Bs[buf][r][c] = bf16_rne(rb[j]);
+      for (int j = 0; j < TileOp<ALAY, AV4>::NL; ++j) rsum += ta.v[j];   // r = lane for every j
     }
+    ta.store(As[buf], tid);
+    tb.store(Bs[buf], tid);
   };
   f32x4 acc[2][2];
 #pragma unroll
@@ -562,9 +598,25 @@ mrf_status gemm(int M, int N, int K, const float* A, int lda, const float* B, in
                 const float* mask, int mld, int S, hipStream_t s, const char* name, float* asum = nullptr) {
   const int ks = (K + S - 1) / S;
   dim3 grid(ceil_div(N, kG), ceil_div(M, kG), S);
-  if (BF16)
-    MRF_LAUNCH(name, s, k_gemm_bf16<AL, BL, EPI><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, mask, mld, ks,
-                                                                     asum));
+  if (BF16) {
+    // float4 operand loads where the leading dimension, the rows and the k slices are multiples of
+    // four (the column sums of A read the scalar tile)
+    const bool a4 = !asum && lda % 4 == 0 && ((uintptr_t)A & 15) == 0 &&
+                    (AL == LAY_K ? (K % 4 == 0 && ks % 4 == 0) : M % 4 == 0);
+    const bool b4 = ldb % 4 == 0 && ((uintptr_t)B & 15) == 0 && (BL == LAY_K ? (K % 4 == 0 && ks % 4 == 0) : N % 4 == 0);
+    if (a4 && b4)
+      MRF_LAUNCH(name, s, k_gemm_bf16<AL, BL, EPI, true, true><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias,
+                                                                                  mask, mld, ks, asum));
+    else if (b4)
+      MRF_LAUNCH(name, s, k_gemm_bf16<AL, BL, EPI, false, true><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc,
+                                                                                   bias, mask, mld, ks, asum));
+    else if (a4)
+      MRF_LAUNCH(name, s, k_gemm_bf16<AL, BL, EPI, true, false><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc,
+                                                                                   bias, mask, mld, ks, asum));
+    else
+      MRF_LAUNCH(name, s, k_gemm_bf16<AL, BL, EPI, false, false><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc,
+                                                                                    bias, mask, mld, ks, asum));
+  }
   else
     MRF_LAUNCH(name, s, k_gemm<false, AL, BL, EPI><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, mask, mld, ks));
   MRF_CHECK_LAUNCH();
