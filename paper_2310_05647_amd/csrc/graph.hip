@@ -652,22 +652,22 @@ __global__ __launch_bounds__(64 * kQuadWpb) void k_lap_quad_edges(const cf* __re
 // both cells from global memory.
 // Launch shapes (measured choices; each may be set with -D when tuning)
 #ifndef MRF_QC_TB
-#define MRF_QC_TB 8
+#define MRF_QC_TB 16
 #endif
 #ifndef MRF_QC_H
 #define MRF_QC_H 4
 #endif
 #ifndef MRF_QC_F
-#define MRF_QC_F 2
+#define MRF_QC_F 1
 #endif
 #ifndef MRF_QC_STAGES
-#define MRF_QC_STAGES 8
+#define MRF_QC_STAGES 16
 #endif
 #ifndef MRF_QC_WAVES
-#define MRF_QC_WAVES 8
+#define MRF_QC_WAVES 16
 #endif
 #ifndef MRF_QC_MINB
-#define MRF_QC_MINB 2
+#define MRF_QC_MINB 1
 #endif
 #ifndef MRF_QC_FARBLOCKS
 #define MRF_QC_FARBLOCKS 16384
@@ -675,7 +675,10 @@ __global__ __launch_bounds__(64 * kQuadWpb) void k_lap_quad_edges(const cf* __re
 constexpr int kQcTB = MRF_QC_TB, kQcH = MRF_QC_H, kQcF = MRF_QC_F;   // tile and halo (cells), frames per stage
 constexpr int kQcStages = MRF_QC_STAGES;    // frame stages per trace block
 constexpr int kQcWaves = MRF_QC_WAVES;      // waves per trace block
-constexpr int kQcEcap = 1024;               // tile entries held in LDS (more are read from global memory)
+#ifndef MRF_QC_ECAP
+#define MRF_QC_ECAP 3072
+#endif
+constexpr int kQcEcap = MRF_QC_ECAP;        // tile entries held in LDS (more are read from global memory)
 constexpr int kQcRcap = 128;                // row entries staged in LDS by the list builder (a multiple of 64)
 constexpr int kQcFarBlocks = MRF_QC_FARBLOCKS;
 
@@ -877,9 +880,9 @@ __global__ __launch_bounds__(1024) void k_qc_scan(const int* __restrict__ cnt, i
 // Trace over in-window pairs. Block: one tile of kQcTB^2 cells and kQcStages x kQcF frames; the
 // tile's entries (up to kQcEcap) and, stage by stage, the window (tile + halo) of kQcF frames are
 // held in LDS (rows padded by S pixels so that the S rows of a cell fall in different banks).
-// Lanes: S^2 pixels x (64 / S^2) cells; each lane keeps its pixel of its cell for the kQcF frames
-// and runs over the cell's entries. Blocks are dealt to XCDs by frame chunk (chunk c on XCD c mod 8),
-// so the tiles of a chunk share an L2.
+// Lanes: S rows x (64 / S) cells; each lane keeps its row of its cell and runs over the cell's
+// entries (a wave holds one row of 16 cells of the tile when S = 4). Blocks are dealt to XCDs by
+// frame chunk (chunk c on XCD c mod 8), so the tiles of a chunk share an L2.
 template <int S>
 __global__ __launch_bounds__(64 * kQcWaves, MRF_QC_MINB) void k_qc_trace(const cf* __restrict__ X,
                                                      const int* __restrict__ ptr,
