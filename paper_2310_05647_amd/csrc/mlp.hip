@@ -21,7 +21,8 @@
 // chunks of 32 from either operand layout (K-contiguous or K-strided), in FP32
 // (v_mfma_f32_16x16x4f32) or BF16 (operands rounded to nearest-even in registers,
 // v_mfma_f32_16x16x32_bf16), FP32 accumulation; epilogues for bias, ReLU and the ReLU mask of the
-// backward pass; split-K with a fixed-order reduction for the weight gradients (K = batch).
+// backward pass; split-K with a fixed-order reduction for the weight gradients (K = batch), which
+// in the BF16 step one launch takes for all layers together with the Adam step.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -56,18 +57,28 @@ constexpr int kMaxR = 16;
 
 // z [B][2r] features and t [B][2] standardised targets of a synthetic training batch; m [B].
 // The rank R is a template parameter so that the noise and coefficient arrays stay in registers.
+struct SynthArgs {
+  const cf* dhr;
+  int M;
+  const float* lut;
+  int nparam;
+  const double* stats;
+  unsigned k0, k1, step;
+  int B;
+  float snr_lo, snr_hi, L;
+  float* z;
+  float* t;
+  int* mo;
+};
 template <int R>
-__global__ __launch_bounds__(256) void k_synth(const cf* __restrict__ dhr, int M, const float* __restrict__ lut,
-                                               int nparam, const double* __restrict__ stats, unsigned k0, unsigned k1,
-                                               unsigned step, int B, float snr_lo, float snr_hi, float L,
-                                               float* __restrict__ z, float* __restrict__ t, int* __restrict__ mo) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= B) return;
+__device__ inline void synth_one(const SynthArgs& a, int i) {
+  if (i >= a.B) return;
+  const unsigned k0 = a.k0, k1 = a.k1, step = a.step;
   const u4 u = philox(u4{(unsigned)i, step, 0u, 0u}, k0, k1);
-  const int m = (int)(((unsigned long long)u.x * (unsigned)M) >> 32);
+  const int m = (int)(((unsigned long long)u.x * (unsigned)a.M) >> 32);
   const float phi = 6.283185307179586f * u01(u.y);
-  const float snr = snr_lo + (snr_hi - snr_lo) * u01(u.z);
-  const float sig = sqrtf(powf(10.f, -snr / 10.f) / L) * 0.70710678118654752f;
+  const float snr = a.snr_lo + (a.snr_hi - a.snr_lo) * u01(u.z);
+  const float sig = sqrtf(powf(10.f, -snr / 10.f) / a.L) * 0.70710678118654752f;
   constexpr int NC = (2 * R + 3) / 4;
   float gs[4 * NC];
 #pragma unroll
@@ -84,7 +95,7 @@ __global__ __launch_bounds__(256) void k_synth(const cf* __restrict__ dhr, int M
   float ar[R], ai[R], nrm = 0.f;
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const cf d = dhr[(size_t)m * R + k];
+    const cf d = a.dhr[(size_t)m * R + k];
     ar[k] = cp * d.x - sp * d.y + gs[k] * sig;
     ai[k] = sp * d.x + cp * d.y + gs[R + k] * sig;
     nrm += ar[k] * ar[k] + ai[k] * ai[k];
@@ -95,24 +106,25 @@ __global__ __launch_bounds__(256) void k_synth(const cf* __restrict__ dhr, int M
   const float inv = nrm > 0.f ? 1.f / nrm : 0.f;
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    z[(size_t)i * 2 * R + k] = (ar[k] * c0 - ai[k] * s0) * inv;
-    z[(size_t)i * 2 * R + R + k] = (ar[k] * s0 + ai[k] * c0) * inv;
+    a.z[(size_t)i * 2 * R + k] = (ar[k] * c0 - ai[k] * s0) * inv;
+    a.z[(size_t)i * 2 * R + R + k] = (ar[k] * s0 + ai[k] * c0) * inv;
   }
-  t[(size_t)i * 2 + 0] = (float)((log((double)lut[(size_t)m * nparam + 0]) - stats[0]) / stats[2]);
-  t[(size_t)i * 2 + 1] = (float)((log((double)lut[(size_t)m * nparam + 1]) - stats[1]) / stats[3]);
-  if (mo) mo[i] = m;
+  const float* lu = a.lut + (size_t)m * a.nparam;
+  a.t[(size_t)i * 2 + 0] = (float)((log((double)lu[0]) - a.stats[0]) / a.stats[2]);
+  a.t[(size_t)i * 2 + 1] = (float)((log((double)lu[1]) - a.stats[1]) / a.stats[3]);
+  if (a.mo) a.mo[i] = m;
+}
+template <int R>
+__global__ __launch_bounds__(256) void k_synth(SynthArgs a) {
+  synth_one<R>(a, blockIdx.x * 256 + threadIdx.x);
 }
 
 // launches k_synth<r> for the dictionary's rank (1 .. kMaxR)
 template <int R = 1>
-static void launch_synth(int r, dim3 grid, hipStream_t s, const cf* dhr, int M, const float* lut, int nparam,
-                         const double* stats, unsigned k0, unsigned k1, unsigned step, int B, float snr_lo,
-                         float snr_hi, float L, float* z, float* t, int* mo) {
+static void launch_synth(int r, dim3 grid, hipStream_t s, const SynthArgs& a) {
   if constexpr (R <= kMaxR) {
-    if (r == R)
-      k_synth<R><<<grid, 256, 0, s>>>(dhr, M, lut, nparam, stats, k0, k1, step, B, snr_lo, snr_hi, L, z, t, mo);
-    else
-      launch_synth<R + 1>(r, grid, s, dhr, M, lut, nparam, stats, k0, k1, step, B, snr_lo, snr_hi, L, z, t, mo);
+    if (r == R) k_synth<R><<<grid, 256, 0, s>>>(a);
+    else launch_synth<R + 1>(r, grid, s, a);
   }
 }
 
@@ -318,23 +330,40 @@ struct TileOp {
   }
 };
 
+// Adam with bias correction for one parameter: c1 = 1 / (1 - b1^t), c2 = 1 / (1 - b2^t)
+struct AdamArgs {
+  float lr, b1, b2, eps, c1, c2;
+};
+__device__ inline void adam_update(float& p, float& m, float& v, float g, const AdamArgs& a) {
+  const float mi = a.b1 * m + (1.f - a.b1) * g;
+  const float vi = a.b2 * v + (1.f - a.b2) * g * g;
+  m = mi;
+  v = vi;
+  p -= a.lr * (mi * a.c1) / (sqrtf(vi * a.c2) + a.eps);
+}
+
+struct GemmLds {
+  unsigned short As[2][kGB][kGBP];
+  unsigned short Bs[2][kGB][kGBP];
+  float sred[4][kGB];
+};
+// output tile (bx, by) of split-K slice bz
 template <int ALAY, int BLAY, int EPI, bool AV4, bool BV4>
-__global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const float* __restrict__ A, int lda,
-                                                   const float* __restrict__ B, int ldb, float* __restrict__ C,
-                                                   int ldc, const float* __restrict__ bias,
-                                                   const float* __restrict__ mask, int mld, int ks,
-                                                   float* __restrict__ asum) {
-  __shared__ __align__(16) unsigned short As[2][kGB][kGBP];
-  __shared__ __align__(16) unsigned short Bs[2][kGB][kGBP];
-  __shared__ float sred[4][kGB];
+__device__ inline void gemm_bf16_tile(int M, int N, int K, const float* __restrict__ A, int lda,
+                                      const float* __restrict__ B, int ldb, float* __restrict__ C, int ldc,
+                                      const float* __restrict__ bias, const float* __restrict__ mask, int mld, int ks,
+                                      float* __restrict__ asum, int bx, int by, int bz, GemmLds& sm) {
+  auto& As = sm.As;
+  auto& Bs = sm.Bs;
+  auto& sred = sm.sred;
   // the column sums read A's scalar tile (r = lane for every element): only without AV4
-  const bool do_sum = ALAY == LAY_MN && !AV4 && asum && blockIdx.x == 0;
+  const bool do_sum = ALAY == LAY_MN && !AV4 && asum && bx == 0;
   float rsum = 0.f;   // this thread's row (m0 + lane) of A over its k values
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int wm = w >> 1, wn = w & 1, q = lane >> 4, n16 = lane & 15;
-  const int n0 = blockIdx.x * kGB, m0 = blockIdx.y * kGB;
-  const int kb = blockIdx.z * ks, ke = min(K, kb + ks);
-  C += (size_t)blockIdx.z * M * ldc;
+  const int n0 = bx * kGB, m0 = by * kGB;
+  const int kb = bz * ks, ke = min(K, kb + ks);
+  C += (size_t)bz * M * ldc;
   TileOp<ALAY, AV4> ta;
   TileOp<BLAY, BV4> tb;
   auto load = [&](int k0) {
@@ -382,7 +411,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const fl
     sred[w][lane] = rsum;
     __syncthreads();
     if (w == 0 && m0 + lane < M)
-      asum[(size_t)blockIdx.z * M + m0 + lane] = (sred[0][lane] + sred[1][lane]) + (sred[2][lane] + sred[3][lane]);
+      asum[(size_t)bz * M + m0 + lane] = (sred[0][lane] + sred[1][lane]) + (sred[2][lane] + sred[3][lane]);
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -401,21 +430,103 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const fl
       }
 }
 
-// out[i] = sum_s part[s n + i] and out2[i] = sum_s part2[s n2 + i] (fixed order): the weight and
-// bias gradients from the split-K slices
-__global__ __launch_bounds__(256) void k_reduce_slices2(const float* __restrict__ part, int S, long n,
-                                                        float* __restrict__ out, const float* __restrict__ part2,
-                                                        long n2, float* __restrict__ out2) {
-  const long i = (long)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) {
-    float s = 0.f;
-    for (int k = 0; k < S; ++k) s += part[(size_t)k * n + i];
-    out[i] = s;
-  } else if (i < n + n2) {
-    const long j = i - n;
-    float s = 0.f;
-    for (int k = 0; k < S; ++k) s += part2[(size_t)k * n2 + j];
-    out2[j] = s;
+template <int ALAY, int BLAY, int EPI, bool AV4, bool BV4>
+__global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const float* __restrict__ A, int lda,
+                                                   const float* __restrict__ B, int ldb, float* __restrict__ C,
+                                                   int ldc, const float* __restrict__ bias,
+                                                   const float* __restrict__ mask, int mld, int ks,
+                                                   float* __restrict__ asum) {
+  __shared__ __align__(16) GemmLds sm;
+  gemm_bf16_tile<ALAY, BLAY, EPI, AV4, BV4>(M, N, K, A, lda, B, ldb, C, ldc, bias, mask, mld, ks, asum, blockIdx.x,
+                                            blockIdx.y, blockIdx.z, sm);
+}
+
+// Operands of one product of a grouped launch, and its tile grid gx x gy (x gz slices)
+struct GemmArgs {
+  int M, N, K;
+  const float* A;
+  int lda;
+  const float* B;
+  int ldb;
+  float* C;
+  int ldc;
+  const float* mask;
+  int mld, ks;
+  float* asum;
+  int gx, gy;
+};
+// A layer's two backward products in one launch: they read the same output gradient and not each
+// other's results. Blocks [0, d.gx d.gy) take the backward product d (masked by the layer's ReLU),
+// the rest the split-K weight-gradient product w with its bias-gradient column sums.
+template <bool DA4>
+__global__ __launch_bounds__(256) void k_gemm_bf16_bwd_pair(GemmArgs d, GemmArgs w) {
+  __shared__ __align__(16) GemmLds sm;
+  const int nd = d.gx * d.gy;
+  int b = blockIdx.x;
+  if (b < nd) {
+    gemm_bf16_tile<LAY_K, LAY_MN, EPI_MASK, DA4, true>(d.M, d.N, d.K, d.A, d.lda, d.B, d.ldb, d.C, d.ldc, nullptr,
+                                                       d.mask, d.mld, d.ks, nullptr, b % d.gx, b / d.gx, 0, sm);
+  } else {
+    b -= nd;
+    const int nt = w.gx * w.gy, t = b % nt;
+    gemm_bf16_tile<LAY_MN, LAY_MN, EPI_STORE, false, true>(w.M, w.N, w.K, w.A, w.lda, w.B, w.ldb, w.C, w.ldc, nullptr,
+                                                           nullptr, 0, w.ks, w.asum, t % w.gx, t / w.gx, b / nt, sm);
+  }
+}
+
+// The end of the BF16 backward pass in one launch: every weight and bias gradient is the sum of
+// its split-K slices (slice order), written to g, and with adam set the Adam step follows.
+// Segment k (blocks k gx .. k gx + gx - 1) holds cnt[k] parameters from offset off[k], slices
+// part[k] [S][cnt[k]].
+constexpr int kMaxSeg = 2 * 9;
+struct GradSegs {
+  int n;
+  const float* part[kMaxSeg];
+  long off[kMaxSeg];
+  int cnt[kMaxSeg];
+  int gx;                   // blocks per segment
+};
+__device__ inline void grad_finish_one(const GradSegs& sg, int S, float* __restrict__ g, float* __restrict__ p,
+                                       float* __restrict__ m, float* __restrict__ v, const AdamArgs& ad, int adam,
+                                       int k, int i) {
+  if (k >= sg.n || i >= sg.cnt[k]) return;
+  const float* pt = sg.part[k];
+  const size_t n = (size_t)sg.cnt[k];
+  float sum = 0.f;
+  for (int z = 0; z < S; ++z) sum += pt[z * n + i];
+  const long o = sg.off[k] + i;
+  g[o] = sum;
+  if (adam) {
+    float pi = p[o], mi = m[o], vi = v[o];
+    adam_update(pi, mi, vi, sum, ad);
+    m[o] = mi;
+    v[o] = vi;
+    p[o] = pi;
+  }
+}
+__global__ __launch_bounds__(256) void k_grad_finish(GradSegs sg, int S, float* __restrict__ g, float* __restrict__ p,
+                                                     float* __restrict__ m, float* __restrict__ v, AdamArgs ad,
+                                                     int adam) {
+  grad_finish_one(sg, S, g, p, m, v, ad, adam, blockIdx.x / sg.gx, (blockIdx.x % sg.gx) * 256 + threadIdx.x);
+}
+// The same, and in the same launch the next training batch (blocks from sg.n sg.gx on): the batch
+// buffers are free once the last weight-gradient product has read them.
+template <int R>
+__global__ __launch_bounds__(256) void k_grad_finish_synth(GradSegs sg, int S, float* __restrict__ g,
+                                                           float* __restrict__ p, float* __restrict__ m,
+                                                           float* __restrict__ v, AdamArgs ad, int adam, SynthArgs sa) {
+  const int nf = sg.n * sg.gx;
+  if ((int)blockIdx.x < nf)
+    grad_finish_one(sg, S, g, p, m, v, ad, adam, blockIdx.x / sg.gx, (blockIdx.x % sg.gx) * 256 + threadIdx.x);
+  else
+    synth_one<R>(sa, (blockIdx.x - nf) * 256 + threadIdx.x);
+}
+template <int R = 1>
+static void launch_finish_synth(int r, int grid, hipStream_t s, const GradSegs& sg, int S, float* g, float* p, float* m,
+                                float* v, const AdamArgs& ad, int adam, const SynthArgs& sa) {
+  if constexpr (R <= kMaxR) {
+    if (r == R) k_grad_finish_synth<R><<<grid, 256, 0, s>>>(sg, S, g, p, m, v, ad, adam, sa);
+    else launch_finish_synth<R + 1>(r, grid, s, sg, S, g, p, m, v, ad, adam, sa);
   }
 }
 
@@ -454,9 +565,12 @@ __global__ __launch_bounds__(256) void k_colsum_final(const float* __restrict__ 
   db[c] = s;
 }
 
-// g = 2 (y - t) / (B nout); per-block partial sums of (y - t)^2 into lpart
+// g = 2 (y - t) / (B nout); per-block partial sums of (y - t)^2 into lpart; the last block to
+// finish (counter *cnt, zero before the launch and reset by that block) sums the partials in block
+// order into loss (and loss2 when set): the mean over batch and outputs.
 __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const float* __restrict__ t, int n, float scale,
-                                              float* __restrict__ g, float* __restrict__ lpart) {
+                                              float* __restrict__ g, float* __restrict__ lpart, unsigned* __restrict__ cnt,
+                                              float* __restrict__ loss, float* __restrict__ loss2) {
   __shared__ float red[256];
   const int i = blockIdx.x * 256 + threadIdx.x;
   float d = 0.f;
@@ -471,19 +585,31 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const
     __syncthreads();
   }
   if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
-}
-__global__ __launch_bounds__(256) void k_loss_final(const float* __restrict__ lpart, int nb, float scale,
-                                                    float* __restrict__ loss) {
-  __shared__ float red[256];
+  __shared__ int last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(cnt, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
   float s = 0.f;
-  for (int i = threadIdx.x; i < nb; i += 256) s += lpart[i];
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += 256) s += lpart[i];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) loss[0] = red[0] * scale;
+  if (threadIdx.x == 0) {
+    loss[0] = red[0] * scale;
+    if (loss2) loss2[0] = red[0] * scale;
+    cnt[0] = 0u;
+  }
+}
+
+__global__ void k_zero_u32(unsigned* __restrict__ p, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0u;
 }
 
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
@@ -491,12 +617,11 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
                                               float c1, float c2) {
   const long i = (long)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  const float gi = g[i];
-  const float mi = b1 * m[i] + (1.f - b1) * gi;
-  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  float pi = p[i], mi = m[i], vi = v[i];
+  adam_update(pi, mi, vi, g[i], AdamArgs{lr, b1, b2, eps, c1, c2});
   m[i] = mi;
   v[i] = vi;
-  p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+  p[i] = pi;
 }
 
 // He-normal initialisation from Philox (counter (index, layer, 0x48e, 0)), zero biases
@@ -604,18 +729,14 @@ mrf_status gemm(int M, int N, int K, const float* A, int lda, const float* B, in
     const bool a4 = !asum && lda % 4 == 0 && ((uintptr_t)A & 15) == 0 &&
                     (AL == LAY_K ? (K % 4 == 0 && ks % 4 == 0) : M % 4 == 0);
     const bool b4 = ldb % 4 == 0 && ((uintptr_t)B & 15) == 0 && (BL == LAY_K ? (K % 4 == 0 && ks % 4 == 0) : N % 4 == 0);
-    if (a4 && b4)
-      MRF_LAUNCH(name, s, k_gemm_bf16<AL, BL, EPI, true, true><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias,
-                                                                                  mask, mld, ks, asum));
-    else if (b4)
-      MRF_LAUNCH(name, s, k_gemm_bf16<AL, BL, EPI, false, true><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc,
-                                                                                   bias, mask, mld, ks, asum));
-    else if (a4)
-      MRF_LAUNCH(name, s, k_gemm_bf16<AL, BL, EPI, true, false><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc,
-                                                                                   bias, mask, mld, ks, asum));
-    else
-      MRF_LAUNCH(name, s, k_gemm_bf16<AL, BL, EPI, false, false><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc,
-                                                                                    bias, mask, mld, ks, asum));
+#define MRF_GB(A4, B4)                                                                                         \
+  MRF_LAUNCH(name, s, k_gemm_bf16<AL, BL, EPI, A4, B4><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, \
+                                                                           mask, mld, ks, asum))
+    if (a4 && b4) MRF_GB(true, true);
+    else if (b4) MRF_GB(false, true);
+    else if (a4) MRF_GB(true, false);
+    else MRF_GB(false, false);
+#undef MRF_GB
   }
   else
     MRF_LAUNCH(name, s, k_gemm<false, AL, BL, EPI><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, mask, mld, ks));
@@ -648,9 +769,11 @@ struct TrainWs {
   float* t;                 // [B][nout]
   std::vector<float*> acts; // nl + 1 activations (acts[0] = z)
   float *g0, *g1;           // [B][max width] gradient ping-pong
-  float* part;              // split-K partials
+  float* part;              // split-K partials: BF16, layer l's [S][out in] and [S][out] at poff[l]
+  std::vector<size_t> poff;
   float* lpart;             // loss partials
   float* loss;              // [1]
+  unsigned* cnt;            // [1] the loss kernel's block counter (zeroed per call)
   size_t bytes;
 };
 constexpr int kSplitK = 16;
@@ -672,38 +795,80 @@ TrainWs train_ws(const mrf_mlp_s* P, int B, void* base) {
   for (int l = 0; l < P->nl; ++l) w.acts.push_back(take((size_t)B * P->lout[l] * 4));
   w.g0 = take((size_t)B * wmax * 4);
   w.g1 = take((size_t)B * wmax * 4);
-  w.part = take((size_t)kSplitK * (wmax * wmax + wmax) * 4);
+  size_t np = 0;
+  for (int l = 0; l < P->nl; ++l) {
+    w.poff.push_back(np);
+    np += (size_t)kSplitK * ((size_t)P->lout[l] * P->lin[l] + P->lout[l]);
+  }
+  w.part = take(std::max(np, (size_t)kSplitK * (wmax * wmax + wmax)) * 4);
   w.lpart = take((size_t)ceil_div((long)B * P->nout, 256) * 4);
   w.loss = take(4);
+  w.cnt = (unsigned*)take(4);
   w.bytes = off;
   return w;
 }
 
-// loss and gradients of a batch (z, t already in the workspace); grads into P->g
-mrf_status mlp_backward(mrf_mlp_s* P, bool bf16, int B, TrainWs& w, hipStream_t s) {
+// the loss kernel's counter starts at zero in every call (the workspace is the caller's)
+mrf_status zero_counters(const TrainWs& w, hipStream_t s) {
+  MRF_LAUNCH("mlp_loss", s, k_zero_u32<<<1, 256, 0, s>>>(w.cnt, 1));
+  MRF_CHECK_LAUNCH();
+  return MRF_OK;
+}
+
+// loss and gradients of a batch (z, t already in the workspace, counter zero); grads into P->g
+// and the loss into w.loss (and loss_out when set). BF16: the weight-gradient products leave
+// their split-K slices per layer and one launch at the end sums them all, followed, with ad,
+// by the Adam step (every backward product has read W by then); with next (rank r) that launch
+// also writes the next training batch into the batch buffers.
+mrf_status mlp_backward(mrf_mlp_s* P, bool bf16, int B, TrainWs& w, hipStream_t s, const AdamArgs* ad = nullptr,
+                        float* loss_out = nullptr, const SynthArgs* next = nullptr, int r = 0) {
   mrf_status e;
   if ((e = mlp_forward(P, bf16, B, w.acts, s))) return e;
   const int n = B * P->nout;
-  const int nb = ceil_div(n, 256);
-  MRF_LAUNCH("mlp_loss", s, k_loss<<<nb, 256, 0, s>>>(w.acts[P->nl], w.t, n, 1.f / (float)n, w.g0, w.lpart));
-  MRF_LAUNCH("mlp_loss", s, k_loss_final<<<1, 256, 0, s>>>(w.lpart, nb, 1.f / (float)n, w.loss));
+  MRF_LAUNCH("mlp_loss", s, k_loss<<<ceil_div(n, 256), 256, 0, s>>>(w.acts[P->nl], w.t, n, 1.f / (float)n, w.g0,
+                                                                    w.lpart, w.cnt, w.loss, loss_out));
+  GradSegs sg{};
+  int segmax = 0;
   float* gout = w.g0;   // dL/d(output of layer l), [B][lout[l]]
   float* gin = w.g1;
   for (int l = P->nl - 1; l >= 0; --l) {
     const int in = P->lin[l], out = P->lout[l];
     float* dW = P->g + P->offW[l];
     float* db = P->g + P->offb[l];
+    const float* W = P->p + P->offW[l];
     // dW[out][in] = sum_b gout[b][out] h[b][in]: split over the batch, fixed-order reduction
     if (bf16) {
-      // the BF16 product also sums gout's columns (the bias gradient, in FP32) per batch slice,
-      // and one reduction finishes both
-      float* dbpart = w.part + (size_t)kSplitK * out * in;
-      e = gemm<true, LAY_MN, LAY_MN, EPI_STORE>(out, in, B, gout, out, w.acts[l], in, w.part, in, nullptr, nullptr, 0,
-                                                kSplitK, s, "mlp_dw", dbpart);
-      if (e) return e;
-      MRF_LAUNCH("mlp_dw_reduce", s, k_reduce_slices2<<<ceil_div((long)out * in + out, 256), 256, 0, s>>>(
-                                         w.part, kSplitK, (long)out * in, dW, dbpart, out, db));
+      // the BF16 product also sums gout's columns (the bias gradient, in FP32) per batch slice
+      float* wpart = w.part + w.poff[l];
+      float* dbpart = wpart + (size_t)kSplitK * out * in;
+      // gin[b][in] = (sum_o gout[b][o] W[o][in]) * (h[b][in] > 0) in the same launch where the
+      // operand layouts allow 16-byte loads of W and of h (as gemm() would choose them)
+      const bool pair = l > 0 && in % 4 == 0 && ((uintptr_t)W & 15) == 0 && ((uintptr_t)w.acts[l] & 15) == 0;
+      if (pair) {
+        const bool da4 = out % 4 == 0 && ((uintptr_t)gout & 15) == 0;
+        const int ksw = ceil_div(B, kSplitK);
+        const GemmArgs d{B, in, out, gout, out, W, in, gin, in, w.acts[l], in, out, nullptr, ceil_div(in, kGB),
+                         ceil_div(B, kGB)};
+        const GemmArgs g{out, in, B, gout, out, w.acts[l], in, wpart, in, nullptr, 0, ksw, dbpart, ceil_div(in, kGB),
+                         ceil_div(out, kGB)};
+        const int nblk = d.gx * d.gy + g.gx * g.gy * kSplitK;
+        if (da4) MRF_LAUNCH("mlp_bwd", s, k_gemm_bf16_bwd_pair<true><<<nblk, 256, 0, s>>>(d, g));
+        else MRF_LAUNCH("mlp_bwd", s, k_gemm_bf16_bwd_pair<false><<<nblk, 256, 0, s>>>(d, g));
+      } else {
+        if (l > 0 && (e = gemm<true, LAY_K, LAY_MN, EPI_MASK>(B, in, out, gout, out, W, in, gin, in, nullptr, w.acts[l],
+                                                               in, 1, s, "mlp_bwd")))
+          return e;
+        e = gemm<true, LAY_MN, LAY_MN, EPI_STORE>(out, in, B, gout, out, w.acts[l], in, wpart, in, nullptr, nullptr, 0,
+                                                  kSplitK, s, "mlp_dw", dbpart);
+        if (e) return e;
+      }
+      sg.part[sg.n] = wpart; sg.off[sg.n] = (long)P->offW[l]; sg.cnt[sg.n] = out * in; ++sg.n;
+      sg.part[sg.n] = dbpart; sg.off[sg.n] = (long)P->offb[l]; sg.cnt[sg.n] = out; ++sg.n;
+      segmax = std::max(segmax, out * in);
     } else {
+      if (l > 0 && (e = gemm<false, LAY_K, LAY_MN, EPI_MASK>(B, in, out, gout, out, W, in, gin, in, nullptr, w.acts[l], in,
+                                                              1, s, "mlp_bwd")))
+        return e;
       e = gemm<false, LAY_MN, LAY_MN, EPI_STORE>(out, in, B, gout, out, w.acts[l], in, w.part, in, nullptr, nullptr, 0, kSplitK, s, "mlp_dw");
       if (e) return e;
       MRF_LAUNCH("mlp_dw_reduce", s, k_reduce_slices<<<ceil_div((long)out * in, 256), 256, 0, s>>>(w.part, kSplitK, (long)out * in, dW));
@@ -712,24 +877,35 @@ mrf_status mlp_backward(mrf_mlp_s* P, bool bf16, int B, TrainWs& w, hipStream_t 
       MRF_LAUNCH("mlp_db", s, k_colsum_part<<<dim3(ceil_div(out, 64), nch), 256, 0, s>>>(gout, B, out, w.part));
       MRF_LAUNCH("mlp_db", s, k_colsum_final<<<ceil_div(out, 256), 256, 0, s>>>(w.part, nch, out, db));
     }
-    if (l > 0) {
-      // gin[b][in] = (sum_o gout[b][o] W[o][in]) * (h[b][in] > 0)
-      const float* W = P->p + P->offW[l];
-      if (bf16) e = gemm<true, LAY_K, LAY_MN, EPI_MASK>(B, in, out, gout, out, W, in, gin, in, nullptr, w.acts[l], in, 1, s, "mlp_bwd");
-      else e = gemm<false, LAY_K, LAY_MN, EPI_MASK>(B, in, out, gout, out, W, in, gin, in, nullptr, w.acts[l], in, 1, s, "mlp_bwd");
-      if (e) return e;
-      std::swap(gout, gin);
-    }
+    if (l > 0) std::swap(gout, gin);
+  }
+  if (bf16) {
+    sg.gx = ceil_div(segmax, 256);
+    const AdamArgs a = ad ? *ad : AdamArgs{};
+    if (next)
+      MRF_LAUNCH("mlp_grad_finish", s,
+                 launch_finish_synth(r, sg.n * sg.gx + ceil_div(next->B, 256), s, sg, kSplitK, P->g, P->p, P->m, P->v, a,
+                                     ad != nullptr, *next));
+    else
+      MRF_LAUNCH("mlp_grad_finish", s, k_grad_finish<<<sg.n * sg.gx, 256, 0, s>>>(sg, kSplitK, P->g, P->p, P->m, P->v, a,
+                                                                                 ad != nullptr));
   }
   MRF_CHECK_LAUNCH();
   return MRF_OK;
 }
 
-mrf_status adam(mrf_mlp_s* P, float lr, float b1, float b2, float eps, hipStream_t s) {
+// the next Adam step's arguments (advances the step count)
+AdamArgs adam_args(mrf_mlp_s* P, float lr, float b1, float b2, float eps) {
   P->t += 1;
   const float c1 = (float)(1.0 / (1.0 - std::pow((double)b1, P->t)));
   const float c2 = (float)(1.0 / (1.0 - std::pow((double)b2, P->t)));
-  MRF_LAUNCH("mlp_adam", s, k_adam<<<ceil_div((long)P->np, 256), 256, 0, s>>>(P->p, P->g, P->m, P->v, (long)P->np, lr, b1, b2, eps, c1, c2));
+  return AdamArgs{lr, b1, b2, eps, c1, c2};
+}
+
+mrf_status adam(mrf_mlp_s* P, float lr, float b1, float b2, float eps, hipStream_t s) {
+  const AdamArgs a = adam_args(P, lr, b1, b2, eps);
+  MRF_LAUNCH("mlp_adam", s, k_adam<<<ceil_div((long)P->np, 256), 256, 0, s>>>(P->p, P->g, P->m, P->v, (long)P->np, a.lr,
+                                                                             a.b1, a.b2, a.eps, a.c1, a.c2));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
 }
@@ -887,9 +1063,9 @@ extern "C" mrf_status mrf_mlp_synth(mrf_mlp_t P, mrf_dict_t D, uint64_t seed, in
   MRF_REQUIRE(D->r >= 1 && 2 * D->r == P->nin, MRF_SHAPE, "mlp_synth: the dictionary needs a basis with 2 r = n_in");
   mrf_status e = ensure_stats(P, D, s);
   if (e) return e;
-  MRF_LAUNCH("mlp_synth", s,
-             launch_synth(D->r, dim3(ceil_div(batch, 256)), s, D->dhr, D->M, D->lut, D->nparam, P->stats, (unsigned)seed,
-                          (unsigned)(seed >> 32), (unsigned)step, batch, snr_lo, snr_hi, (float)D->L, z, t, m));
+  const SynthArgs sa{D->dhr, D->M, D->lut, D->nparam, P->stats, (unsigned)seed, (unsigned)(seed >> 32), (unsigned)step,
+                     batch, snr_lo, snr_hi, (float)D->L, z, t, m};
+  MRF_LAUNCH("mlp_synth", s, launch_synth(D->r, dim3(ceil_div(batch, 256)), s, sa));
   MRF_CHECK_LAUNCH();
   return MRF_OK;
 }
@@ -913,10 +1089,9 @@ extern "C" mrf_status mrf_mlp_grads(mrf_mlp_t P, const float* z, const float* t,
   MRF_REQUIRE(ws && ws_bytes >= w.bytes, MRF_WORKSPACE, "mlp_grads: workspace too small");
   MRF_CHECK_HIP(hipMemcpyAsync(w.z, z, (size_t)batch * P->nin * 4, hipMemcpyDeviceToDevice, s));
   MRF_CHECK_HIP(hipMemcpyAsync(w.t, t, (size_t)batch * P->nout * 4, hipMemcpyDeviceToDevice, s));
-  mrf_status e = mlp_backward(P, bf16 != 0, batch, w, s);
+  mrf_status e = zero_counters(w, s);
   if (e) return e;
-  if (loss) MRF_CHECK_HIP(hipMemcpyAsync(loss, w.loss, 4, hipMemcpyDeviceToDevice, s));
-  return MRF_OK;
+  return mlp_backward(P, bf16 != 0, batch, w, s, nullptr, loss);
 }
 
 extern "C" mrf_status mrf_mlp_adam_step(mrf_mlp_t P, float lr, float beta1, float beta2, float eps, hipStream_t s) {
@@ -937,19 +1112,29 @@ extern "C" mrf_status mrf_mlp_train(mrf_mlp_t P, mrf_dict_t D, const mrf_mlp_tra
   MRF_REQUIRE(ws && ws_bytes >= w.bytes, MRF_WORKSPACE, "mlp_train: workspace too small");
   mrf_status e = ensure_stats(P, D, s);
   if (e) return e;
+  if ((e = zero_counters(w, s))) return e;
   const int B = cfg->batch;
   const double pi = 3.14159265358979323846;
+  auto batch_args = [&](int step) {
+    return SynthArgs{D->dhr, D->M, D->lut, D->nparam, P->stats, (unsigned)cfg->seed, (unsigned)(cfg->seed >> 32),
+                     (unsigned)step, B, cfg->snr_lo, cfg->snr_hi, (float)D->L, w.z, w.t, nullptr};
+  };
+  // BF16: each step's last launch also draws the next step's batch
   for (int it = 0; it < cfg->steps; ++it) {
     const int step = cfg->first_step + it;
-    MRF_LAUNCH("mlp_synth", s,
-               launch_synth(D->r, dim3(ceil_div(B, 256)), s, D->dhr, D->M, D->lut, D->nparam, P->stats,
-                            (unsigned)cfg->seed, (unsigned)(cfg->seed >> 32), (unsigned)step, B, cfg->snr_lo,
-                            cfg->snr_hi, (float)D->L, w.z, w.t, nullptr));
-    if ((e = mlp_backward(P, cfg->bf16 != 0, B, w, s))) return e;
-    if (losses) MRF_CHECK_HIP(hipMemcpyAsync(losses + it, w.loss, 4, hipMemcpyDeviceToDevice, s));
+    if (it == 0 || !cfg->bf16) MRF_LAUNCH("mlp_synth", s, launch_synth(D->r, dim3(ceil_div(B, 256)), s, batch_args(step)));
     const int T = cfg->total_steps > 0 ? cfg->total_steps : cfg->first_step + cfg->steps;
     const float lr = cfg->cosine ? (float)(cfg->lr * 0.5 * (1.0 + std::cos(pi * step / (double)T))) : cfg->lr;
-    if ((e = adam(P, lr, cfg->beta1, cfg->beta2, cfg->eps, s))) return e;
+    float* lo = losses ? losses + it : nullptr;
+    if (cfg->bf16) {
+      // the Adam step runs in the gradients' last launch
+      const AdamArgs a = adam_args(P, lr, cfg->beta1, cfg->beta2, cfg->eps);
+      const SynthArgs nx = batch_args(step + 1);
+      if ((e = mlp_backward(P, true, B, w, s, &a, lo, it + 1 < cfg->steps ? &nx : nullptr, D->r))) return e;
+    } else {
+      if ((e = mlp_backward(P, false, B, w, s, nullptr, lo))) return e;
+      if ((e = adam(P, lr, cfg->beta1, cfg->beta2, cfg->eps, s))) return e;
+    }
   }
   return MRF_OK;
 }

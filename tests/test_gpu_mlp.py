@@ -117,6 +117,33 @@ def test_forward_and_adam_step_match_oracle(setup):
     assert worst <= 1e-6
 
 
+@pytest.mark.parametrize("bf16", [True, False])
+def test_training_run_equals_its_steps_taken_one_by_one(setup, bf16):
+    """The training entry point groups its launches (the BF16 step sums the weight gradients of all
+    layers, takes the Adam step and draws the next batch in one launch); its parameters and losses
+    equal those of the same steps taken through the separate calls: batch synthesis, gradients,
+    Adam step with the cosine rate. A ragged batch (1000) leaves partial tiles everywhere."""
+    from paper_2310_05647_amd import MLP
+    s = setup
+    seed, first, steps, total, lr, B = 0x5EED, 5, 4, 20, 2e-3, 1000
+    lr32 = float(np.float32(lr))                 # the rate as the library holds it
+    a = MLP(n_in=2 * s["V"].shape[1], hidden=256, layers=3, seed=11)
+    b = MLP(n_in=2 * s["V"].shape[1], hidden=256, layers=3, seed=11)
+    losses = a.train(s["d"], steps, batch=B, lr=lr, first_step=first, total_steps=total, seed=seed,
+                     bf16=bf16).cpu().numpy()
+    ref = []
+    for step in range(first, first + steps):
+        z, t, _ = b.synth(s["d"], seed=seed, step=step, batch=B)
+        loss, _ = b.grads(z, t, bf16=bf16)
+        ref.append(loss)
+        b.adam_step(float(np.float32(lr32 * 0.5 * (1.0 + np.cos(np.pi * step / total)))))
+    pa, pb = a.get_params().cpu().numpy(), b.get_params().cpu().numpy()
+    worst = float(np.abs(pa - pb).max())
+    say(f"train vs steps ({'bf16' if bf16 else 'fp32'}): max |dp| {worst:.2e}, losses {losses} vs {np.array(ref)}")
+    assert worst <= 1e-7 * max(1.0, float(np.abs(pb).max()))
+    np.testing.assert_allclose(losses, np.array(ref, dtype=np.float32), rtol=1e-6)
+
+
 def test_learned_match_and_gate_match_oracle(setup):
     s = setup
     params = omlp.init_params(SIZES, 6)
