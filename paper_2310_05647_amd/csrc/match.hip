@@ -7,7 +7,8 @@
 // Every MFMA's K range is split between the two parts: its lane groups q = 0, 1 (of
 // q = lane / 16) carry real parts and q = 2, 3 imaginary parts of the same frames. With
 // A = atoms (rows m) and B = fingerprints (columns v), Re z is the product of A and B as loaded;
-// Im z is the product of A with its imaginary half negated and B with its two halves swapped.
+// Im z is the product of A as loaded and B with its two halves swapped, the second of them
+// (-xr against di) negated.
 //
 // Block: 4 waves in a 2 x 2 grid over a 128-atom x 128-fingerprint tile, each wave 64 x 64
 // (4 x 4 MFMA tiles, separate real and imaginary accumulators). K advances in chunks whose rows
@@ -16,7 +17,7 @@
 // next chunk is loaded into registers. A block walks the atom tiles t = g (mod 8) of its group
 // g = blockIdx mod 8, so the blocks of one XCD stream the same atom tiles through its L2, and
 // keeps per lane a running top-4 (score desc, atom index asc) for each of its 4 fingerprint
-// columns. The 8 candidate lists of a fingerprint column (32 candidates) are merged into the
+// columns (in LDS between atom tiles). The 8 candidate lists of a fingerprint column (32 candidates) are merged into the
 // block's top-kGroupK, written as the group's partial result; k_rerank takes the best `depth` of
 // the 8 groups' candidates and recomputes them exactly in FP32 from the FP32 atoms.
 #include <cfloat>
@@ -84,8 +85,9 @@ __device__ inline void top4_insert(float (&sc)[4], int (&id)[4], float s, int m)
 // A: atom rows, B: fingerprint rows, both in the precision's row format (see above); for P_F32
 // they are interleaved complex [rows][L]; otherwise [rows][2 Lp] split. sa: FP8 atom scales.
 // Partial results: pscore / pidx [Nv][kGroups][4].
+// BF16 fits two waves per SIMD (accumulators in the VGPRs, no spills); the other forms need one
 template <int P>
-__global__ __launch_bounds__(256) void k_match_top4(const void* __restrict__ A, const float* __restrict__ sa, int M,
+__global__ __launch_bounds__(256, P == P_BF16 ? 2 : 1) void k_match_top4(const void* __restrict__ A, const float* __restrict__ sa, int M,
                                                     const void* __restrict__ B, int Nv, int L, int Lp,
                                                     float* __restrict__ pscore, int* __restrict__ pidx,
                                                     const void* __restrict__ A2 = nullptr,
@@ -101,15 +103,15 @@ __global__ __launch_bounds__(256) void k_match_top4(const void* __restrict__ A, 
   const int ntile = (M + kTileM - 1) / kTileM;
   const int nchunk = P == P_F32 ? (L + T::KC - 1) / T::KC : Lp / T::KC;
 
-  float ls[4][4];
-  int li[4][4];
+  // the running top-4 lists of the thread's 4 fingerprint columns live in LDS between atom tiles
+  // (entry (tf, k) of thread t at [4 tf + k][t]), which leaves the registers to the main loop
+  __shared__ float lsS[16][256];
+  __shared__ int liS[16][256];
 #pragma unroll
-  for (int tf = 0; tf < 4; ++tf)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      ls[tf][k] = -1.f;
-      li[tf][k] = -1;
-    }
+  for (int k = 0; k < 16; ++k) {
+    lsS[k][tid] = -1.f;
+    liS[k][tid] = -1;
+  }
 
   // register staging of one chunk: 2048 units of 16 B (P_F32: 4096 units of 8 B; P_BF16X3: 4096 of 16 B)
   constexpr int NU = P == P_F32 ? 16 : (P == P_BF16X3 ? 16 : 8);
@@ -179,40 +181,36 @@ __global__ __launch_bounds__(256) void k_match_top4(const void* __restrict__ A, 
       for (int s = 0; s < T::STEPS; ++s) {
         if constexpr (P == P_F32) {
           const int fb = (2 * s + o) * 8;
-          float a[4], an[4];
+          float a[4];
 #pragma unroll
-          for (int ta = 0; ta < 4; ++ta) {
-            a[ta] = *(const float*)(As + ta * 16 * kRowB + fb + 4 * h);
-            an[ta] = h ? -a[ta] : a[ta];
-          }
+          for (int ta = 0; ta < 4; ++ta) a[ta] = *(const float*)(As + ta * 16 * kRowB + fb + 4 * h);
 #pragma unroll
           for (int tf = 0; tf < 4; ++tf) {
             const float br = *(const float*)(Bs + tf * 16 * kRowB + fb + 4 * h);
-            const float bi = *(const float*)(Bs + tf * 16 * kRowB + fb + 4 * (1 - h));
+            const float bv = *(const float*)(Bs + tf * 16 * kRowB + fb + 4 * (1 - h));
+            const float bi = h ? -bv : bv;   // Im z = dr xi + di (-xr)
 #pragma unroll
             for (int ta = 0; ta < 4; ++ta) {
               re[ta][tf] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ta], br, re[ta][tf], 0, 0, 0);
-              im[ta][tf] = __builtin_amdgcn_mfma_f32_16x16x4f32(an[ta], bi, im[ta][tf], 0, 0, 0);
+              im[ta][tf] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ta], bi, im[ta][tf], 0, 0, 0);
             }
           }
         } else if constexpr (P == P_BF16) {
           const int ob = s * 32 + o * 16;
-          uint4 a[4], an[4];
+          const unsigned sg = h ? 0x80008000u : 0u;
+          uint4 a[4];
 #pragma unroll
-          for (int ta = 0; ta < 4; ++ta) {
-            a[ta] = *(const uint4*)(As + ta * 16 * kRowB + h * 64 + ob);
-            const unsigned sg = h ? 0x80008000u : 0u;
-            an[ta] = make_uint4(a[ta].x ^ sg, a[ta].y ^ sg, a[ta].z ^ sg, a[ta].w ^ sg);
-          }
+          for (int ta = 0; ta < 4; ++ta) a[ta] = *(const uint4*)(As + ta * 16 * kRowB + h * 64 + ob);
 #pragma unroll
           for (int tf = 0; tf < 4; ++tf) {
             const uint4 br = *(const uint4*)(Bs + tf * 16 * kRowB + h * 64 + ob);
-            const uint4 bi = *(const uint4*)(Bs + tf * 16 * kRowB + (1 - h) * 64 + ob);
+            const uint4 bv = *(const uint4*)(Bs + tf * 16 * kRowB + (1 - h) * 64 + ob);
+            const uint4 bi = make_uint4(bv.x ^ sg, bv.y ^ sg, bv.z ^ sg, bv.w ^ sg);   // Im z = dr xi + di (-xr)
 #pragma unroll
             for (int ta = 0; ta < 4; ++ta) {
               re[ta][tf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[ta]),
                                                                    __builtin_bit_cast(bf16x8, br), re[ta][tf], 0, 0, 0);
-              im[ta][tf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, an[ta]),
+              im[ta][tf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[ta]),
                                                                    __builtin_bit_cast(bf16x8, bi), im[ta][tf], 0, 0, 0);
             }
           }
@@ -230,35 +228,35 @@ __global__ __launch_bounds__(256) void k_match_top4(const void* __restrict__ A, 
 #pragma unroll
           for (int tf = 0; tf < 4; ++tf) {
             const uint4 br = *(const uint4*)(Bs + tf * 16 * kRowB + h * 64 + ob);
-            const uint4 bi = *(const uint4*)(Bs + tf * 16 * kRowB + (1 - h) * 64 + ob);
+            const uint4 bv = *(const uint4*)(Bs + tf * 16 * kRowB + (1 - h) * 64 + ob);
             const uint4 brl = *(const uint4*)(Bs2 + tf * 16 * kRowB + h * 64 + ob);
-            const uint4 bil = *(const uint4*)(Bs2 + tf * 16 * kRowB + (1 - h) * 64 + ob);
+            const uint4 bvl = *(const uint4*)(Bs2 + tf * 16 * kRowB + (1 - h) * 64 + ob);
+            // Im z = dr xi + di (-xr)
+            const uint4 bi = make_uint4(bv.x ^ sg, bv.y ^ sg, bv.z ^ sg, bv.w ^ sg);
+            const uint4 bil = make_uint4(bvl.x ^ sg, bvl.y ^ sg, bvl.z ^ sg, bvl.w ^ sg);
 #pragma unroll
             for (int ta = 0; ta < 4; ++ta) {
-              const uint4 an = make_uint4(a[ta].x ^ sg, a[ta].y ^ sg, a[ta].z ^ sg, a[ta].w ^ sg);
-              const uint4 anl = make_uint4(al[ta].x ^ sg, al[ta].y ^ sg, al[ta].z ^ sg, al[ta].w ^ sg);
               // hi hi + hi lo + lo hi; the lo lo product is below the accumulation's rounding
               f32x4 r = re[ta][tf], i = im[ta][tf];
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[ta]), __builtin_bit_cast(bf16x8, brl), r, 0, 0, 0);
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al[ta]), __builtin_bit_cast(bf16x8, br), r, 0, 0, 0);
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[ta]), __builtin_bit_cast(bf16x8, br), r, 0, 0, 0);
-              i = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, an), __builtin_bit_cast(bf16x8, bil), i, 0, 0, 0);
-              i = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, anl), __builtin_bit_cast(bf16x8, bi), i, 0, 0, 0);
-              i = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, an), __builtin_bit_cast(bf16x8, bi), i, 0, 0, 0);
+              i = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[ta]), __builtin_bit_cast(bf16x8, bil), i, 0, 0, 0);
+              i = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al[ta]), __builtin_bit_cast(bf16x8, bi), i, 0, 0, 0);
+              i = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[ta]), __builtin_bit_cast(bf16x8, bi), i, 0, 0, 0);
               re[ta][tf] = r;
               im[ta][tf] = i;
             }
           }
         } else {
           const int ob = o * 32;
-          i32x8 a[4], an[4];
+          const int sg = h ? (int)0x80808080u : 0;
+          i32x8 a[4];
 #pragma unroll
           for (int ta = 0; ta < 4; ++ta) {
             const uint4 lo = *(const uint4*)(As + ta * 16 * kRowB + h * 64 + ob);
             const uint4 hi = *(const uint4*)(As + ta * 16 * kRowB + h * 64 + ob + 16);
             a[ta] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
-            const int sg = h ? (int)0x80808080u : 0;
-            an[ta] = a[ta] ^ sg;
           }
 #pragma unroll
           for (int tf = 0; tf < 4; ++tf) {
@@ -267,12 +265,14 @@ __global__ __launch_bounds__(256) void k_match_top4(const void* __restrict__ A, 
             const uint4 ilo = *(const uint4*)(Bs + tf * 16 * kRowB + (1 - h) * 64 + ob);
             const uint4 ihi = *(const uint4*)(Bs + tf * 16 * kRowB + (1 - h) * 64 + ob + 16);
             const i32x8 br = {(int)rlo.x, (int)rlo.y, (int)rlo.z, (int)rlo.w, (int)rhi.x, (int)rhi.y, (int)rhi.z, (int)rhi.w};
-            const i32x8 bi = {(int)ilo.x, (int)ilo.y, (int)ilo.z, (int)ilo.w, (int)ihi.x, (int)ihi.y, (int)ihi.z, (int)ihi.w};
+            // Im z = dr xi + di (-xr)
+            const i32x8 bi = i32x8{(int)ilo.x, (int)ilo.y, (int)ilo.z, (int)ilo.w, (int)ihi.x, (int)ihi.y, (int)ihi.z,
+                                   (int)ihi.w} ^ sg;
 #pragma unroll
             for (int ta = 0; ta < 4; ++ta) {
               re[ta][tf] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[ta], br, re[ta][tf], 0, 0, 0, 0x7f7f7f7f, 0,
                                                                             0x7f7f7f7f);
-              im[ta][tf] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(an[ta], bi, im[ta][tf], 0, 0, 0, 0x7f7f7f7f,
+              im[ta][tf] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[ta], bi, im[ta][tf], 0, 0, 0, 0x7f7f7f7f,
                                                                             0, 0x7f7f7f7f);
             }
           }
@@ -280,6 +280,15 @@ __global__ __launch_bounds__(256) void k_match_top4(const void* __restrict__ A, 
       }
     }
     // epilogue: |z|^2 (times the atom's squared scale in FP8) into the running top-4 lists
+    float ls[4][4];
+    int li[4][4];
+#pragma unroll
+    for (int tf = 0; tf < 4; ++tf)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        ls[tf][k] = lsS[4 * tf + k][tid];
+        li[tf][k] = liS[4 * tf + k][tid];
+      }
 #pragma unroll
     for (int ta = 0; ta < 4; ++ta)
 #pragma unroll
@@ -294,6 +303,13 @@ __global__ __launch_bounds__(256) void k_match_top4(const void* __restrict__ A, 
           }
         }
       }
+#pragma unroll
+    for (int tf = 0; tf < 4; ++tf)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        lsS[4 * tf + k][tid] = ls[tf][k];
+        liS[4 * tf + k][tid] = li[tf][k];
+      }
   }
   // merge the 8 lists (2 atom waves x 4 lane groups) of each fingerprint column
   __syncthreads();
@@ -304,8 +320,8 @@ __global__ __launch_bounds__(256) void k_match_top4(const void* __restrict__ A, 
     const int col = wf * 64 + tf * 16 + n16, src = wa * 4 + q;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      cs[(col * 8 + src) * 4 + k] = ls[tf][k];
-      ci[(col * 8 + src) * 4 + k] = li[tf][k];
+      cs[(col * 8 + src) * 4 + k] = lsS[4 * tf + k][tid];
+      ci[(col * 8 + src) * 4 + k] = liS[4 * tf + k][tid];
     }
   }
   __syncthreads();
