@@ -957,7 +957,10 @@ __global__ __launch_bounds__(256) void k_coef(const cf* __restrict__ X, const cf
 // on MFMA. Blocks are numbered chunk-major and dealt to the XCDs in contiguous ranges, so each
 // XCD runs through all patch rows of its frames and consecutive rows find their shared pixels in
 // its L2.
-constexpr int kCsF = 16, kCsChunk = 64, kCsW = 20, kCsFS = 8 * kCsW + 1;
+#ifndef MRF_CS_CHUNK
+#define MRF_CS_CHUNK 256
+#endif
+constexpr int kCsF = 16, kCsChunk = MRF_CS_CHUNK, kCsW = 20, kCsFS = 8 * kCsW + 1;
 constexpr int kCsPer = kCsF * 8 * kCsW / 256;   // staged values per thread
 static_assert(kCsF * 8 * kCsW % 256 == 0, "whole stage per thread");
 __global__ __launch_bounds__(256) void k_coef_strip(const cf* __restrict__ X, const cf* __restrict__ U,
@@ -1463,7 +1466,10 @@ bool llr_xupdate_beta_ok(const PatchGeom& g, int rcap, int r) {
 mrf_status llr_xupdate_beta(const cf* beta, const cf* V, int r, const cf* U, const cf* C, const PatchGeom& g, int L,
                             int rcap, const double* kap_dev, double kap_scale, cf* Xout, hipStream_t s) {
   if (!llr_xupdate_beta_ok(g, rcap, r)) return fail(MRF_NOT_SUPPORTED, "x update from beta: geometry not supported");
-  const int fpb = 64;
+#ifndef MRF_XU_FPB
+#define MRF_XU_FPB 256
+#endif
+  const int fpb = MRF_XU_FPB;
   const int rows_per = (g.nc + 7) / 8;
   const int grid = 8 * rows_per * (g.nc / 4) * ((L + fpb - 1) / fpb);
   if (rcap <= 10)
