@@ -11,7 +11,7 @@ struct mrf_dict_s {
   float* bpk;        // [ntile][10][64] MFMA B operands of the subspace match (r <= 10)
   mrf::cf* V;        // [L][r]
   mrf::cf* dn;       // [M][L] unit-norm atoms (full-length matching and the FP32 re-rank)
-  int Lp;            // L rounded up to a multiple of 64: length of each part of the rows below
+  int Lp;            // L rounded up to a multiple of 128: length of each part of the rows below
   uint16_t* d16;     // [M][2 Lp] unit-norm atoms in BF16, real parts then imaginary parts
   uint16_t* d16lo;   // [M][2 Lp] the BF16 remainders (atom - BF16 atom, rounded to BF16)
   uint8_t* d8;       // [M][2 Lp] the same in FP8 (OCP E4M3), scaled per row

@@ -37,33 +37,41 @@ enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2, P_BF16X3 = 3 };
 constexpr int kGroups = 8;        // atom groups (one per XCD)
 constexpr int kTileM = 128;       // atoms per block tile
 constexpr int kTileN = 128;       // fingerprints per block tile
-constexpr int kRowB = 144;        // LDS bytes per staged row (128 + pad)
 constexpr int kE4m3Max = 448;
 constexpr int kGroupK = 8;        // candidates per group and fingerprint in the partial results
 constexpr int kMaxDepth = 32;     // deepest re-rank
 
+// Per precision: frames per chunk KC, MFMA K-steps per chunk, and the staged row: RB bytes of
+// data (RB / 2 of real parts, then RB / 2 of imaginary parts, except FP32's interleaved complex)
+// plus 16 bytes of padding.
 template <int P>
 struct MT;
 template <>
 struct MT<P_F32> {
   static constexpr int KC = 16;     // frames per chunk
   static constexpr int STEPS = 8;   // MFMA K-steps per chunk (2 frames each)
+  static constexpr int RB = 128;
 };
 template <>
 struct MT<P_BF16> {
   static constexpr int KC = 32;
   static constexpr int STEPS = 2;   // 16 frames each
+  static constexpr int RB = 128;
 };
 template <>
 struct MT<P_BF16X3> {   // rows as BF16 (hi, lo) pairs: A hi, B hi, A lo, B lo staged
   static constexpr int KC = 32;
   static constexpr int STEPS = 2;
+  static constexpr int RB = 128;
 };
 template <>
 struct MT<P_FP8> {
-  static constexpr int KC = 64;
-  static constexpr int STEPS = 1;   // 64 frames
+  static constexpr int KC = 128;
+  static constexpr int STEPS = 2;   // 64 frames each
+  static constexpr int RB = 256;
 };
+// the dictionary's padded length Lp (a multiple of 128) is a whole number of chunks of every form
+static_assert(128 % MT<P_FP8>::KC == 0 && 128 % MT<P_BF16>::KC == 0, "chunks divide 128 frames");
 
 __device__ inline void top4_insert(float (&sc)[4], int (&id)[4], float s, int m) {
   if (!(s > sc[3])) return;   // equal scores keep the earlier (lower) index
@@ -94,6 +102,7 @@ __global__ __launch_bounds__(256, P == P_BF16 ? 2 : 1) void k_match_top4(const v
                                                     const void* __restrict__ B2 = nullptr) {
   typedef MT<P> T;
   constexpr int NGRP = P == P_BF16X3 ? 4 : 2;   // staged row groups: A, B (hi), then A, B (lo)
+  constexpr int kRowB = T::RB + 16;             // LDS bytes per staged row
   __shared__ __attribute__((aligned(16))) unsigned char stage[NGRP * kTileM * kRowB];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int wa = w >> 1, wf = w & 1;
@@ -113,8 +122,10 @@ __global__ __launch_bounds__(256, P == P_BF16 ? 2 : 1) void k_match_top4(const v
     liS[k][tid] = -1;
   }
 
-  // register staging of one chunk: 2048 units of 16 B (P_F32: 4096 units of 8 B; P_BF16X3: 4096 of 16 B)
-  constexpr int NU = P == P_F32 ? 16 : (P == P_BF16X3 ? 16 : 8);
+  // register staging of one chunk: NGRP kTileM rows of RB bytes in units of 16 B (P_F32: 8 B)
+  constexpr int SEGS = P == P_F32 ? 16 : T::RB / 16;   // units per row
+  constexpr int NU = NGRP * kTileM * SEGS / 256;
+  static_assert(NGRP * kTileM * SEGS % 256 == 0 && 256 % SEGS == 0, "whole units per thread");
   typedef typename std::conditional<P == P_F32, uint2, uint4>::type U;
   U nxt[NU];
   auto load = [&](int a0, int c) {
@@ -132,18 +143,20 @@ __global__ __launch_bounds__(256, P == P_BF16 ? 2 : 1) void k_match_top4(const v
         if (gr < lim && f < L) v = base[(size_t)gr * L + f];
         nxt[k] = v;
       } else {
-        // u = tid + 256 k with tid >> 3 < 32: the staged row is 32 k + (tid >> 3), so its group
-        // (0 A, 1 B, 2 A lo, 3 B lo) is k / 4, fixed for each unrolled k
-        const int seg = tid & 7;
-        const int grp = k / (kTileM / 32);
-        const int rr = (tid >> 3) + 32 * (k % (kTileM / 32));
+        // u = tid + 256 k: the staged row is RPP k + tid / SEGS (RPP = 256 / SEGS rows per pass),
+        // so its group (0 A, 1 B, 2 A lo, 3 B lo) is k / (kTileM / RPP), fixed for each unrolled k
+        constexpr int RPP = 256 / SEGS, HS = SEGS / 2;   // HS: units per half (real or imaginary)
+        const int seg = tid % SEGS;
+        const int grp = k / (kTileM / RPP);
+        const int rr = tid / SEGS + RPP * (k % (kTileM / RPP));
         const bool isA = (grp & 1) == 0;
         const int gr = isA ? a0 + rr : f0 + rr;
         const int lim = isA ? M : Nv;
         constexpr int EB = P == P_FP8 ? 1 : 2;   // bytes per element
         const unsigned char* base = (const unsigned char*)(grp == 0 ? A : grp == 1 ? B : grp == 2 ? A2 : B2);
         if (gr < lim) {
-          const size_t off = (size_t)gr * 2 * Lp * EB + (size_t)(seg >> 2) * Lp * EB + (size_t)c * T::KC * EB + (seg & 3) * 16;
+          const size_t off = (size_t)gr * 2 * Lp * EB + (size_t)(seg / HS) * Lp * EB + (size_t)c * T::KC * EB +
+                             (seg % HS) * 16;
           v = *(const U*)(base + off);
         }
         nxt[k] = v;
@@ -154,8 +167,7 @@ __global__ __launch_bounds__(256, P == P_BF16 ? 2 : 1) void k_match_top4(const v
 #pragma unroll
     for (int k = 0; k < NU; ++k) {
       const int u = tid + 256 * k;
-      if constexpr (P == P_F32) *(U*)(stage + (u >> 4) * kRowB + (u & 15) * 8) = nxt[k];
-      else *(U*)(stage + (u >> 3) * kRowB + (u & 7) * 16) = nxt[k];
+      *(U*)(stage + (u / SEGS) * kRowB + (u % SEGS) * sizeof(U)) = nxt[k];
     }
   };
 
@@ -249,21 +261,21 @@ __global__ __launch_bounds__(256, P == P_BF16 ? 2 : 1) void k_match_top4(const v
             }
           }
         } else {
-          const int ob = o * 32;
+          const int ob = s * 64 + o * 32;
           const int sg = h ? (int)0x80808080u : 0;
           i32x8 a[4];
 #pragma unroll
           for (int ta = 0; ta < 4; ++ta) {
-            const uint4 lo = *(const uint4*)(As + ta * 16 * kRowB + h * 64 + ob);
-            const uint4 hi = *(const uint4*)(As + ta * 16 * kRowB + h * 64 + ob + 16);
+            const uint4 lo = *(const uint4*)(As + ta * 16 * kRowB + h * 128 + ob);
+            const uint4 hi = *(const uint4*)(As + ta * 16 * kRowB + h * 128 + ob + 16);
             a[ta] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
           }
 #pragma unroll
           for (int tf = 0; tf < 4; ++tf) {
-            const uint4 rlo = *(const uint4*)(Bs + tf * 16 * kRowB + h * 64 + ob);
-            const uint4 rhi = *(const uint4*)(Bs + tf * 16 * kRowB + h * 64 + ob + 16);
-            const uint4 ilo = *(const uint4*)(Bs + tf * 16 * kRowB + (1 - h) * 64 + ob);
-            const uint4 ihi = *(const uint4*)(Bs + tf * 16 * kRowB + (1 - h) * 64 + ob + 16);
+            const uint4 rlo = *(const uint4*)(Bs + tf * 16 * kRowB + h * 128 + ob);
+            const uint4 rhi = *(const uint4*)(Bs + tf * 16 * kRowB + h * 128 + ob + 16);
+            const uint4 ilo = *(const uint4*)(Bs + tf * 16 * kRowB + (1 - h) * 128 + ob);
+            const uint4 ihi = *(const uint4*)(Bs + tf * 16 * kRowB + (1 - h) * 128 + ob + 16);
             const i32x8 br = {(int)rlo.x, (int)rlo.y, (int)rlo.z, (int)rlo.w, (int)rhi.x, (int)rhi.y, (int)rhi.z, (int)rhi.w};
             // Im z = dr xi + di (-xr)
             const i32x8 bi = i32x8{(int)ilo.x, (int)ilo.y, (int)ilo.z, (int)ilo.w, (int)ihi.x, (int)ihi.y, (int)ihi.z,

@@ -497,7 +497,7 @@ extern "C" mrf_status mrf_dict_create(const mrf_c64* atoms, const float* lut, in
   auto* D = new mrf_dict_s{};
   D->M = M; D->L = L; D->r = V ? r : 0; D->nparam = nparam;
   D->ntile = (M + 15) / 16;
-  D->Lp = (L + 63) / 64 * 64;
+  D->Lp = (L + 127) / 128 * 128;   // a whole number of every match form's frame chunks
   bool ok = hipMalloc(&D->lut, (size_t)M * nparam * 4) == hipSuccess && hipMalloc(&D->norms, (size_t)M * 4) == hipSuccess &&
             hipMalloc(&D->dn, (size_t)M * L * sizeof(cf)) == hipSuccess &&
             hipMalloc(&D->d16, (size_t)M * 2 * D->Lp * 2) == hipSuccess &&
