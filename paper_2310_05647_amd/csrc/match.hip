@@ -12,14 +12,15 @@
 //
 // Block: 4 waves in a 2 x 2 grid over a 128-atom x 128-fingerprint tile, each wave 64 x 64
 // (4 x 4 MFMA tiles, separate real and imaginary accumulators). K advances in chunks whose rows
-// are 128 bytes in every precision (16 complex FP32 frames interleaved; 32 BF16 frames as
-// [re | im]; 64 FP8 frames as [re | im]), staged in LDS (rows padded to 144 bytes) while the
-// next chunk is loaded into registers. A block walks the atom tiles t = g (mod 8) of its group
+// are 128 bytes (16 complex FP32 frames interleaved; 32 BF16 frames as [re | im]) or 256 bytes
+// (128 FP8 frames as [re | im]), staged in LDS (rows padded by 16 bytes) while the next chunk is
+// loaded into registers. A block walks the atom tiles t = g (mod 8) of its group
 // g = blockIdx mod 8, so the blocks of one XCD stream the same atom tiles through its L2, and
 // keeps per lane a running top-4 (score desc, atom index asc) for each of its 4 fingerprint
-// columns (in LDS between atom tiles). The 8 candidate lists of a fingerprint column (32 candidates) are merged into the
-// block's top-kGroupK, written as the group's partial result; k_rerank takes the best `depth` of
-// the 8 groups' candidates and recomputes them exactly in FP32 from the FP32 atoms.
+// columns (in LDS between atom tiles). The 8 candidate lists of a fingerprint column (32
+// candidates) are merged into the block's top-kGroupK, written as the group's partial result;
+// k_rerank takes the best `depth` of the 8 groups' candidates and recomputes them exactly in FP32
+// from the FP32 atoms.
 #include <cfloat>
 #include <cmath>
 #include <type_traits>
@@ -95,11 +96,10 @@ __device__ inline void top4_insert(float (&sc)[4], int (&id)[4], float s, int m)
 // Partial results: pscore / pidx [Nv][kGroups][4].
 // BF16 fits two waves per SIMD (accumulators in the VGPRs, no spills); the other forms need one
 template <int P>
-__global__ __launch_bounds__(256, P == P_BF16 ? 2 : 1) void k_match_top4(const void* __restrict__ A, const float* __restrict__ sa, int M,
-                                                    const void* __restrict__ B, int Nv, int L, int Lp,
-                                                    float* __restrict__ pscore, int* __restrict__ pidx,
-                                                    const void* __restrict__ A2 = nullptr,
-                                                    const void* __restrict__ B2 = nullptr) {
+__global__ __launch_bounds__(256, P == P_BF16 ? 2 : 1) void k_match_top4(
+    const void* __restrict__ A, const float* __restrict__ sa, int M, const void* __restrict__ B, int Nv, int L, int Lp,
+    float* __restrict__ pscore, int* __restrict__ pidx, const void* __restrict__ A2 = nullptr,
+    const void* __restrict__ B2 = nullptr) {
   typedef MT<P> T;
   constexpr int NGRP = P == P_BF16X3 ? 4 : 2;   // staged row groups: A, B (hi), then A, B (lo)
   constexpr int kRowB = T::RB + 16;             // LDS bytes per staged row
