@@ -951,10 +951,10 @@ __global__ __launch_bounds__(256) void k_coef(const cf* __restrict__ X, const cf
 
 // Any p^2 <= 64: block per patch, thread per frame.
 // The same coefficients for 8 x 8 patches at stride 4, organised for reuse of X: a block takes 4
-// neighbouring patches of one patch row (one wave each) and a chunk of 64 frames. Per 16 frames
-// the block stages the 8 x 20 pixels its patches cover in LDS (frame stride 161 values: the 16
-// frames read by a quarter-wave fall on distinct bank pairs) and each wave forms its 16 x 16 tile
-// on MFMA. Blocks are numbered chunk-major and dealt to the XCDs in contiguous ranges, so each
+// neighbouring patches of one patch row (one wave each) and a chunk of kCsChunk frames (the
+// patches' U is read once per chunk). Per 16 frames the block stages the 8 x 20 pixels its
+// patches cover in LDS (frame stride 161 values: the 16 frames read by a quarter-wave fall on
+// distinct bank pairs) and each wave forms its 16 x 16 tile on MFMA. Blocks are numbered chunk-major and dealt to the XCDs in contiguous ranges, so each
 // XCD runs through all patch rows of its frames and consecutive rows find their shared pixels in
 // its L2.
 #ifndef MRF_CS_CHUNK
