@@ -97,6 +97,29 @@ def test_gradients_match_oracle(setup, bf16, B):
     assert worst <= tol
 
 
+def test_bf16_gradients_with_unaligned_widths_match_oracle(setup):
+    """Hidden width 30 (not a multiple of 4) and a ragged batch: the backward and weight-gradient
+    products of a layer then run as two launches instead of one (their operands do not allow
+    16-byte loads), and the split-K slices of every layer are still summed by the one finishing
+    launch. BF16 gradients against the oracle with BF16-rounded activations, as above."""
+    from paper_2310_05647_amd import MLP
+    s = setup
+    sizes = [20, 30, 30, 2]
+    net = MLP(n_in=sizes[0], hidden=sizes[1], layers=len(sizes) - 2, seed=2)
+    params = omlp.init_params(sizes, 7)
+    flat = _flat(params)
+    net.set_params(to_dev(flat))
+    z, t = _batch(s, 1000, 2)
+    loss, g = net.grads(to_dev(z), to_dev(t), bf16=True)
+    lref, gref = omlp.loss_and_grads(_unflat(flat, sizes), z.astype(np.float64), t.astype(np.float64),
+                                     act_round=omlp.bf16_round)
+    gg = _unflat(g.cpu().numpy(), sizes)
+    worst = max(max(rel_l2(dW, rW), rel_l2(db, rb)) for (dW, db), (rW, rb) in zip(gg, gref))
+    say(f"grads bf16, widths {sizes}: loss {loss:.6f} vs {lref:.6f}, worst rel-L2 {worst:.2e}")
+    assert abs(loss - lref) <= 1e-2 * lref
+    assert worst <= 3e-2
+
+
 def test_forward_and_adam_step_match_oracle(setup):
     s = setup
     params = omlp.init_params(SIZES, 4)
@@ -117,8 +140,8 @@ def test_forward_and_adam_step_match_oracle(setup):
     assert worst <= 1e-6
 
 
-@pytest.mark.parametrize("bf16", [True, False])
-def test_training_run_equals_its_steps_taken_one_by_one(setup, bf16):
+@pytest.mark.parametrize("bf16,hidden", [(True, 256), (False, 256), (True, 30)])
+def test_training_run_equals_its_steps_taken_one_by_one(setup, bf16, hidden):
     """The training entry point groups its launches (the BF16 step sums the weight gradients of all
     layers, takes the Adam step and draws the next batch in one launch); its parameters and losses
     equal those of the same steps taken through the separate calls: batch synthesis, gradients,
@@ -127,8 +150,8 @@ def test_training_run_equals_its_steps_taken_one_by_one(setup, bf16):
     s = setup
     seed, first, steps, total, lr, B = 0x5EED, 5, 4, 20, 2e-3, 1000
     lr32 = float(np.float32(lr))                 # the rate as the library holds it
-    a = MLP(n_in=2 * s["V"].shape[1], hidden=256, layers=3, seed=11)
-    b = MLP(n_in=2 * s["V"].shape[1], hidden=256, layers=3, seed=11)
+    a = MLP(n_in=2 * s["V"].shape[1], hidden=hidden, layers=3, seed=11)
+    b = MLP(n_in=2 * s["V"].shape[1], hidden=hidden, layers=3, seed=11)
     losses = a.train(s["d"], steps, batch=B, lr=lr, first_step=first, total_steps=total, seed=seed,
                      bf16=bf16).cpu().numpy()
     ref = []
@@ -139,7 +162,8 @@ def test_training_run_equals_its_steps_taken_one_by_one(setup, bf16):
         b.adam_step(float(np.float32(lr32 * 0.5 * (1.0 + np.cos(np.pi * step / total)))))
     pa, pb = a.get_params().cpu().numpy(), b.get_params().cpu().numpy()
     worst = float(np.abs(pa - pb).max())
-    say(f"train vs steps ({'bf16' if bf16 else 'fp32'}): max |dp| {worst:.2e}, losses {losses} vs {np.array(ref)}")
+    say(f"train vs steps ({'bf16' if bf16 else 'fp32'}, hidden {hidden}): max |dp| {worst:.2e}, "
+        f"losses {losses} vs {np.array(ref)}")
     assert worst <= 1e-7 * max(1.0, float(np.abs(pb).max()))
     np.testing.assert_allclose(losses, np.array(ref, dtype=np.float32), rtol=1e-6)
 
